@@ -1,0 +1,221 @@
+"""TBPM oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct FP64 CPU implementation of the TBPM DOS
+path of the paper (Sec. "Tight-binding propagation method" and Sec.
+"Density of states", Eq. (eq:psi_t), Eq. (eq:corr_dos), Eq. (dos_tbpm)).
+It checks the HIP library and shares no code with it.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import it; the product path never does.
+
+Pieces:
+  * :func:`bessel_j` -- J_m(z) by the power series, summed in 60+-digit
+    decimal arithmetic (Abramowitz & Stegun 9.1.10);
+  * :func:`n_terms` -- truncation of the Chebyshev/Bessel series;
+  * :func:`propagate` -- the paper's modified Chebyshev recurrence (plain C,
+    ``tbpm_oracle.c``), recording C_k = <phi0|psi_k> and ||psi_k||^2;
+  * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
+    correlation, summed directly (no FFT);
+  * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
+    check gradients.
+
+Readings of the paper that the oracle fixes (the paper is silent on them):
+  * the Chebyshev series keeps terms m = 0..M-1 where M is the smallest
+    m > z with |J_m(z)| < tol, and at least 3 terms;
+  * the Hann window is w_k = (1 + cos(pi k / N_t)) / 2 over the N_t samples;
+  * DOS grid E_j = j pi / (N_t dt), j = -N_t .. N_t - 1.
+Every function here is pinned by the ``-m "not gpu"`` tests against exact
+diagonalisation, closed forms and identities.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from decimal import Decimal, localcontext
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_propagate.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                         P, ctypes.c_int32, ctypes.c_int32, P, P, P]
+        lib.oracle_propagate.restype = ctypes.c_int
+        lib.oracle_backward.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                        P, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+        lib.oracle_backward.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+# ----------------------------------------------------------------------------
+# Bessel coefficients (Jacobi-Anger expansion of exp(-i z x))
+# ----------------------------------------------------------------------------
+
+def bessel_j(m: int, z: float) -> float:
+    """J_m(z) for integer m >= 0 from the power series
+    J_m(z) = sum_k (-1)^k (z/2)^(2k+m) / (k! (k+m)!), summed in decimal
+    arithmetic with enough digits to absorb the cancellation for large z."""
+    if m < 0:
+        raise ValueError("order must be >= 0")
+    if z == 0.0:
+        return 1.0 if m == 0 else 0.0
+    digits = 60 + int(abs(z) * 0.45)
+    with localcontext() as ctx:
+        ctx.prec = digits
+        x = Decimal(z) / 2
+        x2 = x * x
+        term = x ** m / Decimal(math.factorial(m))
+        total = term
+        k = 0
+        tiny = Decimal(10) ** (-45)
+        while True:
+            k += 1
+            term = -term * x2 / (k * (k + m))
+            total += term
+            if k > abs(x) and abs(term) < tiny:
+                break
+        return float(total)
+
+
+def n_terms(z: float, tol: float = 1e-12) -> int:
+    """Number M of Chebyshev terms kept: the smallest m > |z| with
+    |J_m(z)| < tol (terms m = 0..M-1 are used), and at least 3."""
+    m = int(math.floor(abs(z))) + 1
+    while abs(bessel_j(m, z)) >= tol:
+        m += 1
+    return max(3, m)
+
+
+def gershgorin(row_ptr, val, onsite) -> float:
+    """Gershgorin bound max_i (|eps_i| + sum_j |H_ij|) of the spectral radius."""
+    n = onsite.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    radius = np.zeros(n)
+    np.add.at(radius, rows, np.abs(val))
+    return float(np.max(np.abs(onsite) + radius))
+
+
+def _prep(row_ptr, col, val, onsite, psi0):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.complex128)
+    onsite = np.ascontiguousarray(onsite, dtype=np.float64)
+    psi0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+    if psi0.ndim == 1:
+        psi0 = psi0[:, None].copy()
+    return row_ptr, col, val, onsite, psi0
+
+
+def _scale_and_coeffs(row_ptr, val, onsite, dt, rescale, tol):
+    f = float(rescale) if rescale > 0 else gershgorin(row_ptr, val, onsite)
+    z = f * dt
+    M = n_terms(z, tol)
+    J = np.array([bessel_j(m, z) for m in range(M)], dtype=np.float64)
+    return f, M, J
+
+
+def propagate(row_ptr, col, val, onsite, psi0, n_steps: int, dt: float, rescale: float,
+              tol: float = 1e-12):
+    """C_k = <phi0|psi_k> and ||psi_k||^2 for k = 0..n_steps-1 (paper, Eq. eq:psi_t).
+
+    Returns (corr [n_steps, S] complex128, norm2 [n_steps, S] float64, info dict).
+    """
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    f, M, J = _scale_and_coeffs(row_ptr, val, onsite, dt, rescale, tol)
+    corr = np.zeros((n_steps, S), dtype=np.complex128)
+    norm2 = np.zeros((n_steps, S), dtype=np.float64)
+    rc = _load().oracle_propagate(n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                  onsite.ctypes.data, f, S, psi0.ctypes.data, n_steps, M,
+                                  J.ctypes.data, corr.ctypes.data, norm2.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_propagate failed")
+    return corr, norm2, {"rescale": f, "z": f * dt, "M": M, "J": J}
+
+
+def energies(n_steps: int, dt: float) -> np.ndarray:
+    """DOS grid E_j = j pi / (N_t dt), j = -N_t .. N_t-1."""
+    j = np.arange(-n_steps, n_steps)
+    return j * np.pi / (n_steps * dt)
+
+
+def window(n_steps: int, kind: str = "hann") -> np.ndarray:
+    k = np.arange(n_steps)
+    if kind == "hann":
+        return 0.5 * (1.0 + np.cos(np.pi * k / n_steps))
+    if kind == "none":
+        return np.ones(n_steps)
+    raise ValueError(kind)
+
+
+def dos(corr, dt: float, kind: str = "hann"):
+    """D(E) = (1/S) sum_p (1/2pi) int e^{iEt} C_p(t) dt  (paper, Eq. dos_tbpm).
+
+    Using C(-t) = conj C(t), the integral over the sampled times t_k = k dt is
+    D(E_j) = dt/(2 pi) [w_0 Re Cbar_0 + 2 sum_{k>=1} w_k Re(Cbar_k e^{i E_j t_k})].
+    Summed directly over k for every energy (no FFT).
+    """
+    corr = np.asarray(corr, dtype=np.complex128)
+    if corr.ndim == 1:
+        corr = corr[:, None]
+    n_steps = corr.shape[0]
+    cbar = corr.mean(axis=1)
+    w = window(n_steps, kind)
+    E = energies(n_steps, dt)
+    t = np.arange(n_steps) * dt
+    out = np.empty(E.shape[0])
+    for a in range(0, E.shape[0], 256):
+        ph = np.exp(1j * np.outer(E[a:a + 256], t))
+        terms = (w * cbar)[None, :] * ph
+        out[a:a + 256] = w[0] * cbar[0].real + 2.0 * terms[:, 1:].real.sum(axis=1)
+    return E, out * dt / (2.0 * np.pi)
+
+
+def dos_adjoint(gdos, n_steps: int, n_states: int, dt: float, kind: str = "hann"):
+    """Adjoint of :func:`dos` with respect to the per-state correlations.
+
+    Given gdos_j = dL/dD_j, returns G[k, s] with dL = Re sum conj(G) dC.
+    From D_j above: dD_j/dRe C_k = (dt/pi) w_k cos(E_j t_k)/S,
+    dD_j/dIm C_k = -(dt/pi) w_k sin(E_j t_k)/S for k >= 1, and only Re C_0
+    enters with weight dt/(2 pi) w_0 / S.
+    """
+    gdos = np.asarray(gdos, dtype=np.float64)
+    w = window(n_steps, kind)
+    E = energies(n_steps, dt)
+    t = np.arange(n_steps) * dt
+    g = np.zeros(n_steps, dtype=np.complex128)
+    for k in range(n_steps):
+        s = np.sum(gdos * np.exp(-1j * E * t[k]))
+        g[k] = (dt / np.pi) * w[k] * s if k > 0 else (dt / (2 * np.pi)) * w[0] * s.real
+    return np.repeat((g / n_states)[:, None], n_states, axis=1)
+
+
+def backward(row_ptr, col, val, onsite, psi0, n_steps: int, dt: float, rescale: float,
+             gcorr, tol: float = 1e-12):
+    """Gradient of L through C_k (dL = Re sum conj(gcorr) dC) with respect to the
+    stored off-diagonal entries (complex, dL = Re sum conj(G_pq) dH_pq) and the
+    on-site energies (real).  Rescale f and dt are fixed.  Tiny systems only."""
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    gcorr = np.ascontiguousarray(gcorr, dtype=np.complex128).reshape(n_steps, S)
+    f, M, J = _scale_and_coeffs(row_ptr, val, onsite, dt, rescale, tol)
+    gval = np.zeros(col.shape[0], dtype=np.complex128)
+    gons = np.zeros(n, dtype=np.float64)
+    rc = _load().oracle_backward(n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                 onsite.ctypes.data, f, S, psi0.ctypes.data, n_steps, M,
+                                 J.ctypes.data, gcorr.ctypes.data, gval.ctypes.data, gons.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_backward failed")
+    return gval, gons
