@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""TBPM propagation benchmark on one MI355X.
+
+Workload (one "step" = one pass of the whole TBPM DOS path over one batch):
+disordered periodic graphene, 1024 x 1024 cells (2,097,152 orbitals), Anderson
+disorder W = 1 eV, 8 random-phase states propagated together, 2048
+correlation samples at f = 9 eV, dt = pi/f, Chebyshev terms until
+|J_m| < 1e-12 (18 terms, 17 sparse passes per time step), FP64, then the
+Hann-windowed DOS on 4096 energies.  Inputs are resident in HBM before the
+timed region.
+
+Metric: nnz-updates/s = (stored off-diagonal nnz + N) * S * (M - 1) * (N_t - 1)
+per step / step time.  Extra fields report the FP32-mixed form of the same
+workload (speed and DOS error against FP64), the dominant kernel against the
+HBM roofline, and the CPU oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+KERNEL_SOURCES = ["paper_2209_00806_amd/csrc/kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pass_mid_graphene1024_s8_fp64.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
+    """Algorithmic HBM bytes of one Clenshaw pass: 4 state streams (read the
+    gathered b_{j+1}, b_{j+2} and psi once, write b_j), the sliced-ELL matrix
+    (4-byte column + v-byte value per stored element) and the on-site vector."""
+    return 4 * b * n_orb * S + nnz * (4 + v) + n_orb * v
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cells", type=int, default=1024)
+    ap.add_argument("--states", type=int, default=8)
+    ap.add_argument("--nt", type=int, default=2048, help="correlation samples per step (2048 = the workload)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2209_00806_amd import inputs, tbpm
+
+    dev = torch.device("cuda:0")
+    f = 9.0
+    dt = math.pi / f
+    S = args.states
+    nt = args.nt
+    t0 = time.time()
+    lat, psi0_np = inputs.workload_disordered_graphene(args.cells, S)
+    log(f"workload built: N={lat.n_orb} nnz={lat.nnz} in {time.time() - t0:.1f}s")
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    psi0 = torch.from_numpy(psi0_np).to(dev)
+    del psi0_np
+    M = tbpm.num_terms(f * dt, 1e-12)
+    n_pass = M - 1
+    if args.autotune:
+        cfg, ms = H.autotune(S, "fp64")
+        log(f"autotuned launch config {cfg} ({ms:.3f} ms/step)")
+    stream = torch.cuda.current_stream()
+
+    def one_step(precision="fp64"):
+        corr = tbpm.propagate(H, psi0, nt, dt, f, precision=precision)
+        E, D = tbpm.dos(corr, dt)
+        return corr, E, D
+
+    for w in range(args.warmup):
+        one_step()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        corr64, E, D64 = one_step()
+        log(f"step {k + 1}/{args.steps} done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_per_step = ev0.elapsed_time(ev1) / max(args.steps, 1)
+    updates = (lat.nnz + lat.n_orb) * S * n_pass * (nt - 1)
+    value = updates / (ms_per_step / 1e3)
+    step_bytes = pass_bytes(lat.n_orb, lat.nnz, S, 16, 8) * n_pass * (nt - 1)
+    log(f"fp64: {ms_per_step:.1f} ms/step (wall {t_wall / max(args.steps, 1) * 1e3:.1f}), "
+        f"{value:.3e} nnz-updates/s, {step_bytes / (ms_per_step / 1e3) / 1e9:.0f} GB/s algorithmic")
+
+    # dominant kernel: the interior Clenshaw pass, timed in isolation on the same stream
+    n_launch = 200
+    tbpm.bench_pass(H, S, "fp64", 10)
+    ka = torch.cuda.Event(enable_timing=True)
+    kb = torch.cuda.Event(enable_timing=True)
+    ka.record(stream)
+    tbpm.bench_pass(H, S, "fp64", n_launch)
+    kb.record(stream)
+    torch.cuda.synchronize()
+    pass_ms = ka.elapsed_time(kb) / n_launch
+    alg = pass_bytes(lat.n_orb, lat.nnz, S, 16, 8)
+    achieved = alg / (pass_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_pass<double,real,MID> (interior Clenshaw pass)",
+                "kernel_avg_ms": round(pass_ms, 5), "algorithmic_bytes_per_launch": alg}
+    log(f"interior pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of peak)")
+
+    extra = {}
+    c64 = corr64.cpu().numpy()
+    d64 = D64.cpu().numpy()
+    extra["fp64_norm_dev_max"] = None
+    if not args.no_fp32:
+        one_step("fp32")  # warm-up of the FP32 graph
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        corr32, _, D32 = one_step("fp32")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1)
+        d32 = D32.cpu().numpy()
+        l1 = float(np.sum(np.abs(d32 - d64)) / np.sum(np.abs(d64)))
+        cerr = float(np.max(np.abs(corr32.cpu().numpy().mean(1) - c64.mean(1))) / np.max(np.abs(c64.mean(1))))
+        extra["fp32_mixed"] = {"ms_per_step": round(ms32, 2), "nnz_updates_per_s": updates / (ms32 / 1e3),
+                               "speedup_vs_fp64": round(ms_per_step / ms32, 3),
+                               "dos_l1_rel_err_vs_fp64": l1, "corr_max_rel_err_vs_fp64": cerr,
+                               "alg_GBps": round(pass_bytes(lat.n_orb, lat.nnz, S, 8, 4) * n_pass * (nt - 1)
+                                                 / (ms32 / 1e3) / 1e9, 1)}
+        log(f"fp32-mixed: {ms32:.1f} ms/step, speedup {ms_per_step / ms32:.2f}x, DOS L1 err {l1:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        one_state = np.ascontiguousarray(psi0[:, :1].cpu().numpy())
+        # calibrate: 2 correlation samples = 1 time step
+        tc = time.perf_counter()
+        oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, one_state, 2, dt, f)
+        t1 = time.perf_counter() - tc
+        n_cpu = max(2, int(args.cpu_seconds / max(t1, 1e-3)))
+        tc = time.perf_counter()
+        oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, one_state, n_cpu + 1, dt, f)
+        tcpu = time.perf_counter() - tc
+        cpu_updates = (lat.nnz + lat.n_orb) * 1 * n_pass * n_cpu
+        cpu = {"value": cpu_updates / tcpu, "unit": "nnz-updates/s", "cores": threads, "kind": "oracle",
+               "sample": f"1 of {S} states, {n_cpu} of {nt - 1} time steps of the same workload "
+                         f"({tcpu:.1f} s on the host)"}
+        log(f"cpu oracle: {cpu['value']:.3e} nnz-updates/s on {threads} threads ({tcpu:.1f}s)")
+
+    rec = {
+        "metric": "TBPM propagation nnz-updates/s (FP64), with HBM GB/s vs peak and FP32-mixed vs FP64",
+        "value": value,
+        "unit": "nnz-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"disordered graphene {args.cells}x{args.cells} cells "
+                               f"({lat.n_orb} orbitals, Anderson W=1 eV), {S} random-phase states, "
+                               f"{nt} correlation samples, f=9 eV, dt=pi/f, {M} Chebyshev terms, "
+                               f"Hann DOS on {2 * nt} energies",
+                   "n_orb": lat.n_orb, "nnz_offdiag": lat.nnz, "n_states": S, "n_steps": nt,
+                   "chebyshev_terms": M, "launch": H.launch_config()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "alg_GBps_step": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "extra": extra,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

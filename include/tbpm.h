@@ -1,0 +1,310 @@
+/*
+ * libtbpm -- TBPM (tight-binding propagation method) on AMD Instinct MI355X.
+ *
+ * C ABI over hand-written HIP kernels for gfx950.  The library evolves
+ * random initial states under a sparse Hermitian tight-binding Hamiltonian
+ * with the Chebyshev/Bessel expansion of exp(-i H dt), records the DOS
+ * correlation C(t) = <psi(0)|psi(t)> at every step, and turns the
+ * sample-averaged correlation into a density of states (paper: Sec.
+ * "Tight-binding propagation method", Eq. (eq:psi_t); Sec. "Density of
+ * states", Eq. (eq:corr_dos) and Eq. (dos_tbpm)).  It also provides the
+ * exact adjoint of that computation (gradients of a loss on the DOS with
+ * respect to the hoppings and on-site energies), a batched form that
+ * propagates many Hamiltonians in one launch sequence, and an FP32
+ * recursion with FP64 reductions.
+ *
+ * General conventions
+ *   - Every function returns a tbpm_status and never throws; on error
+ *     tbpm_last_error() gives a message (thread-local).
+ *   - Complex numbers are interleaved (re, im) pairs of double, i.e. the
+ *     memory layout of complex128 / double2.
+ *   - State vectors are orbital-major with the states interleaved:
+ *     psi[(i * n_states + s) * 2 + {0: re, 1: im}], i.e. [n_orb][n_states]
+ *     complex128.  Correlations are [n_steps][n_states] complex128.
+ *   - "device" pointers are HIP device memory on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every
+ *     buffer it passes in; the library owns only what its handles hold.
+ *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *     void*; NULL means the default stream).
+ *   - Inputs are validated on the host before any device work.
+ *   - Limits: n_orb < 2^31 per Hamiltonian and in total per batch.
+ */
+#ifndef TBPM_H
+#define TBPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tbpm_hamiltonian tbpm_hamiltonian; /* opaque, library-owned device copy of H */
+typedef struct tbpm_batch tbpm_batch;             /* opaque, several Hamiltonians concatenated */
+
+typedef enum {
+    TBPM_OK = 0,
+    TBPM_E_ARG = 1,           /* bad argument: NULL pointer, size out of range, non-finite value */
+    TBPM_E_CSR = 2,           /* malformed CSR: row_ptr not monotone, column out of range, diagonal entry */
+    TBPM_E_NOT_HERMITIAN = 3, /* |H_ij - conj(H_ji)| > 1e-13 max|H| for some stored pair */
+    TBPM_E_OOM = 4,           /* device or host allocation failed */
+    TBPM_E_DEVICE = 5,        /* HIP runtime error (no device, launch or copy failure) */
+    TBPM_E_DIVERGED = 6       /* norm check failed: the spectrum is not inside [-rescale, rescale] */
+} tbpm_status;
+
+typedef enum {
+    TBPM_FP64 = 0,      /* complex128 states, FP64 matrix and arithmetic */
+    TBPM_FP32_MIXED = 1 /* complex64 states and FP32 recursion; correlation, norm and DOS in FP64 */
+} tbpm_precision;
+
+typedef enum {
+    TBPM_WIN_HANN = 0, /* w_k = (1 + cos(pi k / n_steps)) / 2 */
+    TBPM_WIN_NONE = 1  /* w_k = 1 */
+} tbpm_window;
+
+/* flags */
+#define TBPM_FLAG_DEVICE_PTRS 0x1u /* set_values: val/onsite are device pointers */
+#define TBPM_FLAG_ASYNC 0x2u       /* propagate: do not synchronise; skip the norm check */
+#define TBPM_FLAG_NO_GRAPH 0x4u    /* propagate: plain kernel launches instead of a replayed HIP graph */
+
+/* ------------------------------------------------------------------------
+ * Hamiltonian
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Build the device Hamiltonian H_ij = eps_i delta_ij + (off-diagonal
+ * element)_ij of a tight-binding model (paper: Sec. "Tight-binding models",
+ * Eq. (hal) and Eq. (eq:ham_mat_finite)).
+ *
+ *   n_orb    number of orbitals (rows), 1 <= n_orb < 2^31.
+ *   row_ptr  host, [n_orb + 1], row_ptr[0] = 0, non-decreasing; nnz = row_ptr[n_orb].
+ *   col_idx  host, [nnz], column of each stored off-diagonal element, in [0, n_orb),
+ *            never equal to its row.  Order inside a row is free; repeated
+ *            (row, col) pairs are summed.
+ *   val      host, [2 * nnz] doubles, the complex matrix elements H_ij (not -t_ij:
+ *            a hopping written "t = -2.7 eV" is passed as -2.7).  The FULL Hermitian
+ *            pattern is required (both (i,j) and (j,i)); the paper's half list with
+ *            t_ij(R) = t_ji(-R)^* must be expanded by the caller.
+ *   onsite   host, [n_orb], real on-site energies eps_i (eV).
+ *   out      receives the handle; release with tbpm_hamiltonian_destroy.
+ * Errors: TBPM_E_ARG, TBPM_E_CSR, TBPM_E_NOT_HERMITIAN (checked on the host
+ * before any device call), TBPM_E_OOM, TBPM_E_DEVICE.  On error *out is NULL.
+ * If every stored element has zero imaginary part the device copy is real.
+ */
+tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const int32_t *col_idx,
+                                    const double *val, const double *onsite,
+                                    tbpm_hamiltonian **out);
+
+/*
+ * Replace the values of H on the same pattern: val [2 * nnz] in the merged
+ * CSR order (rows in order, columns ascending inside a row, duplicates merged;
+ * see tbpm_hamiltonian_pattern -- for an input that is already sorted and
+ * duplicate-free this is the input order), onsite [n_orb].  With
+ * TBPM_FLAG_DEVICE_PTRS both are device pointers, the copy is enqueued on
+ * 'stream' and Hermiticity is NOT re-checked; otherwise host pointers,
+ * validated like create.  A real H stays real: the imaginary parts of val
+ * are ignored unless H was created complex.
+ */
+tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, const double *onsite,
+                                        uint32_t flags, void *stream);
+
+/*
+ * Query H.  Any output pointer may be NULL.
+ *   n_orb, nnz   sizes of the stored pattern (nnz after merging duplicates)
+ *   gershgorin   max_i (|eps_i| + sum_j |H_ij|), an upper bound of ||H|| used
+ *                when a propagate call passes rescale <= 0 (paper, Sec. "Tight-
+ *                binding propagation method": rescaling H~ = H/||H||)
+ *   is_complex   1 if the device copy holds complex elements
+ *   max_row      largest number of stored off-diagonal elements in a row
+ */
+tbpm_status tbpm_hamiltonian_info(const tbpm_hamiltonian *H, int64_t *n_orb, int64_t *nnz,
+                                  double *gershgorin, int32_t *is_complex, int32_t *max_row);
+
+/* The CSR pattern after merging duplicates (host arrays of n_orb+1 and nnz). */
+tbpm_status tbpm_hamiltonian_pattern(const tbpm_hamiltonian *H, int64_t *row_ptr, int32_t *col_idx);
+
+tbpm_status tbpm_hamiltonian_destroy(tbpm_hamiltonian *H);
+
+/* ------------------------------------------------------------------------
+ * Chebyshev/Bessel coefficients (host only; no device needed)
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Number of terms M of the expansion exp(-i z x) = J_0(z) + 2 sum_{m>=1}
+ * (-i)^m J_m(z) T_m(x) (paper, Sec. "Tight-binding propagation method",
+ * Jacobi-Anger expansion): the smallest m > |z| with |J_m(z)| < tol, and at
+ * least 3.  Terms m = 0..M-1 are kept.  0 < tol < 1, |z| <= 1e4.
+ */
+tbpm_status tbpm_num_terms(double z, double tol, int32_t *M);
+
+/* J_0(z) .. J_{M-1}(z) into J[M] (host), by Miller's backward recurrence
+ * normalised with J_0 + 2 sum_k J_2k = 1 (Abramowitz & Stegun 9.1.46, 9.12). */
+tbpm_status tbpm_bessel_j(double z, int32_t M, double *J);
+
+/* ------------------------------------------------------------------------
+ * Propagation and DOS
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Propagate n_states initial states and record the DOS correlation
+ * (paper, Eq. (eq:psi_t) and Eq. (eq:corr_dos)):
+ *   psi(0) = psi0,  psi((k+1) dt) = P psi(k dt),  P = sum_{m<M} c_m T_m(H/f),
+ *   c_0 = J_0(z), c_m = 2 (-i)^m J_m(z),  z = f dt,
+ *   corr[k][s]  = <psi0_s | psi_s(k dt)>,   k = 0 .. n_steps-1,
+ *   norm2[k][s] = ||psi_s(k dt)||^2.
+ * The series is evaluated by Clenshaw's recurrence on the GPU.
+ *
+ *   psi0        device, [n_orb][n_states] complex128; read only.
+ *   n_states    1 .. 64.
+ *   n_steps     number of correlation samples N_t >= 1 (N_t - 1 time steps).
+ *   dt          time step in hbar/eV (> 0); the paper uses dt = pi / f.
+ *   rescale     f in eV (> 0); <= 0 selects the Gershgorin bound.  The
+ *               spectrum of H must lie in [-f, f].
+ *   bessel_tol  truncation threshold of the series (e.g. 1e-12), see tbpm_num_terms.
+ *   prec        TBPM_FP64 or TBPM_FP32_MIXED.
+ *   corr        device, [n_steps][n_states] complex128, written.
+ *   norm2       device, [n_steps][n_states] double, written; may be NULL.
+ *   ckpt_every  K > 0 to store checkpoints for tbpm_backward, else 0.
+ *   ckpt        device, [max(0, (n_steps - 2) / K)][n_orb][n_states] complex128:
+ *               ckpt[m-1] = psi(m K dt) for m K <= n_steps - 2 (TBPM_FP64 only).
+ *   flags       TBPM_FLAG_ASYNC, TBPM_FLAG_NO_GRAPH.
+ *   stream      hipStream_t or NULL.
+ * Unless TBPM_FLAG_ASYNC is set, the call synchronises the stream and
+ * returns TBPM_E_DIVERGED if some ||psi_s(k dt)||^2 / ||psi0_s||^2 leaves
+ * [1 - 1e-3, 1 + 1e-3] or is not finite (H outside [-f, f]).
+ * Calls on the same H must not overlap (they share its work buffers).
+ */
+tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                           double dt, double rescale, double bessel_tol, tbpm_precision prec,
+                           double *corr, double *norm2, int32_t ckpt_every, double *ckpt,
+                           uint32_t flags, void *stream);
+
+/*
+ * DOS from the correlations (paper, Eq. (dos_tbpm), with C(-t) = C(t)^*):
+ *   Cbar_k = (1/S) sum_s corr[k][s],
+ *   E_j = j pi / (N_t dt),  j = -N_t .. N_t - 1   (2 N_t energies),
+ *   D(E_j) = dt/(2 pi) [w_0 Re Cbar_0 + 2 sum_{k=1}^{N_t-1} w_k Re(Cbar_k e^{i E_j k dt})].
+ * corr device [n_steps][n_states] complex128; energies, dos device [2 n_steps].
+ * The sum is direct (no FFT), in FP64 with compensated summation, in a
+ * fixed order.
+ */
+tbpm_status tbpm_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, tbpm_window win,
+                     double *energies, double *dos, void *stream);
+
+/*
+ * Adjoint of tbpm_dos: given grad_dos[j] = dL/dD(E_j) (device, [2 n_steps]),
+ * writes grad_corr (device, [n_steps][n_states] complex128) such that
+ * dL = Re sum_{k,s} conj(grad_corr[k][s]) d corr[k][s].
+ */
+tbpm_status tbpm_dos_backward(const double *grad_dos, int32_t n_steps, int32_t n_states, double dt,
+                              tbpm_window win, double *grad_corr, void *stream);
+
+/*
+ * Gradient of a loss L(corr) with respect to the Hamiltonian, through the
+ * propagation of tbpm_propagate (exact discrete adjoint of the Clenshaw
+ * evaluation; f and dt fixed).
+ *   grad_corr   device, [n_steps][n_states] complex128, with
+ *               dL = Re sum conj(grad_corr) d corr  (PyTorch's convention).
+ *   ckpt_every, ckpt  the checkpoints written by tbpm_propagate with the same
+ *               psi0, n_steps, dt, rescale and bessel_tol (K > 0 required).
+ *   grad_val    device, [2 * nnz] complex128 in the merged CSR order
+ *               (tbpm_hamiltonian_pattern): G_pq with dL = Re sum conj(G_pq) dH_pq.
+ *   grad_onsite device, [n_orb] double: dL/d eps_i.
+ * Both gradients are summed over the states.  FP64 only.  Device memory of
+ * about K * (M - 1) + 8 state-sized vectors is used for the segment replay.
+ */
+tbpm_status tbpm_backward(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                          double dt, double rescale, double bessel_tol, const double *grad_corr,
+                          int32_t ckpt_every, const double *ckpt, double *grad_val,
+                          double *grad_onsite, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched propagation of several Hamiltonians of uneven size
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Concatenate n_ham Hamiltonians into one block-diagonal device operator
+ * so that every Chebyshev pass of all of them is one kernel launch.  The
+ * handles must stay alive while the batch is used; later set_values calls
+ * on them are not seen by the batch.
+ */
+tbpm_status tbpm_batch_create(tbpm_hamiltonian *const *Hs, int32_t n_ham, tbpm_batch **out);
+tbpm_status tbpm_batch_destroy(tbpm_batch *B);
+
+/*
+ * tbpm_propagate for every member of the batch at once (paper: samples and
+ * Hamiltonians are independent, Sec. "TBPM" of the parallelisation part).
+ *   psi0[i], corr[i], norm2[i]: host arrays of n_ham device pointers, laid
+ *   out as in tbpm_propagate for member i (norm2 may be NULL, or contain NULLs).
+ *   dt[i], rescale[i]: host arrays; each member has its own z_i = f_i dt_i
+ *   and coefficient set.  n_states is common.  Flags as tbpm_propagate; the
+ *   norm check covers every member.
+ */
+tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int32_t n_states,
+                                   int32_t n_steps, const double *dt, const double *rescale,
+                                   double bessel_tol, tbpm_precision prec, double *const *corr,
+                                   double *const *norm2, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Launch configuration and autotuning
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Launch shape of the Chebyshev pass kernels:
+ *   wg_chunks   row chunks handled by one workgroup (1, 2, 4, 8, 16 or 32);
+ *               one chunk is 256 state elements
+ *   xcd_remap   1: give each of the 8 XCDs a contiguous range of tiles
+ *   nontemporal 1: stream the read-once vectors with non-temporal hints
+ */
+typedef struct {
+    int32_t wg_chunks;
+    int32_t xcd_remap;
+    int32_t nontemporal;
+} tbpm_launch_config;
+
+tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_launch_config *cfg);
+tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, const tbpm_launch_config *cfg);
+tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, const tbpm_launch_config *cfg);
+tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_launch_config *cfg);
+
+/*
+ * Autotune the launch configuration of H (or of a batch) for n_states and
+ * prec by timing every candidate on a few Chebyshev steps of scratch states
+ * on 'stream' (synchronises).  The best configuration is stored in the
+ * handle and returned in *best (may be NULL); its mean step time in ms in
+ * *best_ms (may be NULL).
+ */
+tbpm_status tbpm_autotune(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec,
+                          tbpm_launch_config *best, double *best_ms, void *stream);
+tbpm_status tbpm_batch_autotune(tbpm_batch *B, int32_t n_states, tbpm_precision prec,
+                                tbpm_launch_config *best, double *best_ms, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------ */
+
+/* Plain streaming copy of 'bytes' (multiple of 16) from src to dst (device),
+ * used to calibrate achievable HBM bandwidth and the profiler's byte counters. */
+tbpm_status tbpm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/*
+ * Enqueue n_launch back-to-back launches of the interior Clenshaw pass kernel
+ * (b_j = c_j v + 2 H~ b_{j+1} - b_{j+2}) on H's work buffers, for timing the
+ * dominant kernel in isolation.  A tbpm_propagate call with the same
+ * n_states and prec must have been made on H first (it sizes and fills the
+ * buffers); the buffers' contents stay bounded but are overwritten.
+ */
+tbpm_status tbpm_bench_pass(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec, int32_t n_launch,
+                            void *stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char *tbpm_last_error(void);
+
+/* Library version string. */
+const char *tbpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBPM_H */

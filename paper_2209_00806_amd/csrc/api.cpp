@@ -1,0 +1,375 @@
+// C ABI of libtbpm (declared in include/tbpm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tbpm_engine.h"
+#include "tbpm_internal.h"
+
+using namespace tbpm;
+
+namespace tbpm {
+tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps, double dt,
+                          double rescale, double tol, const double *grad_corr, int32_t ckpt_every,
+                          const double *ckpt, double *grad_val, double *grad_onsite, hipStream_t stream);
+tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32_t n_states, bool fp32,
+                          tbpm_launch_config *best, double *best_ms, hipStream_t stream);
+}  // namespace tbpm
+
+namespace {
+
+bool valid_cfg(const tbpm_launch_config &c) {
+    const int ok[] = {1, 2, 4, 8, 16, 32};
+    return std::find(std::begin(ok), std::end(ok), c.wg_chunks) != std::end(ok) && (c.xcd_remap == 0 || c.xcd_remap == 1) &&
+           (c.nontemporal == 0 || c.nontemporal == 1);
+}
+
+double resolve_rescale(const HostCsr &h, double rescale) {
+    if (rescale > 0) return rescale;
+    return h.gershgorin > 0 ? h.gershgorin : 1.0;
+}
+
+tbpm_status check_prop_args(int32_t n_states, int32_t n_steps, double dt, double tol, tbpm_precision prec) {
+    if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    if (n_steps < 1) return fail(TBPM_E_ARG, "n_steps must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TBPM_E_ARG, "dt must be positive and finite");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(TBPM_E_ARG, "bessel_tol must be in (0, 1)");
+    if (prec != TBPM_FP64 && prec != TBPM_FP32_MIXED) return fail(TBPM_E_ARG, "unknown precision");
+    return TBPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tbpm_version(void) { return "libtbpm 0.1 (gfx950)"; }
+
+tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const int32_t *col_idx,
+                                    const double *val, const double *onsite, tbpm_hamiltonian **out) {
+    if (!out) return fail(TBPM_E_ARG, "out must not be NULL");
+    *out = nullptr;
+    tbpm_hamiltonian *H = new (std::nothrow) tbpm_hamiltonian();
+    if (!H) return fail(TBPM_E_OOM, "host allocation failed");
+    tbpm_status st;
+    try {
+        st = canonical_csr(n_orb, row_ptr, col_idx, val, onsite, H->csr);
+    } catch (const std::bad_alloc &) {
+        st = fail(TBPM_E_OOM, "host allocation failed");
+    }
+    if (st != TBPM_OK) {
+        delete H;
+        return st;
+    }
+    const HostCsr *m = &H->csr;
+    try {
+        st = H->eng.upload(&m, 1);
+    } catch (const std::bad_alloc &) {
+        st = fail(TBPM_E_OOM, "host allocation failed");
+    }
+    if (st != TBPM_OK) {
+        H->eng.release();
+        delete H;
+        return st;
+    }
+    *out = H;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, const double *onsite,
+                                        uint32_t flags, void *stream) {
+    if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
+    const int64_t nnz = H->csr.nnz(), n = H->csr.n;
+    if ((nnz > 0 && !val) || !onsite) return fail(TBPM_E_ARG, "val and onsite must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (flags & TBPM_FLAG_DEVICE_PTRS) {
+        hipError_t e = launch_convert_values(H->eng.mat, val, onsite, n, st);
+        if (e != hipSuccess) return hip_fail(e, "launch value conversion");
+        return TBPM_OK;
+    }
+    HostCsr copy = H->csr;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(onsite[i])) return fail(TBPM_E_ARG, "non-finite on-site energy");
+    for (int64_t p = 0; p < 2 * nnz; ++p)
+        if (!std::isfinite(val[p])) return fail(TBPM_E_ARG, "non-finite matrix element");
+    std::memcpy(copy.val.data(), val, sizeof(double) * 2 * nnz);
+    if (!H->csr.is_complex)
+        for (int64_t p = 0; p < nnz; ++p) copy.val[2 * p + 1] = 0.0;
+    std::memcpy(copy.onsite.data(), onsite, sizeof(double) * n);
+    double hmax = 0;
+    const bool was_complex = H->csr.is_complex;
+    tbpm_status s = check_values(copy, hmax);
+    if (s != TBPM_OK) return s;
+    copy.is_complex = was_complex;
+    // stage through device scratch and convert with the device path
+    double *dval = nullptr, *dons = nullptr;
+    hipError_t e = hipMalloc(&dval, sizeof(double) * std::max<int64_t>(2 * nnz, 1));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    e = hipMalloc(&dons, sizeof(double) * n);
+    if (e != hipSuccess) {
+        (void)hipFree(dval);
+        return hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(dval, copy.val.data(), sizeof(double) * 2 * nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dons, copy.onsite.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = launch_convert_values(H->eng.mat, dval, dons, n, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dval);
+    (void)hipFree(dons);
+    if (e != hipSuccess) return hip_fail(e, "set_values");
+    H->csr = std::move(copy);
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_hamiltonian_info(const tbpm_hamiltonian *H, int64_t *n_orb, int64_t *nnz, double *gershgorin,
+                                  int32_t *is_complex, int32_t *max_row) {
+    if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
+    if (n_orb) *n_orb = H->csr.n;
+    if (nnz) *nnz = H->csr.nnz();
+    if (gershgorin) *gershgorin = H->csr.gershgorin;
+    if (is_complex) *is_complex = H->csr.is_complex ? 1 : 0;
+    if (max_row) *max_row = (int32_t)H->csr.max_row;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_hamiltonian_pattern(const tbpm_hamiltonian *H, int64_t *row_ptr, int32_t *col_idx) {
+    if (!H || !row_ptr || (!col_idx && H->csr.nnz() > 0)) return fail(TBPM_E_ARG, "NULL argument");
+    std::memcpy(row_ptr, H->csr.row_ptr.data(), sizeof(int64_t) * (H->csr.n + 1));
+    if (H->csr.nnz() > 0) std::memcpy(col_idx, H->csr.col.data(), sizeof(int32_t) * H->csr.nnz());
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_hamiltonian_destroy(tbpm_hamiltonian *H) {
+    if (!H) return TBPM_OK;
+    H->eng.release();
+    delete H;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_num_terms(double z, double tol, int32_t *M) {
+    if (!M) return fail(TBPM_E_ARG, "M must not be NULL");
+    if (!std::isfinite(z) || std::fabs(z) > 1e4) return fail(TBPM_E_ARG, "|z| must be finite and <= 1e4");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(TBPM_E_ARG, "tol must be in (0, 1)");
+    const int32_t m = num_terms(z, tol);
+    if (m < 0) return fail(TBPM_E_ARG, "series does not reach tol");
+    *M = m;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_bessel_j(double z, int32_t M, double *J) {
+    if (!J || M < 1) return fail(TBPM_E_ARG, "J must not be NULL and M >= 1");
+    if (!std::isfinite(z) || std::fabs(z) > 1e4) return fail(TBPM_E_ARG, "|z| must be finite and <= 1e4");
+    bessel_j(z, M, J);
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps, double dt,
+                           double rescale, double bessel_tol, tbpm_precision prec, double *corr, double *norm2,
+                           int32_t ckpt_every, double *ckpt, uint32_t flags, void *stream) {
+    if (!H || !psi0 || !corr) return fail(TBPM_E_ARG, "H, psi0 and corr must not be NULL");
+    tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
+    if (st != TBPM_OK) return st;
+    if (ckpt_every < 0 || (ckpt_every > 0 && !ckpt && n_steps > ckpt_every + 1))
+        return fail(TBPM_E_ARG, "ckpt_every must be >= 0 and ckpt non-NULL when checkpoints are due");
+    if (ckpt_every > 0 && prec != TBPM_FP64) return fail(TBPM_E_ARG, "checkpoints require TBPM_FP64");
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const double f = resolve_rescale(H->csr, rescale);
+    const double *p0 = psi0;
+    double *c0 = corr;
+    double *n0 = norm2;
+    Engine::RunArgs a{};
+    a.psi0 = &p0;
+    a.s_user = n_states;
+    a.n_steps = n_steps;
+    a.dt = &dt;
+    a.rescale = &f;
+    a.tol = bessel_tol;
+    a.fp32 = prec == TBPM_FP32_MIXED;
+    a.corr = &c0;
+    a.norm2 = &n0;
+    a.ckpt_every = ckpt_every;
+    a.ckpt = ckpt_every > 0 ? ckpt : nullptr;
+    a.flags = flags;
+    a.stream = (hipStream_t)stream;
+    try {
+        return H->eng.run(a);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, tbpm_window win,
+                     double *energies, double *dos, void *stream) {
+    if (!corr || !energies || !dos) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_steps < 1 || n_states < 1) return fail(TBPM_E_ARG, "n_steps and n_states must be >= 1");
+    if (n_steps > (1 << 28)) return fail(TBPM_E_ARG, "n_steps too large");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TBPM_E_ARG, "dt must be positive and finite");
+    if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
+    hipError_t e = launch_dos(corr, n_steps, n_states, dt, (int)win, energies, dos, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch dos");
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_dos_backward(const double *grad_dos, int32_t n_steps, int32_t n_states, double dt,
+                              tbpm_window win, double *grad_corr, void *stream) {
+    if (!grad_dos || !grad_corr) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_steps < 1 || n_states < 1) return fail(TBPM_E_ARG, "n_steps and n_states must be >= 1");
+    if (n_steps > (1 << 28)) return fail(TBPM_E_ARG, "n_steps too large");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TBPM_E_ARG, "dt must be positive and finite");
+    if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
+    hipError_t e = launch_dos_backward(grad_dos, n_steps, n_states, dt, (int)win, grad_corr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch dos backward");
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_backward(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps, double dt,
+                          double rescale, double bessel_tol, const double *grad_corr, int32_t ckpt_every,
+                          const double *ckpt, double *grad_val, double *grad_onsite, void *stream) {
+    if (!H || !psi0 || !grad_corr || !grad_val || !grad_onsite)
+        return fail(TBPM_E_ARG, "NULL argument");
+    tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, TBPM_FP64);
+    if (st != TBPM_OK) return st;
+    if (ckpt_every < 1) return fail(TBPM_E_ARG, "ckpt_every must be >= 1");
+    if (!ckpt && n_steps > ckpt_every + 1) return fail(TBPM_E_ARG, "ckpt must not be NULL");
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const double f = resolve_rescale(H->csr, rescale);
+    try {
+        return backward_impl(H, psi0, n_states, n_steps, dt, f, bessel_tol, grad_corr, ckpt_every, ckpt, grad_val,
+                             grad_onsite, (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_batch_create(tbpm_hamiltonian *const *Hs, int32_t n_ham, tbpm_batch **out) {
+    if (!out) return fail(TBPM_E_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!Hs || n_ham < 1) return fail(TBPM_E_ARG, "need at least one Hamiltonian");
+    std::vector<const HostCsr *> m(n_ham);
+    for (int32_t i = 0; i < n_ham; ++i) {
+        if (!Hs[i]) return fail(TBPM_E_ARG, "NULL Hamiltonian in batch");
+        m[i] = &Hs[i]->csr;
+    }
+    tbpm_batch *B = new (std::nothrow) tbpm_batch();
+    if (!B) return fail(TBPM_E_OOM, "host allocation failed");
+    B->members.assign(Hs, Hs + n_ham);
+    tbpm_status st;
+    try {
+        st = B->eng.upload(m.data(), n_ham);
+    } catch (const std::bad_alloc &) {
+        st = fail(TBPM_E_OOM, "host allocation failed");
+    }
+    if (st != TBPM_OK) {
+        B->eng.release();
+        delete B;
+        return st;
+    }
+    *out = B;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_batch_destroy(tbpm_batch *B) {
+    if (!B) return TBPM_OK;
+    B->eng.release();
+    delete B;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int32_t n_states, int32_t n_steps,
+                                   const double *dt, const double *rescale, double bessel_tol, tbpm_precision prec,
+                                   double *const *corr, double *const *norm2, uint32_t flags, void *stream) {
+    if (!B || !psi0 || !corr || !dt || !rescale) return fail(TBPM_E_ARG, "NULL argument");
+    const int32_t n = (int32_t)B->members.size();
+    for (int32_t i = 0; i < n; ++i) {
+        if (!psi0[i] || !corr[i]) return fail(TBPM_E_ARG, "NULL psi0/corr entry in batch");
+        tbpm_status st = check_prop_args(n_states, n_steps, dt[i], bessel_tol, prec);
+        if (st != TBPM_OK) return st;
+        if (!std::isfinite(rescale[i])) return fail(TBPM_E_ARG, "rescale must be finite");
+    }
+    std::vector<double> f(n);
+    for (int32_t i = 0; i < n; ++i) f[i] = resolve_rescale(B->members[i]->csr, rescale[i]);
+    Engine::RunArgs a{};
+    a.psi0 = psi0;
+    a.s_user = n_states;
+    a.n_steps = n_steps;
+    a.dt = dt;
+    a.rescale = f.data();
+    a.tol = bessel_tol;
+    a.fp32 = prec == TBPM_FP32_MIXED;
+    a.corr = corr;
+    a.norm2 = norm2;
+    a.ckpt_every = 0;
+    a.ckpt = nullptr;
+    a.flags = flags;
+    a.stream = (hipStream_t)stream;
+    try {
+        return B->eng.run(a);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_launch_config *cfg) {
+    if (!H || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+    *cfg = H->eng.cfg;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, const tbpm_launch_config *cfg) {
+    if (!H || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+    if (!valid_cfg(*cfg)) return fail(TBPM_E_ARG, "invalid launch configuration");
+    H->eng.cfg = *cfg;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_launch_config *cfg) {
+    if (!B || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+    *cfg = B->eng.cfg;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, const tbpm_launch_config *cfg) {
+    if (!B || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+    if (!valid_cfg(*cfg)) return fail(TBPM_E_ARG, "invalid launch configuration");
+    B->eng.cfg = *cfg;
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_autotune(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec, tbpm_launch_config *best,
+                          double *best_ms, void *stream) {
+    if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
+    if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    std::vector<double> f{resolve_rescale(H->csr, 0.0)};
+    return autotune_impl(H->eng, f, n_states, prec == TBPM_FP32_MIXED, best, best_ms, (hipStream_t)stream);
+}
+
+tbpm_status tbpm_batch_autotune(tbpm_batch *B, int32_t n_states, tbpm_precision prec, tbpm_launch_config *best,
+                                double *best_ms, void *stream) {
+    if (!B) return fail(TBPM_E_ARG, "B must not be NULL");
+    if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    std::vector<double> f;
+    for (auto *h : B->members) f.push_back(resolve_rescale(h->csr, 0.0));
+    return autotune_impl(B->eng, f, n_states, prec == TBPM_FP32_MIXED, best, best_ms, (hipStream_t)stream);
+}
+
+tbpm_status tbpm_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16 != 0) return fail(TBPM_E_ARG, "src/dst NULL or bytes not a multiple of 16");
+    hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch copy");
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_bench_pass(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec, int32_t n_launch,
+                            void *stream) {
+    if (!H || n_launch < 0) return fail(TBPM_E_ARG, "bad argument");
+    return H->eng.bench_pass(n_states, prec == TBPM_FP32_MIXED, n_launch, (hipStream_t)stream);
+}
+
+const char *tbpm_last_error(void) { return tbpm::last_error().c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,526 @@
+// Propagation driver of libtbpm.
+//
+// A time step is the Clenshaw evaluation of psi' = sum_{m<M} c_m T_m(H/f) psi
+// (paper, Eq. (eq:psi_t); c_0 = J_0(z), c_m = 2(-i)^m J_m(z), z = f dt):
+//   b_{M-2} = c_{M-2} v + 2 c_{M-1} H~ v                      (first pass, x = v)
+//   b_{M-3} = (c_{M-3} - c_{M-1}) v + 2 H~ b_{M-2}            (b_{M-1} = c_{M-1} v folded in)
+//   b_j     = c_j v + 2 H~ b_{j+1} - b_{j+2},   j = M-4 .. 1
+//   psi'    = c_0 v + H~ b_1 - b_2                            (+ C_{k+1}, ||psi'||^2)
+// i.e. M-1 sparse passes over three state-sized buffers (v, A, B): every pass
+// writes its output over a buffer that only the same element reads.  The
+// passes of one step and the correlation reduce are captured once in a HIP
+// graph and replayed N_t - 1 times; a device step counter tells the reduce
+// which C_k it is producing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tbpm_engine.h"
+
+namespace tbpm {
+
+using cd = std::complex<double>;
+
+hipError_t DevBuf::ensure(size_t need) {
+    if (need <= bytes && ptr) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    if (need == 0) need = 256;
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    bytes = need;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+hipError_t PinnedBuf::ensure(size_t need) {
+    if (need <= bytes && ptr) return hipSuccess;
+    if (ptr) {
+        (void)hipHostFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    need = std::max<size_t>(need, 4096);
+    hipError_t e = hipHostMalloc(&ptr, need, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    bytes = need;
+    return hipSuccess;
+}
+
+void PinnedBuf::release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+bool GraphKey::operator==(const GraphKey &o) const {
+    if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
+        chunks != o.chunks || remap != o.remap || nt != o.nt || ckpt_every != o.ckpt_every ||
+        ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
+        return false;
+    for (int i = 0; i < 8; ++i)
+        if (bufs[i] != o.bufs[i]) return false;
+    return true;
+}
+
+#define TRY_HIP(expr, what)                            \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// upload of one or several merged CSR matrices as one block-diagonal operator
+// ---------------------------------------------------------------------------
+tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    device = dev;
+    inst_row0.assign(n + 1, 0);
+    int64_t nnz_total = 0;
+    bool cplx = false;
+    for (int32_t i = 0; i < n; ++i) {
+        inst_row0[i + 1] = inst_row0[i] + members[i]->n;
+        nnz_total += members[i]->nnz();
+        cplx = cplx || members[i]->is_complex;
+    }
+    const int64_t N = inst_row0[n];
+    if (N >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "total number of orbitals must be < 2^31");
+    std::vector<int64_t> rp(N + 1, 0);
+    std::vector<int32_t> col;
+    col.reserve(nnz_total);
+    std::vector<double> val;
+    val.reserve(2 * nnz_total);
+    std::vector<double> ons(N);
+    for (int32_t i = 0; i < n; ++i) {
+        const HostCsr &h = *members[i];
+        const int64_t r0 = inst_row0[i];
+        for (int64_t r = 0; r < h.n; ++r) {
+            for (int64_t p = h.row_ptr[r]; p < h.row_ptr[r + 1]; ++p) {
+                col.push_back((int32_t)(h.col[p] + r0));
+                val.push_back(h.val[2 * p]);
+                val.push_back(h.val[2 * p + 1]);
+            }
+            rp[r0 + r + 1] = (int64_t)col.size();
+            ons[r0 + r] = h.onsite[r];
+        }
+    }
+    HostEll e = build_sliced_ell(N, rp.data(), col.data());
+    const int64_t S = (int64_t)e.col.size();
+    std::vector<double> v64(cplx ? 2 * S : S, 0.0);
+    std::vector<float> v32(cplx ? 2 * S : S, 0.0f);
+    for (int64_t q = 0; q < S; ++q) {
+        const int64_t p = e.csr_pos[q];
+        if (p < 0) continue;
+        if (cplx) {
+            v64[2 * q] = val[2 * p];
+            v64[2 * q + 1] = val[2 * p + 1];
+            v32[2 * q] = (float)val[2 * p];
+            v32[2 * q + 1] = (float)val[2 * p + 1];
+        } else {
+            v64[q] = val[2 * p];
+            v32[q] = (float)val[2 * p];
+        }
+    }
+    std::vector<float> ons32(N);
+    for (int64_t r = 0; r < N; ++r) ons32[r] = (float)ons[r];
+
+    mat.n_rows = N;
+    mat.n_slices = (int64_t)e.slice_off.size() - 1;
+    mat.ell_size = S;
+    mat.is_complex = cplx;
+    const size_t vb = (cplx ? 2 : 1) * (size_t)std::max<int64_t>(S, 1);
+    TRY_HIP(hipMalloc(&mat.slice_off, sizeof(int64_t) * e.slice_off.size()), "hipMalloc slice_off");
+    TRY_HIP(hipMalloc(&mat.col, sizeof(int32_t) * std::max<int64_t>(S, 1)), "hipMalloc col");
+    TRY_HIP(hipMalloc(&mat.val64, sizeof(double) * vb), "hipMalloc val64");
+    TRY_HIP(hipMalloc(&mat.val32, sizeof(float) * vb), "hipMalloc val32");
+    TRY_HIP(hipMalloc(&mat.onsite64, sizeof(double) * N), "hipMalloc onsite64");
+    TRY_HIP(hipMalloc(&mat.onsite32, sizeof(float) * N), "hipMalloc onsite32");
+    TRY_HIP(hipMalloc(&mat.ell_csr, sizeof(int64_t) * std::max<int64_t>(S, 1)), "hipMalloc ell_csr");
+    TRY_HIP(hipMemcpy(mat.slice_off, e.slice_off.data(), sizeof(int64_t) * e.slice_off.size(), hipMemcpyHostToDevice),
+            "upload slice_off");
+    if (S > 0) {
+        TRY_HIP(hipMemcpy(mat.col, e.col.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice), "upload col");
+        TRY_HIP(hipMemcpy(mat.val64, v64.data(), sizeof(double) * v64.size(), hipMemcpyHostToDevice), "upload val64");
+        TRY_HIP(hipMemcpy(mat.val32, v32.data(), sizeof(float) * v32.size(), hipMemcpyHostToDevice), "upload val32");
+        TRY_HIP(hipMemcpy(mat.ell_csr, e.csr_pos.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice), "upload ell_csr");
+    }
+    TRY_HIP(hipMemcpy(mat.onsite64, ons.data(), sizeof(double) * N, hipMemcpyHostToDevice), "upload onsite");
+    TRY_HIP(hipMemcpy(mat.onsite32, ons32.data(), sizeof(float) * N, hipMemcpyHostToDevice), "upload onsite32");
+    TRY_HIP(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    TRY_HIP(hipEventCreateWithFlags(&staging_done, hipEventDisableTiming), "hipEventCreate");
+    return TBPM_OK;
+}
+
+void Engine::release() {
+    if (graph_exec) {
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+    }
+    void *ptrs[] = {mat.slice_off, mat.col, mat.val64, mat.val32, mat.onsite64, mat.onsite32, mat.ell_csr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    mat = DevMatrix{};
+    DevBuf *bufs[] = {&v, &ba, &bb, &phi0, &partials, &counter, &coef, &norm2_all, &tiles, &inst_tile0, &ptr_tab,
+                      &inst_row0_dev};
+    for (DevBuf *b : bufs) b->release();
+    staging.release();
+    if (staging_done) (void)hipEventDestroy(staging_done);
+    staging_done = nullptr;
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// tiles: each workgroup handles 256*chunks state elements of one member
+// ---------------------------------------------------------------------------
+tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks) {
+    if (tiles_s == s_pad && tiles_chunks == chunks && tiles.ptr) return TBPM_OK;
+    const int64_t rows_per_tile = std::max<int64_t>(1, (int64_t)kWG * chunks / s_pad);
+    h_tiles.clear();
+    h_inst_tile0.assign(n_inst() + 1, 0);
+    for (int32_t i = 0; i < n_inst(); ++i) {
+        for (int64_t r = inst_row0[i]; r < inst_row0[i + 1]; r += rows_per_tile) {
+            TileDesc t;
+            t.row0 = r;
+            t.rows = (int32_t)std::min<int64_t>(rows_per_tile, inst_row0[i + 1] - r);
+            t.inst = i;
+            h_tiles.push_back(t);
+        }
+        h_inst_tile0[i + 1] = (int32_t)h_tiles.size();
+    }
+    if (h_tiles.size() >= (size_t)INT32_MAX) return fail(TBPM_E_ARG, "too many tiles");
+    TRY_HIP(hipDeviceSynchronize(), "sync before tile rebuild");
+    TRY_HIP(tiles.ensure(sizeof(TileDesc) * std::max<size_t>(h_tiles.size(), 1)), "alloc tiles");
+    TRY_HIP(inst_tile0.ensure(sizeof(int32_t) * h_inst_tile0.size()), "alloc inst_tile0");
+    TRY_HIP(hipMemcpy(tiles.ptr, h_tiles.data(), sizeof(TileDesc) * h_tiles.size(), hipMemcpyHostToDevice),
+            "upload tiles");
+    TRY_HIP(hipMemcpy(inst_tile0.ptr, h_inst_tile0.data(), sizeof(int32_t) * h_inst_tile0.size(),
+                      hipMemcpyHostToDevice),
+            "upload inst_tile0");
+    tiles_s = s_pad;
+    tiles_chunks = chunks;
+    return TBPM_OK;
+}
+
+namespace {
+
+struct PassPlan {
+    int kind;
+    int x, v, b2, out;  // buffer ids: 0 = v, 1 = A, 2 = B, -1 = none
+    std::vector<PassCoef> coef;  // per member
+};
+
+PassCoef make_coef(cd a, cd b) { return PassCoef{a.real(), a.imag(), b.real(), b.imag()}; }
+
+// The Clenshaw schedule of one step for per-member coefficient sets c[i][m]
+// (zero-padded to mmax: extra zero coefficients leave the polynomial and every
+// intermediate b_j unchanged) and scales f[i].
+std::vector<PassPlan> plan_step(const std::vector<std::vector<cd>> &c, const std::vector<double> &f, int mmax) {
+    const size_t n = c.size();
+    std::vector<PassPlan> plan;
+    auto add = [&](int kind, int x, int v, int b2, int out, auto alpha, auto beta) {
+        PassPlan p{kind, x, v, b2, out, {}};
+        p.coef.resize(n);
+        for (size_t i = 0; i < n; ++i) p.coef[i] = make_coef(alpha(i), beta(i));
+        plan.push_back(std::move(p));
+    };
+    const int M = mmax;
+    if (M == 3) {
+        add(kPassFirst, 0, 0, -1, 1, [&](size_t i) { return c[i][1]; },
+            [&](size_t i) { return 2.0 * c[i][2] / f[i]; });
+        add(kPassLastNoB2, 1, 0, -1, 0, [&](size_t i) { return c[i][0] - c[i][2]; },
+            [&](size_t i) { return cd(1.0 / f[i], 0.0); });
+        return plan;
+    }
+    add(kPassFirst, 0, 0, -1, 1, [&](size_t i) { return c[i][M - 2]; },
+        [&](size_t i) { return 2.0 * c[i][M - 1] / f[i]; });
+    add(kPassNoB2, 1, 0, -1, 2, [&](size_t i) { return c[i][M - 3] - c[i][M - 1]; },
+        [&](size_t i) { return cd(2.0 / f[i], 0.0); });
+    int cur = 2, prev = 1;  // cur holds b_{j+1}, prev holds b_{j+2}
+    for (int j = M - 4; j >= 1; --j) {
+        add(kPassMid, cur, 0, prev, prev, [&, j](size_t i) { return c[i][j]; },
+            [&](size_t i) { return cd(2.0 / f[i], 0.0); });
+        std::swap(cur, prev);
+    }
+    add(kPassLast, cur, 0, prev, 0, [&](size_t i) { return c[i][0]; },
+        [&](size_t i) { return cd(1.0 / f[i], 0.0); });
+    return plan;
+}
+
+}  // namespace
+
+tbpm_status Engine::run(const RunArgs &a) {
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != device) return fail(TBPM_E_ARG, "handle was created on another device");
+    const int32_t ni = n_inst();
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < a.s_user) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    const bool fp32 = a.fp32;
+    const size_t esize = fp32 ? 8 : 16;
+
+    // coefficients per member
+    std::vector<std::vector<cd>> c(ni);
+    std::vector<double> f(ni);
+    int mmax = 0;
+    for (int32_t i = 0; i < ni; ++i) {
+        const double z = a.rescale[i] * a.dt[i];
+        const int32_t M = num_terms(z, a.tol);
+        if (M < 0) return fail(TBPM_E_ARG, "Bessel series does not converge for z = " + std::to_string(z));
+        std::vector<double> J(M);
+        bessel_j(z, M, J.data());
+        c[i].resize(M);
+        for (int32_t m = 0; m < M; ++m) {
+            static const cd mi[4] = {cd(1, 0), cd(0, -1), cd(-1, 0), cd(0, 1)};  // (-i)^m
+            c[i][m] = (m == 0 ? 1.0 : 2.0) * J[m] * mi[m & 3];
+        }
+        f[i] = a.rescale[i];
+        mmax = std::max(mmax, M);
+    }
+    for (int32_t i = 0; i < ni; ++i) c[i].resize(mmax, cd(0.0, 0.0));
+    const std::vector<PassPlan> plan = plan_step(c, f, mmax);
+    const int n_passes = (int)plan.size();
+
+    const int32_t chunks = cfg.wg_chunks;
+    tbpm_status st = build_tiles(s_pad, chunks);
+    if (st != TBPM_OK) return st;
+    const int32_t n_tiles = (int32_t)h_tiles.size();
+    const int64_t n_el = mat.n_rows * s_pad;
+
+    TRY_HIP(v.ensure(esize * n_el), "alloc v");
+    TRY_HIP(ba.ensure(esize * n_el), "alloc A");
+    TRY_HIP(bb.ensure(esize * n_el), "alloc B");
+    TRY_HIP(phi0.ensure(16 * n_el), "alloc phi0");
+    TRY_HIP(partials.ensure(sizeof(double) * 3 * (size_t)n_tiles * s_pad), "alloc partials");
+    TRY_HIP(counter.ensure(sizeof(int32_t) * 64), "alloc counter");
+    TRY_HIP(coef.ensure(sizeof(PassCoef) * (size_t)n_passes * ni), "alloc coef");
+    TRY_HIP(norm2_all.ensure(sizeof(double) * (size_t)ni * a.n_steps * a.s_user), "alloc norm2");
+    TRY_HIP(ptr_tab.ensure(sizeof(void *) * 3 * (size_t)ni), "alloc pointer table");
+    TRY_HIP(inst_row0_dev.ensure(sizeof(int64_t) * (ni + 1)), "alloc inst_row0");
+
+    // stage the small tables through pinned memory, stream-ordered
+    const size_t coef_bytes = sizeof(PassCoef) * (size_t)n_passes * ni;
+    const size_t tab_bytes = sizeof(void *) * 3 * (size_t)ni;
+    const size_t row_bytes = sizeof(int64_t) * (ni + 1);
+    TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
+    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes), "alloc staging");
+    char *sp = (char *)staging.ptr;
+    PassCoef *hc = (PassCoef *)sp;
+    for (int p = 0; p < n_passes; ++p)
+        for (int32_t i = 0; i < ni; ++i) hc[p * ni + i] = plan[p].coef[i];
+    const void **ht = (const void **)(sp + coef_bytes);
+    for (int32_t i = 0; i < ni; ++i) {
+        ht[i] = a.psi0[i];
+        ht[ni + i] = a.corr[i];
+        ht[2 * ni + i] = a.norm2 ? a.norm2[i] : nullptr;
+    }
+    std::memcpy(sp + coef_bytes + tab_bytes, inst_row0.data(), row_bytes);
+    TRY_HIP(hipMemcpyAsync(coef.ptr, sp, coef_bytes, hipMemcpyHostToDevice, a.stream), "upload coefficients");
+    TRY_HIP(hipMemcpyAsync(ptr_tab.ptr, sp + coef_bytes, tab_bytes, hipMemcpyHostToDevice, a.stream),
+            "upload pointer table");
+    TRY_HIP(hipMemcpyAsync(inst_row0_dev.ptr, sp + coef_bytes + tab_bytes, row_bytes, hipMemcpyHostToDevice,
+                           a.stream),
+            "upload row offsets");
+    TRY_HIP(hipEventRecord(staging_done, a.stream), "record staging");
+
+    void *bufptr[3] = {v.ptr, ba.ptr, bb.ptr};
+    const double *const *d_psi0 = (const double *const *)ptr_tab.ptr;
+    double *const *d_corr = (double *const *)ptr_tab.ptr + ni;
+    double *const *d_norm2 = (double *const *)ptr_tab.ptr + 2 * ni;
+
+    // C_0
+    InitParams ip{};
+    ip.tiles = (const TileDesc *)tiles.ptr;
+    ip.n_tiles = n_tiles;
+    ip.log2s = log2s;
+    ip.s_user = a.s_user;
+    ip.psi0 = d_psi0;
+    ip.inst_row0 = (const int64_t *)inst_row0_dev.ptr;
+    ip.v = v.ptr;
+    ip.phi0 = (double *)phi0.ptr;
+    ip.partials = (double *)partials.ptr;
+    ip.counter = (int32_t *)counter.ptr;
+    TRY_HIP(launch_init(fp32, ip, a.stream), "launch init");
+    ReduceParams rp{};
+    rp.partials = (const double *)partials.ptr;
+    rp.inst_tile0 = (const int32_t *)inst_tile0.ptr;
+    rp.log2s = log2s;
+    rp.s_user = a.s_user;
+    rp.n_steps = a.n_steps;
+    rp.counter = (const int32_t *)counter.ptr;
+    rp.corr = d_corr;
+    rp.norm2 = d_norm2;
+    rp.norm2_all = (double *)norm2_all.ptr;
+    TRY_HIP(launch_reduce(ni, s_pad, rp, a.stream), "launch reduce");
+
+    // one time step
+    auto enqueue_step = [&](hipStream_t s) -> tbpm_status {
+        for (int p = 0; p < n_passes; ++p) {
+            const PassPlan &pl = plan[p];
+            PassParams pp{};
+            pp.tiles = (const TileDesc *)tiles.ptr;
+            pp.n_tiles = n_tiles;
+            pp.xcd_remap = cfg.xcd_remap;
+            pp.log2s = log2s;
+            pp.bump_counter = (p == 0);
+            pp.col = mat.col;
+            pp.val = fp32 ? mat.val32 : mat.val64;
+            pp.slice_off = mat.slice_off;
+            pp.onsite = fp32 ? (const void *)mat.onsite32 : (const void *)mat.onsite64;
+            pp.x = bufptr[pl.x];
+            pp.v = bufptr[pl.v];
+            pp.b2 = pl.b2 >= 0 ? bufptr[pl.b2] : nullptr;
+            pp.out = bufptr[pl.out];
+            pp.coef = (const PassCoef *)coef.ptr + (size_t)p * ni;
+            pp.counter = (int32_t *)counter.ptr;
+            pp.phi0 = (const double *)phi0.ptr;
+            pp.phi0_ld = s_pad;
+            pp.partials = (double *)partials.ptr;
+            pp.ckpt = a.ckpt;
+            pp.ckpt_stride = mat.n_rows * a.s_user;
+            pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
+            pp.ckpt_max = a.n_steps - 2;
+            pp.s_user = a.s_user;
+            hipError_t e = launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, pp, s);
+            if (e != hipSuccess) return hip_fail(e, "launch pass");
+        }
+        hipError_t e = launch_reduce(ni, s_pad, rp, s);
+        if (e != hipSuccess) return hip_fail(e, "launch reduce");
+        return TBPM_OK;
+    };
+
+    if (a.n_steps > 1) {
+        if (a.flags & TBPM_FLAG_NO_GRAPH) {
+            for (int32_t k = 1; k < a.n_steps; ++k) {
+                st = enqueue_step(a.stream);
+                if (st != TBPM_OK) return st;
+            }
+        } else {
+            GraphKey key;
+            key.s_pad = s_pad;
+            key.s_user = a.s_user;
+            key.fp32 = fp32;
+            key.mmax = mmax;
+            key.n_inst = ni;
+            key.chunks = chunks;
+            key.remap = cfg.xcd_remap;
+            key.nt = cfg.nontemporal;
+            key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
+            key.ckpt_max = a.n_steps - 2;
+            key.n_steps = a.n_steps;
+            key.ckpt = a.ckpt;
+            const void *kb[8] = {v.ptr, ba.ptr, bb.ptr, phi0.ptr, partials.ptr, coef.ptr, tiles.ptr, norm2_all.ptr};
+            std::memcpy(key.bufs, kb, sizeof(kb));
+            if (!graph_exec || !(key == graph_key)) {
+                if (graph_exec) {
+                    TRY_HIP(hipDeviceSynchronize(), "sync before graph rebuild");
+                    TRY_HIP(hipGraphExecDestroy(graph_exec), "hipGraphExecDestroy");
+                    graph_exec = nullptr;
+                }
+                TRY_HIP(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+                tbpm_status cst = enqueue_step(capture_stream);
+                hipGraph_t g = nullptr;
+                hipError_t ee = hipStreamEndCapture(capture_stream, &g);
+                if (cst != TBPM_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return cst;
+                }
+                if (ee != hipSuccess) return hip_fail(ee, "end capture");
+                hipError_t ei = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    graph_exec = nullptr;
+                    return hip_fail(ei, "hipGraphInstantiate");
+                }
+                graph_key = key;
+            }
+            for (int32_t k = 1; k < a.n_steps; ++k) TRY_HIP(hipGraphLaunch(graph_exec, a.stream), "hipGraphLaunch");
+        }
+    }
+
+    last_s_pad = s_pad;
+    last_fp32 = fp32 ? 1 : 0;
+    if (a.flags & TBPM_FLAG_ASYNC) return TBPM_OK;
+    TRY_HIP(hipStreamSynchronize(a.stream), "stream synchronize");
+    TRY_HIP(hipGetLastError(), "kernel execution");
+    // norm check (the spectrum must lie in [-f, f])
+    std::vector<double> n2((size_t)ni * a.n_steps * a.s_user);
+    TRY_HIP(hipMemcpy(n2.data(), norm2_all.ptr, sizeof(double) * n2.size(), hipMemcpyDeviceToHost), "read norms");
+    for (int32_t i = 0; i < ni; ++i) {
+        for (int32_t s = 0; s < a.s_user; ++s) {
+            const double n0 = n2[(size_t)i * a.n_steps * a.s_user + s];
+            if (!(n0 > 0.0)) continue;
+            for (int32_t k = 0; k < a.n_steps; ++k) {
+                const double r = n2[((size_t)i * a.n_steps + k) * a.s_user + s] / n0;
+                if (!std::isfinite(r) || std::fabs(r - 1.0) > 1e-3) {
+                    char buf[256];
+                    std::snprintf(buf, sizeof buf,
+                                  "norm check failed (member %d, state %d, step %d: ||psi||^2/||psi0||^2 = %.6g); "
+                                  "is the spectrum inside [-rescale, rescale]?",
+                                  i, s, k, r);
+                    return fail(TBPM_E_DIVERGED, buf);
+                }
+            }
+        }
+    }
+    return TBPM_OK;
+}
+
+tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream) {
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < s_user) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    if (last_s_pad != s_pad || last_fp32 != (fp32 ? 1 : 0) || !v.ptr || tiles_s != s_pad)
+        return fail(TBPM_E_ARG, "tbpm_bench_pass needs a prior tbpm_propagate with the same n_states and precision");
+    PassParams pp{};
+    pp.tiles = (const TileDesc *)tiles.ptr;
+    pp.n_tiles = (int32_t)h_tiles.size();
+    pp.xcd_remap = cfg.xcd_remap;
+    pp.log2s = log2s;
+    pp.bump_counter = 0;
+    pp.col = mat.col;
+    pp.val = fp32 ? mat.val32 : mat.val64;
+    pp.slice_off = mat.slice_off;
+    pp.onsite = fp32 ? (const void *)mat.onsite32 : (const void *)mat.onsite64;
+    pp.x = ba.ptr;
+    pp.v = v.ptr;
+    pp.b2 = bb.ptr;
+    pp.out = bb.ptr;
+    pp.coef = (const PassCoef *)coef.ptr;  // the first pass's coefficients: finite, bounded
+    pp.counter = (int32_t *)counter.ptr;
+    pp.s_user = s_user;
+    for (int32_t i = 0; i < n_launch; ++i) {
+        hipError_t e = launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, pp, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch pass");
+    }
+    return TBPM_OK;
+}
+
+}  // namespace tbpm

@@ -1,0 +1,234 @@
+// Host side of libtbpm: validation, sliced-ELL build, Chebyshev/Bessel
+// coefficients, the propagation driver (HIP graph replay of one time step)
+// and the C ABI entry points declared in include/tbpm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "tbpm_engine.h"
+#include "tbpm_internal.h"
+
+namespace tbpm {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+const std::string &last_error() { return g_last_error; }
+
+tbpm_status fail(tbpm_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+tbpm_status hip_fail(hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(TBPM_E_OOM, m);
+    return fail(TBPM_E_DEVICE, m);
+}
+
+// ---------------------------------------------------------------------------
+// Bessel functions J_m(z), m = 0..M-1, by Miller's backward recurrence
+// J_{m-1} = (2m/z) J_m - J_{m+1}, started far above max(M, |z|) and
+// normalised with J_0 + 2 sum_{k>=1} J_{2k} = 1 (Abramowitz & Stegun 9.1.46;
+// the method is A&S 9.12 / Miller 1952).  J_m(-z) = (-1)^m J_m(z).
+// ---------------------------------------------------------------------------
+void bessel_j(double z, int32_t M, double *J) {
+    if (M <= 0) return;
+    if (z == 0.0) {
+        J[0] = 1.0;
+        for (int32_t m = 1; m < M; ++m) J[m] = 0.0;
+        return;
+    }
+    const double az = std::fabs(z);
+    const double top = std::max<double>(M, az);
+    int64_t L = (int64_t)(top + 40.0 + 10.0 * std::cbrt(top));
+    if (L & 1) ++L;
+    std::vector<double> j(L + 2, 0.0);
+    double jp1 = 0.0, jm = 1e-280;  // J_{L+1}, J_L (unnormalised)
+    j[L] = jm;
+    double norm = (L % 2 == 0) ? 2.0 * jm : 0.0;
+    for (int64_t m = L; m >= 1; --m) {
+        double jm1 = (2.0 * (double)m / az) * jm - jp1;
+        jp1 = jm;
+        jm = jm1;
+        j[m - 1] = jm;
+        if (m - 1 > 0 && ((m - 1) % 2 == 0)) norm += 2.0 * jm;
+        if (std::fabs(jm) > 1e250) {  // rescale everything kept so far
+            for (int64_t q = m - 1; q <= L; ++q) j[q] *= 1e-250;
+            jm *= 1e-250;
+            jp1 *= 1e-250;
+            norm *= 1e-250;
+        }
+    }
+    norm += j[0];
+    for (int32_t m = 0; m < M; ++m) {
+        double v = j[m] / norm;
+        if (z < 0 && (m & 1)) v = -v;
+        J[m] = v;
+    }
+}
+
+int32_t num_terms(double z, double tol) {
+    const double az = std::fabs(z);
+    int32_t span = (int32_t)az + 64;
+    for (;;) {
+        std::vector<double> J(span + 1);
+        bessel_j(z, span + 1, J.data());
+        for (int32_t m = (int32_t)std::floor(az) + 1; m <= span; ++m)
+            if (std::fabs(J[m]) < tol) return std::max<int32_t>(3, m);
+        span *= 2;
+        if (span > 1 << 22) return -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sliced ELL
+// ---------------------------------------------------------------------------
+HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *col) {
+    HostEll e;
+    const int64_t n_slices = (n_rows + kSliceRows - 1) / kSliceRows;
+    e.slice_off.assign(n_slices + 1, 0);
+    for (int64_t q = 0; q < n_slices; ++q) {
+        int64_t w = 0;
+        const int64_t r1 = std::min(n_rows, (q + 1) * kSliceRows);
+        for (int64_t r = q * kSliceRows; r < r1; ++r) w = std::max(w, row_ptr[r + 1] - row_ptr[r]);
+        e.slice_off[q + 1] = e.slice_off[q] + w * kSliceRows;
+    }
+    const int64_t size = e.slice_off[n_slices];
+    e.col.assign(size, 0);
+    e.csr_pos.assign(size, -1);
+    for (int64_t q = 0; q < n_slices; ++q) {
+        const int64_t w = (e.slice_off[q + 1] - e.slice_off[q]) / kSliceRows;
+        for (int64_t lr = 0; lr < kSliceRows; ++lr) {
+            const int64_t r = q * kSliceRows + lr;
+            const int64_t len = r < n_rows ? row_ptr[r + 1] - row_ptr[r] : 0;
+            for (int64_t k = 0; k < w; ++k) {
+                const int64_t slot = e.slice_off[q] + k * kSliceRows + lr;
+                if (k < len) {
+                    e.col[slot] = col[row_ptr[r] + k];
+                    e.csr_pos[slot] = row_ptr[r] + k;
+                } else {
+                    e.col[slot] = (int32_t)(r < n_rows ? r : 0);
+                }
+            }
+        }
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// CSR validation and canonicalisation (merge duplicates, sort columns)
+// ---------------------------------------------------------------------------
+tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *onsite, HostCsr &out) {
+    if (n < 1 || n >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb must be in [1, 2^31-1)");
+    if (!row_ptr || !onsite) return fail(TBPM_E_ARG, "row_ptr and onsite must not be NULL");
+    if (row_ptr[0] != 0) return fail(TBPM_E_CSR, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i])
+            return fail(TBPM_E_CSR, "row_ptr is not non-decreasing at row " + std::to_string(i));
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && (!col || !val)) return fail(TBPM_E_ARG, "col_idx and val must not be NULL when nnz > 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(onsite[i])) return fail(TBPM_E_ARG, "non-finite on-site energy at " + std::to_string(i));
+    double hmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const int64_t c = col[p];
+            if (c < 0 || c >= n)
+                return fail(TBPM_E_CSR, "column " + std::to_string(c) + " out of range in row " + std::to_string(i));
+            if (c == i)
+                return fail(TBPM_E_CSR, "diagonal entry in row " + std::to_string(i) +
+                                            " (pass on-site energies in 'onsite')");
+            if (!std::isfinite(val[2 * p]) || !std::isfinite(val[2 * p + 1]))
+                return fail(TBPM_E_ARG, "non-finite matrix element in row " + std::to_string(i));
+        }
+    }
+    out.n = n;
+    out.row_ptr.assign(n + 1, 0);
+    out.col.clear();
+    out.val.clear();
+    out.col.reserve(nnz);
+    out.val.reserve(2 * nnz);
+    std::vector<std::pair<int32_t, int64_t>> tmp;
+    for (int64_t i = 0; i < n; ++i) {
+        tmp.clear();
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) tmp.emplace_back(col[p], p);
+        std::stable_sort(tmp.begin(), tmp.end(),
+                         [](const std::pair<int32_t, int64_t> &a, const std::pair<int32_t, int64_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (size_t q = 0; q < tmp.size(); ++q) {
+            const int64_t p = tmp[q].second;
+            if (q > 0 && tmp[q].first == tmp[q - 1].first) {
+                out.val[out.val.size() - 2] += val[2 * p];
+                out.val[out.val.size() - 1] += val[2 * p + 1];
+            } else {
+                out.col.push_back(tmp[q].first);
+                out.val.push_back(val[2 * p]);
+                out.val.push_back(val[2 * p + 1]);
+            }
+        }
+        out.row_ptr[i + 1] = (int64_t)out.col.size();
+    }
+    out.onsite.assign(onsite, onsite + n);
+    return check_values(out, hmax);
+}
+
+tbpm_status check_values(HostCsr &h, double &hmax) {
+    const int64_t n = h.n;
+    hmax = 0.0;
+    bool cplx = false;
+    for (size_t p = 0; p < h.col.size(); ++p) {
+        hmax = std::max(hmax, std::hypot(h.val[2 * p], h.val[2 * p + 1]));
+        if (h.val[2 * p + 1] != 0.0) cplx = true;
+    }
+    for (int64_t i = 0; i < n; ++i) hmax = std::max(hmax, std::fabs(h.onsite[i]));
+    const double tol = 1e-13 * hmax;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) {
+            const int32_t j = h.col[p];
+            const int32_t *b = h.col.data() + h.row_ptr[j];
+            const int32_t *e = h.col.data() + h.row_ptr[j + 1];
+            const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+            if (f == e || *f != i)
+                return fail(TBPM_E_NOT_HERMITIAN, "entry (" + std::to_string(i) + "," + std::to_string(j) +
+                                                      ") has no transposed partner (" + std::to_string(j) + "," +
+                                                      std::to_string(i) + ")");
+            const int64_t q = f - h.col.data();
+            const double dr = h.val[2 * p] - h.val[2 * q];
+            const double di = h.val[2 * p + 1] + h.val[2 * q + 1];
+            if (std::hypot(dr, di) > tol)
+                return fail(TBPM_E_NOT_HERMITIAN, "H(" + std::to_string(i) + "," + std::to_string(j) +
+                                                      ") != conj(H(" + std::to_string(j) + "," +
+                                                      std::to_string(i) + "))");
+        }
+    }
+    h.is_complex = cplx;
+    double g = 0.0;
+    int64_t mr = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double r = std::fabs(h.onsite[i]);
+        for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) r += std::hypot(h.val[2 * p], h.val[2 * p + 1]);
+        g = std::max(g, r);
+        mr = std::max(mr, h.row_ptr[i + 1] - h.row_ptr[i]);
+    }
+    h.gershgorin = g;
+    h.max_row = mr;
+    return TBPM_OK;
+}
+
+}  // namespace tbpm

@@ -1,0 +1,122 @@
+// Internal engine of libtbpm: one block-diagonal device operator (a single
+// Hamiltonian, or a batch of them concatenated) with its work buffers and
+// the cached HIP graph of one time step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tbpm_internal.h"
+
+namespace tbpm {
+
+tbpm_status fail(tbpm_status st, const std::string &msg);
+tbpm_status hip_fail(hipError_t e, const char *what);
+
+// Merged host CSR (rows in order, columns ascending, no duplicates).
+struct HostCsr {
+    int64_t n = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;  // 2 * nnz
+    std::vector<double> onsite;
+    bool is_complex = false;
+    double gershgorin = 0.0;
+    int64_t max_row = 0;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *onsite, HostCsr &out);
+tbpm_status check_values(HostCsr &h, double &hmax);
+
+// Device buffer that only grows.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need);
+    void release();
+};
+
+struct PinnedBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need);
+    void release();
+};
+
+// Everything a time step's launches depend on; a cached graph is reused only
+// if the key is equal.
+struct GraphKey {
+    int32_t s_pad = 0, s_user = 0, fp32 = 0, mmax = 0, n_inst = 0;
+    int32_t chunks = 0, remap = 0, nt = 0;
+    int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
+    const void *ckpt = nullptr;
+    const void *bufs[8] = {};
+    bool operator==(const GraphKey &o) const;
+};
+
+struct Engine {
+    DevMatrix mat;
+    std::vector<int64_t> inst_row0;  // [n_inst + 1]
+    tbpm_launch_config cfg{8, 1, 0};
+    int device = -1;
+
+    // work buffers
+    DevBuf v, ba, bb, phi0, partials, counter, coef, norm2_all, tiles, inst_tile0, ptr_tab, inst_row0_dev;
+    PinnedBuf staging;
+    hipEvent_t staging_done = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    // tile tables (host) for the current (S, chunks)
+    int32_t tiles_s = 0, tiles_chunks = 0;
+    std::vector<TileDesc> h_tiles;
+    std::vector<int32_t> h_inst_tile0;
+
+    // cached graph of one step
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
+
+    int32_t n_inst() const { return (int32_t)inst_row0.size() - 1; }
+
+    tbpm_status upload(const HostCsr *const *members, int32_t n);
+    void release();
+
+    // the propagation driver (shared by single and batched entry points)
+    struct RunArgs {
+        const double *const *psi0;  // n_inst device pointers
+        int32_t s_user;
+        int32_t n_steps;
+        const double *dt;       // n_inst
+        const double *rescale;  // n_inst, already resolved (> 0)
+        double tol;
+        bool fp32;
+        double *const *corr;   // n_inst device pointers
+        double *const *norm2;  // n_inst device pointers (entries may be null) or null
+        int32_t ckpt_every;
+        double *ckpt;
+        uint32_t flags;
+        hipStream_t stream;
+    };
+    tbpm_status run(const RunArgs &a);
+    // back-to-back launches of the interior pass on the current buffers
+    tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
+    int32_t last_s_pad = 0, last_fp32 = -1;
+
+    tbpm_status build_tiles(int32_t s_pad, int32_t chunks);
+};
+
+}  // namespace tbpm
+
+struct tbpm_hamiltonian {
+    tbpm::HostCsr csr;
+    tbpm::Engine eng;
+};
+
+struct tbpm_batch {
+    std::vector<tbpm_hamiltonian *> members;
+    tbpm::Engine eng;
+};

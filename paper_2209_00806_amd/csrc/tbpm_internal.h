@@ -1,0 +1,150 @@
+// Internal declarations shared by the host side of libtbpm and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tbpm.h"
+
+namespace tbpm {
+
+// ---------------------------------------------------------------------------
+// Device layout
+// ---------------------------------------------------------------------------
+// Off-diagonal part of H in sliced ELL: slices of kSliceRows consecutive
+// rows; slice q holds width_q = (slice_off[q+1]-slice_off[q])/kSliceRows
+// entries per row, stored column-major inside the slice, i.e. entry k of
+// row r lives at slice_off[q] + k*kSliceRows + (r % kSliceRows).  Rows
+// shorter than width_q are padded with (col = row, value = 0).
+constexpr int kSliceRows = 32;
+// Threads per workgroup of every streaming kernel (4 wave64s).
+constexpr int kWG = 256;
+
+// One workgroup's share of a Chebyshev pass: 'rows' consecutive rows of a
+// single batch member 'inst', starting at global row 'row0'.
+struct TileDesc {
+    int64_t row0;
+    int32_t rows;
+    int32_t inst;
+};
+
+// Per-member coefficients of one pass: out = alpha*v + beta*(H x) - b2.
+struct PassCoef {
+    double ar, ai, br, bi;
+};
+
+struct DevMatrix {
+    int64_t n_rows = 0;      // total rows (sum over batch members)
+    int64_t n_slices = 0;
+    int64_t ell_size = 0;    // slots incl. padding
+    bool is_complex = false;
+    int64_t *slice_off = nullptr;  // [n_slices + 1]
+    int32_t *col = nullptr;        // [ell_size]
+    void *val64 = nullptr;         // double or double2 [ell_size]
+    void *val32 = nullptr;         // float or float2 [ell_size]
+    double *onsite64 = nullptr;    // [n_rows]
+    float *onsite32 = nullptr;     // [n_rows]
+    int64_t *ell_csr = nullptr;    // [ell_size] merged-CSR position of each slot, -1 for padding
+};
+
+// Host-side image of the sliced ELL build (also used by tests of the layout).
+struct HostEll {
+    std::vector<int64_t> slice_off;
+    std::vector<int32_t> col;
+    std::vector<int64_t> csr_pos;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launch parameters
+// ---------------------------------------------------------------------------
+enum PassKind : int {
+    kPassFirst = 0,   // x = v, no b2 buffer
+    kPassNoB2 = 1,    // no b2 buffer
+    kPassMid = 2,     // b2 buffer
+    kPassLast = 3,    // b2 buffer, fused correlation
+    kPassLastNoB2 = 4 // no b2 buffer, fused correlation
+};
+
+struct PassParams {
+    const TileDesc *tiles;
+    int32_t n_tiles;
+    int32_t xcd_remap;
+    int32_t log2s;  // log2 of the (padded) number of states
+    int32_t bump_counter;
+    const int32_t *col;
+    const void *val;
+    const int64_t *slice_off;
+    const void *onsite;
+    const void *x;   // gathered vector (b_{j+1}, or v for the first pass)
+    const void *v;   // psi_k
+    const void *b2;  // b_{j+2}
+    void *out;       // b_j or psi_{k+1}; may alias b2 or v element-wise
+    const PassCoef *coef;  // [n_inst] of this pass
+    int32_t *counter;      // device step counter
+    // fused correlation (last pass)
+    const double *phi0;    // complex128 [rows][S]
+    int64_t phi0_ld;       // states per row of phi0 (>= S padded or the caller's S)
+    double *partials;      // [n_tiles][S][3]
+    // checkpoints (last pass, FP64 only)
+    double *ckpt;          // complex128 [n_ckpt][rows][s_user]
+    int64_t ckpt_stride;   // complex elements per checkpoint (rows * s_user)
+    int32_t ckpt_every;
+    int32_t ckpt_max;      // largest step index that is stored
+    int32_t s_user;
+};
+
+struct InitParams {
+    const TileDesc *tiles;
+    int32_t n_tiles;
+    int32_t log2s;
+    int32_t s_user;
+    const double *const *psi0;   // per member, [N_i][s_user] complex128
+    const int64_t *inst_row0;    // per member, first global row
+    void *v;                     // state buffer [rows][S] (R precision)
+    double *phi0;                // padded FP64 copy [rows][S], or null
+    double *partials;            // [n_tiles][S][3]
+    int32_t *counter;
+};
+
+struct ReduceParams {
+    const double *partials;
+    const int32_t *inst_tile0;   // [n_inst + 1]
+    int32_t log2s;
+    int32_t s_user;
+    int32_t n_steps;
+    const int32_t *counter;
+    double *const *corr;          // per member [n_steps][s_user] complex128
+    double *const *norm2;         // per member, entries may be null
+    double *norm2_all;            // [n_inst][n_steps][s_user]
+};
+
+// launchers (kernels.hip)
+hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, const PassParams &p,
+                       hipStream_t st);
+hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st);
+hipError_t launch_reduce(int n_inst, int s_pad, const ReduceParams &p, hipStream_t st);
+hipError_t launch_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, int window,
+                      double *energies, double *dos, hipStream_t st);
+hipError_t launch_dos_backward(const double *gdos, int32_t n_steps, int32_t n_states, double dt,
+                               int window, double *gcorr, hipStream_t st);
+hipError_t launch_convert_values(const DevMatrix &m, const double *csr_val, const double *csr_onsite,
+                                 int64_t n_rows, hipStream_t st);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+
+// backward launchers (backward.hip)
+struct AdjParams;
+hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Host helpers (host.cpp)
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+const std::string &last_error();
+int32_t num_terms(double z, double tol);
+void bessel_j(double z, int32_t M, double *J);
+HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *col);
+
+}  // namespace tbpm

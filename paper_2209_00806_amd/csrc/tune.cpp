@@ -1,0 +1,96 @@
+// Autotuner of the Chebyshev pass launch shape: times every candidate
+// (workgroup chunks x XCD remap x non-temporal streaming) on a few time steps
+// of scratch states and keeps the fastest in the handle.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "tbpm_engine.h"
+
+namespace tbpm {
+
+tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32_t n_states, bool fp32,
+                          tbpm_launch_config *best, double *best_ms, hipStream_t stream) {
+    const int32_t ni = eng.n_inst();
+    const int32_t n_steps = 4;  // three timed Chebyshev steps
+    int64_t max_rows = 0;
+    for (int32_t i = 0; i < ni; ++i) max_rows = std::max(max_rows, eng.inst_row0[i + 1] - eng.inst_row0[i]);
+    std::vector<double> h_psi(2 * (size_t)max_rows * n_states);
+    for (int64_t r = 0; r < max_rows * n_states; ++r) {
+        h_psi[2 * r] = std::cos(0.37 * (double)r) / std::sqrt((double)max_rows);
+        h_psi[2 * r + 1] = std::sin(0.37 * (double)r) / std::sqrt((double)max_rows);
+    }
+    DevBuf psi, corr;
+    hipError_t e = psi.ensure(sizeof(double) * h_psi.size());
+    if (e != hipSuccess) return hip_fail(e, "autotune alloc");
+    e = corr.ensure(sizeof(double) * 2 * (size_t)ni * n_steps * n_states);
+    if (e != hipSuccess) {
+        psi.release();
+        return hip_fail(e, "autotune alloc");
+    }
+    e = hipMemcpy(psi.ptr, h_psi.data(), sizeof(double) * h_psi.size(), hipMemcpyHostToDevice);
+    std::vector<const double *> p0(ni, (const double *)psi.ptr);
+    std::vector<double *> c0(ni);
+    for (int32_t i = 0; i < ni; ++i) c0[i] = (double *)corr.ptr + 2 * (size_t)i * n_steps * n_states;
+    std::vector<double> dt(ni);
+    for (int32_t i = 0; i < ni; ++i) dt[i] = M_PI / rescale[i];
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    tbpm_status st = TBPM_OK;
+    tbpm_launch_config keep = eng.cfg, win = eng.cfg;
+    double win_ms = 1e300;
+    if (e != hipSuccess) st = hip_fail(e, "autotune setup");
+    const int chunk_list[] = {1, 2, 4, 8, 16, 32};
+    for (int ch : chunk_list) {
+        for (int remap = 0; remap <= 1 && st == TBPM_OK; ++remap) {
+            for (int nt = 0; nt <= 1 && st == TBPM_OK; ++nt) {
+                eng.cfg = tbpm_launch_config{ch, remap, nt};
+                Engine::RunArgs a{};
+                a.psi0 = p0.data();
+                a.s_user = n_states;
+                a.n_steps = n_steps;
+                a.dt = dt.data();
+                a.rescale = rescale.data();
+                a.tol = 1e-12;
+                a.fp32 = fp32;
+                a.corr = c0.data();
+                a.norm2 = nullptr;
+                a.flags = TBPM_FLAG_ASYNC;
+                a.stream = stream;
+                st = eng.run(a);  // warm-up (builds tiles and the graph)
+                if (st != TBPM_OK) break;
+                e = hipEventRecord(t0, stream);
+                if (e == hipSuccess) st = eng.run(a);
+                if (e == hipSuccess && st == TBPM_OK) e = hipEventRecord(t1, stream);
+                if (e == hipSuccess && st == TBPM_OK) e = hipEventSynchronize(t1);
+                float ms = 0;
+                if (e == hipSuccess && st == TBPM_OK) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+                if (st != TBPM_OK) break;
+                const double per_step = ms / (n_steps - 1);
+                if (per_step < win_ms) {
+                    win_ms = per_step;
+                    win = eng.cfg;
+                }
+            }
+        }
+        if (st != TBPM_OK) break;
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipStreamSynchronize(stream);
+    psi.release();
+    corr.release();
+    if (st != TBPM_OK) {
+        eng.cfg = keep;
+        return st;
+    }
+    eng.cfg = win;
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return TBPM_OK;
+}
+
+}  // namespace tbpm

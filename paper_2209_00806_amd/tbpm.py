@@ -1,0 +1,382 @@
+"""Thin Python binding of libtbpm (argument marshalling only).
+
+Every step of the TBPM path runs in the library's HIP kernels; this module
+only converts numpy arrays / torch tensors to pointers, picks the current
+torch stream, and turns status codes into exceptions.  It raises
+:class:`TBPMError` if the compiled library is missing -- there is no
+fallback implementation.
+
+Layouts (see ``include/tbpm.h``): states ``[n_orb, n_states]`` complex128,
+correlations ``[n_steps, n_states]`` complex128, DOS on ``2*n_steps``
+energies.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtbpm.so")
+
+STATUS = {0: "TBPM_OK", 1: "TBPM_E_ARG", 2: "TBPM_E_CSR", 3: "TBPM_E_NOT_HERMITIAN", 4: "TBPM_E_OOM",
+          5: "TBPM_E_DEVICE", 6: "TBPM_E_DIVERGED"}
+FP64, FP32_MIXED = 0, 1
+WIN = {"hann": 0, "none": 1}
+FLAG_DEVICE_PTRS, FLAG_ASYNC, FLAG_NO_GRAPH = 1, 2, 4
+
+
+class TBPMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("wg_chunks", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"wg_chunks": self.wg_chunks, "xcd_remap": self.xcd_remap, "nontemporal": self.nontemporal}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtbpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TBPMError(5, f"{LIB_PATH} not found: build it with paper_2209_00806_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, U32, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                               ctypes.c_uint32, ctypes.c_size_t)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "tbpm_hamiltonian_create": [I64, P, P, P, P, PP],
+        "tbpm_hamiltonian_set_values": [P, P, P, U32, P],
+        "tbpm_hamiltonian_info": [P, P, P, P, P, P],
+        "tbpm_hamiltonian_pattern": [P, P, P],
+        "tbpm_hamiltonian_destroy": [P],
+        "tbpm_num_terms": [D, D, P],
+        "tbpm_bessel_j": [D, I32, P],
+        "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
+        "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
+        "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
+        "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
+        "tbpm_batch_create": [P, I32, PP],
+        "tbpm_batch_destroy": [P],
+        "tbpm_propagate_batched": [P, P, I32, I32, P, P, D, ctypes.c_int, P, P, U32, P],
+        "tbpm_get_launch_config": [P, P],
+        "tbpm_set_launch_config": [P, P],
+        "tbpm_batch_get_launch_config": [P, P],
+        "tbpm_batch_set_launch_config": [P, P],
+        "tbpm_autotune": [P, I32, ctypes.c_int, P, P, P],
+        "tbpm_batch_autotune": [P, I32, ctypes.c_int, P, P, P],
+        "tbpm_stream_copy": [P, P, SZ, P],
+        "tbpm_bench_pass": [P, I32, ctypes.c_int, I32, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.tbpm_last_error.argtypes = []
+    L.tbpm_last_error.restype = ctypes.c_char_p
+    L.tbpm_version.argtypes = []
+    L.tbpm_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise TBPMError(status, lib().tbpm_last_error().decode())
+
+
+def _ptr(a) -> int:
+    """Data pointer of a contiguous numpy array or torch tensor."""
+    if a is None:
+        return 0
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return a.ctypes.data
+
+
+def _stream(stream=None) -> int:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _require_cuda(t, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def version() -> str:
+    return lib().tbpm_version().decode()
+
+
+def num_terms(z: float, tol: float = 1e-12) -> int:
+    m = ctypes.c_int32()
+    _check(lib().tbpm_num_terms(float(z), float(tol), ctypes.byref(m)))
+    return m.value
+
+
+def bessel_j(z: float, M: int) -> np.ndarray:
+    out = np.zeros(M)
+    _check(lib().tbpm_bessel_j(float(z), int(M), out.ctypes.data))
+    return out
+
+
+class Hamiltonian:
+    """Library-owned device copy of a tight-binding Hamiltonian."""
+
+    def __init__(self, n_orb: int, row_ptr, col, val, onsite):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.complex128)
+        on = np.ascontiguousarray(onsite, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().tbpm_hamiltonian_create(int(n_orb), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                                             on.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_lattice(cls, lat) -> "Hamiltonian":
+        return cls(lat.n_orb, lat.row_ptr, lat.col, lat.val, lat.onsite)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("Hamiltonian has been closed")
+        return self._h
+
+    def info(self) -> dict:
+        n, nnz, g, c, mr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tbpm_hamiltonian_info(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(g),
+                                           ctypes.byref(c), ctypes.byref(mr)))
+        return {"n_orb": n.value, "nnz": nnz.value, "gershgorin": g.value, "is_complex": bool(c.value),
+                "max_row": mr.value}
+
+    def pattern(self):
+        inf = self.info()
+        rp = np.zeros(inf["n_orb"] + 1, dtype=np.int64)
+        ci = np.zeros(max(inf["nnz"], 1), dtype=np.int32)
+        _check(lib().tbpm_hamiltonian_pattern(self.handle, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci[: inf["nnz"]]
+
+    def set_values(self, val, onsite, stream=None):
+        """New values on the same (merged) pattern: numpy (host, validated) or
+        CUDA torch tensors (device, complex128 [nnz] and float64 [n_orb])."""
+        if hasattr(val, "is_cuda") and val.is_cuda:
+            _check(lib().tbpm_hamiltonian_set_values(self.handle, _ptr(val), _ptr(onsite), FLAG_DEVICE_PTRS,
+                                                     _stream(stream)))
+        else:
+            va = np.ascontiguousarray(val, dtype=np.complex128)
+            on = np.ascontiguousarray(onsite, dtype=np.float64)
+            _check(lib().tbpm_hamiltonian_set_values(self.handle, va.ctypes.data, on.ctypes.data, 0, 0))
+
+    def launch_config(self) -> dict:
+        c = LaunchConfig()
+        _check(lib().tbpm_get_launch_config(self.handle, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_launch_config(self, wg_chunks=8, xcd_remap=1, nontemporal=0):
+        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal)
+        _check(lib().tbpm_set_launch_config(self.handle, ctypes.byref(c)))
+
+    def autotune(self, n_states: int, precision: str = "fp64", stream=None):
+        c = LaunchConfig()
+        ms = ctypes.c_double()
+        _check(lib().tbpm_autotune(self.handle, int(n_states), _prec(precision), ctypes.byref(c),
+                                   ctypes.byref(ms), _stream(stream)))
+        return c.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tbpm_hamiltonian_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _prec(precision: str) -> int:
+    if precision in ("fp64", FP64):
+        return FP64
+    if precision in ("fp32", "fp32_mixed", FP32_MIXED):
+        return FP32_MIXED
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def propagate(H: Hamiltonian, psi0, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,
+              precision: str = "fp64", return_norm: bool = False, ckpt_every: int = 0, graph: bool = True,
+              sync: bool = True, stream=None, out=None):
+    """C_k = <psi0|psi(k dt)>, k < n_steps, for psi0 a CUDA complex128 tensor [n_orb, S].
+
+    Returns corr [n_steps, S] (and norm2 [n_steps, S] if return_norm, and the
+    checkpoint tensor if ckpt_every > 0).
+    """
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    if psi0.dim() == 1:
+        psi0 = psi0.reshape(-1, 1)
+    n, S = psi0.shape
+    corr = out if out is not None else torch.empty((n_steps, S), dtype=torch.complex128, device=psi0.device)
+    norm2 = torch.empty((n_steps, S), dtype=torch.float64, device=psi0.device) if return_norm else None
+    ckpt = None
+    if ckpt_every > 0:
+        n_ck = max(0, (n_steps - 2) // ckpt_every)
+        ckpt = torch.empty((max(n_ck, 1), n, S), dtype=torch.complex128, device=psi0.device)
+    flags = (0 if graph else FLAG_NO_GRAPH) | (0 if sync else FLAG_ASYNC)
+    _check(lib().tbpm_propagate(H.handle, _ptr(psi0), S, int(n_steps), float(dt), float(rescale), float(tol),
+                                _prec(precision), _ptr(corr), _ptr(norm2), int(ckpt_every), _ptr(ckpt), flags,
+                                _stream(stream)))
+    res = [corr]
+    if return_norm:
+        res.append(norm2)
+    if ckpt_every > 0:
+        res.append(ckpt)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def dos(corr, dt: float, window: str = "hann", stream=None):
+    """(energies, dos) on the 2*n_steps grid E_j = j pi/(n_steps dt), j = -n_steps..n_steps-1."""
+    import torch
+
+    _require_cuda(corr, torch.complex128, "corr")
+    if corr.dim() == 1:
+        corr = corr.reshape(-1, 1)
+    nt, S = corr.shape
+    e = torch.empty(2 * nt, dtype=torch.float64, device=corr.device)
+    d = torch.empty(2 * nt, dtype=torch.float64, device=corr.device)
+    _check(lib().tbpm_dos(_ptr(corr), nt, S, float(dt), WIN[window], _ptr(e), _ptr(d), _stream(stream)))
+    return e, d
+
+
+def dos_backward(grad_dos, n_steps: int, n_states: int, dt: float, window: str = "hann", stream=None):
+    import torch
+
+    _require_cuda(grad_dos, torch.float64, "grad_dos")
+    g = torch.empty((n_steps, n_states), dtype=torch.complex128, device=grad_dos.device)
+    _check(lib().tbpm_dos_backward(_ptr(grad_dos), int(n_steps), int(n_states), float(dt), WIN[window], _ptr(g),
+                                   _stream(stream)))
+    return g
+
+
+def backward(H: Hamiltonian, psi0, n_steps: int, dt: float, rescale: float, grad_corr, ckpt_every: int, ckpt,
+             tol: float = 1e-12, stream=None):
+    """(grad_val complex128 [nnz], grad_onsite float64 [n_orb]) of L through C (see include/tbpm.h)."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    _require_cuda(grad_corr, torch.complex128, "grad_corr")
+    n, S = psi0.shape
+    inf = H.info()
+    gv = torch.empty(max(inf["nnz"], 1), dtype=torch.complex128, device=psi0.device)
+    go = torch.empty(n, dtype=torch.float64, device=psi0.device)
+    _check(lib().tbpm_backward(H.handle, _ptr(psi0), S, int(n_steps), float(dt), float(rescale), float(tol),
+                               _ptr(grad_corr), int(ckpt_every), _ptr(ckpt), _ptr(gv), _ptr(go), _stream(stream)))
+    return gv[: inf["nnz"]], go
+
+
+class Batch:
+    """Several Hamiltonians propagated together (one launch per Chebyshev pass)."""
+
+    def __init__(self, hams: Sequence[Hamiltonian]):
+        self.hams = list(hams)
+        arr = (ctypes.c_void_p * len(self.hams))(*[h.handle.value for h in self.hams])
+        b = ctypes.c_void_p()
+        _check(lib().tbpm_batch_create(arr, len(self.hams), ctypes.byref(b)))
+        self._b = b
+
+    def propagate(self, psi0s, n_steps: int, dts, rescales=None, tol: float = 1e-12, precision: str = "fp64",
+                  return_norm: bool = False, graph: bool = True, sync: bool = True, stream=None):
+        import torch
+
+        n = len(self.hams)
+        if len(psi0s) != n:
+            raise ValueError("one psi0 per Hamiltonian")
+        S = psi0s[0].shape[1]
+        for p in psi0s:
+            _require_cuda(p, torch.complex128, "psi0")
+            if p.shape[1] != S:
+                raise ValueError("all members need the same number of states")
+        corrs = [torch.empty((n_steps, S), dtype=torch.complex128, device=psi0s[0].device) for _ in range(n)]
+        norms = [torch.empty((n_steps, S), dtype=torch.float64, device=psi0s[0].device) for _ in range(n)] \
+            if return_norm else None
+        P = ctypes.c_void_p * n
+        p_arr = P(*[_ptr(p) for p in psi0s])
+        c_arr = P(*[_ptr(c) for c in corrs])
+        n_arr = P(*[_ptr(x) for x in norms]) if norms else None
+        dt_arr = np.ascontiguousarray(dts, dtype=np.float64)
+        f_arr = np.zeros(n) if rescales is None else np.ascontiguousarray(rescales, dtype=np.float64)
+        flags = (0 if graph else FLAG_NO_GRAPH) | (0 if sync else FLAG_ASYNC)
+        _check(lib().tbpm_propagate_batched(self._b, p_arr, S, int(n_steps), dt_arr.ctypes.data, f_arr.ctypes.data,
+                                            float(tol), _prec(precision), c_arr,
+                                            n_arr if n_arr is not None else None, flags, _stream(stream)))
+        return (corrs, norms) if return_norm else corrs
+
+    def launch_config(self) -> dict:
+        c = LaunchConfig()
+        _check(lib().tbpm_batch_get_launch_config(self._b, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_launch_config(self, wg_chunks=8, xcd_remap=1, nontemporal=0):
+        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal)
+        _check(lib().tbpm_batch_set_launch_config(self._b, ctypes.byref(c)))
+
+    def autotune(self, n_states: int, precision: str = "fp64", stream=None):
+        c = LaunchConfig()
+        ms = ctypes.c_double()
+        _check(lib().tbpm_batch_autotune(self._b, int(n_states), _prec(precision), ctypes.byref(c),
+                                         ctypes.byref(ms), _stream(stream)))
+        return c.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().tbpm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stream_copy(src, dst, stream=None):
+    """Plain device copy of src into dst (bandwidth calibration)."""
+    nbytes = src.numel() * src.element_size()
+    _check(lib().tbpm_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
+
+
+def bench_pass(H: Hamiltonian, n_states: int, precision: str, n_launch: int, stream=None):
+    """Enqueue n_launch launches of the interior Clenshaw pass (timing only)."""
+    _check(lib().tbpm_bench_pass(H.handle, int(n_states), _prec(precision), int(n_launch), _stream(stream)))
+
+
+def default_dt(rescale: float) -> float:
+    """The paper's time step dt = pi / f (usage section, TBPM example)."""
+    return math.pi / rescale

@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (FP64): max_k |dCbar_k| / max_k |Cbar_k| <= 1e-10 and
+max_j |dD_j| / max_j |D_j| <= 1e-10; FP32-mixed: sum_j |dD_j| / sum_j |D_j|
+<= 1e-4 against the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_00806_amd import inputs, tbpm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _l1(a, b):
+    return float(np.sum(np.abs(np.asarray(a) - np.asarray(b))) / np.sum(np.abs(np.asarray(b))))
+
+
+def _complex_graphene(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    bi, bj, _, _ = inputs.graphene_bonds(nx, ny, pbc=True)
+    bt = -2.7 * np.exp(1j * rng.uniform(0, 2 * np.pi, bi.shape[0]))
+    ons = inputs.anderson(rng, 2 * nx * ny, 1.5)
+    return inputs.from_bonds(2 * nx * ny, bi, bj, bt, ons)
+
+
+LATTICES = {
+    "single_site": lambda: inputs.from_bonds(1, np.zeros(0, int), np.zeros(0, int), np.zeros(0), np.array([1.3])),
+    "dimer": lambda: inputs.from_bonds(2, np.array([0]), np.array([1]), np.array([1.7]), np.array([0.2, -0.1])),
+    "graphene6x6_disorder": lambda: inputs.graphene(6, 6, onsite=inputs.anderson(np.random.default_rng(1), 72, 1.0)),
+    "square5x7_open": lambda: inputs.square(5, 7, pbc=False, onsite=inputs.anderson(np.random.default_rng(2), 35, 2.0)),
+    "graphene4x5_complex": lambda: _complex_graphene(4, 5, 3),
+    "tbg8x8": lambda: inputs.twisted_bilayer(8, 8, angle_deg=5.0),
+    "graphene2x2_duplicates": lambda: inputs.graphene(2, 1),
+}
+
+
+def _run_pair(lat, S, nt, seed=7, precision="fp64", f=None, tol=1e-12, **kw):
+    rng = np.random.default_rng(seed)
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    if f is None:
+        f = max(oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite), 1e-3) * 1.05
+    dt = math.pi / f
+    ref, ref_n2, info = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f, tol=tol)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if "cfg" in kw:
+        H.set_launch_config(**kw.pop("cfg"))
+    corr, n2 = tbpm.propagate(H, _dev(psi0), nt, dt, f, tol=tol, precision=precision, return_norm=True, **kw)
+    return H, psi0, dt, ref, ref_n2, corr.cpu().numpy(), n2.cpu().numpy()
+
+
+@pytest.mark.parametrize("S", [1, 3, 8])
+@pytest.mark.parametrize("name", sorted(LATTICES))
+def test_small_lattices_fp64(name, S):
+    print(f"case {name} S={S}", flush=True)
+    lat = LATTICES[name]()
+    nt = 96
+    H, psi0, dt, ref, ref_n2, got, n2 = _run_pair(lat, S, nt)
+    assert _rel(got.mean(axis=1), ref.mean(axis=1)) < 1e-10
+    assert _rel(got, ref) < 1e-10
+    assert np.max(np.abs(n2 - ref_n2)) < 1e-10
+    E, D = tbpm.dos(_dev(got), dt)
+    Er, Dr = oracle.dos(ref, dt)
+    assert np.max(np.abs(E.cpu().numpy() - Er)) < 1e-12 * np.max(np.abs(Er))
+    assert _rel(D.cpu().numpy(), Dr) < 1e-10
+
+
+@pytest.mark.parametrize("S", [1, 4])
+@pytest.mark.parametrize("chunks", [1, 8, 32])
+def test_multi_tile_ragged_tail(S, chunks):
+    # 10366 orbitals: many tiles of 256*chunks/S rows plus a ragged last tile and slice
+    print(f"case graphene71x73 S={S} chunks={chunks}", flush=True)
+    rng = np.random.default_rng(3)
+    lat = inputs.graphene(71, 73, onsite=inputs.anderson(rng, 2 * 71 * 73, 1.0))
+    _, _, dt, ref, ref_n2, got, n2 = _run_pair(lat, S, 48, cfg=dict(wg_chunks=chunks, xcd_remap=1, nontemporal=0))
+    assert _rel(got, ref) < 1e-10
+    assert np.max(np.abs(n2 - ref_n2)) < 1e-10
+
+
+def test_config1_full_size():
+    """64x64 periodic graphene, 1 state, 512 steps, f = 9 eV, dt = pi/f, 1024 energies."""
+    print("case config1 64x64 S=1 nt=512", flush=True)
+    lat, psi0 = inputs.workload_graphene_dos(64, 1)
+    f = 9.0
+    dt = math.pi / f
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 512, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    corr = tbpm.propagate(H, _dev(psi0), 512, dt, f).cpu().numpy()
+    assert _rel(corr, ref) < 1e-10
+    E, D = tbpm.dos(_dev(corr), dt)
+    assert D.shape[0] == 1024
+    Er, Dr = oracle.dos(ref, dt)
+    assert _rel(D.cpu().numpy(), Dr) < 1e-10
+
+
+def test_launch_configs_and_graph_agree():
+    print("case launch configs", flush=True)
+    rng = np.random.default_rng(5)
+    lat = inputs.graphene(40, 33, onsite=inputs.anderson(rng, 2 * 40 * 33, 1.0))
+    psi0 = _dev(inputs.random_phase_states(rng, lat.n_orb, 4))
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    f = 9.0
+    dt = math.pi / f
+    base = tbpm.propagate(H, psi0, 40, dt, f, graph=False).cpu().numpy()
+    for ch in (1, 2, 4, 8, 16, 32):
+        for remap in (0, 1):
+            for nt in (0, 1):
+                H.set_launch_config(ch, remap, nt)
+                got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+                assert _rel(got, base) < 1e-13, (ch, remap, nt)
+    # a repeated call reuses the cached graph and gives the same bits
+    again = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+    assert np.array_equal(again, got)
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex", "tbg8x8"])
+def test_fp32_mixed_small(name):
+    print(f"case fp32 {name}", flush=True)
+    lat = LATTICES[name]()
+    _, _, dt, ref, ref_n2, got, n2 = _run_pair(lat, 4, 256, precision="fp32")
+    _, Dr = oracle.dos(ref, dt)
+    _, D = tbpm.dos(_dev(got), dt)
+    assert _l1(D.cpu().numpy(), Dr) < 1e-4
+    assert np.max(np.abs(n2 - 1)) < 1e-4
+
+
+def test_fp32_mixed_config1():
+    print("case fp32 config1", flush=True)
+    lat, psi0 = inputs.workload_graphene_dos(64, 2)
+    f = 9.0
+    dt = math.pi / f
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 512, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    got = tbpm.propagate(H, _dev(psi0), 512, dt, f, precision="fp32").cpu().numpy()
+    _, Dr = oracle.dos(ref, dt)
+    _, D = tbpm.dos(_dev(got), dt)
+    err = _l1(D.cpu().numpy(), Dr)
+    print(f"fp32 config1 DOS L1-relative error {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_vs_single_and_oracle(precision):
+    print(f"case batched {precision}", flush=True)
+    rng = np.random.default_rng(9)
+    lats = [inputs.graphene(9, 7, onsite=inputs.anderson(rng, 126, 0.7)),
+            inputs.square(13, 11, onsite=inputs.anderson(rng, 143, 1.9)),
+            _complex_graphene(5, 4, 11),
+            inputs.graphene(30, 31, onsite=inputs.anderson(rng, 1860, 1.2)),
+            inputs.from_bonds(1, np.zeros(0, int), np.zeros(0, int), np.zeros(0), np.array([0.4]))]
+    S, nt = 3, 64
+    psis = [inputs.random_phase_states(rng, l.n_orb, S) for l in lats]
+    fs = [max(oracle.gershgorin(l.row_ptr, l.val, l.onsite), 0.5) * 1.1 for l in lats]
+    dts = [math.pi / f for f in fs]
+    dts[2] *= 1.7  # a member with a different z (more Chebyshev terms)
+    hams = [tbpm.Hamiltonian.from_lattice(l) for l in lats]
+    B = tbpm.Batch(hams)
+    corrs = B.propagate([_dev(p) for p in psis], nt, dts, fs, precision=precision)
+    for l, h, p, f, dt, c in zip(lats, hams, psis, fs, dts, corrs):
+        single = tbpm.propagate(h, _dev(p), nt, dt, f, precision=precision).cpu().numpy()
+        c = c.cpu().numpy()
+        assert _rel(c, single) < 1e-12
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, nt, dt, f)
+        if precision == "fp64":
+            assert _rel(c, ref) < 1e-10
+        else:
+            assert _rel(c, ref) < 1e-4
+
+
+def test_dos_kernel_and_adjoint_vs_oracle():
+    print("case dos kernel", flush=True)
+    rng = np.random.default_rng(12)
+    for nt, S, dt in ((300, 3, 0.37), (1024, 8, math.pi / 9.0), (1, 1, 0.5), (7, 2, 1.1)):
+        c = rng.standard_normal((nt, S)) + 1j * rng.standard_normal((nt, S))
+        for win in ("hann", "none"):
+            E, D = tbpm.dos(_dev(c), dt, window=win)
+            Er, Dr = oracle.dos(c, dt, kind=win)
+            assert _rel(D.cpu().numpy(), Dr) < 1e-12
+            assert _rel(E.cpu().numpy(), Er) < 1e-14
+            g = rng.standard_normal(2 * nt)
+            G = tbpm.dos_backward(_dev(g), nt, S, dt, window=win).cpu().numpy()
+            Gr = oracle.dos_adjoint(g, nt, S, dt, kind=win)
+            assert _rel(G, Gr) < 1e-12
+
+
+def test_diverged_when_rescale_too_small():
+    print("case diverged", flush=True)
+    lat = inputs.graphene(8, 8)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    psi0 = _dev(inputs.random_phase_states(np.random.default_rng(1), lat.n_orb, 1))
+    with pytest.raises(tbpm.TBPMError) as ei:
+        tbpm.propagate(H, psi0, 16, math.pi / 4.0, 4.0)
+    assert ei.value.name == "TBPM_E_DIVERGED"
+    # the same call with a valid rescale works afterwards
+    corr = tbpm.propagate(H, psi0, 16, math.pi / 9.0, 9.0)
+    assert abs(complex(corr[0, 0].item()) - 1.0) < 1e-12
+
+
+def test_gershgorin_default_rescale_and_set_values():
+    print("case set_values", flush=True)
+    rng = np.random.default_rng(2)
+    lat = inputs.graphene(10, 10, onsite=inputs.anderson(rng, 200, 1.0))
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    info = H.info()
+    g = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite)
+    assert abs(info["gershgorin"] - g) < 1e-12
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, 2)
+    dt = math.pi / g
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 64, dt, 0.0)
+    got = tbpm.propagate(H, _dev(psi0), 64, dt, 0.0).cpu().numpy()
+    assert _rel(got, ref) < 1e-10
+    # new values on the same pattern: host path and device path
+    val2 = lat.val * 1.1
+    ons2 = lat.onsite[::-1].copy()
+    lat2 = inputs.Lattice(lat.n_orb, lat.row_ptr, lat.col, val2, ons2)
+    ref2, _, _ = oracle.propagate(lat.row_ptr, lat.col, val2, ons2, psi0, 64, dt, 11.0)
+    H.set_values(val2, ons2)
+    got2 = tbpm.propagate(H, _dev(psi0), 64, dt, 11.0).cpu().numpy()
+    assert _rel(got2, ref2) < 1e-10
+    H.set_values(lat.val, lat.onsite)
+    H.set_values(_dev(val2), _dev(ons2))
+    got3 = tbpm.propagate(H, _dev(psi0), 64, dt, 11.0).cpu().numpy()
+    assert _rel(got3, ref2) < 1e-10
+    del lat2
+
+
+def test_config2_full_size_sampled_states():
+    """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, FP64, the
+    bench launch shape: a prefix of steps for two sampled states against the
+    oracle, and at every step the norm and C_0 = ||psi0||^2."""
+    print("case config2 full size", flush=True)
+    lat, psi0 = inputs.workload_disordered_graphene(1024, 8)
+    f = 9.0
+    dt = math.pi / f
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    nt = 24
+    corr, n2 = tbpm.propagate(H, _dev(psi0), nt, dt, f, return_norm=True)
+    corr = corr.cpu().numpy()
+    n2 = n2.cpu().numpy()
+    assert np.max(np.abs(n2 - 1)) < 1e-10
+    for s in (0, 5):
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), nt, dt, f)
+        assert _rel(corr[:, s], ref[:, 0]) < 1e-10

@@ -1,0 +1,115 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side logic (Bessel coefficients, truncation rule, input
+validation) is right.  No compute call is made (there is no GPU here);
+invalid inputs are rejected on the host before any device call."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_00806_amd import inputs, tbpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "tbpm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tbpm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tbpm.lib()
+    names = _declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert "gfx950" in tbpm.version()
+
+
+@pytest.mark.parametrize("z", [math.pi / 2, math.pi, 2 * math.pi, 10.3, 37.0, -2.5, 1e-9])
+def test_library_bessel_vs_oracle(z):
+    M = 60
+    got = tbpm.bessel_j(z, M)
+    ref = np.array([oracle.bessel_j(m, abs(z)) * ((-1) ** m if z < 0 else 1) for m in range(M)])
+    assert np.max(np.abs(got - ref)) < 2e-16 * max(1.0, abs(z)) ** 0.5 * 4
+
+
+@pytest.mark.parametrize("z,tol", [(math.pi, 1e-12), (2 * math.pi, 1e-12), (math.pi, 1e-16), (0.01, 1e-12),
+                                   (1e-14, 1e-12), (25.0, 1e-10), (9.5 * math.pi / 9.0, 1e-12)])
+def test_library_num_terms_matches_oracle(z, tol):
+    assert tbpm.num_terms(z, tol) == oracle.n_terms(z, tol)
+
+
+def _create(n, rp, col, val, ons):
+    return tbpm.Hamiltonian(n, rp, col, val, ons)
+
+
+def _expect(status_name, *args):
+    with pytest.raises(tbpm.TBPMError) as ei:
+        _create(*args)
+    assert ei.value.name == status_name, str(ei.value)
+
+
+def test_create_rejects_non_hermitian():
+    lat = inputs.graphene(3, 3)
+    val = lat.val.copy()
+    val[5] *= 1.5
+    _expect("TBPM_E_NOT_HERMITIAN", lat.n_orb, lat.row_ptr, lat.col, val, lat.onsite)
+    # complex element whose partner is not its conjugate
+    val = lat.val.copy()
+    val[0] = val[0] + 0.3j
+    _expect("TBPM_E_NOT_HERMITIAN", lat.n_orb, lat.row_ptr, lat.col, val, lat.onsite)
+
+
+def test_create_rejects_missing_partner():
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    _expect("TBPM_E_NOT_HERMITIAN", 2, rp, np.array([1], np.int32), np.array([1.0 + 0j]), np.zeros(2))
+
+
+def test_create_rejects_bad_csr():
+    lat = inputs.graphene(2, 2)
+    rp = lat.row_ptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]
+    _expect("TBPM_E_CSR", lat.n_orb, rp, lat.col, lat.val, lat.onsite)
+    col = lat.col.copy()
+    col[0] = lat.n_orb
+    _expect("TBPM_E_CSR", lat.n_orb, lat.row_ptr, col, lat.val, lat.onsite)
+    col = lat.col.copy()
+    col[0] = 0  # row 0 diagonal
+    _expect("TBPM_E_CSR", lat.n_orb, lat.row_ptr, col, lat.val, lat.onsite)
+    rp = lat.row_ptr.copy()
+    rp[0] = 1
+    _expect("TBPM_E_CSR", lat.n_orb, rp, lat.col, lat.val, lat.onsite)
+
+
+def test_create_rejects_non_finite_and_bad_sizes():
+    lat = inputs.graphene(2, 2)
+    val = lat.val.copy()
+    val[2] = np.nan
+    _expect("TBPM_E_ARG", lat.n_orb, lat.row_ptr, lat.col, val, lat.onsite)
+    ons = lat.onsite.copy()
+    ons[1] = np.inf
+    _expect("TBPM_E_ARG", lat.n_orb, lat.row_ptr, lat.col, lat.val, ons)
+    L = tbpm.lib()
+    h = ctypes.c_void_p()
+    assert L.tbpm_hamiltonian_create(0, None, None, None, None, ctypes.byref(h)) == 1
+    assert L.tbpm_hamiltonian_create(-5, None, None, None, None, ctypes.byref(h)) == 1
+    assert L.tbpm_hamiltonian_create(4, None, None, None, None, None) == 1
+
+
+def test_entry_points_reject_null_and_bad_arguments():
+    L = tbpm.lib()
+    m = ctypes.c_int32()
+    assert L.tbpm_num_terms(1.0, 0.0, ctypes.byref(m)) == 1
+    assert L.tbpm_num_terms(float("nan"), 1e-12, ctypes.byref(m)) == 1
+    assert L.tbpm_propagate(None, None, 1, 1, 0.1, 9.0, 1e-12, 0, None, None, 0, None, 0, None) == 1
+    assert L.tbpm_dos(None, 4, 1, 0.1, 0, None, None, None) == 1
+    assert L.tbpm_backward(None, None, 1, 1, 0.1, 9.0, 1e-12, None, 1, None, None, None, None) == 1
+    assert L.tbpm_batch_create(None, 0, ctypes.byref(ctypes.c_void_p())) == 1
+    assert L.tbpm_stream_copy(None, None, 16, None) == 1
+    assert b"NULL" in L.tbpm_last_error() or len(L.tbpm_last_error()) > 0
