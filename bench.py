@@ -53,6 +53,124 @@ def pass_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
     return 4 * b * n_orb * S + nnz * (4 + v) + n_orb * v
 
 
+def bench_batched(args, log):
+    """Uneven batch: square/graphene lattices of 1e4..1e6 orbitals with Anderson
+    disorder, 4 states each, propagated in one launch sequence (FP64 and FP32)."""
+    import numpy as np
+    import torch
+
+    from paper_2209_00806_amd import inputs, tbpm
+
+    t0 = time.time()
+    lats, states = inputs.workload_batch(args.batch_members)
+    hams = [tbpm.Hamiltonian.from_lattice(l) for l in lats]
+    fs = [h.info()["gershgorin"] for h in hams]
+    dts = [math.pi / f for f in fs]
+    B = tbpm.Batch(hams)
+    psis = [torch.from_numpy(s).cuda() for s in states]
+    S = states[0].shape[1]
+    nt = args.batch_nt
+    n_orb = sum(l.n_orb for l in lats)
+    log(f"batch built: {len(lats)} members, {n_orb} orbitals in {time.time() - t0:.1f}s")
+    out = {"members": len(lats), "n_orb_total": n_orb, "n_states": S, "n_steps": nt,
+           "sizes_min_max": [min(l.n_orb for l in lats), max(l.n_orb for l in lats)]}
+    updates = 0
+    alg64 = alg32 = 0
+    for l, f, dt in zip(lats, fs, dts):
+        M = tbpm.num_terms(f * dt, 1e-12)
+        updates += (l.nnz + l.n_orb) * S * (M - 1) * (nt - 1)
+        alg64 += pass_bytes(l.n_orb, l.nnz, S, 16, 8) * (M - 1) * (nt - 1)
+        alg32 += pass_bytes(l.n_orb, l.nnz, S, 8, 4) * (M - 1) * (nt - 1)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for prec in ("fp64", "fp32"):
+        B.propagate(psis, 8, dts, fs, precision=prec)  # warm-up
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        corrs = B.propagate(psis, nt, dts, fs, precision=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[prec] = [c.cpu().numpy() for c in corrs]
+        out[prec] = {"ms": round(ms, 1), "nnz_updates_per_s": updates / (ms / 1e3),
+                     "alg_GBps": round((alg64 if prec == "fp64" else alg32) / (ms / 1e3) / 1e9, 1)}
+        log(f"batched {prec}: {ms:.1f} ms, {updates / (ms / 1e3):.3e} nnz-updates/s")
+    errs = []
+    for c64, c32, dt in zip(res["fp64"], res["fp32"], dts):
+        _, d64 = tbpm.dos(torch.from_numpy(c64).cuda(), dt)
+        _, d32 = tbpm.dos(torch.from_numpy(c32).cuda(), dt)
+        d64 = d64.cpu().numpy()
+        d32 = d32.cpu().numpy()
+        errs.append(float(np.sum(np.abs(d32 - d64)) / np.sum(np.abs(d64))))
+    out["fp32_dos_l1_rel_err_max"] = max(errs)
+    out["fp32_speedup_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32"]["ms"], 3)
+    B.close()
+    for h in hams:
+        h.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_backward(args, log):
+    """Differentiable DOS: graphene with per-bond hoppings, loss = sum over 256
+    energies of (D(E) - target)^2; forward and backward (adjoint) timed."""
+    import numpy as np
+    import torch
+
+    from paper_2209_00806_amd import autograd as ag
+    from paper_2209_00806_amd import inputs, tbpm
+
+    t0 = time.time()
+    lat, target_lat, psi0_np = inputs.workload_bond_graphene(args.bwd_cells, 4)
+    f = 9.0
+    dt = math.pi / f
+    nt = args.bwd_nt
+    K = 64
+    psi0 = torch.from_numpy(psi0_np).cuda()
+    Ht = tbpm.Hamiltonian.from_lattice(target_lat)
+    _, target = tbpm.dos(tbpm.propagate(Ht, psi0, nt, dt, f), dt)
+    Ht.close()
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    slot_ij = torch.from_numpy(lat.slot_ij).cuda()
+    slot_ji = torch.from_numpy(lat.slot_ji).cuda()
+    sel = torch.arange(0, 2 * nt, 8, device="cuda")  # 256 energies
+    t_param = torch.from_numpy(lat.bond_t.copy()).cuda().requires_grad_(True)
+    e_param = torch.zeros(lat.n_orb, dtype=torch.float64, device="cuda", requires_grad=True)
+    log(f"backward workload built: N={lat.n_orb}, {lat.bond_t.shape[0]} bonds in {time.time() - t0:.1f}s")
+
+    def forward():
+        val = ag.bond_values(lat.nnz, slot_ij, slot_ji, t_param)
+        _, D = ag.tbpm_dos(H, val, e_param, psi0, nt, dt, f, ckpt_every=K)
+        return torch.sum((D[sel] - target[sel]) ** 2)
+
+    L = forward()  # warm-up
+    L.backward()
+    torch.cuda.synchronize()
+    t_param.grad = None
+    e_param.grad = None
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    L = forward()
+    e1.record(stream)
+    L.backward()
+    e2.record(stream)
+    torch.cuda.synchronize()
+    fwd = e0.elapsed_time(e1)
+    bwd = e1.elapsed_time(e2)
+    g = t_param.grad
+    out = {"n_orb": lat.n_orb, "bond_params": int(lat.bond_t.shape[0]), "n_states": 4, "n_steps": nt,
+           "ckpt_every": K, "loss": L.item(), "forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+           "backward_over_forward": round(bwd / fwd, 3), "grad_norm": float(torch.linalg.norm(g).item())}
+    log(f"backward: fwd {fwd:.1f} ms, bwd {bwd:.1f} ms, ratio {bwd / fwd:.2f}")
+    H.close()
+    torch.cuda.empty_cache()
+    del np
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +183,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--batch-members", type=int, default=64)
+    ap.add_argument("--batch-nt", type=int, default=1024)
+    ap.add_argument("--bwd-cells", type=int, default=512)
+    ap.add_argument("--bwd-nt", type=int, default=1024)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,7 +273,24 @@ def main():
     extra = {}
     c64 = corr64.cpu().numpy()
     d64 = D64.cpu().numpy()
-    extra["fp64_norm_dev_max"] = None
+    # plain FP64 with a single state (the per-GPU share of an 8-way state split)
+    psi1 = psi0[:, :1].contiguous()
+    nt1 = min(nt, 256)
+    tbpm.propagate(H, psi1, nt1, dt, f)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    tbpm.propagate(H, psi1, nt1, dt, f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    rate_s1 = (lat.nnz + lat.n_orb) * n_pass * (nt1 - 1) / (ms1 / 1e3)
+    extra["fp64_single_state"] = {"nnz_updates_per_s": rate_s1, "n_steps_timed": nt1,
+                                  "alg_GBps": round(pass_bytes(lat.n_orb, lat.nnz, 1, 16, 8) * n_pass * (nt1 - 1)
+                                                    / (ms1 / 1e3) / 1e9, 1)}
+    log(f"fp64 S=1: {rate_s1:.3e} nnz-updates/s")
+    del psi1
     if not args.no_fp32:
         one_step("fp32")  # warm-up of the FP32 graph
         torch.cuda.synchronize()
@@ -168,7 +309,16 @@ def main():
                                "dos_l1_rel_err_vs_fp64": l1, "corr_max_rel_err_vs_fp64": cerr,
                                "alg_GBps": round(pass_bytes(lat.n_orb, lat.nnz, S, 8, 4) * n_pass * (nt - 1)
                                                  / (ms32 / 1e3) / 1e9, 1)}
+        extra["fp32_mixed"]["speedup_vs_fp64_single_state"] = round(updates / (ms32 / 1e3) / rate_s1, 3)
         log(f"fp32-mixed: {ms32:.1f} ms/step, speedup {ms_per_step / ms32:.2f}x, DOS L1 err {l1:.2e}")
+    launch_cfg = H.launch_config()
+    H.close()
+    del H
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        extra["batched"] = bench_batched(args, log)
+    if not args.no_backward:
+        extra["backward"] = bench_backward(args, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,7 +358,7 @@ def main():
                                f"{nt} correlation samples, f=9 eV, dt=pi/f, {M} Chebyshev terms, "
                                f"Hann DOS on {2 * nt} energies",
                    "n_orb": lat.n_orb, "nnz_offdiag": lat.nnz, "n_states": S, "n_steps": nt,
-                   "chebyshev_terms": M, "launch": H.launch_config()},
+                   "chebyshev_terms": M, "launch": launch_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "alg_GBps_step": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),

@@ -255,11 +255,13 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *               one chunk is 256 state elements
  *   xcd_remap   1: give each of the 8 XCDs a contiguous range of tiles
  *   nontemporal 1: stream the read-once vectors with non-temporal hints
+ *   unroll      elements each thread handles at once (1, 2 or 4)
  */
 typedef struct {
     int32_t wg_chunks;
     int32_t xcd_remap;
     int32_t nontemporal;
+    int32_t unroll;
 } tbpm_launch_config;
 
 tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_launch_config *cfg);

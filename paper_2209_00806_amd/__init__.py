@@ -7,7 +7,7 @@ lattices and random-phase states.  Importing the package does not load the
 library; the binding loads it on first use and raises if it is missing.
 """
 
-__all__ = ["inputs", "tbpm"]
+__all__ = ["inputs", "tbpm", "autograd"]
 
 
 def __getattr__(name):

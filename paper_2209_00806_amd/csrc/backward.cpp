@@ -1,8 +1,205 @@
-// placeholder, replaced by the adjoint implementation
+// Driver of tbpm_backward: exact discrete adjoint of the Clenshaw propagation.
+//
+// Segments of K steps are replayed forward from their checkpoints (psi_0 =
+// phi0, psi_{mK} from tbpm_propagate), keeping every step's Clenshaw vectors
+// b_1 .. b_{M-2} (b_{M-1} = c_{M-1} psi_l is recomputed on the fly); the
+// adjoint then runs backwards through the segment, one fused kernel per
+// Chebyshev order j (see backward.hip).  Device memory: (K+1) + K (M-2)
+// state vectors for the segment plus four adjoint vectors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <complex>
+#include <cstring>
+#include <vector>
+
 #include "tbpm_engine.h"
+
 namespace tbpm {
-tbpm_status backward_impl(tbpm_hamiltonian *, const double *, int32_t, int32_t, double, double, double, const double *,
-                          int32_t, const double *, double *, double *, hipStream_t) {
-    return fail(TBPM_E_ARG, "tbpm_backward: not built yet");
+
+using cd = std::complex<double>;
+
+#define TRY_HIP(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_user, int32_t N, double dt, double f,
+                          double tol, const double *gcorr, int32_t K, const double *ckpt, double *grad_val,
+                          double *grad_onsite, hipStream_t st) {
+    Engine &eng = H->eng;
+    int dev = 0;
+    TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != eng.device) return fail(TBPM_E_ARG, "handle was created on another device");
+    const bool cplx = eng.mat.is_complex;
+    const int64_t n_rows = eng.mat.n_rows;
+    const int64_t nnz = H->csr.nnz();
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < s_user) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    std::vector<cd> c;
+    const int32_t M = cheb_coeffs(f * dt, tol, c);
+    if (M < 3) return fail(TBPM_E_ARG, "Bessel series does not converge");
+    const std::vector<PassPlan> plan = plan_step({c}, {f}, M);
+    const int n_passes = (int)plan.size();
+
+    tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks);
+    if (s != TBPM_OK) return s;
+    const int32_t n_tiles = (int32_t)eng.h_tiles.size();
+    const int64_t n_el = n_rows * s_pad;
+    if (n_el >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb * n_states (padded to a power of two) must be < 2^31");
+    const size_t vb = sizeof(double) * 2 * (size_t)n_el;
+
+    if (N < 2) {
+        TRY_HIP(launch_fill_zero(grad_val, 2 * nnz, st), "zero grad");
+        TRY_HIP(launch_fill_zero(grad_onsite, n_rows, st), "zero grad");
+        TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
+        return TBPM_OK;
+    }
+    const int32_t seg_len = std::min<int32_t>(K, N - 1);
+    const int32_t n_b = M - 2;  // stored b_1 .. b_{M-2} per step
+    const size_t n_store = (size_t)(seg_len + 1) + (size_t)seg_len * n_b;
+    TRY_HIP(eng.bwd_store.ensure(vb * n_store), "alloc segment store (reduce ckpt_every)");
+    TRY_HIP(eng.bwd_adj.ensure(vb * 4), "alloc adjoint vectors");
+    TRY_HIP(eng.phi0.ensure(vb), "alloc phi0");
+    TRY_HIP(eng.bwd_gacc.ensure((cplx ? 16 : 8) * (size_t)std::max<int64_t>(eng.mat.ell_size, 1)), "alloc gradient");
+    TRY_HIP(eng.bwd_gdiag.ensure(8 * (size_t)n_rows), "alloc gradient");
+    TRY_HIP(eng.bwd_coef.ensure(sizeof(PassCoef) * n_passes), "alloc coefficients");
+    TRY_HIP(eng.partials.ensure(sizeof(double) * 3 * (size_t)n_tiles * s_pad), "alloc partials");
+    TRY_HIP(eng.counter.ensure(sizeof(int32_t) * 64), "alloc counter");
+    std::vector<PassCoef> hc(n_passes);
+    for (int p = 0; p < n_passes; ++p) hc[p] = plan[p].coef[0];
+    TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
+    TRY_HIP(hipMemcpy(eng.bwd_coef.ptr, hc.data(), sizeof(PassCoef) * n_passes, hipMemcpyHostToDevice),
+            "upload coefficients");
+
+    double *store = (double *)eng.bwd_store.ptr;
+    auto psi_slot = [&](int t) { return store + (size_t)t * 2 * n_el; };
+    auto b_slot = [&](int t, int j) {  // b_j, j = 1 .. M-2, of local step t
+        return store + ((size_t)(seg_len + 1) + (size_t)t * n_b + (size_t)(j - 1)) * 2 * n_el;
+    };
+    double *adj = (double *)eng.bwd_adj.ptr;
+    double *lam = adj, *acc = adj + 2 * n_el;
+    double *rot[3] = {lam, adj + 4 * n_el, adj + 6 * n_el};
+    double *phi0p = (double *)eng.phi0.ptr;
+
+    TRY_HIP(launch_expand_states(psi0, s_user, phi0p, log2s, n_rows, st), "expand psi0");
+    TRY_HIP(launch_lam_init(lam, phi0p, gcorr + 2 * (size_t)(N - 1) * s_user, s_user, log2s, n_rows, st),
+            "adjoint init");
+    TRY_HIP(launch_fill_zero((double *)eng.bwd_gacc.ptr, (cplx ? 2 : 1) * eng.mat.ell_size, st), "zero gradient");
+    TRY_HIP(launch_fill_zero((double *)eng.bwd_gdiag.ptr, n_rows, st), "zero gradient");
+
+    // Clenshaw pass j of each plan entry (FIRST, NOB2, MID..., LAST)
+    std::vector<int> pass_j(n_passes);
+    if (M == 3) {
+        pass_j = {1, 0};
+    } else {
+        pass_j[0] = M - 2;
+        pass_j[1] = M - 3;
+        for (int p = 2; p < n_passes - 1; ++p) pass_j[p] = M - 2 - p;
+        pass_j[n_passes - 1] = 0;
+    }
+
+    PassParams pp{};
+    pp.tiles = (const TileDesc *)eng.tiles.ptr;
+    pp.n_tiles = n_tiles;
+    pp.xcd_remap = eng.cfg.xcd_remap;
+    pp.log2s = log2s;
+    pp.bump_counter = 0;
+    pp.col = eng.mat.col;
+    pp.val = eng.mat.val64;
+    pp.slice_off = eng.mat.slice_off;
+    pp.onsite = eng.mat.onsite64;
+    pp.counter = (int32_t *)eng.counter.ptr;
+    pp.phi0 = phi0p;
+    pp.phi0_ld = s_pad;
+    pp.partials = (double *)eng.partials.ptr;
+    pp.ckpt = nullptr;
+    pp.ckpt_every = 0;
+    pp.s_user = s_user;
+
+    AdjParams ap{};
+    ap.tiles = (const TileDesc *)eng.tiles.ptr;
+    ap.n_tiles = n_tiles;
+    ap.xcd_remap = eng.cfg.xcd_remap;
+    ap.log2s = log2s;
+    ap.s_user = s_user;
+    ap.col = eng.mat.col;
+    ap.val = eng.mat.val64;
+    ap.slice_off = eng.mat.slice_off;
+    ap.onsite = eng.mat.onsite64;
+    ap.inv_f = 1.0 / f;
+    ap.gacc = eng.bwd_gacc.ptr;
+    ap.gdiag = (double *)eng.bwd_gdiag.ptr;
+    ap.phi0 = phi0p;
+
+    const int32_t n_seg = (N - 1 + K - 1) / K;
+    for (int32_t seg = n_seg - 1; seg >= 0; --seg) {
+        const int32_t l0 = seg * K;
+        const int32_t len = std::min(l0 + K, N - 1) - l0;
+        if (seg == 0)
+            TRY_HIP(hipMemcpyAsync(psi_slot(0), phi0p, vb, hipMemcpyDeviceToDevice, st), "segment start");
+        else
+            TRY_HIP(launch_expand_states(ckpt + 2 * (size_t)(seg - 1) * n_rows * s_user, s_user, psi_slot(0), log2s,
+                                         n_rows, st),
+                    "segment start");
+        // forward replay, keeping b_1 .. b_{M-2} of every step
+        for (int32_t t = 0; t < len; ++t) {
+            for (int p = 0; p < n_passes; ++p) {
+                const int j = pass_j[p];
+                const PassPlan &pl = plan[p];
+                pp.v = psi_slot(t);
+                if (pl.kind == kPassFirst)
+                    pp.x = psi_slot(t);
+                else
+                    pp.x = b_slot(t, j + 1);
+                pp.b2 = (pl.kind == kPassMid || pl.kind == kPassLast) ? b_slot(t, j + 2) : nullptr;
+                pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
+                pp.coef = (const PassCoef *)eng.bwd_coef.ptr + p;
+                TRY_HIP(launch_pass(pl.kind, false, cplx, false, eng.cfg.unroll, pp, st), "replay pass");
+            }
+        }
+        // adjoint sweep through the segment
+        for (int32_t t = len - 1; t >= 0; --t) {
+            const int32_t l = l0 + t;
+            for (int j = 0; j <= M - 2; ++j) {
+                const int kind = (j == 0) ? kAdjFirst : (j == M - 2 ? kAdjFinal : kAdjMid);
+                ap.a_cur = rot[j % 3];
+                ap.a_prev = j > 0 ? rot[(j + 2) % 3] : nullptr;
+                ap.a_next = rot[(j + 1) % 3];
+                ap.lam_acc = acc;
+                if (j + 1 <= M - 2) {
+                    ap.bq = b_slot(t, j + 1);
+                    ap.bs_re = 1.0;
+                    ap.bs_im = 0.0;
+                } else {  // b_{M-1} = c_{M-1} psi_l
+                    ap.bq = psi_slot(t);
+                    ap.bs_re = c[M - 1].real();
+                    ap.bs_im = c[M - 1].imag();
+                }
+                ap.gw = (j == 0) ? 1.0 : 2.0;
+                ap.cc0_re = c[0].real();
+                ap.cc0_im = -c[0].imag();
+                ap.ccn_re = c[j + 1].real();
+                ap.ccn_im = -c[j + 1].imag();
+                ap.gcorr_l = gcorr + 2 * (size_t)l * s_user;
+                // the first pass (j = 0) writes alpha_1 = H~ lambda; the final pass
+                // (j = M-2) leaves the new lambda in 'acc'
+                TRY_HIP(launch_adjoint_pass(kind, cplx, ap, st), "adjoint pass");
+            }
+            // lambda_l is in acc; the old lambda buffer becomes the accumulator
+            std::swap(rot[0], acc);
+        }
+    }
+    TRY_HIP(launch_grad_scatter(eng.bwd_gacc.ptr, (const double *)eng.bwd_gdiag.ptr, eng.mat.ell_csr,
+                                eng.mat.ell_size, cplx, 1.0 / f, grad_val, grad_onsite, n_rows, st),
+            "gradient scatter");
+    TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
+    TRY_HIP(hipGetLastError(), "kernel execution");
+    return TBPM_OK;
 }
+
 }  // namespace tbpm

@@ -1,0 +1,108 @@
+// Device helpers shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tbpm_internal.h"
+
+namespace tbpm {
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+template <typename R>
+struct CxT;
+template <>
+struct CxT<double> {
+    using T = d2;
+};
+template <>
+struct CxT<float> {
+    using T = f2;
+};
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// acc += h * x for a real or complex matrix element h
+template <typename C, typename R>
+__device__ __forceinline__ C hmad(R h, C x, C acc) {
+    acc.x = fma(h, x.x, acc.x);
+    acc.y = fma(h, x.y, acc.y);
+    return acc;
+}
+template <typename C>
+__device__ __forceinline__ C hmad(C h, C x, C acc) {
+    acc.x = fma(h.x, x.x, acc.x);
+    acc.x = fma(-h.y, x.y, acc.x);
+    acc.y = fma(h.x, x.y, acc.y);
+    acc.y = fma(h.y, x.x, acc.y);
+    return acc;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ldv(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stv(T *p, T v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that XCD x
+// works through one contiguous range of tiles (the neighbour rows gathered
+// by a tile were then most likely brought into the same XCD's L2).
+__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap) {
+    if (!remap) return b;
+    const int q = n_tiles >> 3, r = n_tiles & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Sum (dre, dim, nrm) over the threads of the workgroup that hold the same
+// state (thread t holds state t & (S-1)) in a fixed order, and write the
+// workgroup's partial sums for each state.
+__device__ __forceinline__ void block_state_partials(double dre, double dim, double nrm, int log2s,
+                                                     double *__restrict__ out /* [S][3] */) {
+    __shared__ double red[kWG / 64][64][3];
+    const int S = 1 << log2s;
+    for (int off = 32; off >= S; off >>= 1) {
+        dre += __shfl_xor(dre, off);
+        dim += __shfl_xor(dim, off);
+        nrm += __shfl_xor(nrm, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < S) {
+        red[wave][lane][0] = dre;
+        red[wave][lane][1] = dim;
+        red[wave][lane][2] = nrm;
+    }
+    __syncthreads();
+    if (threadIdx.x < S) {
+        double a = 0, b = 0, c = 0;
+#pragma unroll
+        for (int w = 0; w < kWG / 64; ++w) {
+            a += red[w][threadIdx.x][0];
+            b += red[w][threadIdx.x][1];
+            c += red[w][threadIdx.x][2];
+        }
+        out[threadIdx.x * 3 + 0] = a;
+        out[threadIdx.x * 3 + 1] = b;
+        out[threadIdx.x * 3 + 2] = c;
+    }
+}
+
+}  // namespace
+}  // namespace tbpm

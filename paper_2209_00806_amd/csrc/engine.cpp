@@ -75,7 +75,7 @@ void PinnedBuf::release() {
 
 bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
-        chunks != o.chunks || remap != o.remap || nt != o.nt || ckpt_every != o.ckpt_every ||
+        chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || ckpt_every != o.ckpt_every ||
         ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
         return false;
     for (int i = 0; i < 8; ++i)
@@ -150,14 +150,16 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
     mat.ell_size = S;
     mat.is_complex = cplx;
     const size_t vb = (cplx ? 2 : 1) * (size_t)std::max<int64_t>(S, 1);
-    TRY_HIP(hipMalloc(&mat.slice_off, sizeof(int64_t) * e.slice_off.size()), "hipMalloc slice_off");
+    if (S >= (int64_t)UINT32_MAX) return fail(TBPM_E_ARG, "sliced-ELL size must be < 2^32 entries");
+    std::vector<uint32_t> soff32(e.slice_off.begin(), e.slice_off.end());
+    TRY_HIP(hipMalloc(&mat.slice_off, sizeof(uint32_t) * soff32.size()), "hipMalloc slice_off");
     TRY_HIP(hipMalloc(&mat.col, sizeof(int32_t) * std::max<int64_t>(S, 1)), "hipMalloc col");
     TRY_HIP(hipMalloc(&mat.val64, sizeof(double) * vb), "hipMalloc val64");
     TRY_HIP(hipMalloc(&mat.val32, sizeof(float) * vb), "hipMalloc val32");
     TRY_HIP(hipMalloc(&mat.onsite64, sizeof(double) * N), "hipMalloc onsite64");
     TRY_HIP(hipMalloc(&mat.onsite32, sizeof(float) * N), "hipMalloc onsite32");
     TRY_HIP(hipMalloc(&mat.ell_csr, sizeof(int64_t) * std::max<int64_t>(S, 1)), "hipMalloc ell_csr");
-    TRY_HIP(hipMemcpy(mat.slice_off, e.slice_off.data(), sizeof(int64_t) * e.slice_off.size(), hipMemcpyHostToDevice),
+    TRY_HIP(hipMemcpy(mat.slice_off, soff32.data(), sizeof(uint32_t) * soff32.size(), hipMemcpyHostToDevice),
             "upload slice_off");
     if (S > 0) {
         TRY_HIP(hipMemcpy(mat.col, e.col.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice), "upload col");
@@ -182,8 +184,9 @@ void Engine::release() {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     mat = DevMatrix{};
-    DevBuf *bufs[] = {&v, &ba, &bb, &phi0, &partials, &counter, &coef, &norm2_all, &tiles, &inst_tile0, &ptr_tab,
-                      &inst_row0_dev};
+    DevBuf *bufs[] = {&v,        &ba,        &bb,      &phi0,      &partials,  &counter,  &coef,
+                      &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
+                      &bwd_gacc, &bwd_gdiag, &bwd_coef};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -224,15 +227,7 @@ tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks) {
     return TBPM_OK;
 }
 
-namespace {
-
-struct PassPlan {
-    int kind;
-    int x, v, b2, out;  // buffer ids: 0 = v, 1 = A, 2 = B, -1 = none
-    std::vector<PassCoef> coef;  // per member
-};
-
-PassCoef make_coef(cd a, cd b) { return PassCoef{a.real(), a.imag(), b.real(), b.imag()}; }
+static PassCoef make_coef(cd a, cd b) { return PassCoef{a.real(), a.imag(), b.real(), b.imag()}; }
 
 // The Clenshaw schedule of one step for per-member coefficient sets c[i][m]
 // (zero-padded to mmax: extra zero coefficients leave the polynomial and every
@@ -269,7 +264,17 @@ std::vector<PassPlan> plan_step(const std::vector<std::vector<cd>> &c, const std
     return plan;
 }
 
-}  // namespace
+
+int32_t cheb_coeffs(double z, double tol, std::vector<cd> &c) {
+    const int32_t M = num_terms(z, tol);
+    if (M < 0) return M;
+    std::vector<double> J(M);
+    bessel_j(z, M, J.data());
+    c.resize(M);
+    static const cd mi[4] = {cd(1, 0), cd(0, -1), cd(-1, 0), cd(0, 1)};  // (-i)^m
+    for (int32_t m = 0; m < M; ++m) c[m] = (m == 0 ? 1.0 : 2.0) * J[m] * mi[m & 3];
+    return M;
+}
 
 tbpm_status Engine::run(const RunArgs &a) {
     int dev = 0;
@@ -290,15 +295,8 @@ tbpm_status Engine::run(const RunArgs &a) {
     int mmax = 0;
     for (int32_t i = 0; i < ni; ++i) {
         const double z = a.rescale[i] * a.dt[i];
-        const int32_t M = num_terms(z, a.tol);
+        const int32_t M = cheb_coeffs(z, a.tol, c[i]);
         if (M < 0) return fail(TBPM_E_ARG, "Bessel series does not converge for z = " + std::to_string(z));
-        std::vector<double> J(M);
-        bessel_j(z, M, J.data());
-        c[i].resize(M);
-        for (int32_t m = 0; m < M; ++m) {
-            static const cd mi[4] = {cd(1, 0), cd(0, -1), cd(-1, 0), cd(0, 1)};  // (-i)^m
-            c[i][m] = (m == 0 ? 1.0 : 2.0) * J[m] * mi[m & 3];
-        }
         f[i] = a.rescale[i];
         mmax = std::max(mmax, M);
     }
@@ -311,6 +309,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     if (st != TBPM_OK) return st;
     const int32_t n_tiles = (int32_t)h_tiles.size();
     const int64_t n_el = mat.n_rows * s_pad;
+    if (n_el >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb * n_states (padded to a power of two) must be < 2^31");
 
     TRY_HIP(v.ensure(esize * n_el), "alloc v");
     TRY_HIP(ba.ensure(esize * n_el), "alloc A");
@@ -406,7 +405,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             pp.ckpt_max = a.n_steps - 2;
             pp.s_user = a.s_user;
-            hipError_t e = launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, pp, s);
+            hipError_t e = launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, pp, s);
             if (e != hipSuccess) return hip_fail(e, "launch pass");
         }
         hipError_t e = launch_reduce(ni, s_pad, rp, s);
@@ -430,6 +429,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.chunks = chunks;
             key.remap = cfg.xcd_remap;
             key.nt = cfg.nontemporal;
+            key.unroll = cfg.unroll;
             key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             key.ckpt_max = a.n_steps - 2;
             key.n_steps = a.n_steps;
@@ -517,7 +517,7 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.counter = (int32_t *)counter.ptr;
     pp.s_user = s_user;
     for (int32_t i = 0; i < n_launch; ++i) {
-        hipError_t e = launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, pp, stream);
+        hipError_t e = launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, pp, stream);
         if (e != hipSuccess) return hip_fail(e, "launch pass");
     }
     return TBPM_OK;

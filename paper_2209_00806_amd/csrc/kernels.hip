@@ -19,94 +19,78 @@
 
 #include <type_traits>
 
+#include "device_util.h"
 #include "tbpm_internal.h"
 
 namespace tbpm {
 namespace {
 
-typedef double d2 __attribute__((ext_vector_type(2)));
-typedef float f2 __attribute__((ext_vector_type(2)));
+// ---------------------------------------------------------------------------
+// Chebyshev/Clenshaw pass
+//
+// A thread owns "units" of VS consecutive states of one row (VS = 2 packs two
+// complex64 states into one 16-byte access) and handles NE units at a time,
+// 256 units apart.  Every load that does not depend on a column index (own
+// x, on-site, psi, b2, the slice offsets) is issued first; the stored
+// elements of a row are then taken KG at a time, with all their column and
+// value loads in flight before the KG gathers of x.  Indices are 32-bit
+// (the host keeps rows*S < 2^31 and the ELL size < 2^32).
+// ---------------------------------------------------------------------------
+template <typename R, int VS>
+using VecT = R __attribute__((ext_vector_type(2 * VS)));
 
+template <typename R, bool CH>
+struct HValT {
+    using T = R;
+};
 template <typename R>
-struct CxT;
-template <>
-struct CxT<double> {
-    using T = d2;
-};
-template <>
-struct CxT<float> {
-    using T = f2;
+struct HValT<R, true> {
+    using T = typename CxT<R>::T;
 };
 
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-    C r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
+// acc_i += h * x_i for the VS complex components of a unit
+template <typename R, int VS>
+__device__ __forceinline__ void unit_mad_real(R h, VecT<R, VS> x, VecT<R, VS> &acc) {
+#pragma unroll
+    for (int i = 0; i < 2 * VS; ++i) acc[i] = fma(h, x[i], acc[i]);
 }
-
-// acc += h * x for a real or complex matrix element h
-template <typename C, typename R>
-__device__ __forceinline__ C hmad(R h, C x, C acc) {
-    acc.x = fma(h, x.x, acc.x);
-    acc.y = fma(h, x.y, acc.y);
-    return acc;
-}
-template <typename C>
-__device__ __forceinline__ C hmad(C h, C x, C acc) {
-    acc.x = fma(h.x, x.x, acc.x);
-    acc.x = fma(-h.y, x.y, acc.x);
-    acc.y = fma(h.x, x.y, acc.y);
-    acc.y = fma(h.y, x.x, acc.y);
-    return acc;
-}
-
-template <bool NT, typename T>
-__device__ __forceinline__ T ldv(const T *p) {
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-template <bool NT, typename T>
-__device__ __forceinline__ void stv(T *p, T v) {
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that XCD x
-// works through one contiguous range of tiles (the neighbour rows gathered
-// by a tile were then most likely brought into the same XCD's L2).
-__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap) {
-    if (!remap) return b;
-    const int q = n_tiles >> 3, r = n_tiles & 7;
-    const int x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
-// Sum (dre, dim, nrm) over the threads of the workgroup that hold the same
-// state (thread t holds state t & (S-1)) in a fixed order, and write the
-// workgroup's partial sums for each state.
-__device__ __forceinline__ void block_state_partials(double dre, double dim, double nrm, int log2s,
-                                                     double *__restrict__ out /* [S][3] */) {
-    __shared__ double red[kWG / 64][64][3];
-    const int S = 1 << log2s;
-    for (int off = 32; off >= S; off >>= 1) {
-        dre += __shfl_xor(dre, off);
-        dim += __shfl_xor(dim, off);
-        nrm += __shfl_xor(nrm, off);
+template <typename R, int VS, typename C>
+__device__ __forceinline__ void unit_mad_cplx(C h, VecT<R, VS> x, VecT<R, VS> &acc) {
+#pragma unroll
+    for (int i = 0; i < VS; ++i) {
+        acc[2 * i] = fma(h.x, x[2 * i], acc[2 * i]);
+        acc[2 * i] = fma(-h.y, x[2 * i + 1], acc[2 * i]);
+        acc[2 * i + 1] = fma(h.x, x[2 * i + 1], acc[2 * i + 1]);
+        acc[2 * i + 1] = fma(h.y, x[2 * i], acc[2 * i + 1]);
     }
+}
+
+// Per-state partial sums for units of VS states: lane l holds states
+// (l & (U-1))*VS + i, U = units per row.
+template <int VS>
+__device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
+                                                    const double (&nrm)[VS], int log2u,
+                                                    double *__restrict__ out /* [S][3] */) {
+    __shared__ double red[kWG / 64][64][3];
+    const int U = 1 << log2u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane < S) {
-        red[wave][lane][0] = dre;
-        red[wave][lane][1] = dim;
-        red[wave][lane][2] = nrm;
+#pragma unroll
+    for (int i = 0; i < VS; ++i) {
+        double a = dre[i], b = dim[i], c = nrm[i];
+        for (int off = 32; off >= U; off >>= 1) {
+            a += __shfl_xor(a, off);
+            b += __shfl_xor(b, off);
+            c += __shfl_xor(c, off);
+        }
+        if (lane < U) {
+            red[wave][lane * VS + i][0] = a;
+            red[wave][lane * VS + i][1] = b;
+            red[wave][lane * VS + i][2] = c;
+        }
     }
     __syncthreads();
-    if (threadIdx.x < S) {
+    const int S = U * VS;
+    if ((int)threadIdx.x < S) {
         double a = 0, b = 0, c = 0;
 #pragma unroll
         for (int w = 0; w < kWG / 64; ++w) {
@@ -120,95 +104,147 @@ __device__ __forceinline__ void block_state_partials(double dre, double dim, dou
     }
 }
 
-// ---------------------------------------------------------------------------
-// Chebyshev/Clenshaw pass
-// ---------------------------------------------------------------------------
-template <typename R, bool CH, int KIND, bool NT>
+template <typename R, bool CH, int KIND, bool NT, int VS, int NE>
 __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
-    using C = typename CxT<R>::T;
-    using HV = std::conditional_t<CH, C, R>;
+    using V = VecT<R, VS>;
+    using HV = typename HValT<R, CH>::T;
+    constexpr int KG = 4;
     constexpr bool X_IS_V = (KIND == kPassFirst);
     constexpr bool HAS_B2 = (KIND == kPassMid || KIND == kPassLast);
     constexpr bool CORR = (KIND == kPassLast || KIND == kPassLastNoB2);
+    constexpr int LOG2VS = VS == 2 ? 1 : 0;
 
     const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
     const TileDesc td = p.tiles[tile];
     const PassCoef pc = p.coef[td.inst];
-    C alpha, beta;
-    alpha.x = (R)pc.ar;
-    alpha.y = (R)pc.ai;
-    beta.x = (R)pc.br;
-    beta.y = (R)pc.bi;
+    const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
     const int log2s = p.log2s;
-    const int64_t smask = (1 << log2s) - 1;
-    const int64_t n_el = (int64_t)td.rows << log2s;
-    const int64_t e0 = td.row0 << log2s;
+    const int log2u = log2s - LOG2VS;
+    const uint32_t umask = (1u << log2u) - 1u;
+    const uint32_t n_u = (uint32_t)td.rows << log2u;
+    const uint32_t row0 = (uint32_t)td.row0;
+    const uint32_t u0 = row0 << log2u;
 
     if (p.bump_counter && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(p.counter, 1);
 
-    const C *__restrict__ x = (const C *)p.x;
-    const C *v = (const C *)p.v;
-    const C *b2 = (const C *)p.b2;
-    C *out = (C *)p.out;
+    const V *__restrict__ x = (const V *)p.x;
+    const V *v = (const V *)p.v;
+    const V *b2 = (const V *)p.b2;
+    V *out = (V *)p.out;
     const R *__restrict__ ons = (const R *)p.onsite;
     const HV *__restrict__ val = (const HV *)p.val;
     const int32_t *__restrict__ col = p.col;
-    const int64_t *__restrict__ soff = p.slice_off;
+    const uint32_t *__restrict__ soff = p.slice_off;
+    const uint32_t usub = threadIdx.x & umask;  // this thread's unit inside a row
 
-    double dre = 0.0, dim = 0.0, nrm = 0.0;
+    double dre[VS], dim[VS], nrm[VS];
+#pragma unroll
+    for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
     bool do_ckpt = false;
-    int64_t ckpt_base = 0;
+    uint32_t ckpt_base = 0;
     if constexpr (CORR) {
         if (p.ckpt_every > 0) {
             const int step = *(volatile const int32_t *)p.counter;
             do_ckpt = (step % p.ckpt_every == 0) && step <= p.ckpt_max && step > 0;
-            ckpt_base = (int64_t)(step / p.ckpt_every - 1);
+            ckpt_base = (uint32_t)(step / p.ckpt_every - 1);
         }
     }
 
-    for (int64_t e = threadIdx.x; e < n_el; e += kWG) {
-        const int64_t row = td.row0 + (e >> log2s);
-        const int s = (int)(e & smask);
-        const int64_t g = e0 + e;
-        const int64_t sl = row / kSliceRows;
-        const int64_t off = soff[sl];
-        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const int64_t base = off + (row % kSliceRows);
-        const C xo = x[g];
-        C acc;
-        acc.x = ons[row] * xo.x;
-        acc.y = ons[row] * xo.y;
-        for (int k = 0; k < w; ++k) {
-            const int c = col[base + (int64_t)k * kSliceRows];
-            const HV h = val[base + (int64_t)k * kSliceRows];
-            const C xc = x[((int64_t)c << log2s) + s];
-            acc = hmad(h, xc, acc);
+    for (uint32_t ub = threadIdx.x; ub < n_u; ub += kWG * NE) {
+        uint32_t row[NE], gu[NE], base[NE];
+        int w[NE];
+        bool ok[NE];
+        V xo[NE], vv[NE], bq[NE];
+        R on[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            uint32_t u = ub + q * kWG;
+            ok[q] = u < n_u;
+            if (!ok[q]) u = ub;  // a valid unit; its result is not stored
+            row[q] = row0 + (u >> log2u);
+            gu[q] = u0 + u;
+            const uint32_t sl = row[q] / kSliceRows;
+            const uint32_t off = soff[sl];
+            w[q] = (int)((soff[sl + 1] - off) / kSliceRows);
+            base[q] = off + row[q] % kSliceRows;
+            xo[q] = x[gu[q]];
+            on[q] = ons[row[q]];
+            if constexpr (!X_IS_V) vv[q] = ldv<NT>(v + gu[q]);
+            if constexpr (HAS_B2) bq[q] = ldv<NT>(b2 + gu[q]);
         }
-        C vv;
-        if constexpr (X_IS_V)
-            vv = xo;
-        else
-            vv = ldv<NT>(v + g);
-        C o = cmul(alpha, vv) + cmul(beta, acc);
-        if constexpr (HAS_B2) o -= ldv<NT>(b2 + g);
-        if constexpr (CORR) {
-            stv<false>(out + g, o);
-            const d2 ph = ((const d2 *)p.phi0)[row * p.phi0_ld + s];
-            const double oxr = (double)o.x, oyi = (double)o.y;
-            dre = fma(ph.x, oxr, fma(ph.y, oyi, dre));
-            dim = fma(ph.x, oyi, fma(-ph.y, oxr, dim));
-            nrm = fma(oxr, oxr, fma(oyi, oyi, nrm));
-            if (do_ckpt && s < p.s_user) {
-                d2 oc;
-                oc.x = oxr;
-                oc.y = oyi;
-                ((d2 *)p.ckpt)[ckpt_base * p.ckpt_stride + row * p.s_user + s] = oc;
+        V acc[NE];
+        int wmax = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            acc[q] = on[q] * xo[q];
+            wmax = max(wmax, w[q]);
+        }
+        for (int k = 0; k < wmax; k += KG) {
+            uint32_t cu[NE][KG];
+            HV h[NE][KG];
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+#pragma unroll
+                for (int i = 0; i < KG; ++i) {
+                    const bool valid = k + i < w[q];
+                    const uint32_t slot = valid ? base[q] + (uint32_t)(k + i) * kSliceRows : 0u;
+                    const int32_t c = col[slot];
+                    const HV hv = val[slot];
+                    cu[q][i] = ((valid ? (uint32_t)c : row[q]) << log2u) + usub;
+                    h[q][i] = valid ? hv : HV{};
+                }
             }
-        } else {
-            stv<NT>(out + g, o);
+            V xc[NE][KG];
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+#pragma unroll
+                for (int i = 0; i < KG; ++i) xc[q][i] = x[cu[q][i]];
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+#pragma unroll
+                for (int i = 0; i < KG; ++i) {
+                    if constexpr (CH)
+                        unit_mad_cplx<R, VS>(h[q][i], xc[q][i], acc[q]);
+                    else
+                        unit_mad_real<R, VS>(h[q][i], xc[q][i], acc[q]);
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const V src = X_IS_V ? xo[q] : vv[q];
+            V o;
+#pragma unroll
+            for (int i = 0; i < VS; ++i) {
+                const R vr = src[2 * i], vi = src[2 * i + 1];
+                const R hr = acc[q][2 * i], hi = acc[q][2 * i + 1];
+                o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
+                o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
+            }
+            if constexpr (HAS_B2) o -= bq[q];
+            if (!ok[q]) continue;
+            if constexpr (CORR) {
+                stv<false>(out + gu[q], o);
+                const uint32_t s0 = usub << LOG2VS;
+#pragma unroll
+                for (int i = 0; i < VS; ++i) {
+                    const d2 ph = ((const d2 *)p.phi0)[(int64_t)row[q] * p.phi0_ld + s0 + i];
+                    const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
+                    dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
+                    dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
+                    nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
+                    if (do_ckpt && (int)(s0 + i) < p.s_user) {
+                        d2 oc;
+                        oc.x = oxr;
+                        oc.y = oyi;
+                        ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + (int64_t)row[q] * p.s_user + s0 + i] = oc;
+                    }
+                }
+            } else {
+                stv<NT>(out + gu[q], o);
+            }
         }
     }
-    if constexpr (CORR) block_state_partials(dre, dim, nrm, log2s, p.partials + (int64_t)tile * (3 << log2s));
+    if constexpr (CORR) block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials + (int64_t)tile * (3 << log2s));
 }
 
 // ---------------------------------------------------------------------------
@@ -430,24 +466,24 @@ __global__ __launch_bounds__(kWG) void k_copy(const d2 *__restrict__ src, d2 *__
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-template <typename R, bool CH, bool NT>
+template <typename R, bool CH, bool NT, int VS, int NE>
 hipError_t launch_pass_t(int kind, const PassParams &p, hipStream_t st) {
     const dim3 grid(p.n_tiles), block(kWG);
     switch (kind) {
         case kPassFirst:
-            hipLaunchKernelGGL((k_pass<R, CH, kPassFirst, NT>), grid, block, 0, st, p);
+            hipLaunchKernelGGL((k_pass<R, CH, kPassFirst, NT, VS, NE>), grid, block, 0, st, p);
             break;
         case kPassNoB2:
-            hipLaunchKernelGGL((k_pass<R, CH, kPassNoB2, NT>), grid, block, 0, st, p);
+            hipLaunchKernelGGL((k_pass<R, CH, kPassNoB2, NT, VS, NE>), grid, block, 0, st, p);
             break;
         case kPassMid:
-            hipLaunchKernelGGL((k_pass<R, CH, kPassMid, NT>), grid, block, 0, st, p);
+            hipLaunchKernelGGL((k_pass<R, CH, kPassMid, NT, VS, NE>), grid, block, 0, st, p);
             break;
         case kPassLast:
-            hipLaunchKernelGGL((k_pass<R, CH, kPassLast, NT>), grid, block, 0, st, p);
+            hipLaunchKernelGGL((k_pass<R, CH, kPassLast, NT, VS, NE>), grid, block, 0, st, p);
             break;
         case kPassLastNoB2:
-            hipLaunchKernelGGL((k_pass<R, CH, kPassLastNoB2, NT>), grid, block, 0, st, p);
+            hipLaunchKernelGGL((k_pass<R, CH, kPassLastNoB2, NT, VS, NE>), grid, block, 0, st, p);
             break;
         default:
             return hipErrorInvalidValue;
@@ -455,17 +491,37 @@ hipError_t launch_pass_t(int kind, const PassParams &p, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename R, bool CH, bool NT, int VS>
+hipError_t launch_pass_ne(int kind, int ne, const PassParams &p, hipStream_t st) {
+    switch (ne) {
+        case 1:
+            return launch_pass_t<R, CH, NT, VS, 1>(kind, p, st);
+        case 2:
+            return launch_pass_t<R, CH, NT, VS, 2>(kind, p, st);
+        case 4:
+            return launch_pass_t<R, CH, NT, VS, 4>(kind, p, st);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int VS>
+hipError_t launch_pass_r(int kind, bool cplx, bool nt, int ne, const PassParams &p, hipStream_t st) {
+    if (cplx)
+        return nt ? launch_pass_ne<R, true, true, VS>(kind, ne, p, st) : launch_pass_ne<R, true, false, VS>(kind, ne, p, st);
+    return nt ? launch_pass_ne<R, false, true, VS>(kind, ne, p, st) : launch_pass_ne<R, false, false, VS>(kind, ne, p, st);
+}
+
 }  // namespace
 
-hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, const PassParams &p,
+hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, const PassParams &p,
                        hipStream_t st) {
     if (p.n_tiles <= 0) return hipSuccess;
     if (fp32) {
-        if (cplx) return nontemporal ? launch_pass_t<float, true, true>(kind, p, st) : launch_pass_t<float, true, false>(kind, p, st);
-        return nontemporal ? launch_pass_t<float, false, true>(kind, p, st) : launch_pass_t<float, false, false>(kind, p, st);
+        if (p.log2s >= 1) return launch_pass_r<float, 2>(kind, cplx, nontemporal, ne, p, st);
+        return launch_pass_r<float, 1>(kind, cplx, nontemporal, ne, p, st);
     }
-    if (cplx) return nontemporal ? launch_pass_t<double, true, true>(kind, p, st) : launch_pass_t<double, true, false>(kind, p, st);
-    return nontemporal ? launch_pass_t<double, false, true>(kind, p, st) : launch_pass_t<double, false, false>(kind, p, st);
+    return launch_pass_r<double, 1>(kind, cplx, nontemporal, ne, p, st);
 }
 
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st) {

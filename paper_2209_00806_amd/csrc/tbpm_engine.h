@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -33,6 +34,21 @@ tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col,
                           const double *onsite, HostCsr &out);
 tbpm_status check_values(HostCsr &h, double &hmax);
 
+// One pass of the Clenshaw schedule of a time step: kernel kind, buffer ids
+// (0 = psi, 1 = A, 2 = B, -1 = none) and per-member (alpha, beta).
+struct PassPlan {
+    int kind;
+    int x, v, b2, out;
+    std::vector<PassCoef> coef;
+};
+
+// c_0 = J_0(z), c_m = 2 (-i)^m J_m(z) for m < M; returns M (or < 0)
+int32_t cheb_coeffs(double z, double tol, std::vector<std::complex<double>> &c);
+// schedule of one step (passes FIRST, NOB2, MID j = M-4..1, LAST; or FIRST,
+// LAST_NOB2 when M = 3) for zero-padded coefficient sets c[i] and scales f[i]
+std::vector<PassPlan> plan_step(const std::vector<std::vector<std::complex<double>>> &c,
+                                const std::vector<double> &f, int mmax);
+
 // Device buffer that only grows.
 struct DevBuf {
     void *ptr = nullptr;
@@ -52,7 +68,7 @@ struct PinnedBuf {
 // if the key is equal.
 struct GraphKey {
     int32_t s_pad = 0, s_user = 0, fp32 = 0, mmax = 0, n_inst = 0;
-    int32_t chunks = 0, remap = 0, nt = 0;
+    int32_t chunks = 0, remap = 0, nt = 0, unroll = 0;
     int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
     const void *ckpt = nullptr;
     const void *bufs[8] = {};
@@ -62,11 +78,13 @@ struct GraphKey {
 struct Engine {
     DevMatrix mat;
     std::vector<int64_t> inst_row0;  // [n_inst + 1]
-    tbpm_launch_config cfg{8, 1, 0};
+    tbpm_launch_config cfg{2, 1, 1, 1};
     int device = -1;
 
     // work buffers
     DevBuf v, ba, bb, phi0, partials, counter, coef, norm2_all, tiles, inst_tile0, ptr_tab, inst_row0_dev;
+    // adjoint: segment store, four adjoint vectors, gradient accumulators
+    DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
     hipEvent_t staging_done = nullptr;
     hipStream_t capture_stream = nullptr;

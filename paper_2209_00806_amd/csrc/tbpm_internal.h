@@ -41,7 +41,7 @@ struct DevMatrix {
     int64_t n_slices = 0;
     int64_t ell_size = 0;    // slots incl. padding
     bool is_complex = false;
-    int64_t *slice_off = nullptr;  // [n_slices + 1]
+    uint32_t *slice_off = nullptr; // [n_slices + 1]
     int32_t *col = nullptr;        // [ell_size]
     void *val64 = nullptr;         // double or double2 [ell_size]
     void *val32 = nullptr;         // float or float2 [ell_size]
@@ -76,7 +76,7 @@ struct PassParams {
     int32_t bump_counter;
     const int32_t *col;
     const void *val;
-    const int64_t *slice_off;
+    const uint32_t *slice_off;
     const void *onsite;
     const void *x;   // gathered vector (b_{j+1}, or v for the first pass)
     const void *v;   // psi_k
@@ -122,7 +122,7 @@ struct ReduceParams {
 };
 
 // launchers (kernels.hip)
-hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, const PassParams &p,
+hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, const PassParams &p,
                        hipStream_t st);
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st);
 hipError_t launch_reduce(int n_inst, int s_pad, const ReduceParams &p, hipStream_t st);
@@ -134,9 +134,54 @@ hipError_t launch_convert_values(const DevMatrix &m, const double *csr_val, cons
                                  int64_t n_rows, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Adjoint (backward) pass: alpha_{j+1} = 2 H~ alpha_j - alpha_{j-1}
+// (alpha_1 = H~ alpha_0), lam_acc += conj(c_{j+1}) alpha_{j+1}, and the
+// gradient G_pq += gw * alpha_j[p] * conj(bscale * b_{j+1}[q]) on every stored
+// entry and the diagonal, summed over the states.
+// ---------------------------------------------------------------------------
+enum AdjKind : int {
+    kAdjFirst = 0,  // j = 0: no alpha_{j-1}; lam_acc = conj(c_0) alpha_0 + conj(c_1) alpha_1
+    kAdjMid = 1,    // 0 < j < M-2
+    kAdjFinal = 2   // j = M-2: lam_new = lam_acc + conj(c_{M-1}) alpha_{M-1} + g_l phi0
+};
+
+struct AdjParams {
+    const TileDesc *tiles;
+    int32_t n_tiles;
+    int32_t xcd_remap;
+    int32_t log2s;
+    int32_t s_user;
+    const int32_t *col;
+    const void *val;        // double or double2 (FP64)
+    const uint32_t *slice_off;
+    const double *onsite;
+    double inv_f;           // 1/f
+    const double *a_cur;    // alpha_j (gathered), complex [rows][S]
+    const double *a_prev;   // alpha_{j-1} (streamed)
+    double *a_next;         // alpha_{j+1} (written; unused by the final pass)
+    double *lam_acc;        // complex [rows][S], read-modify-write
+    const double *bq;       // b_{j+1} (gathered), complex [rows][S]
+    double bs_re, bs_im;    // b_{j+1} = bscale * bq
+    double gw;              // gradient weight (1 for j = 0, else 2)
+    double cc0_re, cc0_im;  // conj(c_0)   (first pass)
+    double ccn_re, ccn_im;  // conj(c_{j+1})
+    void *gacc;             // per ELL slot: double (real H) or double2
+    double *gdiag;          // [rows] real part of the diagonal gradient
+    const double *phi0;     // complex [rows][S] (final pass)
+    const double *gcorr_l;  // complex [s_user]: dL/dC at this step (final pass)
+};
+
 // backward launchers (backward.hip)
-struct AdjParams;
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
+hipError_t launch_expand_states(const double *src, int32_t s_user, double *dst, int32_t log2s, int64_t n_rows,
+                                hipStream_t st);
+hipError_t launch_lam_init(double *lam, const double *phi0, const double *gcorr_last, int32_t s_user,
+                           int32_t log2s, int64_t n_rows, hipStream_t st);
+hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t st);
+hipError_t launch_grad_scatter(const void *gacc, const double *gdiag, const int64_t *ell_csr, int64_t ell_size,
+                               bool cplx, double inv_f, double *grad_val, double *grad_onsite, int64_t n_rows,
+                               hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Host helpers (host.cpp)

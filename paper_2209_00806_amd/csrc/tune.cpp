@@ -1,5 +1,6 @@
 // Autotuner of the Chebyshev pass launch shape: times every candidate
-// (workgroup chunks x XCD remap x non-temporal streaming) on a few time steps
+// (workgroup chunks x XCD remap x non-temporal streaming x elements per
+// thread) on a few time steps
 // of scratch states and keeps the fastest in the handle.
 #include <hip/hip_runtime.h>
 
@@ -43,10 +44,13 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
     const int chunk_list[] = {1, 2, 4, 8, 16, 32};
+    const int unroll_list[] = {1, 2, 4};
     for (int ch : chunk_list) {
-        for (int remap = 0; remap <= 1 && st == TBPM_OK; ++remap) {
-            for (int nt = 0; nt <= 1 && st == TBPM_OK; ++nt) {
-                eng.cfg = tbpm_launch_config{ch, remap, nt};
+        for (int cand = 0; cand < 12 && st == TBPM_OK; ++cand) {
+            const int remap = cand & 1, nt = (cand >> 1) & 1, un = unroll_list[cand >> 2];
+            if (un > ch) continue;  // a tile of ch chunks keeps at most ch elements per thread busy
+            {
+                eng.cfg = tbpm_launch_config{ch, remap, nt, un};
                 Engine::RunArgs a{};
                 a.psi0 = p0.data();
                 a.s_user = n_states;

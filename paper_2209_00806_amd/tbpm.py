@@ -37,10 +37,12 @@ class TBPMError(RuntimeError):
 
 
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("wg_chunks", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+    _fields_ = [("wg_chunks", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("unroll", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"wg_chunks": self.wg_chunks, "xcd_remap": self.xcd_remap, "nontemporal": self.nontemporal}
+        return {"wg_chunks": self.wg_chunks, "xcd_remap": self.xcd_remap, "nontemporal": self.nontemporal,
+                "unroll": self.unroll}
 
 
 _lib = None
@@ -198,8 +200,8 @@ class Hamiltonian:
         _check(lib().tbpm_get_launch_config(self.handle, ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=8, xcd_remap=1, nontemporal=0):
-        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal)
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1):
+        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
         _check(lib().tbpm_set_launch_config(self.handle, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
@@ -343,8 +345,8 @@ class Batch:
         _check(lib().tbpm_batch_get_launch_config(self._b, ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=8, xcd_remap=1, nontemporal=0):
-        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal)
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1):
+        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
         _check(lib().tbpm_batch_set_launch_config(self._b, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):

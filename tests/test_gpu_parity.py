@@ -174,7 +174,9 @@ def test_batched_vs_single_and_oracle(precision):
     for l, h, p, f, dt, c in zip(lats, hams, psis, fs, dts, corrs):
         single = tbpm.propagate(h, _dev(p), nt, dt, f, precision=precision).cpu().numpy()
         c = c.cpu().numpy()
-        assert _rel(c, single) < 1e-12
+        # zero-padded coefficients of members with fewer terms change the
+        # rounding order only: ~1e-16 in FP64, ~1e-7 in FP32
+        assert _rel(c, single) < (1e-12 if precision == "fp64" else 1e-5)
         ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, nt, dt, f)
         if precision == "fp64":
             assert _rel(c, ref) < 1e-10
