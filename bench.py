@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-KERNEL_SOURCES = ["paper_2209_00806_amd/csrc/kernels.hip"]
+KERNEL_SOURCES = ["paper_2209_00806_amd/csrc/kernels.hip", "paper_2209_00806_amd/csrc/device_util.h",
+                  "paper_2209_00806_amd/csrc/tbpm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pass_mid_graphene1024_s8_fp64.json")
 
 
@@ -182,7 +183,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="JSON file that stores/reuses autotuned launch shapes")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-bandwidth calibration")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--batch-members", type=int, default=64)
@@ -215,10 +218,32 @@ def main():
     del psi0_np
     M = tbpm.num_terms(f * dt, 1e-12)
     n_pass = M - 1
-    if args.autotune:
-        cfg, ms = H.autotune(S, "fp64")
-        log(f"autotuned launch config {cfg} ({ms:.3f} ms/step)")
     stream = torch.cuda.current_stream()
+
+    # copy calibration: a plain streaming copy of known size (1 GiB read + 1 GiB written)
+    n_copy = args.copy_mib * 1024 * 1024 // 8
+    csrc = torch.ones(n_copy, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    tbpm.stream_copy(csrc, cdst)
+    ca = torch.cuda.Event(enable_timing=True)
+    cb = torch.cuda.Event(enable_timing=True)
+    ca.record(stream)
+    for _ in range(10):
+        tbpm.stream_copy(csrc, cdst)
+    cb.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = ca.elapsed_time(cb) / 10
+    copy_gbs = 2 * n_copy * 8 / (copy_ms / 1e3) / 1e9
+    del csrc, cdst
+    torch.cuda.empty_cache()
+    log(f"copy calibration: {copy_gbs:.0f} GB/s (read + write of {args.copy_mib} MiB)")
+
+    tuned = {}
+    if not args.no_autotune:
+        for prec in ("fp64", "fp32"):
+            cfg, ms, hit = tbpm.autotune_cached(H, S, prec, args.tune_cache)
+            tuned[prec] = {"config": cfg, "ms_per_step": round(ms, 4), "cached": hit}
+            log(f"autotuned {prec}: {cfg} ({ms:.3f} ms per time step{', cached' if hit else ''})")
 
     def one_step(precision="fp64"):
         corr = tbpm.propagate(H, psi0, nt, dt, f, precision=precision)
@@ -267,7 +292,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_pass<double,real,MID> (interior Clenshaw pass)",
-                "kernel_avg_ms": round(pass_ms, 5), "algorithmic_bytes_per_launch": alg}
+                "kernel_avg_ms": round(pass_ms, 5), "algorithmic_bytes_per_launch": alg,
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     log(f"interior pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of peak)")
 
     extra = {}
@@ -311,7 +337,7 @@ def main():
                                                  / (ms32 / 1e3) / 1e9, 1)}
         extra["fp32_mixed"]["speedup_vs_fp64_single_state"] = round(updates / (ms32 / 1e3) / rate_s1, 3)
         log(f"fp32-mixed: {ms32:.1f} ms/step, speedup {ms_per_step / ms32:.2f}x, DOS L1 err {l1:.2e}")
-    launch_cfg = H.launch_config()
+    launch_cfg = {"fp64": H.launch_config("fp64"), "fp32": H.launch_config("fp32"), "autotuned": bool(tuned)}
     H.close()
     del H
     torch.cuda.empty_cache()

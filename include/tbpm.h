@@ -264,17 +264,19 @@ typedef struct {
     int32_t unroll;
 } tbpm_launch_config;
 
-tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_launch_config *cfg);
-tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, const tbpm_launch_config *cfg);
-tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, const tbpm_launch_config *cfg);
-tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_launch_config *cfg);
+/* Each handle keeps one launch configuration per precision. */
+tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_precision prec, tbpm_launch_config *cfg);
+tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, tbpm_precision prec, const tbpm_launch_config *cfg);
+tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, tbpm_precision prec, const tbpm_launch_config *cfg);
+tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_precision prec, tbpm_launch_config *cfg);
 
 /*
  * Autotune the launch configuration of H (or of a batch) for n_states and
  * prec by timing every candidate on a few Chebyshev steps of scratch states
  * on 'stream' (synchronises).  The best configuration is stored in the
- * handle and returned in *best (may be NULL); its mean step time in ms in
- * *best_ms (may be NULL).
+ * handle for that precision and returned in *best (may be NULL); its mean
+ * step time in ms in *best_ms (may be NULL).  Candidates with more elements
+ * per thread than chunks per workgroup are skipped (they idle threads).
  */
 tbpm_status tbpm_autotune(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec,
                           tbpm_launch_config *best, double *best_ms, void *stream);

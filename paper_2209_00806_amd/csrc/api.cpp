@@ -314,29 +314,31 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
     }
 }
 
-tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_launch_config *cfg) {
-    if (!H || !cfg) return fail(TBPM_E_ARG, "NULL argument");
-    *cfg = H->eng.cfg;
+static bool valid_prec(tbpm_precision p) { return p == TBPM_FP64 || p == TBPM_FP32_MIXED; }
+
+tbpm_status tbpm_get_launch_config(const tbpm_hamiltonian *H, tbpm_precision prec, tbpm_launch_config *cfg) {
+    if (!H || !cfg || !valid_prec(prec)) return fail(TBPM_E_ARG, "bad argument");
+    *cfg = H->eng.cfgs[prec];
     return TBPM_OK;
 }
 
-tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, const tbpm_launch_config *cfg) {
-    if (!H || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+tbpm_status tbpm_set_launch_config(tbpm_hamiltonian *H, tbpm_precision prec, const tbpm_launch_config *cfg) {
+    if (!H || !cfg || !valid_prec(prec)) return fail(TBPM_E_ARG, "bad argument");
     if (!valid_cfg(*cfg)) return fail(TBPM_E_ARG, "invalid launch configuration");
-    H->eng.cfg = *cfg;
+    H->eng.cfgs[prec] = *cfg;
     return TBPM_OK;
 }
 
-tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_launch_config *cfg) {
-    if (!B || !cfg) return fail(TBPM_E_ARG, "NULL argument");
-    *cfg = B->eng.cfg;
+tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_precision prec, tbpm_launch_config *cfg) {
+    if (!B || !cfg || !valid_prec(prec)) return fail(TBPM_E_ARG, "bad argument");
+    *cfg = B->eng.cfgs[prec];
     return TBPM_OK;
 }
 
-tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, const tbpm_launch_config *cfg) {
-    if (!B || !cfg) return fail(TBPM_E_ARG, "NULL argument");
+tbpm_status tbpm_batch_set_launch_config(tbpm_batch *B, tbpm_precision prec, const tbpm_launch_config *cfg) {
+    if (!B || !cfg || !valid_prec(prec)) return fail(TBPM_E_ARG, "bad argument");
     if (!valid_cfg(*cfg)) return fail(TBPM_E_ARG, "invalid launch configuration");
-    B->eng.cfg = *cfg;
+    B->eng.cfgs[prec] = *cfg;
     return TBPM_OK;
 }
 

@@ -46,6 +46,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     const std::vector<PassPlan> plan = plan_step({c}, {f}, M);
     const int n_passes = (int)plan.size();
 
+    eng.cfg = eng.cfgs[0];
     tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks);
     if (s != TBPM_OK) return s;
     const int32_t n_tiles = (int32_t)eng.h_tiles.size();

@@ -288,6 +288,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     }
     const bool fp32 = a.fp32;
     const size_t esize = fp32 ? 8 : 16;
+    cfg = cfgs[fp32 ? 1 : 0];
 
     // coefficients per member
     std::vector<std::vector<cd>> c(ni);
@@ -499,6 +500,7 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     }
     if (last_s_pad != s_pad || last_fp32 != (fp32 ? 1 : 0) || !v.ptr || tiles_s != s_pad)
         return fail(TBPM_E_ARG, "tbpm_bench_pass needs a prior tbpm_propagate with the same n_states and precision");
+    cfg = cfgs[fp32 ? 1 : 0];
     PassParams pp{};
     pp.tiles = (const TileDesc *)tiles.ptr;
     pp.n_tiles = (int32_t)h_tiles.size();

@@ -78,7 +78,8 @@ struct GraphKey {
 struct Engine {
     DevMatrix mat;
     std::vector<int64_t> inst_row0;  // [n_inst + 1]
-    tbpm_launch_config cfg{2, 1, 1, 1};
+    tbpm_launch_config cfgs[2] = {{2, 1, 1, 1}, {4, 0, 1, 2}};  // FP64, FP32-mixed
+    tbpm_launch_config cfg{2, 1, 1, 1};                          // the one in use
     int device = -1;
 
     // work buffers

@@ -40,7 +40,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     if (e == hipSuccess) e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     tbpm_status st = TBPM_OK;
-    tbpm_launch_config keep = eng.cfg, win = eng.cfg;
+    tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
     const int chunk_list[] = {1, 2, 4, 8, 16, 32};
@@ -50,7 +50,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
             const int remap = cand & 1, nt = (cand >> 1) & 1, un = unroll_list[cand >> 2];
             if (un > ch) continue;  // a tile of ch chunks keeps at most ch elements per thread busy
             {
-                eng.cfg = tbpm_launch_config{ch, remap, nt, un};
+                eng.cfgs[fp32 ? 1 : 0] = tbpm_launch_config{ch, remap, nt, un};
                 Engine::RunArgs a{};
                 a.psi0 = p0.data();
                 a.s_user = n_states;
@@ -76,7 +76,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
                 const double per_step = ms / (n_steps - 1);
                 if (per_step < win_ms) {
                     win_ms = per_step;
-                    win = eng.cfg;
+                    win = eng.cfgs[fp32 ? 1 : 0];
                 }
             }
         }
@@ -88,10 +88,10 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     psi.release();
     corr.release();
     if (st != TBPM_OK) {
-        eng.cfg = keep;
+        eng.cfgs[fp32 ? 1 : 0] = keep;
         return st;
     }
-    eng.cfg = win;
+    eng.cfgs[fp32 ? 1 : 0] = win;
     if (best) *best = win;
     if (best_ms) *best_ms = win_ms;
     return TBPM_OK;

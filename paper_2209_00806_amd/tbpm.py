@@ -74,10 +74,10 @@ def lib() -> ctypes.CDLL:
         "tbpm_batch_create": [P, I32, PP],
         "tbpm_batch_destroy": [P],
         "tbpm_propagate_batched": [P, P, I32, I32, P, P, D, ctypes.c_int, P, P, U32, P],
-        "tbpm_get_launch_config": [P, P],
-        "tbpm_set_launch_config": [P, P],
-        "tbpm_batch_get_launch_config": [P, P],
-        "tbpm_batch_set_launch_config": [P, P],
+        "tbpm_get_launch_config": [P, ctypes.c_int, P],
+        "tbpm_set_launch_config": [P, ctypes.c_int, P],
+        "tbpm_batch_get_launch_config": [P, ctypes.c_int, P],
+        "tbpm_batch_set_launch_config": [P, ctypes.c_int, P],
         "tbpm_autotune": [P, I32, ctypes.c_int, P, P, P],
         "tbpm_batch_autotune": [P, I32, ctypes.c_int, P, P, P],
         "tbpm_stream_copy": [P, P, SZ, P],
@@ -195,14 +195,16 @@ class Hamiltonian:
             on = np.ascontiguousarray(onsite, dtype=np.float64)
             _check(lib().tbpm_hamiltonian_set_values(self.handle, va.ctypes.data, on.ctypes.data, 0, 0))
 
-    def launch_config(self) -> dict:
+    def launch_config(self, precision: str = "fp64") -> dict:
         c = LaunchConfig()
-        _check(lib().tbpm_get_launch_config(self.handle, ctypes.byref(c)))
+        _check(lib().tbpm_get_launch_config(self.handle, _prec(precision), ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1):
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, precision=None):
+        """Launch shape for one precision, or for both when precision is None."""
         c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
-        _check(lib().tbpm_set_launch_config(self.handle, ctypes.byref(c)))
+        for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
+            _check(lib().tbpm_set_launch_config(self.handle, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
         c = LaunchConfig()
@@ -340,14 +342,15 @@ class Batch:
                                             n_arr if n_arr is not None else None, flags, _stream(stream)))
         return (corrs, norms) if return_norm else corrs
 
-    def launch_config(self) -> dict:
+    def launch_config(self, precision: str = "fp64") -> dict:
         c = LaunchConfig()
-        _check(lib().tbpm_batch_get_launch_config(self._b, ctypes.byref(c)))
+        _check(lib().tbpm_batch_get_launch_config(self._b, _prec(precision), ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1):
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, precision=None):
         c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
-        _check(lib().tbpm_batch_set_launch_config(self._b, ctypes.byref(c)))
+        for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
+            _check(lib().tbpm_batch_set_launch_config(self._b, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
         c = LaunchConfig()
@@ -377,6 +380,37 @@ def stream_copy(src, dst, stream=None):
 def bench_pass(H: Hamiltonian, n_states: int, precision: str, n_launch: int, stream=None):
     """Enqueue n_launch launches of the interior Clenshaw pass (timing only)."""
     _check(lib().tbpm_bench_pass(H.handle, int(n_states), _prec(precision), int(n_launch), _stream(stream)))
+
+
+def autotune_cached(H: Hamiltonian, n_states: int, precision: str, path: str | None = None, stream=None):
+    """Autotune H for (n_states, precision), reusing a result stored in the JSON
+    file ``path`` under the key (device, n_orb, nnz, max row, n_states,
+    precision); the library's autotuner runs only on a cache miss."""
+    import json
+
+    import torch
+
+    inf = H.info()
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    device = f"{getattr(props, 'gcnArchName', '')}:{props.multi_processor_count}"
+    key = "|".join(str(x) for x in (device, inf["n_orb"], inf["nnz"], inf["max_row"], n_states, precision))
+    cache = {}
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        cfg = cache[key]["config"]
+        H.set_launch_config(cfg["wg_chunks"], cfg["xcd_remap"], cfg["nontemporal"], cfg["unroll"],
+                            precision=precision)
+        return cfg, cache[key]["ms_per_step"], True
+    cfg, ms = H.autotune(n_states, precision, stream=stream)
+    if path:
+        cache[key] = {"config": cfg, "ms_per_step": ms}
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, path)
+    return cfg, ms, False
 
 
 def default_dt(rescale: float) -> float:

@@ -120,9 +120,10 @@ def test_launch_configs_and_graph_agree():
     for ch in (1, 2, 4, 8, 16, 32):
         for remap in (0, 1):
             for nt in (0, 1):
-                H.set_launch_config(ch, remap, nt)
-                got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
-                assert _rel(got, base) < 1e-13, (ch, remap, nt)
+                for un in (1, 2, 4):
+                    H.set_launch_config(ch, remap, nt, un)
+                    got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+                    assert _rel(got, base) < 1e-13, (ch, remap, nt, un)
     # a repeated call reuses the cached graph and gives the same bits
     again = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
     assert np.array_equal(again, got)
