@@ -71,6 +71,12 @@ def bench_batched(args, log):
     psis = [torch.from_numpy(s).cuda() for s in states]
     S = states[0].shape[1]
     nt = args.batch_nt
+    tuned = {}
+    if not args.no_autotune:
+        for prec in ("fp64", "fp32"):
+            cfg, ms = B.autotune(S, prec)
+            tuned[prec] = cfg
+            log(f"batch autotuned {prec}: {cfg} ({ms:.3f} ms per time step)")
     n_orb = sum(l.n_orb for l in lats)
     log(f"batch built: {len(lats)} members, {n_orb} orbitals in {time.time() - t0:.1f}s")
     out = {"members": len(lats), "n_orb_total": n_orb, "n_states": S, "n_steps": nt,
@@ -107,9 +113,60 @@ def bench_batched(args, log):
         errs.append(float(np.sum(np.abs(d32 - d64)) / np.sum(np.abs(d64))))
     out["fp32_dos_l1_rel_err_max"] = max(errs)
     out["fp32_speedup_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32"]["ms"], 3)
+    out["launch"] = tuned or {"fp64": B.launch_config("fp64"), "fp32": B.launch_config("fp32")}
     B.close()
     for h in hams:
         h.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_tbg(args, log):
+    """Twisted bilayer flake (two 1024^2-cell layers, 1.05 deg, ~19 stored elements per
+    row, irregular rows, open boundaries): 16 states, 1024 steps, FP32-mixed, with a
+    full FP64 run of the same states for the DOS error."""
+    import numpy as np
+    import torch
+
+    from paper_2209_00806_amd import inputs, tbpm
+
+    t0 = time.time()
+    lat, psi0_np = inputs.workload_twisted_bilayer(args.tbg_cells, 16)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    f = H.info()["gershgorin"]
+    dt = math.pi / f
+    nt = args.tbg_nt
+    M = tbpm.num_terms(f * dt, 1e-12)
+    psi0 = torch.from_numpy(psi0_np).cuda()
+    del psi0_np
+    log(f"twisted bilayer built: N={lat.n_orb}, nnz={lat.nnz} ({lat.nnz / lat.n_orb:.1f}/row), "
+        f"f={f:.3f} eV in {time.time() - t0:.1f}s")
+    updates = (lat.nnz + lat.n_orb) * 16 * (M - 1) * (nt - 1)
+    stream = torch.cuda.current_stream()
+    out = {"n_orb": lat.n_orb, "nnz_offdiag": lat.nnz, "nnz_per_row": round(lat.nnz / lat.n_orb, 2),
+           "max_row": H.info()["max_row"], "n_states": 16, "n_steps": nt, "rescale_eV": f}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        cfg, ms_t, _ = tbpm.autotune_cached(H, 16, prec, args.tune_cache)
+        tbpm.propagate(H, psi0, 4, dt, f, precision=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        corr = tbpm.propagate(H, psi0, nt, dt, f, precision=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        b, v = (8, 4) if prec == "fp32" else (16, 8)
+        alg = pass_bytes(lat.n_orb, lat.nnz, 16, b, v) * (M - 1) * (nt - 1)
+        _, D = tbpm.dos(corr, dt)
+        res[prec] = D.cpu().numpy()
+        out[prec] = {"ms": round(ms, 1), "nnz_updates_per_s": updates / (ms / 1e3),
+                     "alg_GBps": round(alg / (ms / 1e3) / 1e9, 1), "launch": cfg}
+        log(f"tbg {prec}: {ms:.1f} ms, {updates / (ms / 1e3):.3e} nnz-updates/s, {alg / (ms / 1e3) / 1e9:.0f} GB/s")
+    out["fp32_dos_l1_rel_err_vs_fp64"] = float(np.sum(np.abs(res["fp32"] - res["fp64"])) / np.sum(np.abs(res["fp64"])))
+    out["fp32_speedup_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32"]["ms"], 3)
+    H.close()
     torch.cuda.empty_cache()
     return out
 
@@ -192,6 +249,9 @@ def main():
     ap.add_argument("--batch-nt", type=int, default=1024)
     ap.add_argument("--bwd-cells", type=int, default=512)
     ap.add_argument("--bwd-nt", type=int, default=1024)
+    ap.add_argument("--no-tbg", action="store_true")
+    ap.add_argument("--tbg-cells", type=int, default=1024)
+    ap.add_argument("--tbg-nt", type=int, default=1024)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -345,6 +405,8 @@ def main():
         extra["batched"] = bench_batched(args, log)
     if not args.no_backward:
         extra["backward"] = bench_backward(args, log)
+    if not args.no_tbg:
+        extra["twisted_bilayer"] = bench_tbg(args, log)
 
     cpu = None
     if not args.no_cpu_baseline:

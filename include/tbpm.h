@@ -255,13 +255,20 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *               one chunk is 256 state elements
  *   xcd_remap   1: give each of the 8 XCDs a contiguous range of tiles
  *   nontemporal 1: stream the read-once vectors with non-temporal hints
- *   unroll      elements each thread handles at once (1, 2 or 4)
+ *   unroll      elements each thread handles at once (1 or 2)
+ *   vec         states of a row each thread holds (1, 2 or 4; capped by the
+ *               padded state count)
+ *   staged      1: each workgroup first copies the distinct rows of x that its
+ *               tile reads into LDS and gathers from there (pays off for rows
+ *               with many stored elements); wg_chunks and unroll are then unused
  */
 typedef struct {
     int32_t wg_chunks;
     int32_t xcd_remap;
     int32_t nontemporal;
     int32_t unroll;
+    int32_t staged;
+    int32_t vec;
 } tbpm_launch_config;
 
 /* Each handle keeps one launch configuration per precision. */

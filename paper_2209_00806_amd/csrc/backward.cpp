@@ -47,7 +47,9 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     const int n_passes = (int)plan.size();
 
     eng.cfg = eng.cfgs[0];
-    tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks);
+    eng.cfg.staged = 0;  // the replay and the adjoint use plain tiles of single-state units
+    eng.cfg.vec = 1;
+    tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks, 1);
     if (s != TBPM_OK) return s;
     const int32_t n_tiles = (int32_t)eng.h_tiles.size();
     const int64_t n_el = n_rows * s_pad;
@@ -160,7 +162,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
                 pp.b2 = (pl.kind == kPassMid || pl.kind == kPassLast) ? b_slot(t, j + 2) : nullptr;
                 pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
                 pp.coef = (const PassCoef *)eng.bwd_coef.ptr + p;
-                TRY_HIP(launch_pass(pl.kind, false, cplx, false, eng.cfg.unroll, pp, st), "replay pass");
+                TRY_HIP(launch_pass(pl.kind, false, cplx, false, eng.cfg.unroll, 1, pp, st), "replay pass");
             }
         }
         // adjoint sweep through the segment

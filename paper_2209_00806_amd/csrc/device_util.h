@@ -73,9 +73,9 @@ __device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap) {
 
 // Sum (dre, dim, nrm) over the threads of the workgroup that hold the same
 // state (thread t holds state t & (S-1)) in a fixed order, and write the
-// workgroup's partial sums for each state.
+// workgroup's partial sums for each state to out[(s*3 + q)*n_tiles + tile].
 __device__ __forceinline__ void block_state_partials(double dre, double dim, double nrm, int log2s,
-                                                     double *__restrict__ out /* [S][3] */) {
+                                                     double *__restrict__ out, int tile, int n_tiles) {
     __shared__ double red[kWG / 64][64][3];
     const int S = 1 << log2s;
     for (int off = 32; off >= S; off >>= 1) {
@@ -98,9 +98,10 @@ __device__ __forceinline__ void block_state_partials(double dre, double dim, dou
             b += red[w][threadIdx.x][1];
             c += red[w][threadIdx.x][2];
         }
-        out[threadIdx.x * 3 + 0] = a;
-        out[threadIdx.x * 3 + 1] = b;
-        out[threadIdx.x * 3 + 2] = c;
+        const int64_t o = (int64_t)threadIdx.x * 3 * n_tiles + tile;
+        out[o] = a;
+        out[o + n_tiles] = b;
+        out[o + 2 * (int64_t)n_tiles] = c;
     }
 }
 

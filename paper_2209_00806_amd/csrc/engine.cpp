@@ -75,7 +75,8 @@ void PinnedBuf::release() {
 
 bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
-        chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || ckpt_every != o.ckpt_every ||
+        chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
+        ckpt_every != o.ckpt_every ||
         ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
         return false;
     for (int i = 0; i < 8; ++i)
@@ -127,6 +128,8 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
     }
     HostEll e = build_sliced_ell(N, rp.data(), col.data());
     const int64_t S = (int64_t)e.col.size();
+    h_slice_off = e.slice_off;
+    h_col = e.col;
     std::vector<double> v64(cplx ? 2 * S : S, 0.0);
     std::vector<float> v32(cplx ? 2 * S : S, 0.0f);
     for (int64_t q = 0; q < S; ++q) {
@@ -186,7 +189,7 @@ void Engine::release() {
     mat = DevMatrix{};
     DevBuf *bufs[] = {&v,        &ba,        &bb,      &phi0,      &partials,  &counter,  &coef,
                       &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
-                      &bwd_gacc, &bwd_gdiag, &bwd_coef};
+                      &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -198,9 +201,11 @@ void Engine::release() {
 // ---------------------------------------------------------------------------
 // tiles: each workgroup handles 256*chunks state elements of one member
 // ---------------------------------------------------------------------------
-tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks) {
-    if (tiles_s == s_pad && tiles_chunks == chunks && tiles.ptr) return TBPM_OK;
-    const int64_t rows_per_tile = std::max<int64_t>(1, (int64_t)kWG * chunks / s_pad);
+tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks, int32_t vs) {
+    if (tiles_s == s_pad && tiles_chunks == chunks && tiles_unit == -vs && tiles.ptr) return TBPM_OK;
+    tiles_unit = -vs;
+    // a chunk is one workgroup's worth of units (vs states each)
+    const int64_t rows_per_tile = std::max<int64_t>(1, (int64_t)kWG * chunks * vs / s_pad);
     h_tiles.clear();
     h_inst_tile0.assign(n_inst() + 1, 0);
     for (int32_t i = 0; i < n_inst(); ++i) {
@@ -224,6 +229,99 @@ tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks) {
             "upload inst_tile0");
     tiles_s = s_pad;
     tiles_chunks = chunks;
+    return TBPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// staged tiles: R consecutive rows of one member; the rows of x a tile reads
+// are its own rows plus a sorted list of external rows.  R is the largest
+// power of two (<= 256) whose biggest staged set fits the LDS budget.
+// ---------------------------------------------------------------------------
+tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes) {
+    const int32_t key = unit_bytes * 64 + log2u;
+    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) return TBPM_OK;
+    const size_t budget = 48 * 1024;
+    const int64_t SR = kSliceRows;
+    std::vector<int32_t> ext;
+    auto collect = [&](int64_t r0, int64_t rows) {
+        ext.clear();
+        for (int64_t r = r0; r < r0 + rows; ++r) {
+            const int64_t q = r / SR, w = (h_slice_off[q + 1] - h_slice_off[q]) / SR;
+            for (int64_t k = 0; k < w; ++k) {
+                const int32_t c = h_col[h_slice_off[q] + k * SR + r % SR];
+                if (c < r0 || c >= r0 + rows) ext.push_back(c);
+            }
+        }
+        std::sort(ext.begin(), ext.end());
+        ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+    };
+    int64_t R = 0;
+    size_t max_stage = 0;
+    for (int64_t cand : {256, 128, 64, 32, 16, 8, 4, 2, 1}) {
+        size_t mx = 0;
+        for (int32_t i = 0; i < n_inst(); ++i)
+            for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += cand) {
+                const int64_t rows = std::min<int64_t>(cand, inst_row0[i + 1] - r0);
+                collect(r0, rows);
+                mx = std::max(mx, (size_t)rows + ext.size());
+            }
+        if ((mx << log2u) * (size_t)unit_bytes <= budget) {
+            R = cand;
+            max_stage = mx;
+            break;
+        }
+    }
+    if (R == 0) return fail(TBPM_E_ARG, "no staged tile fits the LDS budget");
+    h_tiles.clear();
+    h_inst_tile0.assign(n_inst() + 1, 0);
+    std::vector<int32_t> uoff(1, 0), ucol;
+    std::vector<uint16_t> lidx(std::max<size_t>(h_col.size(), 1), 0);
+    for (int32_t i = 0; i < n_inst(); ++i) {
+        for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += R) {
+            const int64_t rows = std::min<int64_t>(R, inst_row0[i + 1] - r0);
+            collect(r0, rows);
+            for (int64_t r = r0; r < r0 + rows; ++r) {
+                const int64_t q = r / SR, w = (h_slice_off[q + 1] - h_slice_off[q]) / SR;
+                for (int64_t k = 0; k < w; ++k) {
+                    const int64_t slot = h_slice_off[q] + k * SR + r % SR;
+                    const int32_t c = h_col[slot];
+                    int64_t local;
+                    if (c >= r0 && c < r0 + rows)
+                        local = c - r0;
+                    else
+                        local = rows + (std::lower_bound(ext.begin(), ext.end(), c) - ext.begin());
+                    lidx[slot] = (uint16_t)local;
+                }
+            }
+            ucol.insert(ucol.end(), ext.begin(), ext.end());
+            uoff.push_back((int32_t)ucol.size());
+            h_tiles.push_back(TileDesc{r0, (int32_t)rows, i});
+        }
+        h_inst_tile0[i + 1] = (int32_t)h_tiles.size();
+    }
+    if (ucol.size() >= (size_t)INT32_MAX) return fail(TBPM_E_ARG, "staged lists too large");
+    TRY_HIP(hipDeviceSynchronize(), "sync before tile rebuild");
+    TRY_HIP(tiles.ensure(sizeof(TileDesc) * h_tiles.size()), "alloc tiles");
+    TRY_HIP(inst_tile0.ensure(sizeof(int32_t) * h_inst_tile0.size()), "alloc inst_tile0");
+    TRY_HIP(st_uoff.ensure(sizeof(int32_t) * uoff.size()), "alloc staged offsets");
+    TRY_HIP(st_ucol.ensure(sizeof(int32_t) * std::max<size_t>(ucol.size(), 1)), "alloc staged rows");
+    TRY_HIP(st_lidx.ensure(sizeof(uint16_t) * lidx.size()), "alloc staged indices");
+    TRY_HIP(hipMemcpy(tiles.ptr, h_tiles.data(), sizeof(TileDesc) * h_tiles.size(), hipMemcpyHostToDevice),
+            "upload tiles");
+    TRY_HIP(hipMemcpy(inst_tile0.ptr, h_inst_tile0.data(), sizeof(int32_t) * h_inst_tile0.size(),
+                      hipMemcpyHostToDevice),
+            "upload inst_tile0");
+    TRY_HIP(hipMemcpy(st_uoff.ptr, uoff.data(), sizeof(int32_t) * uoff.size(), hipMemcpyHostToDevice),
+            "upload staged offsets");
+    if (!ucol.empty())
+        TRY_HIP(hipMemcpy(st_ucol.ptr, ucol.data(), sizeof(int32_t) * ucol.size(), hipMemcpyHostToDevice),
+                "upload staged rows");
+    TRY_HIP(hipMemcpy(st_lidx.ptr, lidx.data(), sizeof(uint16_t) * lidx.size(), hipMemcpyHostToDevice),
+            "upload staged indices");
+    stage_units = (int32_t)(max_stage << log2u);
+    tiles_s = s_pad;
+    tiles_chunks = -(int32_t)R;
+    tiles_unit = key;
     return TBPM_OK;
 }
 
@@ -306,7 +404,13 @@ tbpm_status Engine::run(const RunArgs &a) {
     const int n_passes = (int)plan.size();
 
     const int32_t chunks = cfg.wg_chunks;
-    tbpm_status st = build_tiles(s_pad, chunks);
+    const int32_t vs = std::min(cfg.vec, s_pad);
+    const int32_t log2u = log2s - (vs == 4 ? 2 : (vs == 2 ? 1 : 0));
+    const int32_t unit_bytes = (int32_t)esize * vs;
+    bool staged = cfg.staged != 0;
+    tbpm_status st = TBPM_OK;
+    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes) != TBPM_OK) staged = false;  // fall back
+    if (!staged) st = build_tiles(s_pad, chunks, vs);
     if (st != TBPM_OK) return st;
     const int32_t n_tiles = (int32_t)h_tiles.size();
     const int64_t n_el = mat.n_rows * s_pad;
@@ -368,6 +472,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     TRY_HIP(launch_init(fp32, ip, a.stream), "launch init");
     ReduceParams rp{};
     rp.partials = (const double *)partials.ptr;
+    rp.n_tiles = n_tiles;
     rp.inst_tile0 = (const int32_t *)inst_tile0.ptr;
     rp.log2s = log2s;
     rp.s_user = a.s_user;
@@ -406,7 +511,13 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             pp.ckpt_max = a.n_steps - 2;
             pp.s_user = a.s_user;
-            hipError_t e = launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, pp, s);
+            pp.uoff = (const int32_t *)st_uoff.ptr;
+            pp.ucol = (const int32_t *)st_ucol.ptr;
+            pp.lidx = (const uint16_t *)st_lidx.ptr;
+            pp.stage_units = stage_units;
+            hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, pp, s)
+                                  : launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs,
+                                                pp, s);
             if (e != hipSuccess) return hip_fail(e, "launch pass");
         }
         hipError_t e = launch_reduce(ni, s_pad, rp, s);
@@ -431,6 +542,8 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.remap = cfg.xcd_remap;
             key.nt = cfg.nontemporal;
             key.unroll = cfg.unroll;
+            key.staged = staged ? 1 : 0;
+            key.vec = vs;
             key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             key.ckpt_max = a.n_steps - 2;
             key.n_steps = a.n_steps;
@@ -466,6 +579,8 @@ tbpm_status Engine::run(const RunArgs &a) {
 
     last_s_pad = s_pad;
     last_fp32 = fp32 ? 1 : 0;
+    last_staged = staged ? 1 : 0;
+    last_vs = vs;
     if (a.flags & TBPM_FLAG_ASYNC) return TBPM_OK;
     TRY_HIP(hipStreamSynchronize(a.stream), "stream synchronize");
     TRY_HIP(hipGetLastError(), "kernel execution");
@@ -518,8 +633,15 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.coef = (const PassCoef *)coef.ptr;  // the first pass's coefficients: finite, bounded
     pp.counter = (int32_t *)counter.ptr;
     pp.s_user = s_user;
+    pp.uoff = (const int32_t *)st_uoff.ptr;
+    pp.ucol = (const int32_t *)st_ucol.ptr;
+    pp.lidx = (const uint16_t *)st_lidx.ptr;
+    pp.stage_units = stage_units;
     for (int32_t i = 0; i < n_launch; ++i) {
-        hipError_t e = launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, pp, stream);
+        hipError_t e = last_staged
+                           ? launch_pass_staged(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, pp, stream)
+                           : launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, last_vs, pp,
+                                         stream);
         if (e != hipSuccess) return hip_fail(e, "launch pass");
     }
     return TBPM_OK;

@@ -70,7 +70,7 @@ __device__ __forceinline__ void unit_mad_cplx(C h, VecT<R, VS> x, VecT<R, VS> &a
 template <int VS>
 __device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
                                                     const double (&nrm)[VS], int log2u,
-                                                    double *__restrict__ out /* [S][3] */) {
+                                                    double *__restrict__ out, int tile, int n_tiles) {
     __shared__ double red[kWG / 64][64][3];
     const int U = 1 << log2u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -98,9 +98,10 @@ __device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], con
             b += red[w][threadIdx.x][1];
             c += red[w][threadIdx.x][2];
         }
-        out[threadIdx.x * 3 + 0] = a;
-        out[threadIdx.x * 3 + 1] = b;
-        out[threadIdx.x * 3 + 2] = c;
+        const int64_t o = (int64_t)threadIdx.x * 3 * n_tiles + tile;
+        out[o] = a;
+        out[o + n_tiles] = b;
+        out[o + 2 * (int64_t)n_tiles] = c;
     }
 }
 
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
     constexpr bool X_IS_V = (KIND == kPassFirst);
     constexpr bool HAS_B2 = (KIND == kPassMid || KIND == kPassLast);
     constexpr bool CORR = (KIND == kPassLast || KIND == kPassLastNoB2);
-    constexpr int LOG2VS = VS == 2 ? 1 : 0;
+    constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
 
     const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
     const TileDesc td = p.tiles[tile];
@@ -244,7 +245,141 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
             }
         }
     }
-    if constexpr (CORR) block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials + (int64_t)tile * (3 << log2s));
+    if constexpr (CORR) block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials, tile, p.n_tiles);
+}
+
+// ---------------------------------------------------------------------------
+// Clenshaw pass with the gathered vector staged in LDS.  The workgroup of
+// tile t first copies the rows of x it will read -- its own rows, then the
+// tile's sorted list of external rows -- into LDS (each row is read from
+// global memory once per tile instead of once per stored element that
+// references it), then evaluates the pass with every neighbour read from
+// LDS through the slot's precomputed local index.  Same arithmetic as
+// k_pass, so results are identical.
+// ---------------------------------------------------------------------------
+template <typename R, bool CH, int KIND, bool NT, int VS>
+__global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
+    extern __shared__ __align__(16) unsigned char stage_mem[];
+    using V = VecT<R, VS>;
+    using HV = typename HValT<R, CH>::T;
+    constexpr int KG = 4;
+    constexpr bool X_IS_V = (KIND == kPassFirst);
+    constexpr bool HAS_B2 = (KIND == kPassMid || KIND == kPassLast);
+    constexpr bool CORR = (KIND == kPassLast || KIND == kPassLastNoB2);
+    constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
+    V *xs = reinterpret_cast<V *>(stage_mem);
+
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const TileDesc td = p.tiles[tile];
+    const PassCoef pc = p.coef[td.inst];
+    const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
+    const int log2s = p.log2s;
+    const int log2u = log2s - LOG2VS;
+    const uint32_t umask = (1u << log2u) - 1u;
+    const uint32_t n_own = (uint32_t)td.rows;
+    const uint32_t n_u = n_own << log2u;
+    const uint32_t row0 = (uint32_t)td.row0;
+    const uint32_t u0 = row0 << log2u;
+    const int32_t x0 = p.uoff[tile], x1 = p.uoff[tile + 1];
+    const uint32_t n_stage = (n_own + (uint32_t)(x1 - x0)) << log2u;
+
+    if (p.bump_counter && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(p.counter, 1);
+
+    const V *__restrict__ x = (const V *)p.x;
+    const V *v = (const V *)p.v;
+    const V *b2 = (const V *)p.b2;
+    V *out = (V *)p.out;
+    const R *__restrict__ ons = (const R *)p.onsite;
+    const HV *__restrict__ val = (const HV *)p.val;
+    const uint16_t *__restrict__ lidx = p.lidx;
+    const uint32_t *__restrict__ soff = p.slice_off;
+
+    for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
+        const uint32_t lr = i >> log2u;
+        const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
+        xs[i] = x[(grow << log2u) + (i & umask)];
+    }
+    __syncthreads();
+
+    const uint32_t usub = threadIdx.x & umask;
+    double dre[VS], dim[VS], nrm[VS];
+#pragma unroll
+    for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
+    bool do_ckpt = false;
+    uint32_t ckpt_base = 0;
+    if constexpr (CORR) {
+        if (p.ckpt_every > 0) {
+            const int step = *(volatile const int32_t *)p.counter;
+            do_ckpt = (step % p.ckpt_every == 0) && step <= p.ckpt_max && step > 0;
+            ckpt_base = (uint32_t)(step / p.ckpt_every - 1);
+        }
+    }
+
+    for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
+        const uint32_t lrow = u >> log2u;
+        const uint32_t row = row0 + lrow;
+        const uint32_t gu = u0 + u;
+        const uint32_t sl = row / kSliceRows;
+        const uint32_t off = soff[sl];
+        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+        const uint32_t base = off + row % kSliceRows;
+        V vv, bq;
+        if constexpr (!X_IS_V) vv = ldv<NT>(v + gu);
+        if constexpr (HAS_B2) bq = ldv<NT>(b2 + gu);
+        const V xo = xs[u];
+        V acc = ons[row] * xo;
+        for (int k = 0; k < w; k += KG) {
+            uint32_t li[KG];
+            HV h[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const uint32_t l = lidx[slot];
+                const HV hv = val[slot];
+                li[i] = ((valid ? l : lrow) << log2u) + usub;
+                h[i] = valid ? hv : HV{};
+            }
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                if constexpr (CH)
+                    unit_mad_cplx<R, VS>(h[i], xs[li[i]], acc);
+                else
+                    unit_mad_real<R, VS>(h[i], xs[li[i]], acc);
+            }
+        }
+        const V src = X_IS_V ? xo : vv;
+        V o;
+#pragma unroll
+        for (int i = 0; i < VS; ++i) {
+            const R vr = src[2 * i], vi = src[2 * i + 1];
+            const R hr = acc[2 * i], hi = acc[2 * i + 1];
+            o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
+            o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
+        }
+        if constexpr (HAS_B2) o -= bq;
+        if constexpr (CORR) {
+            stv<false>(out + gu, o);
+            const uint32_t s0 = usub << LOG2VS;
+#pragma unroll
+            for (int i = 0; i < VS; ++i) {
+                const d2 ph = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + s0 + i];
+                const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
+                dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
+                dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
+                nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
+                if (do_ckpt && (int)(s0 + i) < p.s_user) {
+                    d2 oc;
+                    oc.x = oxr;
+                    oc.y = oyi;
+                    ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + (int64_t)row * p.s_user + s0 + i] = oc;
+                }
+            }
+        } else {
+            stv<NT>(out + gu, o);
+        }
+    }
+    if constexpr (CORR) block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials, tile, p.n_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,7 +417,7 @@ __global__ __launch_bounds__(kWG) void k_init(const InitParams p) {
         nrm = fma(ox, ox, fma(oy, oy, nrm));
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(p.counter, 0);
-    block_state_partials(dre, dim, nrm, log2s, p.partials + (int64_t)blockIdx.x * (3 << log2s));
+    block_state_partials(dre, dim, nrm, log2s, p.partials, blockIdx.x, p.n_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,21 +429,32 @@ __global__ __launch_bounds__(kWG) void k_reduce(const ReduceParams p) {
     __shared__ double red[3][kWG];
     const int inst = blockIdx.x / p.s_user;
     const int s = blockIdx.x % p.s_user;
-    const int S = 1 << p.log2s;
     const int t0 = p.inst_tile0[inst], t1 = p.inst_tile0[inst + 1];
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int t = t0 + threadIdx.x; t < t1; t += kWG) {
-        const double *q = p.partials + ((int64_t)t * S + s) * 3;
-        a += q[0];
-        b += q[1];
-        c += q[2];
+    const int64_t nt = p.n_tiles;
+    const double *q0 = p.partials + (int64_t)s * 3 * nt;
+    // four independent accumulators per component keep several loads in flight;
+    // the summation order is fixed
+    double a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    int t = t0 + threadIdx.x;
+    for (; t + 3 * kWG < t1; t += 4 * kWG) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] += q0[t + u * kWG];
+            b[u] += q0[nt + t + u * kWG];
+            c[u] += q0[2 * nt + t + u * kWG];
+        }
     }
-    red[0][threadIdx.x] = a;
-    red[1][threadIdx.x] = b;
-    red[2][threadIdx.x] = c;
+    for (; t < t1; t += kWG) {
+        a[0] += q0[t];
+        b[0] += q0[nt + t];
+        c[0] += q0[2 * nt + t];
+    }
+    red[0][threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+    red[1][threadIdx.x] = (b[0] + b[1]) + (b[2] + b[3]);
+    red[2][threadIdx.x] = (c[0] + c[1]) + (c[2] + c[3]);
     __syncthreads();
     for (int h = kWG / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
+        if ((int)threadIdx.x < h) {
             red[0][threadIdx.x] += red[0][threadIdx.x + h];
             red[1][threadIdx.x] += red[1][threadIdx.x + h];
             red[2][threadIdx.x] += red[2][threadIdx.x + h];
@@ -498,8 +644,6 @@ hipError_t launch_pass_ne(int kind, int ne, const PassParams &p, hipStream_t st)
             return launch_pass_t<R, CH, NT, VS, 1>(kind, p, st);
         case 2:
             return launch_pass_t<R, CH, NT, VS, 2>(kind, p, st);
-        case 4:
-            return launch_pass_t<R, CH, NT, VS, 4>(kind, p, st);
         default:
             return hipErrorInvalidValue;
     }
@@ -512,16 +656,64 @@ hipError_t launch_pass_r(int kind, bool cplx, bool nt, int ne, const PassParams 
     return nt ? launch_pass_ne<R, false, true, VS>(kind, ne, p, st) : launch_pass_ne<R, false, false, VS>(kind, ne, p, st);
 }
 
+template <typename R, bool CH, bool NT, int VS>
+hipError_t launch_staged_t(int kind, const PassParams &p, hipStream_t st) {
+    const dim3 grid(p.n_tiles), block(kWG);
+    const size_t lds = (size_t)p.stage_units * sizeof(VecT<R, VS>);
+    switch (kind) {
+        case kPassFirst:
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassFirst, NT, VS>), grid, block, lds, st, p);
+            break;
+        case kPassNoB2:
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassNoB2, NT, VS>), grid, block, lds, st, p);
+            break;
+        case kPassMid:
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassMid, NT, VS>), grid, block, lds, st, p);
+            break;
+        case kPassLast:
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLast, NT, VS>), grid, block, lds, st, p);
+            break;
+        case kPassLastNoB2:
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLastNoB2, NT, VS>), grid, block, lds, st, p);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int VS>
+hipError_t launch_staged_r(int kind, bool cplx, bool nt, const PassParams &p, hipStream_t st) {
+    if (cplx) return nt ? launch_staged_t<R, true, true, VS>(kind, p, st) : launch_staged_t<R, true, false, VS>(kind, p, st);
+    return nt ? launch_staged_t<R, false, true, VS>(kind, p, st) : launch_staged_t<R, false, false, VS>(kind, p, st);
+}
+
 }  // namespace
 
-hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, const PassParams &p,
+hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, int vs, const PassParams &p,
                        hipStream_t st) {
     if (p.n_tiles <= 0) return hipSuccess;
     if (fp32) {
-        if (p.log2s >= 1) return launch_pass_r<float, 2>(kind, cplx, nontemporal, ne, p, st);
+        if (vs == 4) return launch_pass_r<float, 4>(kind, cplx, nontemporal, ne, p, st);
+        if (vs == 2) return launch_pass_r<float, 2>(kind, cplx, nontemporal, ne, p, st);
         return launch_pass_r<float, 1>(kind, cplx, nontemporal, ne, p, st);
     }
+    if (vs == 4) return launch_pass_r<double, 4>(kind, cplx, nontemporal, ne, p, st);
+    if (vs == 2) return launch_pass_r<double, 2>(kind, cplx, nontemporal, ne, p, st);
     return launch_pass_r<double, 1>(kind, cplx, nontemporal, ne, p, st);
+}
+
+hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const PassParams &p,
+                              hipStream_t st) {
+    if (p.n_tiles <= 0) return hipSuccess;
+    if (fp32) {
+        if (vs == 4) return launch_staged_r<float, 4>(kind, cplx, nontemporal, p, st);
+        if (vs == 2) return launch_staged_r<float, 2>(kind, cplx, nontemporal, p, st);
+        return launch_staged_r<float, 1>(kind, cplx, nontemporal, p, st);
+    }
+    if (vs == 4) return launch_staged_r<double, 4>(kind, cplx, nontemporal, p, st);
+    if (vs == 2) return launch_staged_r<double, 2>(kind, cplx, nontemporal, p, st);
+    return launch_staged_r<double, 1>(kind, cplx, nontemporal, p, st);
 }
 
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st) {

@@ -68,7 +68,7 @@ struct PinnedBuf {
 // if the key is equal.
 struct GraphKey {
     int32_t s_pad = 0, s_user = 0, fp32 = 0, mmax = 0, n_inst = 0;
-    int32_t chunks = 0, remap = 0, nt = 0, unroll = 0;
+    int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0;
     int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
     const void *ckpt = nullptr;
     const void *bufs[8] = {};
@@ -78,8 +78,14 @@ struct GraphKey {
 struct Engine {
     DevMatrix mat;
     std::vector<int64_t> inst_row0;  // [n_inst + 1]
-    tbpm_launch_config cfgs[2] = {{2, 1, 1, 1}, {4, 0, 1, 2}};  // FP64, FP32-mixed
-    tbpm_launch_config cfg{2, 1, 1, 1};                          // the one in use
+    tbpm_launch_config cfgs[2] = {{2, 1, 1, 1, 0, 1}, {4, 0, 1, 2, 0, 2}};  // FP64, FP32-mixed
+    tbpm_launch_config cfg{2, 1, 1, 1, 0, 1};                                // the one in use
+    // host copy of the sliced ELL columns (for building staged tiles)
+    std::vector<int64_t> h_slice_off;
+    std::vector<int32_t> h_col;
+    // staged tiles: external-row lists and per-slot local indices
+    DevBuf st_uoff, st_ucol, st_lidx;
+    int32_t stage_units = 0;
     int device = -1;
 
     // work buffers
@@ -91,7 +97,9 @@ struct Engine {
     hipStream_t capture_stream = nullptr;
 
     // tile tables (host) for the current (S, chunks)
-    int32_t tiles_s = 0, tiles_chunks = 0;
+    // tiles_chunks < 0: staged tiles of -chunks rows (tiles_unit = unit bytes*64 + log2u);
+    // else plain tiles of chunks*256 units of tiles_unit = -vs states
+    int32_t tiles_s = 0, tiles_chunks = 0, tiles_unit = 0;
     std::vector<TileDesc> h_tiles;
     std::vector<int32_t> h_inst_tile0;
 
@@ -123,9 +131,12 @@ struct Engine {
     tbpm_status run(const RunArgs &a);
     // back-to-back launches of the interior pass on the current buffers
     tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
-    int32_t last_s_pad = 0, last_fp32 = -1;
+    int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1;
 
-    tbpm_status build_tiles(int32_t s_pad, int32_t chunks);
+    tbpm_status build_tiles(int32_t s_pad, int32_t chunks, int32_t vs);
+    // staged tiles for s_pad states of unit_bytes per VS states (log2u units per row);
+    // TBPM_E_ARG if no tile size fits the LDS budget
+    tbpm_status build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes);
 };
 
 }  // namespace tbpm

@@ -87,13 +87,20 @@ struct PassParams {
     // fused correlation (last pass)
     const double *phi0;    // complex128 [rows][S]
     int64_t phi0_ld;       // states per row of phi0 (>= S padded or the caller's S)
-    double *partials;      // [n_tiles][S][3]
+    double *partials;      // [S][3][n_tiles]
     // checkpoints (last pass, FP64 only)
     double *ckpt;          // complex128 [n_ckpt][rows][s_user]
     int64_t ckpt_stride;   // complex elements per checkpoint (rows * s_user)
     int32_t ckpt_every;
     int32_t ckpt_max;      // largest step index that is stored
     int32_t s_user;
+    // LDS staging (staged launch shape): tile t reads its own rows and the
+    // external rows ucol[uoff[t] .. uoff[t+1]); lidx[slot] is the local row of
+    // each ELL slot in that staged set
+    const int32_t *uoff;
+    const int32_t *ucol;
+    const uint16_t *lidx;
+    int32_t stage_units;   // LDS capacity in units (VS states)
 };
 
 struct InitParams {
@@ -105,12 +112,13 @@ struct InitParams {
     const int64_t *inst_row0;    // per member, first global row
     void *v;                     // state buffer [rows][S] (R precision)
     double *phi0;                // padded FP64 copy [rows][S], or null
-    double *partials;            // [n_tiles][S][3]
+    double *partials;            // [S][3][n_tiles]
     int32_t *counter;
 };
 
 struct ReduceParams {
-    const double *partials;
+    const double *partials;      // [S][3][n_tiles]
+    int32_t n_tiles;
     const int32_t *inst_tile0;   // [n_inst + 1]
     int32_t log2s;
     int32_t s_user;
@@ -122,8 +130,11 @@ struct ReduceParams {
 };
 
 // launchers (kernels.hip)
-hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, const PassParams &p,
+// vs = states per thread (1, 2 or 4; at most the padded state count)
+hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, int vs, const PassParams &p,
                        hipStream_t st);
+hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const PassParams &p,
+                              hipStream_t st);
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st);
 hipError_t launch_reduce(int n_inst, int s_pad, const ReduceParams &p, hipStream_t st);
 hipError_t launch_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, int window,

@@ -43,14 +43,25 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
-    const int chunk_list[] = {1, 2, 4, 8, 16, 32};
-    const int unroll_list[] = {1, 2, 4};
-    for (int ch : chunk_list) {
-        for (int cand = 0; cand < 12 && st == TBPM_OK; ++cand) {
-            const int remap = cand & 1, nt = (cand >> 1) & 1, un = unroll_list[cand >> 2];
-            if (un > ch) continue;  // a tile of ch chunks keeps at most ch elements per thread busy
+    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal)
+    std::vector<tbpm_launch_config> cands;
+    int32_t s_pad = 1;
+    while (s_pad < n_states) s_pad <<= 1;
+    const int chunk_list[] = {1, 2, 4, 8, 16};
+    for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
+        if (fp32 && vec == 1 && s_pad > 1) continue;  // 8-byte units are never better than 16
+        for (int ch : chunk_list)
+            for (int un = 1; un <= 2; ++un)
+                for (int remap = 0; remap <= 1; ++remap)
+                    for (int nt = 0; nt <= 1; ++nt)
+                        if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec});
+        for (int remap = 0; remap <= 1; ++remap)
+            for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec});
+    }
+    for (const tbpm_launch_config &cand : cands) {
+        {
             {
-                eng.cfgs[fp32 ? 1 : 0] = tbpm_launch_config{ch, remap, nt, un};
+                eng.cfgs[fp32 ? 1 : 0] = cand;
                 Engine::RunArgs a{};
                 a.psi0 = p0.data();
                 a.s_user = n_states;

@@ -218,9 +218,28 @@ def random_phase_states(rng: np.random.Generator, n: int, n_states: int) -> np.n
     return np.ascontiguousarray((np.exp(1j * theta) / np.sqrt(n)).T)
 
 
+def morton_order(xy: np.ndarray, cell: float) -> np.ndarray:
+    """Permutation that sorts points along a Z-order (Morton) curve of their 2D
+    positions quantised to ``cell``; points in the same quantum keep their order."""
+    q = np.floor((xy - xy.min(axis=0)) / cell).astype(np.uint64)
+
+    def spread(v):  # interleave zeros between the low 32 bits
+        v = v & np.uint64(0xFFFFFFFF)
+        v = (v | (v << np.uint64(16))) & np.uint64(0x0000FFFF0000FFFF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF00FF00FF)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F0F0F0F0F)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x3333333333333333)
+        v = (v | (v << np.uint64(1))) & np.uint64(0x5555555555555555)
+        return v
+
+    code = spread(q[:, 0]) | (spread(q[:, 1]) << np.uint64(1))
+    return np.argsort(code, kind="stable")
+
+
 def twisted_bilayer(nx: int, ny: int, angle_deg: float = 1.05, d: float = 3.35,
                     a_cc: float = 1.42, t_intra: float = -2.7, t0: float = 0.48,
-                    decay: float = 0.184, cutoff: float = 5.0, max_neighbors: int = 48) -> Lattice:
+                    decay: float = 0.184, cutoff: float = 5.0, max_neighbors: int = 48,
+                    order: str = "morton") -> Lattice:
     """Twisted bilayer honeycomb flake with open boundaries.
 
     Layer 1 is an nx x ny graphene flake (nearest-neighbour distance a_cc)
@@ -228,6 +247,11 @@ def twisted_bilayer(nx: int, ny: int, angle_deg: float = 1.05, d: float = 3.35,
     about the z axis and lifted to z = d.  Intralayer nearest neighbours carry
     ``t_intra``; every interlayer pair at 3D distance <= cutoff carries
     ``t0 * exp(-(r - d)/decay)``.
+
+    ``order="layer"`` numbers layer 1 then layer 2 (each in graphene order);
+    ``order="morton"`` numbers the atoms of both layers along a Z-order curve
+    of their in-plane positions (quantum a_cc), so that orbitals close in
+    space -- in either layer -- are close in index.
     """
     from scipy.spatial import cKDTree  # input generation only
 
@@ -258,8 +282,15 @@ def twisted_bilayer(nx: int, ny: int, angle_deg: float = 1.05, d: float = 3.35,
     pos[:n1, :2] = p1
     pos[n1:, :2] = p2
     pos[n1:, 2] = d
+    if order == "morton":
+        perm = morton_order(pos[:, :2], a_cc)  # new index -> old index
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.shape[0])
+        bi, bj, pos = inv[bi], inv[bj], pos[perm]
+    elif order != "layer":
+        raise ValueError(order)
     lat = from_bonds(2 * n1, bi, bj, bt, np.zeros(2 * n1), name=f"tbg{nx}x{ny}", pos=pos)
-    lat.meta.update(kind="tbg", nx=nx, ny=ny, angle=angle_deg)
+    lat.meta.update(kind="tbg", nx=nx, ny=ny, angle=angle_deg, order=order)
     return lat
 
 

@@ -38,11 +38,11 @@ class TBPMError(RuntimeError):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("wg_chunks", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("unroll", ctypes.c_int32)]
+                ("unroll", ctypes.c_int32), ("staged", ctypes.c_int32), ("vec", ctypes.c_int32)]
 
     def as_dict(self):
         return {"wg_chunks": self.wg_chunks, "xcd_remap": self.xcd_remap, "nontemporal": self.nontemporal,
-                "unroll": self.unroll}
+                "unroll": self.unroll, "staged": self.staged, "vec": self.vec}
 
 
 _lib = None
@@ -200,10 +200,13 @@ class Hamiltonian:
         _check(lib().tbpm_get_launch_config(self.handle, _prec(precision), ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, precision=None):
-        """Launch shape for one precision, or for both when precision is None."""
-        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, staged=0, vec=None,
+                          precision=None):
+        """Launch shape for one precision, or for both when precision is None
+        (vec=None: 1 state per thread in FP64, 2 in FP32)."""
         for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
+            c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll, staged,
+                             vec if vec is not None else (2 if p == FP32_MIXED else 1))
             _check(lib().tbpm_set_launch_config(self.handle, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
@@ -347,9 +350,11 @@ class Batch:
         _check(lib().tbpm_batch_get_launch_config(self._b, _prec(precision), ctypes.byref(c)))
         return c.as_dict()
 
-    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, precision=None):
-        c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll)
+    def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, staged=0, vec=None,
+                          precision=None):
         for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
+            c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll, staged,
+                             vec if vec is not None else (2 if p == FP32_MIXED else 1))
             _check(lib().tbpm_batch_set_launch_config(self._b, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
@@ -401,7 +406,7 @@ def autotune_cached(H: Hamiltonian, n_states: int, precision: str, path: str | N
     if key in cache:
         cfg = cache[key]["config"]
         H.set_launch_config(cfg["wg_chunks"], cfg["xcd_remap"], cfg["nontemporal"], cfg["unroll"],
-                            precision=precision)
+                            cfg.get("staged", 0), cfg.get("vec"), precision=precision)
         return cfg, cache[key]["ms_per_step"], True
     cfg, ms = H.autotune(n_states, precision, stream=stream)
     if path:

@@ -120,10 +120,17 @@ def test_launch_configs_and_graph_agree():
     for ch in (1, 2, 4, 8, 16, 32):
         for remap in (0, 1):
             for nt in (0, 1):
-                for un in (1, 2, 4):
-                    H.set_launch_config(ch, remap, nt, un)
-                    got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
-                    assert _rel(got, base) < 1e-13, (ch, remap, nt, un)
+                for un in (1, 2):
+                    for vec in (1, 2, 4):
+                        H.set_launch_config(ch, remap, nt, un, vec=vec)
+                        got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+                        assert _rel(got, base) < 1e-13, (ch, remap, nt, un, vec)
+    for remap in (0, 1):
+        for nt in (0, 1):
+            for vec in (1, 2, 4):
+                H.set_launch_config(2, remap, nt, 1, staged=1, vec=vec)
+                got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+                assert _rel(got, base) < 1e-13, ("staged", remap, nt, vec)
     # a repeated call reuses the cached graph and gives the same bits
     again = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
     assert np.array_equal(again, got)
@@ -259,3 +266,110 @@ def test_config2_full_size_sampled_states():
     for s in (0, 5):
         ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), nt, dt, f)
         assert _rel(corr[:, s], ref[:, 0]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_twisted_bilayer_irregular_rows(precision):
+    """Twisted bilayer flake (irregular rows, 2..21 stored elements, open
+    boundaries), 16 states: FP64 to 1e-10, FP32-mixed DOS to 1e-4 (L1)."""
+    print(f"case tbg {precision}", flush=True)
+    rng = np.random.default_rng(21)
+    lat = inputs.twisted_bilayer(40, 40, angle_deg=1.05)
+    assert np.diff(lat.row_ptr).max() > 16
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, 16)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite)
+    dt = math.pi / f
+    nt = 160
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision).cpu().numpy()
+    _, Dr = oracle.dos(ref, dt)
+    _, D = tbpm.dos(_dev(got), dt)
+    if precision == "fp64":
+        assert _rel(got, ref) < 1e-10
+        assert _rel(D.cpu().numpy(), Dr) < 1e-10
+    else:
+        assert _l1(D.cpu().numpy(), Dr) < 1e-4
+
+
+@pytest.mark.parametrize("S", [33, 64])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_maximum_state_count(S, precision):
+    """S up to the maximum of 64 (33 is padded to 64 internally)."""
+    print(f"case S={S} {precision}", flush=True)
+    lat = LATTICES["graphene6x6_disorder"]()
+    H, psi0, dt, ref, ref_n2, got, n2 = _run_pair(lat, S, 64, precision=precision)
+    if precision == "fp64":
+        assert _rel(got, ref) < 1e-10
+        assert np.max(np.abs(n2 - ref_n2)) < 1e-10
+    else:
+        _, Dr = oracle.dos(ref, dt)
+        _, D = tbpm.dos(_dev(got), dt)
+        assert _l1(D.cpu().numpy(), Dr) < 1e-4
+    with pytest.raises(tbpm.TBPMError):
+        tbpm.propagate(H, _dev(inputs.random_phase_states(np.random.default_rng(0), lat.n_orb, 65)), 4, dt, 9.0)
+
+
+def test_batched_async_and_plain_launches():
+    print("case batched async/no-graph", flush=True)
+    rng = np.random.default_rng(31)
+    lats = [inputs.graphene(7, 5, onsite=inputs.anderson(rng, 70, 1.0)), inputs.square(9, 8)]
+    psis = [inputs.random_phase_states(rng, l.n_orb, 2) for l in lats]
+    fs = [oracle.gershgorin(l.row_ptr, l.val, l.onsite) * 1.02 for l in lats]
+    dts = [math.pi / f for f in fs]
+    B = tbpm.Batch([tbpm.Hamiltonian.from_lattice(l) for l in lats])
+    a = B.propagate([_dev(p) for p in psis], 50, dts, fs, graph=False)
+    b = B.propagate([_dev(p) for p in psis], 50, dts, fs, sync=False)
+    torch.cuda.synchronize()
+    for l, p, f, dt, x, y in zip(lats, psis, fs, dts, a, b):
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 50, dt, f)
+        assert _rel(x.cpu().numpy(), ref) < 1e-10
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["tbg_s16_fp64", "tbg_s16_fp32", "graphene_s64_fp64", "graphene_s1_fp32",
+                                  "batch_s4_fp64"])
+def test_lds_staged_launch_shape(case):
+    """The LDS-staged pass (every tile copies the rows of x it reads into LDS
+    first) against the oracle, on wide irregular rows, the largest state count,
+    a single state and a batch."""
+    print(f"case staged {case}", flush=True)
+    rng = np.random.default_rng(41)
+    prec = "fp32" if case.endswith("fp32") else "fp64"
+    if case.startswith("batch"):
+        lats = [inputs.graphene(11, 9, onsite=inputs.anderson(rng, 198, 1.0)), inputs.square(17, 13),
+                inputs.twisted_bilayer(12, 12, angle_deg=4.0)]
+        psis = [inputs.random_phase_states(rng, l.n_orb, 4) for l in lats]
+        fs = [oracle.gershgorin(l.row_ptr, l.val, l.onsite) * 1.02 for l in lats]
+        dts = [math.pi / f for f in fs]
+        B = tbpm.Batch([tbpm.Hamiltonian.from_lattice(l) for l in lats])
+        B.set_launch_config(2, 1, 1, 1, staged=1)
+        corrs = B.propagate([_dev(p) for p in psis], 48, dts, fs)
+        for l, p, f, dt, c in zip(lats, psis, fs, dts, corrs):
+            ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 48, dt, f)
+            assert _rel(c.cpu().numpy(), ref) < 1e-10
+        return
+    if case.startswith("tbg"):
+        lat, S = inputs.twisted_bilayer(32, 32, angle_deg=1.05), 16
+    elif "s64" in case:
+        lat, S = inputs.graphene(12, 10, onsite=inputs.anderson(rng, 240, 1.0)), 64
+    else:
+        lat, S = inputs.graphene(40, 37, onsite=inputs.anderson(rng, 2960, 1.0)), 1
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    dt = math.pi / f
+    nt = 96
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, staged=1, vec=min(4, S))
+    got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec).cpu().numpy()
+    H.set_launch_config(2, 1, 1, 1, staged=0)
+    plain = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec).cpu().numpy()
+    if prec == "fp64":
+        assert _rel(got, ref) < 1e-10
+        assert _rel(got, plain) < 1e-13
+    else:
+        _, Dr = oracle.dos(ref, dt)
+        _, D = tbpm.dos(_dev(got), dt)
+        assert _l1(D.cpu().numpy(), Dr) < 1e-4
+        assert _rel(got, plain) < 1e-12
