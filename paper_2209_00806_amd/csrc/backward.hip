@@ -33,17 +33,21 @@ __device__ __forceinline__ double row_sum(double x, int log2s) {
 template <bool CH, int KIND>
 __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
     using HV = std::conditional_t<CH, d2, double>;
+    using GV = std::conditional_t<CH, d2, double>;
+    constexpr int KG = 4;
     const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
     const TileDesc td = p.tiles[tile];
     const int log2s = p.log2s;
-    const int64_t smask = (1 << log2s) - 1;
-    const int64_t n_el = (int64_t)td.rows << log2s;
-    const int64_t e0 = td.row0 << log2s;
+    const uint32_t smask = (1u << log2s) - 1u;
+    const uint32_t n_el = (uint32_t)td.rows << log2s;
+    const uint32_t row0 = (uint32_t)td.row0;
+    const uint32_t e0 = row0 << log2s;
     const d2 *__restrict__ acur = (const d2 *)p.a_cur;
     const d2 *__restrict__ bq = (const d2 *)p.bq;
     const int32_t *__restrict__ col = p.col;
     const HV *__restrict__ val = (const HV *)p.val;
     const uint32_t *__restrict__ soff = p.slice_off;
+    GV *gacc = (GV *)p.gacc;
     d2 bs, ccn, cc0;
     bs.x = p.bs_re;
     bs.y = p.bs_im;
@@ -54,46 +58,74 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
     const double gw = p.gw, inv_f = p.inv_f;
 
     // n_el is a multiple of S and every row's S elements sit in consecutive
-    // lanes of one wave, so all lanes of a row take the same trip count.
-    for (int64_t e = threadIdx.x; e < n_el; e += kWG) {
-        const int64_t row = td.row0 + (e >> log2s);
-        const int s = (int)(e & smask);
-        const int64_t g = e0 + e;
-        const int64_t sl = row / kSliceRows;
-        const int64_t off = soff[sl];
+    // lanes of one wave, so all lanes of a row take the same trip counts.
+    for (uint32_t e = threadIdx.x; e < n_el; e += kWG) {
+        const uint32_t row = row0 + (e >> log2s);
+        const uint32_t s = e & smask;
+        const uint32_t g = e0 + e;
+        const uint32_t sl = row / kSliceRows;
+        const uint32_t off = soff[sl];
         const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const int64_t base = off + (row % kSliceRows);
+        const uint32_t base = off + row % kSliceRows;
+        // every load that does not depend on a column index first
         const d2 a = acur[g];  // alpha_j at this row
+        const d2 bown = bq[g];
+        const double on = p.onsite[row];
+        d2 aprev, lacc, ph;
+        if constexpr (KIND != kAdjFirst) {
+            aprev = ((const d2 *)p.a_prev)[g];
+            lacc = ((const d2 *)p.lam_acc)[g];
+        }
+        if constexpr (KIND == kAdjFinal) ph = ((const d2 *)p.phi0)[g];
+        const double gd_old = p.gdiag[row];
         const d2 ga = a * gw;
         d2 acc;
-        acc.x = p.onsite[row] * a.x;
-        acc.y = p.onsite[row] * a.y;
+        acc.x = on * a.x;
+        acc.y = on * a.y;
         {
             // diagonal gradient: Re(alpha_j[p] conj(b[p])) summed over states
-            const d2 b = cmul(bs, bq[g]);
+            const d2 b = cmul(bs, bown);
             const double dg = row_sum(ga.x * b.x + ga.y * b.y, log2s);
-            if (s == 0) p.gdiag[row] += dg;
+            if (s == 0) p.gdiag[row] = gd_old + dg;
         }
-        for (int k = 0; k < w; ++k) {
-            const int64_t slot = base + (int64_t)k * kSliceRows;
-            const int c = col[slot];
-            const HV h = val[slot];
-            const int64_t gc = ((int64_t)c << log2s) + s;
-            acc = hmad(h, acur[gc], acc);
-            const d2 b = cmul(bs, bq[gc]);
-            // alpha_j[p] * conj(b[q])
-            const double gr = row_sum(ga.x * b.x + ga.y * b.y, log2s);
-            if constexpr (CH) {
-                const double gi = row_sum(ga.y * b.x - ga.x * b.y, log2s);
-                if (s == 0) {
-                    d2 *gp = (d2 *)p.gacc + slot;
-                    d2 old = *gp;
-                    old.x += gr;
-                    old.y += gi;
-                    *gp = old;
+        for (int k = 0; k < w; k += KG) {
+            uint32_t slot[KG], gc[KG];
+            HV h[KG];
+            bool valid[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                valid[i] = k + i < w;
+                slot[i] = valid[i] ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const int32_t c = col[slot[i]];
+                const HV hv = val[slot[i]];
+                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2s) + s;
+                h[i] = valid[i] ? hv : HV{};
+            }
+            d2 xa[KG], xb[KG];
+            GV gold[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                xa[i] = acur[gc[i]];
+                xb[i] = bq[gc[i]];
+                gold[i] = gacc[slot[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                acc = hmad(h[i], xa[i], acc);
+                const d2 b = cmul(bs, xb[i]);
+                // alpha_j[p] * conj(b[q]) summed over the states of the row
+                const double gr = row_sum(ga.x * b.x + ga.y * b.y, log2s);
+                if constexpr (CH) {
+                    const double gi = row_sum(ga.y * b.x - ga.x * b.y, log2s);
+                    if (s == 0 && valid[i]) {
+                        d2 nv = gold[i];
+                        nv.x += gr;
+                        nv.y += gi;
+                        gacc[slot[i]] = nv;
+                    }
+                } else {
+                    if (s == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
                 }
-            } else {
-                if (s == 0) ((double *)p.gacc)[slot] += gr;
             }
         }
         acc *= inv_f;  // (H~ alpha_j)[row]
@@ -101,16 +133,16 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
         if constexpr (KIND == kAdjFirst)
             an = acc;
         else
-            an = 2.0 * acc - ((const d2 *)p.a_prev)[g];
+            an = 2.0 * acc - aprev;
         d2 lam;
         if constexpr (KIND == kAdjFirst)
             lam = cmul(cc0, a) + cmul(ccn, an);
         else
-            lam = ((const d2 *)p.lam_acc)[g] + cmul(ccn, an);
+            lam = lacc + cmul(ccn, an);
         if constexpr (KIND == kAdjFinal) {
-            if (s < p.s_user) {
+            if ((int)s < p.s_user) {
                 const d2 gl = ((const d2 *)p.gcorr_l)[s];
-                lam += cmul(gl, ((const d2 *)p.phi0)[g]);
+                lam += cmul(gl, ph);
             }
         } else {
             ((d2 *)p.a_next)[g] = an;

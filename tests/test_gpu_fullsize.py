@@ -1,0 +1,111 @@
+"""GPU checks at the full sizes of the benchmark workloads, on outputs the
+oracle can compute one by one (sampled members/states, a prefix of steps)
+or through properties that hold at any size (finite differences, exact
+gradient identities)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_00806_amd import inputs, tbpm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+def test_differentiable_workload_full_size_fd():
+    """512x512 graphene with 786,432 bond parameters and 524,288 on-site
+    energies, 4 states; a 64-step prefix keeps the finite differences cheap.
+    Central FD of the GPU forward on 32 seeded bonds and along one random
+    direction of all bonds, and the shift identity for the on-site gradient."""
+    print("case differentiable 512x512 FD", flush=True)
+    from paper_2209_00806_amd import autograd as ag
+
+    lat, target_lat, psi0_np = inputs.workload_bond_graphene(512, 4)
+    f = 9.0
+    dt = math.pi / f
+    nt = 64
+    K = 16
+    psi0 = _dev(psi0_np)
+    Ht = tbpm.Hamiltonian.from_lattice(target_lat)
+    _, target = tbpm.dos(tbpm.propagate(Ht, psi0, nt, dt, f), dt)
+    Ht.close()
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    slot_ij = _dev(lat.slot_ij)
+    slot_ji = _dev(lat.slot_ji)
+    sel = torch.arange(0, 2 * nt, 8, device="cuda")
+
+    def loss(t_b, eps):
+        val = ag.bond_values(lat.nnz, slot_ij, slot_ji, t_b)
+        _, D = ag.tbpm_dos(H, val, eps, psi0, nt, dt, f, ckpt_every=K)
+        return torch.sum((D[sel] - target[sel]) ** 2)
+
+    t_p = _dev(lat.bond_t.copy()).requires_grad_(True)
+    e_p = torch.zeros(lat.n_orb, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = loss(t_p, e_p)
+    L.backward()
+    g = t_p.grad.detach().clone()
+    ge = e_p.grad.detach().clone()
+    gmax = float(g.abs().max())
+    assert gmax > 0
+    rng = np.random.default_rng(77)
+    h = 1e-4
+    with torch.no_grad():
+        for b in rng.choice(lat.bond_t.shape[0], 32, replace=False):
+            vals = []
+            for sgn in (1, -1):
+                tt = t_p.detach().clone()
+                tt[b] += sgn * h
+                vals.append(loss(tt, e_p.detach()).item())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[b].item()) < 1e-4 * gmax, (int(b), fd, g[b].item())
+        d = torch.from_numpy(rng.standard_normal(lat.bond_t.shape[0])).cuda()
+        d /= torch.linalg.norm(d)
+        hd = 1e-3
+        lp = loss(t_p.detach() + hd * d, e_p.detach()).item()
+        lm = loss(t_p.detach() - hd * d, e_p.detach()).item()
+        fd = (lp - lm) / (2 * hd)
+        an = float(torch.dot(g, d))
+        assert abs(fd - an) < 1e-4 * abs(an) + 1e-12, (fd, an)
+    # shift identity: adding d to every on-site energy multiplies C_k by e^{-i d k dt}
+    corr, ckpt = tbpm.propagate(H, psi0, nt, dt, f, ckpt_every=K)
+    gcorr = torch.from_numpy(np.random.default_rng(5).standard_normal((nt, 4))
+                             + 1j * np.random.default_rng(6).standard_normal((nt, 4))).cuda()
+    gval, gons = tbpm.backward(H, psi0, nt, dt, f, gcorr, K, ckpt)
+    k = torch.arange(nt, device="cuda", dtype=torch.float64)[:, None]
+    rhs = float(torch.real(torch.sum(torch.conj(gcorr) * (-1j * k * dt) * corr)))
+    assert abs(float(gons.sum()) - rhs) < 1e-8 * max(1.0, abs(rhs))
+    del ge
+
+
+def test_batch_workload_full_size_sampled():
+    """64 uneven members (square/graphene, 1e4..1e6 orbitals), 4 states, one
+    launch sequence: a 24-step prefix of sampled members/states against the
+    oracle, and norm conservation of every member."""
+    print("case batch 64 members", flush=True)
+    lats, states = inputs.workload_batch(64)
+    hams = [tbpm.Hamiltonian.from_lattice(l) for l in lats]
+    fs = [h.info()["gershgorin"] for h in hams]
+    dts = [math.pi / f for f in fs]
+    B = tbpm.Batch(hams)
+    nt = 24
+    corrs, norms = B.propagate([_dev(s) for s in states], nt, dts, fs, return_norm=True)
+    for n2 in norms:
+        assert float((n2 - 1).abs().max()) < 1e-10
+    order = np.argsort([l.n_orb for l in lats])
+    for i in (order[0], order[len(order) // 2], order[-1]):
+        s = int(i) % 4
+        l = lats[i]
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, states[i][:, s:s + 1].copy(), nt,
+                                     dts[i], fs[i])
+        assert _rel(corrs[i].cpu().numpy()[:, s], ref[:, 0]) < 1e-10, (int(i), l.n_orb)
