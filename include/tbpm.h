@@ -109,6 +109,25 @@ tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, 
                                         uint32_t flags, void *stream);
 
 /*
+ * Row order used on the device.  The library may renumber the orbitals
+ * internally so that rows coupled by H sit close together (recursive
+ * bisection of the graph of H: compact groups of rows, which the two-order
+ * launch shape needs for small halos); every array crossing this interface
+ * (states, checkpoints, values, gradients) stays in the caller's order.
+ *   order  -1: automatic (the default): renumber Hamiltonians of at least
+ *              16384 orbitals when it shrinks the rows a 128-row tile
+ *              references outside itself by 15% or more
+ *           0: keep the caller's order;  1: always renumber
+ * Setting it re-uploads H from the values last given on the host (at
+ * creation or by a host-pointer tbpm_hamiltonian_set_values) and drops
+ * cached launch state; the launch configurations are kept.  A batch takes
+ * the order of each member's handle at tbpm_batch_create.
+ * tbpm_hamiltonian_get_row_order reports the order in use (0 or 1).
+ */
+tbpm_status tbpm_hamiltonian_set_row_order(tbpm_hamiltonian *H, int32_t order);
+tbpm_status tbpm_hamiltonian_get_row_order(const tbpm_hamiltonian *H, int32_t *order);
+
+/*
  * Query H.  Any output pointer may be NULL.
  *   n_orb, nnz   sizes of the stored pattern (nnz after merging duplicates)
  *   gershgorin   max_i (|eps_i| + sum_j |H_ij|), an upper bound of ||H|| used
@@ -256,11 +275,22 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *   xcd_remap   1: give each of the 8 XCDs a contiguous range of tiles
  *   nontemporal 1: stream the read-once vectors with non-temporal hints
  *   unroll      elements each thread handles at once (1 or 2)
- *   vec         states of a row each thread holds (1, 2 or 4; capped by the
- *               padded state count)
  *   staged      1: each workgroup first copies the distinct rows of x that its
  *               tile reads into LDS and gathers from there (pays off for rows
  *               with many stored elements); wg_chunks and unroll are then unused
+ *   vec         states of a row each thread holds (1, 2 or 4; capped by the
+ *               padded state count)
+ *   fused       1, 2 or 3: evaluate two Clenshaw orders per launch: each tile
+ *               stages its rows and their two-hop neighbourhood in LDS and
+ *               computes the first order on its rows and their neighbours,
+ *               the second on its own rows.  The value is the LDS tier: a
+ *               tile uses at most 1/3, 1/4 or 1/5 of a CU's 160 KiB (bigger
+ *               tiles and smaller halos, or more resident workgroups).  Two
+ *               extra state-sized work vectors are allocated; staged and
+ *               wg_chunks are unused and unroll applies to the orders left
+ *               unpaired (the last one, and a middle one when their count is
+ *               odd).  Falls back to the plain shape when the series has
+ *               fewer than 4 terms or no tile fits.  0: one order per launch.
  */
 typedef struct {
     int32_t wg_chunks;
@@ -269,6 +299,7 @@ typedef struct {
     int32_t unroll;
     int32_t staged;
     int32_t vec;
+    int32_t fused;
 } tbpm_launch_config;
 
 /* Each handle keeps one launch configuration per precision. */

@@ -27,7 +27,8 @@ bool valid_cfg(const tbpm_launch_config &c) {
     const int ok[] = {1, 2, 4, 8, 16, 32};
     return std::find(std::begin(ok), std::end(ok), c.wg_chunks) != std::end(ok) && (c.xcd_remap == 0 || c.xcd_remap == 1) &&
            (c.nontemporal == 0 || c.nontemporal == 1) && (c.unroll == 1 || c.unroll == 2) &&
-           (c.staged == 0 || c.staged == 1) && (c.vec == 1 || c.vec == 2 || c.vec == 4);
+           (c.staged == 0 || c.staged == 1) && (c.vec == 1 || c.vec == 2 || c.vec == 4) &&
+           (c.fused >= 0 && c.fused <= 3);
 }
 
 double resolve_rescale(const HostCsr &h, double rescale) {
@@ -124,6 +125,31 @@ tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, 
     (void)hipFree(dons);
     if (e != hipSuccess) return hip_fail(e, "set_values");
     H->csr = std::move(copy);
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_hamiltonian_set_row_order(tbpm_hamiltonian *H, int32_t order) {
+    if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
+    if (order < -1 || order > 1) return fail(TBPM_E_ARG, "order must be -1, 0 or 1");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != H->eng.device) return fail(TBPM_E_ARG, "handle was created on another device");
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronize before re-upload");
+    H->eng.release();
+    H->eng.row_order = order;
+    const HostCsr *m = &H->csr;
+    try {
+        return H->eng.upload(&m, 1);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_hamiltonian_get_row_order(const tbpm_hamiltonian *H, int32_t *order) {
+    if (!H || !order) return fail(TBPM_E_ARG, "NULL argument");
+    *order = (!H->eng.member_perm.empty() && !H->eng.member_perm[0].empty()) ? 1 : 0;
     return TBPM_OK;
 }
 
@@ -252,16 +278,22 @@ tbpm_status tbpm_batch_create(tbpm_hamiltonian *const *Hs, int32_t n_ham, tbpm_b
     *out = nullptr;
     if (!Hs || n_ham < 1) return fail(TBPM_E_ARG, "need at least one Hamiltonian");
     std::vector<const HostCsr *> m(n_ham);
+    std::vector<const std::vector<int32_t> *> orders(n_ham);
     for (int32_t i = 0; i < n_ham; ++i) {
         if (!Hs[i]) return fail(TBPM_E_ARG, "NULL Hamiltonian in batch");
         m[i] = &Hs[i]->csr;
+        // each member keeps the row order of its own handle
+        orders[i] = Hs[i]->eng.member_perm.empty() ? nullptr : &Hs[i]->eng.member_perm[0];
     }
+    static const std::vector<int32_t> keep;
+    for (auto &o : orders)
+        if (!o) o = &keep;
     tbpm_batch *B = new (std::nothrow) tbpm_batch();
     if (!B) return fail(TBPM_E_OOM, "host allocation failed");
     B->members.assign(Hs, Hs + n_ham);
     tbpm_status st;
     try {
-        st = B->eng.upload(m.data(), n_ham);
+        st = B->eng.upload(m.data(), n_ham, orders.data());
     } catch (const std::bad_alloc &) {
         st = fail(TBPM_E_OOM, "host allocation failed");
     }

@@ -49,6 +49,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     eng.cfg = eng.cfgs[0];
     eng.cfg.staged = 0;  // the replay and the adjoint use plain tiles of single-state units
     eng.cfg.vec = 1;
+    eng.cfg.fused = 0;
     tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks, 1);
     if (s != TBPM_OK) return s;
     const int32_t n_tiles = (int32_t)eng.h_tiles.size();
@@ -89,7 +90,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     double *rot[3] = {lam, adj + 4 * n_el, adj + 6 * n_el};
     double *phi0p = (double *)eng.phi0.ptr;
 
-    TRY_HIP(launch_expand_states(psi0, s_user, phi0p, log2s, n_rows, st), "expand psi0");
+    TRY_HIP(launch_expand_states(psi0, eng.mat.perm, s_user, phi0p, log2s, n_rows, st), "expand psi0");
     TRY_HIP(launch_lam_init(lam, phi0p, gcorr + 2 * (size_t)(N - 1) * s_user, s_user, log2s, n_rows, st),
             "adjoint init");
     TRY_HIP(launch_fill_zero((double *)eng.bwd_gacc.ptr, (cplx ? 2 : 1) * eng.mat.ell_size, st), "zero gradient");
@@ -146,8 +147,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
         if (seg == 0)
             TRY_HIP(hipMemcpyAsync(psi_slot(0), phi0p, vb, hipMemcpyDeviceToDevice, st), "segment start");
         else
-            TRY_HIP(launch_expand_states(ckpt + 2 * (size_t)(seg - 1) * n_rows * s_user, s_user, psi_slot(0), log2s,
-                                         n_rows, st),
+            TRY_HIP(launch_expand_states(ckpt + 2 * (size_t)(seg - 1) * n_rows * s_user, eng.mat.perm, s_user,
+                                         psi_slot(0), log2s, n_rows, st),
                     "segment start");
         // forward replay, keeping b_1 .. b_{M-2} of every step
         for (int32_t t = 0; t < len; ++t) {
@@ -198,7 +199,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
         }
     }
     TRY_HIP(launch_grad_scatter(eng.bwd_gacc.ptr, (const double *)eng.bwd_gdiag.ptr, eng.mat.ell_csr,
-                                eng.mat.ell_size, cplx, 1.0 / f, grad_val, grad_onsite, n_rows, st),
+                                eng.mat.ell_size, cplx, 1.0 / f, grad_val, grad_onsite, eng.mat.perm, n_rows, st),
             "gradient scatter");
     TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
     TRY_HIP(hipGetLastError(), "kernel execution");

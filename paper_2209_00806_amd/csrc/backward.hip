@@ -151,11 +151,11 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_expand(const d2 *__restrict__ src, int s_user, d2 *__restrict__ dst,
-                                                int log2s, int64_t n_el) {
+__global__ __launch_bounds__(kWG) void k_expand(const d2 *__restrict__ src, const int32_t *__restrict__ perm,
+                                                int s_user, d2 *__restrict__ dst, int log2s, int64_t n_el) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < n_el; e += stride) {
-        const int64_t row = e >> log2s;
+        const int64_t row = perm ? (int64_t)perm[e >> log2s] : (e >> log2s);
         const int s = (int)(e & ((1 << log2s) - 1));
         d2 a;
         a.x = 0.0;
@@ -187,7 +187,8 @@ template <bool CH>
 __global__ __launch_bounds__(kWG) void k_grad_scatter(const void *__restrict__ gacc, const double *__restrict__ gdiag,
                                                       const int64_t *__restrict__ ell_csr, int64_t ell_size,
                                                       double inv_f, d2 *__restrict__ grad_val,
-                                                      double *__restrict__ grad_onsite, int64_t n_rows) {
+                                                      double *__restrict__ grad_onsite,
+                                                      const int32_t *__restrict__ perm, int64_t n_rows) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < ell_size; q += stride) {
         const int64_t pos = ell_csr[q];
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(kWG) void k_grad_scatter(const void *__restrict__ g
         }
         grad_val[pos] = v;
     }
-    for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < n_rows; r += stride) grad_onsite[r] = gdiag[r] * inv_f;
+    for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < n_rows; r += stride)
+        grad_onsite[perm ? perm[r] : r] = gdiag[r] * inv_f;
 }
 
 int64_t grid_for(int64_t n) {
@@ -235,11 +237,11 @@ hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_expand_states(const double *src, int32_t s_user, double *dst, int32_t log2s, int64_t n_rows,
-                                hipStream_t st) {
+hipError_t launch_expand_states(const double *src, const int32_t *perm, int32_t s_user, double *dst, int32_t log2s,
+                                int64_t n_rows, hipStream_t st) {
     const int64_t n_el = n_rows << log2s;
-    hipLaunchKernelGGL(k_expand, dim3((unsigned)grid_for(n_el)), dim3(kWG), 0, st, (const d2 *)src, s_user, (d2 *)dst,
-                       log2s, n_el);
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)grid_for(n_el)), dim3(kWG), 0, st, (const d2 *)src, perm, s_user,
+                       (d2 *)dst, log2s, n_el);
     return hipGetLastError();
 }
 
@@ -257,15 +259,15 @@ hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_grad_scatter(const void *gacc, const double *gdiag, const int64_t *ell_csr, int64_t ell_size,
-                               bool cplx, double inv_f, double *grad_val, double *grad_onsite, int64_t n_rows,
-                               hipStream_t st) {
+                               bool cplx, double inv_f, double *grad_val, double *grad_onsite, const int32_t *perm,
+                               int64_t n_rows, hipStream_t st) {
     const int64_t work = ell_size > n_rows ? ell_size : n_rows;
     if (cplx)
         hipLaunchKernelGGL(k_grad_scatter<true>, dim3((unsigned)grid_for(work)), dim3(kWG), 0, st, gacc, gdiag, ell_csr,
-                           ell_size, inv_f, (d2 *)grad_val, grad_onsite, n_rows);
+                           ell_size, inv_f, (d2 *)grad_val, grad_onsite, perm, n_rows);
     else
         hipLaunchKernelGGL(k_grad_scatter<false>, dim3((unsigned)grid_for(work)), dim3(kWG), 0, st, gacc, gdiag,
-                           ell_csr, ell_size, inv_f, (d2 *)grad_val, grad_onsite, n_rows);
+                           ell_csr, ell_size, inv_f, (d2 *)grad_val, grad_onsite, perm, n_rows);
     return hipGetLastError();
 }
 

@@ -105,5 +105,74 @@ __device__ __forceinline__ void block_state_partials(double dre, double dim, dou
     }
 }
 
+template <typename R, int VS>
+using VecT = R __attribute__((ext_vector_type(2 * VS)));
+
+template <typename R, bool CH>
+struct HValT {
+    using T = R;
+};
+template <typename R>
+struct HValT<R, true> {
+    using T = typename CxT<R>::T;
+};
+
+// acc_i += h * x_i for the VS complex components of a unit
+template <typename R, int VS>
+__device__ __forceinline__ void unit_mad_real(R h, VecT<R, VS> x, VecT<R, VS> &acc) {
+#pragma unroll
+    for (int i = 0; i < 2 * VS; ++i) acc[i] = fma(h, x[i], acc[i]);
+}
+template <typename R, int VS, typename C>
+__device__ __forceinline__ void unit_mad_cplx(C h, VecT<R, VS> x, VecT<R, VS> &acc) {
+#pragma unroll
+    for (int i = 0; i < VS; ++i) {
+        acc[2 * i] = fma(h.x, x[2 * i], acc[2 * i]);
+        acc[2 * i] = fma(-h.y, x[2 * i + 1], acc[2 * i]);
+        acc[2 * i + 1] = fma(h.x, x[2 * i + 1], acc[2 * i + 1]);
+        acc[2 * i + 1] = fma(h.y, x[2 * i], acc[2 * i + 1]);
+    }
+}
+
+// Per-state partial sums for units of VS states: lane l holds states
+// (l & (U-1))*VS + i, U = units per row.
+template <int VS>
+__device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
+                                                    const double (&nrm)[VS], int log2u,
+                                                    double *__restrict__ out, int tile, int n_tiles) {
+    __shared__ double red[kWG / 64][64][3];
+    const int U = 1 << log2u;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < VS; ++i) {
+        double a = dre[i], b = dim[i], c = nrm[i];
+        for (int off = 32; off >= U; off >>= 1) {
+            a += __shfl_xor(a, off);
+            b += __shfl_xor(b, off);
+            c += __shfl_xor(c, off);
+        }
+        if (lane < U) {
+            red[wave][lane * VS + i][0] = a;
+            red[wave][lane * VS + i][1] = b;
+            red[wave][lane * VS + i][2] = c;
+        }
+    }
+    __syncthreads();
+    const int S = U * VS;
+    if ((int)threadIdx.x < S) {
+        double a = 0, b = 0, c = 0;
+#pragma unroll
+        for (int w = 0; w < kWG / 64; ++w) {
+            a += red[w][threadIdx.x][0];
+            b += red[w][threadIdx.x][1];
+            c += red[w][threadIdx.x][2];
+        }
+        const int64_t o = (int64_t)threadIdx.x * 3 * n_tiles + tile;
+        out[o] = a;
+        out[o + n_tiles] = b;
+        out[o + 2 * (int64_t)n_tiles] = c;
+    }
+}
+
 }  // namespace
 }  // namespace tbpm

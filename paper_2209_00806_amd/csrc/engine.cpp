@@ -76,10 +76,10 @@ void PinnedBuf::release() {
 bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
-        ckpt_every != o.ckpt_every ||
+        fused != o.fused || ckpt_every != o.ckpt_every ||
         ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
         return false;
-    for (int i = 0; i < 8; ++i)
+    for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         if (bufs[i] != o.bufs[i]) return false;
     return true;
 }
@@ -93,7 +93,49 @@ bool GraphKey::operator==(const GraphKey &o) const {
 // ---------------------------------------------------------------------------
 // upload of one or several merged CSR matrices as one block-diagonal operator
 // ---------------------------------------------------------------------------
-tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
+// Sum over tiles of 128 consecutive rows of the distinct rows outside the tile
+// that its rows reference: the 1-hop halo a tile of the fused shape stages.
+static double halo_cost(const HostCsr &h, const std::vector<int32_t> &perm, const std::vector<int32_t> &inv) {
+    const int64_t T = 128;
+    double cost = 0;
+    std::vector<int32_t> ext;
+    for (int64_t t0 = 0; t0 < h.n; t0 += T) {
+        const int64_t t1 = std::min<int64_t>(h.n, t0 + T);
+        ext.clear();
+        for (int64_t r = t0; r < t1; ++r) {
+            const int64_t src = perm.empty() ? r : perm[r];
+            for (int64_t p = h.row_ptr[src]; p < h.row_ptr[src + 1]; ++p) {
+                const int32_t c = perm.empty() ? h.col[p] : inv[h.col[p]];
+                if (c < t0 || c >= t1) ext.push_back(c);
+            }
+        }
+        std::sort(ext.begin(), ext.end());
+        cost += (double)(std::unique(ext.begin(), ext.end()) - ext.begin());
+    }
+    return cost;
+}
+
+// Row order of one member: empty = the caller's order.  mode 0 keeps it,
+// 1 takes the bisection order, -1 takes the bisection order for members of
+// at least kReorderMinRows rows when it cuts the halo cost by 15% or more.
+static std::vector<int32_t> member_order(const HostCsr &h, int32_t mode) {
+    constexpr int64_t kReorderMinRows = 16384;
+    if (mode == 0 || h.n < 2 || (mode < 0 && h.n < kReorderMinRows)) return {};
+    std::vector<int32_t> perm = bisection_order(h.n, h.row_ptr.data(), h.col.data(), 32);
+    if (mode < 0) {
+        std::vector<int32_t> inv(h.n);
+        for (int64_t i = 0; i < h.n; ++i) inv[perm[i]] = (int32_t)i;
+        if (halo_cost(h, perm, inv) > 0.85 * halo_cost(h, {}, {})) return {};
+    }
+    return perm;
+}
+
+// ---------------------------------------------------------------------------
+// upload of one or several merged CSR matrices as one block-diagonal operator
+// (each member's rows in its chosen order; values, on-site energies, states
+// and gradients are mapped to and from the caller's order)
+// ---------------------------------------------------------------------------
+tbpm_status Engine::upload(const HostCsr *const *members, int32_t n, const std::vector<int32_t> *const *orders) {
     int dev = 0;
     TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
     device = dev;
@@ -107,24 +149,50 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
     }
     const int64_t N = inst_row0[n];
     if (N >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "total number of orbitals must be < 2^31");
+    member_perm.assign(n, {});
+    bool any_perm = false;
+    for (int32_t i = 0; i < n; ++i) {
+        member_perm[i] = orders ? *orders[i] : member_order(*members[i], row_order);
+        any_perm = any_perm || !member_perm[i].empty();
+    }
+    // merged CSR in the internal order; src_pos = position in the caller's merged CSR
     std::vector<int64_t> rp(N + 1, 0);
     std::vector<int32_t> col;
     col.reserve(nnz_total);
     std::vector<double> val;
     val.reserve(2 * nnz_total);
+    std::vector<int64_t> src_pos;
+    src_pos.reserve(nnz_total);
     std::vector<double> ons(N);
+    std::vector<int32_t> perm_all(any_perm ? N : 0);
+    int64_t base = 0;
+    std::vector<int32_t> inv;
+    std::vector<std::pair<int32_t, int64_t>> row;
     for (int32_t i = 0; i < n; ++i) {
         const HostCsr &h = *members[i];
+        const std::vector<int32_t> &pm = member_perm[i];
         const int64_t r0 = inst_row0[i];
+        if (!pm.empty()) {
+            inv.assign(h.n, 0);
+            for (int64_t k = 0; k < h.n; ++k) inv[pm[k]] = (int32_t)k;
+        }
         for (int64_t r = 0; r < h.n; ++r) {
-            for (int64_t p = h.row_ptr[r]; p < h.row_ptr[r + 1]; ++p) {
-                col.push_back((int32_t)(h.col[p] + r0));
+            const int64_t src = pm.empty() ? r : pm[r];
+            row.clear();
+            for (int64_t p = h.row_ptr[src]; p < h.row_ptr[src + 1]; ++p)
+                row.push_back({pm.empty() ? h.col[p] : inv[h.col[p]], p});
+            if (!pm.empty()) std::sort(row.begin(), row.end());
+            for (const auto &[c, p] : row) {
+                col.push_back((int32_t)(c + r0));
                 val.push_back(h.val[2 * p]);
                 val.push_back(h.val[2 * p + 1]);
+                src_pos.push_back(base + p);
             }
             rp[r0 + r + 1] = (int64_t)col.size();
-            ons[r0 + r] = h.onsite[r];
+            ons[r0 + r] = h.onsite[src];
+            if (any_perm) perm_all[r0 + r] = (int32_t)src;
         }
+        base += h.nnz();
     }
     HostEll e = build_sliced_ell(N, rp.data(), col.data());
     const int64_t S = (int64_t)e.col.size();
@@ -135,6 +203,8 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
     for (int64_t q = 0; q < S; ++q) {
         const int64_t p = e.csr_pos[q];
         if (p < 0) continue;
+        const int64_t p_src = src_pos[p];
+        e.csr_pos[q] = p_src;
         if (cplx) {
             v64[2 * q] = val[2 * p];
             v64[2 * q + 1] = val[2 * p + 1];
@@ -172,6 +242,10 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n) {
     }
     TRY_HIP(hipMemcpy(mat.onsite64, ons.data(), sizeof(double) * N, hipMemcpyHostToDevice), "upload onsite");
     TRY_HIP(hipMemcpy(mat.onsite32, ons32.data(), sizeof(float) * N, hipMemcpyHostToDevice), "upload onsite32");
+    if (any_perm) {
+        TRY_HIP(hipMalloc(&mat.perm, sizeof(int32_t) * N), "hipMalloc perm");
+        TRY_HIP(hipMemcpy(mat.perm, perm_all.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice), "upload perm");
+    }
     TRY_HIP(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking), "hipStreamCreate");
     TRY_HIP(hipEventCreateWithFlags(&staging_done, hipEventDisableTiming), "hipEventCreate");
     return TBPM_OK;
@@ -183,13 +257,14 @@ void Engine::release() {
         (void)hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
     }
-    void *ptrs[] = {mat.slice_off, mat.col, mat.val64, mat.val32, mat.onsite64, mat.onsite32, mat.ell_csr};
+    void *ptrs[] = {mat.slice_off, mat.col, mat.val64, mat.val32, mat.onsite64, mat.onsite32, mat.ell_csr, mat.perm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     mat = DevMatrix{};
     DevBuf *bufs[] = {&v,        &ba,        &bb,      &phi0,      &partials,  &counter,  &coef,
                       &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
-                      &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx};
+                      &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx, &fu_n1, &fu_hoff,
+                      &fu_hw,    &fu_hidx,  &bc,       &bd};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -325,6 +400,46 @@ tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t uni
     return TBPM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// two-hop tiles for the fused launch shape (tables built on the host by
+// two_hop_tables, then uploaded)
+// ---------------------------------------------------------------------------
+tbpm_status Engine::build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier) {
+    const int32_t key = unit_bytes * 64 + log2u + (tier << 20);
+    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) return TBPM_OK;
+    TwoHopTables t;
+    if (!two_hop_tables(h_slice_off, h_col, inst_row0, log2u, unit_bytes, fused_lds_budget(tier), t))
+        return fail(TBPM_E_ARG, "no two-hop tile fits the LDS budget");
+    h_tiles = t.tiles;
+    h_inst_tile0 = t.inst_tile0;
+    const size_t nt = h_tiles.size();
+    TRY_HIP(hipDeviceSynchronize(), "sync before tile rebuild");
+    TRY_HIP(tiles.ensure(sizeof(TileDesc) * nt), "alloc tiles");
+    TRY_HIP(inst_tile0.ensure(sizeof(int32_t) * h_inst_tile0.size()), "alloc inst_tile0");
+    TRY_HIP(st_uoff.ensure(sizeof(int32_t) * t.uoff.size()), "alloc two-hop offsets");
+    TRY_HIP(st_ucol.ensure(sizeof(int32_t) * std::max<size_t>(t.ucol.size(), 1)), "alloc two-hop rows");
+    TRY_HIP(st_lidx.ensure(sizeof(uint16_t) * t.lidx.size()), "alloc two-hop indices");
+    TRY_HIP(fu_n1.ensure(sizeof(int32_t) * nt), "alloc two-hop counts");
+    TRY_HIP(fu_hoff.ensure(sizeof(int32_t) * nt), "alloc two-hop offsets");
+    TRY_HIP(fu_hw.ensure(sizeof(int32_t) * nt), "alloc two-hop widths");
+    TRY_HIP(fu_hidx.ensure(sizeof(uint16_t) * t.hidx.size()), "alloc two-hop halo indices");
+    auto up = [](DevBuf &d, const void *src, size_t bytes) { return hipMemcpy(d.ptr, src, bytes, hipMemcpyHostToDevice); };
+    TRY_HIP(up(tiles, h_tiles.data(), sizeof(TileDesc) * nt), "upload tiles");
+    TRY_HIP(up(inst_tile0, h_inst_tile0.data(), sizeof(int32_t) * h_inst_tile0.size()), "upload inst_tile0");
+    TRY_HIP(up(st_uoff, t.uoff.data(), sizeof(int32_t) * t.uoff.size()), "upload two-hop offsets");
+    if (!t.ucol.empty()) TRY_HIP(up(st_ucol, t.ucol.data(), sizeof(int32_t) * t.ucol.size()), "upload two-hop rows");
+    TRY_HIP(up(st_lidx, t.lidx.data(), sizeof(uint16_t) * t.lidx.size()), "upload two-hop indices");
+    TRY_HIP(up(fu_n1, t.n1.data(), sizeof(int32_t) * nt), "upload two-hop counts");
+    TRY_HIP(up(fu_hoff, t.hoff.data(), sizeof(int32_t) * nt), "upload two-hop offsets");
+    TRY_HIP(up(fu_hw, t.hw.data(), sizeof(int32_t) * nt), "upload two-hop widths");
+    TRY_HIP(up(fu_hidx, t.hidx.data(), sizeof(uint16_t) * t.hidx.size()), "upload two-hop halo indices");
+    fu_lds_units = (int32_t)(t.max_xy << log2u);
+    tiles_s = s_pad;
+    tiles_chunks = -(int32_t)t.R;
+    tiles_unit = key;
+    return TBPM_OK;
+}
+
 static PassCoef make_coef(cd a, cd b) { return PassCoef{a.real(), a.imag(), b.real(), b.imag()}; }
 
 // The Clenshaw schedule of one step for per-member coefficient sets c[i][m]
@@ -407,10 +522,12 @@ tbpm_status Engine::run(const RunArgs &a) {
     const int32_t vs = std::min(cfg.vec, s_pad);
     const int32_t log2u = log2s - (vs == 4 ? 2 : (vs == 2 ? 1 : 0));
     const int32_t unit_bytes = (int32_t)esize * vs;
-    bool staged = cfg.staged != 0;
+    bool fused = cfg.fused != 0 && mmax >= 4;
+    bool staged = cfg.staged != 0 && !fused;
     tbpm_status st = TBPM_OK;
-    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes) != TBPM_OK) staged = false;  // fall back
-    if (!staged) st = build_tiles(s_pad, chunks, vs);
+    if (fused && build_fused_tiles(s_pad, log2u, unit_bytes, cfg.fused) != TBPM_OK) fused = false;  // fall back
+    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes) != TBPM_OK) staged = false;
+    if (!staged && !fused) st = build_tiles(s_pad, chunks, vs);
     if (st != TBPM_OK) return st;
     const int32_t n_tiles = (int32_t)h_tiles.size();
     const int64_t n_el = mat.n_rows * s_pad;
@@ -419,6 +536,10 @@ tbpm_status Engine::run(const RunArgs &a) {
     TRY_HIP(v.ensure(esize * n_el), "alloc v");
     TRY_HIP(ba.ensure(esize * n_el), "alloc A");
     TRY_HIP(bb.ensure(esize * n_el), "alloc B");
+    if (fused) {
+        TRY_HIP(bc.ensure(esize * n_el), "alloc C");
+        TRY_HIP(bd.ensure(esize * n_el), "alloc D");
+    }
     TRY_HIP(phi0.ensure(16 * n_el), "alloc phi0");
     TRY_HIP(partials.ensure(sizeof(double) * 3 * (size_t)n_tiles * s_pad), "alloc partials");
     TRY_HIP(counter.ensure(sizeof(int32_t) * 64), "alloc counter");
@@ -452,7 +573,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             "upload row offsets");
     TRY_HIP(hipEventRecord(staging_done, a.stream), "record staging");
 
-    void *bufptr[3] = {v.ptr, ba.ptr, bb.ptr};
+    void *bufptr[5] = {v.ptr, ba.ptr, bb.ptr, bc.ptr, bd.ptr};
     const double *const *d_psi0 = (const double *const *)ptr_tab.ptr;
     double *const *d_corr = (double *const *)ptr_tab.ptr + ni;
     double *const *d_norm2 = (double *const *)ptr_tab.ptr + 2 * ni;
@@ -469,6 +590,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     ip.phi0 = (double *)phi0.ptr;
     ip.partials = (double *)partials.ptr;
     ip.counter = (int32_t *)counter.ptr;
+    ip.perm = mat.perm;
     TRY_HIP(launch_init(fp32, ip, a.stream), "launch init");
     ReduceParams rp{};
     rp.partials = (const double *)partials.ptr;
@@ -483,8 +605,102 @@ tbpm_status Engine::run(const RunArgs &a) {
     rp.norm2_all = (double *)norm2_all.ptr;
     TRY_HIP(launch_reduce(ni, s_pad, rp, a.stream), "launch reduce");
 
+    // Fused schedule: FIRST and NOB2 as one pair (psi -> A, B), then MID
+    // orders in pairs alternating between (A, B) and (C, D), since a pair
+    // reads its inputs on rows other tiles write; a leftover MID runs alone
+    // (in place), and LAST alone.  Entries: {plan index, kind, x, b2, out1, out2}
+    // with kind < 0 for an unpaired pass.
+    struct Launch {
+        int p, kind, x, b2, o1, o2;
+    };
+    std::vector<Launch> sched;
+    if (fused) {
+        // plan: 0 FIRST, 1 NOB2, 2 .. n_passes-2 MID, n_passes-1 LAST
+        sched.push_back({0, kPairFirst, 0, -1, 1, 2});
+        int cur = 2;  // buffer of b_{j+1} (2 or 4); b_{j+2} is in buffer cur - 1
+        int p = 2;
+        for (; p + 1 <= n_passes - 2; p += 2) {
+            const int o1 = (cur <= 2) ? 3 : 1;
+            sched.push_back({p, kPairMid, cur, cur - 1, o1, o1 + 1});
+            cur = o1 + 1;
+        }
+        for (; p < n_passes; ++p) sched.push_back({p, -1, -1, -1, -1, -1});
+    }
+
     // one time step
     auto enqueue_step = [&](hipStream_t s) -> tbpm_status {
+        if (fused) {
+            int cur = 2, prev = 1;
+            for (size_t q = 0; q < sched.size(); ++q) {
+                const Launch &l = sched[q];
+                if (l.kind >= 0) {
+                    FusedParams fp{};
+                    fp.tiles = (const TileDesc *)tiles.ptr;
+                    fp.n_tiles = n_tiles;
+                    fp.xcd_remap = cfg.xcd_remap;
+                    fp.log2s = log2s;
+                    fp.bump_counter = (q == 0);
+                    fp.col = mat.col;
+                    fp.val = fp32 ? mat.val32 : mat.val64;
+                    fp.slice_off = mat.slice_off;
+                    fp.onsite = fp32 ? (const void *)mat.onsite32 : (const void *)mat.onsite64;
+                    fp.x = bufptr[l.x];
+                    fp.v = bufptr[0];
+                    fp.b2 = l.b2 >= 0 ? bufptr[l.b2] : nullptr;
+                    fp.out1 = bufptr[l.o1];
+                    fp.out2 = bufptr[l.o2];
+                    fp.coef1 = (const PassCoef *)coef.ptr + (size_t)l.p * ni;
+                    fp.coef2 = (const PassCoef *)coef.ptr + (size_t)(l.p + 1) * ni;
+                    fp.counter = (int32_t *)counter.ptr;
+                    fp.uoff = (const int32_t *)st_uoff.ptr;
+                    fp.n1 = (const int32_t *)fu_n1.ptr;
+                    fp.ucol = (const int32_t *)st_ucol.ptr;
+                    fp.lidx = (const uint16_t *)st_lidx.ptr;
+                    fp.hoff = (const int32_t *)fu_hoff.ptr;
+                    fp.hw = (const int32_t *)fu_hw.ptr;
+                    fp.hidx = (const uint16_t *)fu_hidx.ptr;
+                    fp.lds_units = fu_lds_units;
+                    hipError_t e = launch_pair(l.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, fp, s);
+                    if (e != hipSuccess) return hip_fail(e, "launch pair");
+                    prev = l.o1;
+                    cur = l.o2;
+                    continue;
+                }
+                const PassPlan &pl = plan[l.p];
+                PassParams pp{};
+                pp.tiles = (const TileDesc *)tiles.ptr;
+                pp.n_tiles = n_tiles;
+                pp.xcd_remap = cfg.xcd_remap;
+                pp.log2s = log2s;
+                pp.bump_counter = 0;
+                pp.col = mat.col;
+                pp.val = fp32 ? mat.val32 : mat.val64;
+                pp.slice_off = mat.slice_off;
+                pp.onsite = fp32 ? (const void *)mat.onsite32 : (const void *)mat.onsite64;
+                pp.x = bufptr[cur];
+                pp.v = bufptr[0];
+                pp.b2 = bufptr[prev];
+                pp.out = pl.kind == kPassLast ? bufptr[0] : bufptr[prev];
+                pp.coef = (const PassCoef *)coef.ptr + (size_t)l.p * ni;
+                pp.counter = (int32_t *)counter.ptr;
+                pp.phi0 = (const double *)phi0.ptr;
+                pp.phi0_ld = s_pad;
+                pp.partials = (double *)partials.ptr;
+                pp.ckpt = a.ckpt;
+                pp.perm = mat.perm;
+                pp.ckpt_stride = mat.n_rows * a.s_user;
+                pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
+                pp.ckpt_max = a.n_steps - 2;
+                pp.s_user = a.s_user;
+                hipError_t e =
+                    launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs, pp, s);
+                if (e != hipSuccess) return hip_fail(e, "launch pass");
+                if (pl.kind == kPassMid) std::swap(cur, prev);
+            }
+            hipError_t e = launch_reduce(ni, s_pad, rp, s);
+            if (e != hipSuccess) return hip_fail(e, "launch reduce");
+            return TBPM_OK;
+        }
         for (int p = 0; p < n_passes; ++p) {
             const PassPlan &pl = plan[p];
             PassParams pp{};
@@ -507,6 +723,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.phi0_ld = s_pad;
             pp.partials = (double *)partials.ptr;
             pp.ckpt = a.ckpt;
+            pp.perm = mat.perm;
             pp.ckpt_stride = mat.n_rows * a.s_user;
             pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             pp.ckpt_max = a.n_steps - 2;
@@ -544,11 +761,15 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.unroll = cfg.unroll;
             key.staged = staged ? 1 : 0;
             key.vec = vs;
+            key.fused = fused ? 1 : 0;
             key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             key.ckpt_max = a.n_steps - 2;
             key.n_steps = a.n_steps;
             key.ckpt = a.ckpt;
-            const void *kb[8] = {v.ptr, ba.ptr, bb.ptr, phi0.ptr, partials.ptr, coef.ptr, tiles.ptr, norm2_all.ptr};
+            const void *kb[14] = {v.ptr,         ba.ptr,     bb.ptr,      phi0.ptr,    partials.ptr,
+                                  coef.ptr,      tiles.ptr,  norm2_all.ptr, bc.ptr,    bd.ptr,
+                                  st_uoff.ptr,   st_ucol.ptr, st_lidx.ptr,  fu_hidx.ptr};
+            static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
             if (!graph_exec || !(key == graph_key)) {
                 if (graph_exec) {
@@ -579,7 +800,7 @@ tbpm_status Engine::run(const RunArgs &a) {
 
     last_s_pad = s_pad;
     last_fp32 = fp32 ? 1 : 0;
-    last_staged = staged ? 1 : 0;
+    last_staged = fused ? 2 : (staged ? 1 : 0);
     last_vs = vs;
     if (a.flags & TBPM_FLAG_ASYNC) return TBPM_OK;
     TRY_HIP(hipStreamSynchronize(a.stream), "stream synchronize");
@@ -637,6 +858,39 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.ucol = (const int32_t *)st_ucol.ptr;
     pp.lidx = (const uint16_t *)st_lidx.ptr;
     pp.stage_units = stage_units;
+    if (last_staged == 2) {
+        // the interior launch of the fused shape: a MID pair (b_{j+1} in B,
+        // b_{j+2} in A, outputs to C and D)
+        FusedParams fp{};
+        fp.tiles = pp.tiles;
+        fp.n_tiles = pp.n_tiles;
+        fp.xcd_remap = cfg.xcd_remap;
+        fp.log2s = log2s;
+        fp.col = mat.col;
+        fp.val = pp.val;
+        fp.slice_off = mat.slice_off;
+        fp.onsite = pp.onsite;
+        fp.x = bb.ptr;
+        fp.v = v.ptr;
+        fp.b2 = ba.ptr;
+        fp.out1 = bc.ptr;
+        fp.out2 = bd.ptr;
+        fp.coef1 = fp.coef2 = pp.coef;
+        fp.counter = pp.counter;
+        fp.uoff = pp.uoff;
+        fp.n1 = (const int32_t *)fu_n1.ptr;
+        fp.ucol = pp.ucol;
+        fp.lidx = pp.lidx;
+        fp.hoff = (const int32_t *)fu_hoff.ptr;
+        fp.hw = (const int32_t *)fu_hw.ptr;
+        fp.hidx = (const uint16_t *)fu_hidx.ptr;
+        fp.lds_units = fu_lds_units;
+        for (int32_t i = 0; i < n_launch; ++i) {
+            hipError_t e = launch_pair(kPairMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, fp, stream);
+            if (e != hipSuccess) return hip_fail(e, "launch pair");
+        }
+        return TBPM_OK;
+    }
     for (int32_t i = 0; i < n_launch; ++i) {
         hipError_t e = last_staged
                            ? launch_pass_staged(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, pp, stream)

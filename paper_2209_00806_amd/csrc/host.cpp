@@ -231,4 +231,222 @@ tbpm_status check_values(HostCsr &h, double &hmax) {
     return TBPM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// two-hop tile tables (fused launch shape)
+// ---------------------------------------------------------------------------
+bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int32_t> &col,
+                    const std::vector<int64_t> &inst_row0, int32_t log2u, int32_t unit_bytes, size_t budget,
+                    TwoHopTables &t) {
+    const int64_t SR = kSliceRows;
+    const int32_t n_inst = (int32_t)inst_row0.size() - 1;
+    std::vector<int32_t> e1, e2;
+    auto width = [&](int64_t r) { return (slice_off[r / SR + 1] - slice_off[r / SR]) / SR; };
+    auto slot_of = [&](int64_t r, int64_t k) { return slice_off[r / SR] + k * SR + r % SR; };
+    auto outside = [](int32_t c, int64_t r0, int64_t rows) { return c < r0 || c >= r0 + rows; };
+    auto collect = [&](int64_t r0, int64_t rows) {
+        e1.clear();
+        e2.clear();
+        for (int64_t r = r0; r < r0 + rows; ++r)
+            for (int64_t k = 0, w = width(r); k < w; ++k) {
+                const int32_t c = col[slot_of(r, k)];
+                if (outside(c, r0, rows)) e1.push_back(c);
+            }
+        std::sort(e1.begin(), e1.end());
+        e1.erase(std::unique(e1.begin(), e1.end()), e1.end());
+        for (int32_t h : e1)
+            for (int64_t k = 0, w = width(h); k < w; ++k) {
+                const int32_t c = col[slot_of(h, k)];
+                if (outside(c, r0, rows) && !std::binary_search(e1.begin(), e1.end(), c)) e2.push_back(c);
+            }
+        std::sort(e2.begin(), e2.end());
+        e2.erase(std::unique(e2.begin(), e2.end()), e2.end());
+    };
+    // a tile fits if both staged arrays fit the budget (local indices are 16-bit)
+    auto fits = [&](int64_t rows) {
+        const size_t x = (size_t)rows + e1.size() + e2.size(), y = (size_t)rows + e1.size();
+        return ((x + y) << log2u) * (size_t)unit_bytes <= budget && x <= 65535;
+    };
+    // tiles of R rows, halved until they fit; visit(r0, rows) for each
+    auto tiling = [&](int64_t R, auto &&visit) {
+        std::vector<std::pair<int64_t, int64_t>> st;
+        for (int32_t i = 0; i < n_inst; ++i)
+            for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += R) {
+                st.push_back({r0, std::min<int64_t>(R, inst_row0[i + 1] - r0)});
+                while (!st.empty()) {
+                    const auto [a, rows] = st.back();
+                    st.pop_back();
+                    collect(a, rows);
+                    if (!fits(rows)) {
+                        if (rows == 1) return false;
+                        st.push_back({a + rows / 2, rows - rows / 2});
+                        st.push_back({a, rows / 2});
+                        continue;
+                    }
+                    visit(i, a, rows);
+                }
+            }
+        return true;
+    };
+    // R: the target tile size with the least staged traffic per pair of orders
+    // (x on own + 1-hop + 2-hop rows, psi and b_{j+2} on own + 1-hop rows, two
+    // outputs on own rows); ties go to the larger R
+    t.R = 0;
+    double best = 0;
+    for (int64_t cand : {256, 128, 64, 32, 16, 8, 4, 2, 1}) {
+        double cost = 0;
+        const bool ok = tiling(cand, [&](int32_t, int64_t, int64_t rows) {
+            cost += (double)(rows + e1.size() + e2.size()) + 2.0 * (double)(rows + e1.size()) + 2.0 * (double)rows;
+        });
+        if (ok && (t.R == 0 || cost < best * (1 - 1e-9))) {
+            t.R = cand;
+            best = cost;
+        }
+        if (t.R != 0 && t.R >= 4 * cand) break;  // smaller targets only split more
+    }
+    if (t.R == 0) return false;
+    t.tiles.clear();
+    t.inst_tile0.assign(n_inst + 1, 0);
+    t.uoff.assign(1, 0);
+    t.ucol.clear();
+    t.n1.clear();
+    t.hoff.clear();
+    t.hw.clear();
+    t.hidx.clear();
+    t.max_x = t.max_y = t.max_xy = 0;
+    t.lidx.assign(std::max<size_t>(col.size(), 1), 0);
+    tiling(t.R, [&](int32_t i, int64_t r0, int64_t rows) {
+        const int64_t n1 = (int64_t)e1.size();
+        t.max_x = std::max(t.max_x, (size_t)(rows + n1) + e2.size());
+        t.max_y = std::max(t.max_y, (size_t)(rows + n1));
+        t.max_xy = std::max(t.max_xy, (size_t)(2 * (rows + n1)) + e2.size());
+        // local row numbering: own rows, then the 1-hop rows, then the 2-hop rows
+        auto local = [&](int32_t c) -> uint16_t {
+            if (!outside(c, r0, rows)) return (uint16_t)(c - r0);
+            auto it = std::lower_bound(e1.begin(), e1.end(), c);
+            if (it != e1.end() && *it == c) return (uint16_t)(rows + (it - e1.begin()));
+            return (uint16_t)(rows + n1 + (std::lower_bound(e2.begin(), e2.end(), c) - e2.begin()));
+        };
+        for (int64_t r = r0; r < r0 + rows; ++r)
+            for (int64_t k = 0, w = width(r); k < w; ++k) t.lidx[slot_of(r, k)] = local(col[slot_of(r, k)]);
+        int64_t hw = 0;
+        for (int32_t h : e1) hw = std::max<int64_t>(hw, width(h));
+        t.hoff.push_back((int32_t)t.hidx.size());
+        t.hw.push_back((int32_t)hw);
+        for (int32_t h : e1) {
+            const size_t at = t.hidx.size();
+            t.hidx.resize(at + hw, 0);
+            for (int64_t k = 0, w = width(h); k < w; ++k) t.hidx[at + k] = local(col[slot_of(h, k)]);
+        }
+        t.ucol.insert(t.ucol.end(), e1.begin(), e1.end());
+        t.ucol.insert(t.ucol.end(), e2.begin(), e2.end());
+        t.uoff.push_back((int32_t)t.ucol.size());
+        t.n1.push_back((int32_t)n1);
+        t.tiles.push_back(TileDesc{r0, (int32_t)rows, i});
+        t.inst_tile0[i + 1] = (int32_t)t.tiles.size();
+    });
+    for (int32_t i = 0; i < n_inst; ++i) t.inst_tile0[i + 1] = std::max(t.inst_tile0[i + 1], t.inst_tile0[i]);
+    if (t.ucol.size() >= (size_t)INT32_MAX || t.hidx.size() >= (size_t)INT32_MAX) return false;
+    if (t.hidx.empty()) t.hidx.push_back(0);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// locality order: rows regrouped into compact clusters grown breadth-first
+// ---------------------------------------------------------------------------
+std::vector<int32_t> cluster_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t cluster) {
+    std::vector<int32_t> perm;
+    perm.reserve(n);
+    std::vector<int32_t> label(n, -1);
+    std::vector<int32_t> cand;
+    int64_t scan = 0;
+    auto free_nb = [&](int32_t r) {
+        int cnt = 0;
+        for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) cnt += label[col[p]] < 0;
+        return cnt;
+    };
+    while ((int64_t)perm.size() < n) {
+        // seed: the most enclosed unassigned neighbour of the previous cluster
+        // (fills pockets before they become fragments), else the first free row
+        int32_t seed = -1;
+        int best = 1 << 30;
+        for (int32_t c : cand)
+            if (label[c] < 0) {
+                const int k = free_nb(c);
+                if (k < best) {
+                    best = k;
+                    seed = c;
+                }
+            }
+        if (seed < 0) {
+            while (label[scan] >= 0) ++scan;
+            seed = (int32_t)scan;
+        }
+        const size_t start = perm.size();
+        label[seed] = (int32_t)perm.size();
+        perm.push_back(seed);
+        for (size_t head = start; head < perm.size() && perm.size() - start < (size_t)cluster; ++head) {
+            const int32_t r = perm[head];
+            for (int64_t p = row_ptr[r]; p < row_ptr[r + 1] && perm.size() - start < (size_t)cluster; ++p) {
+                const int32_t c = col[p];
+                if (label[c] < 0) {
+                    label[c] = (int32_t)perm.size();
+                    perm.push_back(c);
+                }
+            }
+        }
+        cand.clear();
+        for (size_t k = start; k < perm.size(); ++k)
+            for (int64_t p = row_ptr[perm[k]]; p < row_ptr[perm[k] + 1]; ++p)
+                if (label[col[p]] < 0) cand.push_back(col[p]);
+    }
+    return perm;
+}
+
+std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf) {
+    std::vector<int32_t> order(n), mark(n, 0), seen(n, 0), q;
+    for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+    int32_t stamp = 0, visit = 0;
+    // breadth-first order of the part (rows with mark == stamp) from s, then
+    // from the first unvisited row of each remaining piece; returns the last row
+    auto bfs = [&](int32_t s, int64_t lo, int64_t hi) {
+        ++visit;
+        q.clear();
+        int64_t next = lo;
+        while ((int64_t)q.size() < hi - lo) {
+            if (q.size() > 0 || seen[s] == visit) {
+                while (seen[order[next]] == visit) ++next;
+                s = order[next];
+            }
+            seen[s] = visit;
+            q.push_back(s);
+            for (size_t h = q.size() - 1; h < q.size(); ++h)
+                for (int64_t p = row_ptr[q[h]]; p < row_ptr[q[h] + 1]; ++p) {
+                    const int32_t c = col[p];
+                    if (mark[c] == stamp && seen[c] != visit) {
+                        seen[c] = visit;
+                        q.push_back(c);
+                    }
+                }
+        }
+        return q.back();
+    };
+    std::vector<std::pair<int64_t, int64_t>> stack{{0, n}};
+    while (!stack.empty()) {
+        const auto [lo, hi] = stack.back();
+        stack.pop_back();
+        if (hi - lo < 2) continue;
+        ++stamp;
+        for (int64_t k = lo; k < hi; ++k) mark[order[k]] = stamp;
+        // a pseudo-peripheral start: the row reached last from the first row
+        const int32_t far = bfs(order[lo], lo, hi);
+        bfs(far, lo, hi);
+        std::copy(q.begin(), q.end(), order.begin() + lo);
+        if (hi - lo <= std::max<int64_t>(leaf, 2)) continue;
+        const int64_t mid = lo + (hi - lo) / 2;
+        stack.push_back({mid, hi});
+        stack.push_back({lo, mid});
+    }
+    return order;
+}
+
 }  // namespace tbpm

@@ -36,75 +36,6 @@ namespace {
 // value loads in flight before the KG gathers of x.  Indices are 32-bit
 // (the host keeps rows*S < 2^31 and the ELL size < 2^32).
 // ---------------------------------------------------------------------------
-template <typename R, int VS>
-using VecT = R __attribute__((ext_vector_type(2 * VS)));
-
-template <typename R, bool CH>
-struct HValT {
-    using T = R;
-};
-template <typename R>
-struct HValT<R, true> {
-    using T = typename CxT<R>::T;
-};
-
-// acc_i += h * x_i for the VS complex components of a unit
-template <typename R, int VS>
-__device__ __forceinline__ void unit_mad_real(R h, VecT<R, VS> x, VecT<R, VS> &acc) {
-#pragma unroll
-    for (int i = 0; i < 2 * VS; ++i) acc[i] = fma(h, x[i], acc[i]);
-}
-template <typename R, int VS, typename C>
-__device__ __forceinline__ void unit_mad_cplx(C h, VecT<R, VS> x, VecT<R, VS> &acc) {
-#pragma unroll
-    for (int i = 0; i < VS; ++i) {
-        acc[2 * i] = fma(h.x, x[2 * i], acc[2 * i]);
-        acc[2 * i] = fma(-h.y, x[2 * i + 1], acc[2 * i]);
-        acc[2 * i + 1] = fma(h.x, x[2 * i + 1], acc[2 * i + 1]);
-        acc[2 * i + 1] = fma(h.y, x[2 * i], acc[2 * i + 1]);
-    }
-}
-
-// Per-state partial sums for units of VS states: lane l holds states
-// (l & (U-1))*VS + i, U = units per row.
-template <int VS>
-__device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
-                                                    const double (&nrm)[VS], int log2u,
-                                                    double *__restrict__ out, int tile, int n_tiles) {
-    __shared__ double red[kWG / 64][64][3];
-    const int U = 1 << log2u;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < VS; ++i) {
-        double a = dre[i], b = dim[i], c = nrm[i];
-        for (int off = 32; off >= U; off >>= 1) {
-            a += __shfl_xor(a, off);
-            b += __shfl_xor(b, off);
-            c += __shfl_xor(c, off);
-        }
-        if (lane < U) {
-            red[wave][lane * VS + i][0] = a;
-            red[wave][lane * VS + i][1] = b;
-            red[wave][lane * VS + i][2] = c;
-        }
-    }
-    __syncthreads();
-    const int S = U * VS;
-    if ((int)threadIdx.x < S) {
-        double a = 0, b = 0, c = 0;
-#pragma unroll
-        for (int w = 0; w < kWG / 64; ++w) {
-            a += red[w][threadIdx.x][0];
-            b += red[w][threadIdx.x][1];
-            c += red[w][threadIdx.x][2];
-        }
-        const int64_t o = (int64_t)threadIdx.x * 3 * n_tiles + tile;
-        out[o] = a;
-        out[o + n_tiles] = b;
-        out[o + 2 * (int64_t)n_tiles] = c;
-    }
-}
-
 template <typename R, bool CH, int KIND, bool NT, int VS, int NE>
 __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
     using V = VecT<R, VS>;
@@ -237,7 +168,8 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
                         d2 oc;
                         oc.x = oxr;
                         oc.y = oyi;
-                        ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + (int64_t)row[q] * p.s_user + s0 + i] = oc;
+                        const int64_t crow = p.perm ? (int64_t)p.perm[row[q]] : (int64_t)row[q];
+                        ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
                     }
                 }
             } else {
@@ -372,7 +304,8 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
                     d2 oc;
                     oc.x = oxr;
                     oc.y = oyi;
-                    ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + (int64_t)row * p.s_user + s0 + i] = oc;
+                    const int64_t crow = p.perm ? (int64_t)p.perm[row] : (int64_t)row;
+                    ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
                 }
             }
         } else {
@@ -400,7 +333,7 @@ __global__ __launch_bounds__(kWG) void k_init(const InitParams p) {
     d2 *phi0 = (d2 *)p.phi0;
     double dre = 0.0, dim = 0.0, nrm = 0.0;
     for (int64_t e = threadIdx.x; e < n_el; e += kWG) {
-        const int64_t lrow = lrow0 + (e >> log2s);
+        const int64_t lrow = p.perm ? (int64_t)p.perm[td.row0 + (e >> log2s)] : lrow0 + (e >> log2s);
         const int s = (int)(e & smask);
         d2 a;
         a.x = 0.0;
@@ -576,8 +509,8 @@ template <bool CH>
 __global__ __launch_bounds__(kWG) void k_convert_values(const int64_t *__restrict__ ell_csr, int64_t ell_size,
                                                         const double *__restrict__ csr_val,
                                                         const double *__restrict__ csr_onsite,
-                                                        int64_t n_rows, void *val64, void *val32,
-                                                        double *ons64, float *ons32) {
+                                                        int64_t n_rows, const int32_t *__restrict__ perm,
+                                                        void *val64, void *val32, double *ons64, float *ons32) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < ell_size; q += stride) {
         const int64_t pos = ell_csr[q];
@@ -601,8 +534,9 @@ __global__ __launch_bounds__(kWG) void k_convert_values(const int64_t *__restric
         }
     }
     for (int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x; r < n_rows; r += stride) {
-        ons64[r] = csr_onsite[r];
-        ons32[r] = (float)csr_onsite[r];
+        const double e = csr_onsite[perm ? perm[r] : r];
+        ons64[r] = e;
+        ons32[r] = (float)e;
     }
 }
 
@@ -754,10 +688,10 @@ hipError_t launch_convert_values(const DevMatrix &m, const double *csr_val, cons
     if (blocks < 1) blocks = 1;
     if (m.is_complex)
         hipLaunchKernelGGL(k_convert_values<true>, dim3((unsigned)blocks), dim3(kWG), 0, st, m.ell_csr, m.ell_size,
-                           csr_val, csr_onsite, n_rows, m.val64, m.val32, m.onsite64, m.onsite32);
+                           csr_val, csr_onsite, n_rows, m.perm, m.val64, m.val32, m.onsite64, m.onsite32);
     else
         hipLaunchKernelGGL(k_convert_values<false>, dim3((unsigned)blocks), dim3(kWG), 0, st, m.ell_csr, m.ell_size,
-                           csr_val, csr_onsite, n_rows, m.val64, m.val32, m.onsite64, m.onsite32);
+                           csr_val, csr_onsite, n_rows, m.perm, m.val64, m.val32, m.onsite64, m.onsite32);
     return hipGetLastError();
 }
 

@@ -68,24 +68,27 @@ struct PinnedBuf {
 // if the key is equal.
 struct GraphKey {
     int32_t s_pad = 0, s_user = 0, fp32 = 0, mmax = 0, n_inst = 0;
-    int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0;
+    int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
     int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
     const void *ckpt = nullptr;
-    const void *bufs[8] = {};
+    const void *bufs[14] = {};
     bool operator==(const GraphKey &o) const;
 };
 
 struct Engine {
     DevMatrix mat;
     std::vector<int64_t> inst_row0;  // [n_inst + 1]
-    tbpm_launch_config cfgs[2] = {{2, 1, 1, 1, 0, 1}, {4, 0, 1, 2, 0, 2}};  // FP64, FP32-mixed
-    tbpm_launch_config cfg{2, 1, 1, 1, 0, 1};                                // the one in use
+    tbpm_launch_config cfgs[2] = {{2, 1, 1, 1, 0, 1, 0}, {4, 0, 1, 2, 0, 2, 0}};  // FP64, FP32-mixed
+    tbpm_launch_config cfg{2, 1, 1, 1, 0, 1, 0};                                   // the one in use
     // host copy of the sliced ELL columns (for building staged tiles)
     std::vector<int64_t> h_slice_off;
     std::vector<int32_t> h_col;
     // staged tiles: external-row lists and per-slot local indices
     DevBuf st_uoff, st_ucol, st_lidx;
     int32_t stage_units = 0;
+    // two-hop tiles of the fused launch shape, and its two extra work vectors
+    DevBuf fu_n1, fu_hoff, fu_hw, fu_hidx, bc, bd;
+    int32_t fu_lds_units = 0;
     int device = -1;
 
     // work buffers
@@ -109,7 +112,12 @@ struct Engine {
 
     int32_t n_inst() const { return (int32_t)inst_row0.size() - 1; }
 
-    tbpm_status upload(const HostCsr *const *members, int32_t n);
+    // row order of each member (empty: the caller's order); mode for new
+    // uploads: -1 automatic, 0 the caller's order, 1 bisection order
+    std::vector<std::vector<int32_t>> member_perm;
+    int32_t row_order = -1;
+    // orders: per-member row orders to use instead of choosing them (or null)
+    tbpm_status upload(const HostCsr *const *members, int32_t n, const std::vector<int32_t> *const *orders = nullptr);
     void release();
 
     // the propagation driver (shared by single and batched entry points)
@@ -137,6 +145,9 @@ struct Engine {
     // staged tiles for s_pad states of unit_bytes per VS states (log2u units per row);
     // TBPM_E_ARG if no tile size fits the LDS budget
     tbpm_status build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes);
+    // two-hop tiles for the fused launch shape with the LDS budget of a tier
+    // (tiles_chunks = -R, tiles_unit = key + tier<<20)
+    tbpm_status build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier);
 };
 
 }  // namespace tbpm

@@ -48,6 +48,9 @@ struct DevMatrix {
     double *onsite64 = nullptr;    // [n_rows]
     float *onsite32 = nullptr;     // [n_rows]
     int64_t *ell_csr = nullptr;    // [ell_size] merged-CSR position of each slot, -1 for padding
+    // [n_rows] for each internal row, its row in the caller's order (local to
+    // its member); null when every member keeps the caller's order
+    int32_t *perm = nullptr;
 };
 
 // Host-side image of the sliced ELL build (also used by tests of the layout).
@@ -89,7 +92,8 @@ struct PassParams {
     int64_t phi0_ld;       // states per row of phi0 (>= S padded or the caller's S)
     double *partials;      // [S][3][n_tiles]
     // checkpoints (last pass, FP64 only)
-    double *ckpt;          // complex128 [n_ckpt][rows][s_user]
+    double *ckpt;          // complex128 [n_ckpt][rows][s_user], rows in the caller's order
+    const int32_t *perm;   // internal row -> caller's row (single member), or null
     int64_t ckpt_stride;   // complex elements per checkpoint (rows * s_user)
     int32_t ckpt_every;
     int32_t ckpt_max;      // largest step index that is stored
@@ -103,6 +107,40 @@ struct PassParams {
     int32_t stage_units;   // LDS capacity in units (VS states)
 };
 
+// Two Clenshaw orders per launch (fused.hip).
+enum PairKind : int {
+    kPairFirst = 0,  // b_{M-2}, b_{M-3} from psi (x = psi, no b_{j+2})
+    kPairMid = 1     // b_j, b_{j-1} from b_{j+1} (x) and b_{j+2}
+};
+
+struct FusedParams {
+    const TileDesc *tiles;
+    int32_t n_tiles;
+    int32_t xcd_remap;
+    int32_t log2s;
+    int32_t bump_counter;
+    const int32_t *col;
+    const void *val;
+    const uint32_t *slice_off;
+    const void *onsite;
+    const void *x;     // b_{j+1} (or psi for kPairFirst), staged
+    const void *v;     // psi
+    const void *b2;    // b_{j+2} (kPairMid)
+    void *out1;        // b_j on own rows
+    void *out2;        // b_{j-1} on own rows
+    const PassCoef *coef1, *coef2;  // [n_inst] for orders j and j-1
+    int32_t *counter;
+    // 2-hop tiles: staged rows are own, then 1-hop (n1 of them), then 2-hop
+    const int32_t *uoff;   // [n_tiles + 1] offsets into ucol
+    const int32_t *n1;     // [n_tiles]
+    const int32_t *ucol;   // 1-hop then 2-hop global rows of every tile
+    const uint16_t *lidx;  // per ELL slot of an own row: local index (own or 1-hop)
+    const int32_t *hoff;   // [n_tiles] offset of the tile's 1-hop index block in hidx
+    const int32_t *hw;     // [n_tiles] entries per 1-hop row in that block
+    const uint16_t *hidx;  // local indices of the stored elements of the 1-hop rows
+    int32_t lds_units;     // LDS capacity in units: the most staged plus b_j units of a tile
+};
+
 struct InitParams {
     const TileDesc *tiles;
     int32_t n_tiles;
@@ -114,6 +152,7 @@ struct InitParams {
     double *phi0;                // padded FP64 copy [rows][S], or null
     double *partials;            // [S][3][n_tiles]
     int32_t *counter;
+    const int32_t *perm;         // internal row -> caller's row in its member, or null
 };
 
 struct ReduceParams {
@@ -183,15 +222,21 @@ struct AdjParams {
     const double *gcorr_l;  // complex [s_user]: dL/dC at this step (final pass)
 };
 
+hipError_t launch_pair(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const FusedParams &p,
+                       hipStream_t st);
+
 // backward launchers (backward.hip)
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
-hipError_t launch_expand_states(const double *src, int32_t s_user, double *dst, int32_t log2s, int64_t n_rows,
+// dst[r][s] = src[perm[r]][s] (src[r][s] if perm is null), zero for s >= s_user
+hipError_t launch_expand_states(const double *src, const int32_t *perm, int32_t s_user, double *dst, int32_t log2s,
+                                int64_t n_rows,
                                 hipStream_t st);
 hipError_t launch_lam_init(double *lam, const double *phi0, const double *gcorr_last, int32_t s_user,
                            int32_t log2s, int64_t n_rows, hipStream_t st);
 hipError_t launch_fill_zero(double *p, int64_t n, hipStream_t st);
 hipError_t launch_grad_scatter(const void *gacc, const double *gdiag, const int64_t *ell_csr, int64_t ell_size,
-                               bool cplx, double inv_f, double *grad_val, double *grad_onsite, int64_t n_rows,
+                               bool cplx, double inv_f, double *grad_val, double *grad_onsite, const int32_t *perm,
+                               int64_t n_rows,
                                hipStream_t st);
 
 // ---------------------------------------------------------------------------
@@ -202,5 +247,40 @@ const std::string &last_error();
 int32_t num_terms(double z, double tol);
 void bessel_j(double z, int32_t M, double *J);
 HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *col);
+
+// Tiles of the fused launch shape: runs of at most R consecutive rows of one
+// member (R chosen for the least staged traffic; a run whose staged rows do
+// not fit the budget is halved until they do); staged
+// rows are the tile's own rows, then its 1-hop rows (neighbours outside the
+// tile, sorted), then its 2-hop rows (neighbours of the 1-hop rows outside
+// both, sorted).  lidx holds, for each ELL slot of a row, the local index of
+// its column in the numbering of that row's tile; hidx holds, per tile, hw
+// local indices for each 1-hop row (slot order, zero past the row's width).
+struct TwoHopTables {
+    int64_t R = 0;                // target rows per tile
+    size_t max_x = 0, max_y = 0;  // most staged rows / most rows of b_j in a tile
+    size_t max_xy = 0;            // most staged plus b_j rows in a tile (LDS size)
+    std::vector<TileDesc> tiles;
+    std::vector<int32_t> inst_tile0, uoff, ucol, n1, hoff, hw;
+    std::vector<uint16_t> lidx, hidx;
+};
+// LDS budget of a fused-shape tile for tier 1, 2, 3: a third, a quarter or a
+// fifth of a CU's 160 KiB, i.e. 3, 4 or 5 resident workgroups per CU
+inline size_t fused_lds_budget(int tier) { return (size_t)(160 * 1024 / (tier + 2)) & ~(size_t)255; }
+
+// Row order with locality: clusters of up to 'cluster' rows, each grown
+// breadth-first over the stored elements from a seed next to the previous
+// cluster.  Returns perm with perm[new row] = old row.
+std::vector<int32_t> cluster_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t cluster);
+// Row order with locality at every scale, without coordinates: recursive
+// bisection of the row graph, each part split at the middle of a
+// breadth-first order started from a pseudo-peripheral row; parts of at most
+// 'leaf' rows keep that breadth-first order.  perm[new row] = old row.
+std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf);
+// false if no R fits the LDS budget of budget bytes (units of unit_bytes,
+// 2^log2u units per row)
+bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int32_t> &col,
+                    const std::vector<int64_t> &inst_row0, int32_t log2u, int32_t unit_bytes, size_t budget,
+                    TwoHopTables &t);
 
 }  // namespace tbpm

@@ -1,6 +1,7 @@
 // Autotuner of the Chebyshev pass launch shape: times every candidate
 // (workgroup chunks x XCD remap x non-temporal streaming x elements per
-// thread) on a few time steps
+// thread x states per thread; LDS-staged and two-order fused shapes) on a few
+// time steps
 // of scratch states and keeps the fastest in the handle.
 #include <hip/hip_runtime.h>
 
@@ -43,7 +44,8 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
-    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal)
+    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal);
+    // fused shapes: vec x LDS tier x (remap, non-temporal)
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
     while (s_pad < n_states) s_pad <<= 1;
@@ -54,9 +56,12 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
             for (int un = 1; un <= 2; ++un)
                 for (int remap = 0; remap <= 1; ++remap)
                     for (int nt = 0; nt <= 1; ++nt)
-                        if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec});
+                        if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec, 0});
         for (int remap = 0; remap <= 1; ++remap)
-            for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec});
+            for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec, 0});
+        for (int tier = 1; tier <= 3; ++tier)
+            for (int remap = 0; remap <= 1; ++remap)
+                for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 0, vec, tier});
     }
     for (const tbpm_launch_config &cand : cands) {
         {

@@ -38,11 +38,12 @@ class TBPMError(RuntimeError):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("wg_chunks", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("unroll", ctypes.c_int32), ("staged", ctypes.c_int32), ("vec", ctypes.c_int32)]
+                ("unroll", ctypes.c_int32), ("staged", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("fused", ctypes.c_int32)]
 
     def as_dict(self):
         return {"wg_chunks": self.wg_chunks, "xcd_remap": self.xcd_remap, "nontemporal": self.nontemporal,
-                "unroll": self.unroll, "staged": self.staged, "vec": self.vec}
+                "unroll": self.unroll, "staged": self.staged, "vec": self.vec, "fused": self.fused}
 
 
 _lib = None
@@ -65,6 +66,8 @@ def lib() -> ctypes.CDLL:
         "tbpm_hamiltonian_info": [P, P, P, P, P, P],
         "tbpm_hamiltonian_pattern": [P, P, P],
         "tbpm_hamiltonian_destroy": [P],
+        "tbpm_hamiltonian_set_row_order": [P, I32],
+        "tbpm_hamiltonian_get_row_order": [P, P],
         "tbpm_num_terms": [D, D, P],
         "tbpm_bessel_j": [D, I32, P],
         "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
@@ -195,18 +198,28 @@ class Hamiltonian:
             on = np.ascontiguousarray(onsite, dtype=np.float64)
             _check(lib().tbpm_hamiltonian_set_values(self.handle, va.ctypes.data, on.ctypes.data, 0, 0))
 
+    def set_row_order(self, order: int):
+        """-1: automatic, 0: the caller's orbital order, 1: bisection order on
+        the device (re-uploads the matrix from its host values)."""
+        _check(lib().tbpm_hamiltonian_set_row_order(self.handle, int(order)))
+
+    def row_order(self) -> int:
+        o = ctypes.c_int32()
+        _check(lib().tbpm_hamiltonian_get_row_order(self.handle, ctypes.byref(o)))
+        return o.value
+
     def launch_config(self, precision: str = "fp64") -> dict:
         c = LaunchConfig()
         _check(lib().tbpm_get_launch_config(self.handle, _prec(precision), ctypes.byref(c)))
         return c.as_dict()
 
     def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, staged=0, vec=None,
-                          precision=None):
+                          precision=None, fused=0):
         """Launch shape for one precision, or for both when precision is None
         (vec=None: 1 state per thread in FP64, 2 in FP32)."""
         for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
             c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll, staged,
-                             vec if vec is not None else (2 if p == FP32_MIXED else 1))
+                             vec if vec is not None else (2 if p == FP32_MIXED else 1), fused)
             _check(lib().tbpm_set_launch_config(self.handle, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
@@ -351,10 +364,10 @@ class Batch:
         return c.as_dict()
 
     def set_launch_config(self, wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1, staged=0, vec=None,
-                          precision=None):
+                          precision=None, fused=0):
         for p in ((FP64, FP32_MIXED) if precision is None else (_prec(precision),)):
             c = LaunchConfig(wg_chunks, xcd_remap, nontemporal, unroll, staged,
-                             vec if vec is not None else (2 if p == FP32_MIXED else 1))
+                             vec if vec is not None else (2 if p == FP32_MIXED else 1), fused)
             _check(lib().tbpm_batch_set_launch_config(self._b, p, ctypes.byref(c)))
 
     def autotune(self, n_states: int, precision: str = "fp64", stream=None):
@@ -406,7 +419,7 @@ def autotune_cached(H: Hamiltonian, n_states: int, precision: str, path: str | N
     if key in cache:
         cfg = cache[key]["config"]
         H.set_launch_config(cfg["wg_chunks"], cfg["xcd_remap"], cfg["nontemporal"], cfg["unroll"],
-                            cfg.get("staged", 0), cfg.get("vec"), precision=precision)
+                            cfg.get("staged", 0), cfg.get("vec"), precision=precision, fused=cfg.get("fused", 0))
         return cfg, cache[key]["ms_per_step"], True
     cfg, ms = H.autotune(n_states, precision, stream=stream)
     if path:

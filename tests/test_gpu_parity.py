@@ -131,6 +131,13 @@ def test_launch_configs_and_graph_agree():
                 H.set_launch_config(2, remap, nt, 1, staged=1, vec=vec)
                 got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
                 assert _rel(got, base) < 1e-13, ("staged", remap, nt, vec)
+    for tier in (1, 2, 3):
+        for remap, nt, un in ((0, 0, 1), (1, 1, 2), (0, 1, 1)):
+            for vec in (1, 2, 4):
+                H.set_launch_config(2, remap, nt, un, vec=vec, fused=tier)
+                assert H.launch_config()["fused"] == tier
+                got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
+                assert _rel(got, base) < 1e-13, ("fused", tier, remap, nt, un, vec)
     # a repeated call reuses the cached graph and gives the same bits
     again = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
     assert np.array_equal(again, got)
@@ -373,3 +380,82 @@ def test_lds_staged_launch_shape(case):
         _, D = tbpm.dos(_dev(got), dt)
         assert _l1(D.cpu().numpy(), Dr) < 1e-4
         assert _rel(got, plain) < 1e-12
+
+
+def _dt_for_terms(f, parity):
+    """A time step whose Bessel series has M terms of the given parity (M >= 5),
+    so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
+    for scale in np.linspace(1.0, 0.3, 141):
+        M = tbpm.num_terms(scale * math.pi)
+        if M >= 5 and M % 2 == parity:
+            return scale * math.pi / f, M
+    raise AssertionError("no time step found")
+
+
+@pytest.mark.parametrize("case", ["graphene_s8_fp64", "graphene_s8_odd_fp64", "graphene_s4_m4_fp64",
+                                  "graphene_s3_complex_fp64", "tbg_s16_fp32", "graphene_s64_fp64",
+                                  "graphene_s1_fp32", "batch_s4_fp64", "ckpt_s2_fp64"])
+def test_fused_two_order_launch_shape(case):
+    """The fused shape (two Clenshaw orders per launch, each tile staging its
+    rows and their two-hop neighbourhood in LDS) against the oracle and the
+    plain shape: an even and an odd number of middle orders, the shortest
+    series that pairs (M = 4), complex hoppings with padded states, wide
+    irregular rows, the largest state count, one state, a batch and
+    checkpoints."""
+    print(f"case fused {case}", flush=True)
+    rng = np.random.default_rng(43)
+    prec = "fp32" if case.endswith("fp32") else "fp64"
+    if case.startswith("batch"):
+        lats = [inputs.graphene(11, 9, onsite=inputs.anderson(rng, 198, 1.0)), inputs.square(17, 13),
+                inputs.twisted_bilayer(12, 12, angle_deg=4.0), inputs.graphene(2, 1)]
+        psis = [inputs.random_phase_states(rng, l.n_orb, 4) for l in lats]
+        fs = [oracle.gershgorin(l.row_ptr, l.val, l.onsite) * 1.02 for l in lats]
+        dts = [math.pi / f for f in fs]
+        B = tbpm.Batch([tbpm.Hamiltonian.from_lattice(l) for l in lats])
+        B.set_launch_config(2, 1, 1, 1, fused=2)
+        corrs = B.propagate([_dev(p) for p in psis], 48, dts, fs)
+        for l, p, f, dt, c in zip(lats, psis, fs, dts, corrs):
+            ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 48, dt, f)
+            assert _rel(c.cpu().numpy(), ref) < 1e-10
+        return
+    if case.startswith("tbg"):
+        lat, S = inputs.twisted_bilayer(32, 32, angle_deg=1.05), 16
+    elif "s64" in case:
+        lat, S = inputs.graphene(12, 10, onsite=inputs.anderson(rng, 240, 1.0)), 64
+    elif "complex" in case:
+        lat, S = _complex_graphene(23, 19, 9), 3
+    elif case.startswith("ckpt"):
+        lat, S = inputs.graphene(30, 27, onsite=inputs.anderson(rng, 1620, 1.0)), 2
+    else:
+        S = int(case.split("_s")[1].split("_")[0])
+        lat = inputs.graphene(40, 37, onsite=inputs.anderson(rng, 2960, 1.0))
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    dt = math.pi / f
+    if "odd" in case:
+        dt, M = _dt_for_terms(f, 1)
+        assert M % 2 == 1
+    elif "m4" in case:
+        dt = 0.002 / f
+        assert tbpm.num_terms(f * dt) == 4
+    nt = 96
+    ref, _, info = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    kw = {"ckpt_every": 8} if case.startswith("ckpt") else {}
+    H.set_launch_config(2, 1, 1, 1, vec=min(4, 1 << (S.bit_length() - 1)), fused=1 + sum(map(ord, case)) % 3)
+    got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
+    H.set_launch_config(2, 1, 1, 1, fused=0)
+    plain = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
+    if kw:
+        got, ck = got
+        plain, ck_plain = plain
+        assert _rel(ck.cpu().numpy(), ck_plain.cpu().numpy()) < 1e-13
+    got, plain = got.cpu().numpy(), plain.cpu().numpy()
+    if prec == "fp64":
+        assert _rel(got, ref) < 1e-10
+        assert _rel(got, plain) < 1e-13
+    else:
+        _, Dr = oracle.dos(ref, dt)
+        _, D = tbpm.dos(_dev(got), dt)
+        assert _l1(D.cpu().numpy(), Dr) < 1e-4
+        assert _rel(got, plain) < 1e-5

@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in tbpm.version()
 
 
+def test_launch_config_struct_matches_header():
+    text = open(os.path.join(ROOT, "include", "tbpm.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} tbpm_launch_config;", text).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == [f[0] for f in tbpm.LaunchConfig._fields_]
+    assert ctypes.sizeof(tbpm.LaunchConfig) == 4 * len(fields)
+
+
 @pytest.mark.parametrize("z", [math.pi / 2, math.pi, 2 * math.pi, 10.3, 37.0, -2.5, 1e-9])
 def test_library_bessel_vs_oracle(z):
     M = 60
