@@ -33,15 +33,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 KERNEL_SOURCES = ["paper_2209_00806_amd/csrc/kernels.hip", "paper_2209_00806_amd/csrc/device_util.h",
                   "paper_2209_00806_amd/csrc/tbpm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pass_mid_graphene1024_s8_fp64.json")
+PAIR_SOURCES = ["paper_2209_00806_amd/csrc/fused.hip", "paper_2209_00806_amd/csrc/device_util.h",
+                "paper_2209_00806_amd/csrc/tbpm_internal.h"]
+PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pair_mid_graphene1024_s8_fp64.json")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -52,6 +55,25 @@ def pass_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
     gathered b_{j+1}, b_{j+2} and psi once, write b_j), the sliced-ELL matrix
     (4-byte column + v-byte value per stored element) and the on-site vector."""
     return 4 * b * n_orb * S + nnz * (4 + v) + n_orb * v
+
+
+def pair_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
+    """Algorithmic HBM bytes of one fused launch (two Clenshaw orders): 5 state
+    streams (read b_{j+1}, b_{j+2} and psi once, write b_j and b_{j-1}) and the
+    matrix and on-site vector once."""
+    return 5 * b * n_orb * S + nnz * (4 + v) + n_orb * v
+
+
+def step_bytes(M: int, fused: bool, n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
+    """Algorithmic bytes of one time step for the launch schedule in use: M-1
+    passes, or (fused) FIRST+NOB2 as one launch (read psi, write two vectors),
+    the middle orders in pairs, a leftover middle order and LAST alone."""
+    mat = nnz * (4 + v) + n_orb * v
+    vec = b * n_orb * S
+    if not fused or M < 4:
+        return (M - 1) * (4 * vec + mat)
+    n_mid = M - 4
+    return (3 * vec + mat) + (n_mid // 2) * (5 * vec + mat) + (n_mid % 2) * (4 * vec + mat) + (4 * vec + mat)
 
 
 def bench_batched(args, log):
@@ -74,6 +96,7 @@ def bench_batched(args, log):
     tuned = {}
     if not args.no_autotune:
         for prec in ("fp64", "fp32"):
+            log(f"batch: autotuning {prec}")
             cfg, ms = B.autotune(S, prec)
             tuned[prec] = cfg
             log(f"batch autotuned {prec}: {cfg} ({ms:.3f} ms per time step)")
@@ -83,11 +106,15 @@ def bench_batched(args, log):
            "sizes_min_max": [min(l.n_orb for l in lats), max(l.n_orb for l in lats)]}
     updates = 0
     alg64 = alg32 = 0
+    # every member runs the schedule of the longest series (zero-padded coefficients)
+    m_max = max(tbpm.num_terms(f * dt, 1e-12) for f, dt in zip(fs, dts))
+    fu64 = B.launch_config("fp64").get("fused", 0) > 0
+    fu32 = B.launch_config("fp32").get("fused", 0) > 0
     for l, f, dt in zip(lats, fs, dts):
         M = tbpm.num_terms(f * dt, 1e-12)
         updates += (l.nnz + l.n_orb) * S * (M - 1) * (nt - 1)
-        alg64 += pass_bytes(l.n_orb, l.nnz, S, 16, 8) * (M - 1) * (nt - 1)
-        alg32 += pass_bytes(l.n_orb, l.nnz, S, 8, 4) * (M - 1) * (nt - 1)
+        alg64 += step_bytes(m_max, fu64, l.n_orb, l.nnz, S, 16, 8) * (nt - 1)
+        alg32 += step_bytes(m_max, fu32, l.n_orb, l.nnz, S, 8, 4) * (nt - 1)
     stream = torch.cuda.current_stream()
     res = {}
     for prec in ("fp64", "fp32"):
@@ -147,6 +174,7 @@ def bench_tbg(args, log):
            "max_row": H.info()["max_row"], "n_states": 16, "n_steps": nt, "rescale_eV": f}
     res = {}
     for prec in ("fp32", "fp64"):
+        log(f"tbg {prec}: autotuning")
         cfg, ms_t, _ = tbpm.autotune_cached(H, 16, prec, args.tune_cache)
         tbpm.propagate(H, psi0, 4, dt, f, precision=prec)
         torch.cuda.synchronize()
@@ -158,7 +186,7 @@ def bench_tbg(args, log):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         b, v = (8, 4) if prec == "fp32" else (16, 8)
-        alg = pass_bytes(lat.n_orb, lat.nnz, 16, b, v) * (M - 1) * (nt - 1)
+        alg = step_bytes(M, cfg.get("fused", 0) > 0, lat.n_orb, lat.nnz, 16, b, v) * (nt - 1)
         _, D = tbpm.dos(corr, dt)
         res[prec] = D.cpu().numpy()
         out[prec] = {"ms": round(ms, 1), "nnz_updates_per_s": updates / (ms / 1e3),
@@ -301,6 +329,7 @@ def main():
     tuned = {}
     if not args.no_autotune:
         for prec in ("fp64", "fp32"):
+            log(f"autotuning {prec}")
             cfg, ms, hit = tbpm.autotune_cached(H, S, prec, args.tune_cache)
             tuned[prec] = {"config": cfg, "ms_per_step": round(ms, 4), "cached": hit}
             log(f"autotuned {prec}: {cfg} ({ms:.3f} ms per time step{', cached' if hit else ''})")
@@ -327,11 +356,13 @@ def main():
     ms_per_step = ev0.elapsed_time(ev1) / max(args.steps, 1)
     updates = (lat.nnz + lat.n_orb) * S * n_pass * (nt - 1)
     value = updates / (ms_per_step / 1e3)
-    step_bytes = pass_bytes(lat.n_orb, lat.nnz, S, 16, 8) * n_pass * (nt - 1)
+    fused64 = H.launch_config("fp64").get("fused", 0) > 0
+    run_bytes = step_bytes(M, fused64, lat.n_orb, lat.nnz, S, 16, 8) * (nt - 1)
     log(f"fp64: {ms_per_step:.1f} ms/step (wall {t_wall / max(args.steps, 1) * 1e3:.1f}), "
-        f"{value:.3e} nnz-updates/s, {step_bytes / (ms_per_step / 1e3) / 1e9:.0f} GB/s algorithmic")
+        f"{value:.3e} nnz-updates/s, {run_bytes / (ms_per_step / 1e3) / 1e9:.0f} GB/s algorithmic")
 
-    # dominant kernel: the interior Clenshaw pass, timed in isolation on the same stream
+    # dominant kernel: the interior launch (a Clenshaw pass, or a fused pair of
+    # orders), timed in isolation on the same stream
     n_launch = 200
     tbpm.bench_pass(H, S, "fp64", 10)
     ka = torch.cuda.Event(enable_timing=True)
@@ -341,17 +372,24 @@ def main():
     kb.record(stream)
     torch.cuda.synchronize()
     pass_ms = ka.elapsed_time(kb) / n_launch
-    alg = pass_bytes(lat.n_orb, lat.nnz, S, 16, 8)
+    if fused64:
+        alg = pair_bytes(lat.n_orb, lat.nnz, S, 16, 8)
+        tfile, tsrc = PAIR_TRAFFIC_FILE, PAIR_SOURCES
+        kname = "k_pair<double,real,MID> (two interior Clenshaw orders per launch)"
+    else:
+        alg = pass_bytes(lat.n_orb, lat.nnz, S, 16, 8)
+        tfile, tsrc = TRAFFIC_FILE, KERNEL_SOURCES
+        kname = "k_pass<double,real,MID> (interior Clenshaw pass)"
     achieved = alg / (pass_ms / 1e3) / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash():
+        if tr.get("kernel_hash") == kernel_hash(tsrc):
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_pass<double,real,MID> (interior Clenshaw pass)",
+                "kernel": kname,
                 "kernel_avg_ms": round(pass_ms, 5), "algorithmic_bytes_per_launch": alg,
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     log(f"interior pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of peak)")
@@ -373,7 +411,7 @@ def main():
     ms1 = e0.elapsed_time(e1)
     rate_s1 = (lat.nnz + lat.n_orb) * n_pass * (nt1 - 1) / (ms1 / 1e3)
     extra["fp64_single_state"] = {"nnz_updates_per_s": rate_s1, "n_steps_timed": nt1,
-                                  "alg_GBps": round(pass_bytes(lat.n_orb, lat.nnz, 1, 16, 8) * n_pass * (nt1 - 1)
+                                  "alg_GBps": round(step_bytes(M, fused64, lat.n_orb, lat.nnz, 1, 16, 8) * (nt1 - 1)
                                                     / (ms1 / 1e3) / 1e9, 1)}
     log(f"fp64 S=1: {rate_s1:.3e} nnz-updates/s")
     del psi1
@@ -393,11 +431,13 @@ def main():
         extra["fp32_mixed"] = {"ms_per_step": round(ms32, 2), "nnz_updates_per_s": updates / (ms32 / 1e3),
                                "speedup_vs_fp64": round(ms_per_step / ms32, 3),
                                "dos_l1_rel_err_vs_fp64": l1, "corr_max_rel_err_vs_fp64": cerr,
-                               "alg_GBps": round(pass_bytes(lat.n_orb, lat.nnz, S, 8, 4) * n_pass * (nt - 1)
+                               "alg_GBps": round(step_bytes(M, H.launch_config("fp32").get("fused", 0) > 0,
+                                                            lat.n_orb, lat.nnz, S, 8, 4) * (nt - 1)
                                                  / (ms32 / 1e3) / 1e9, 1)}
         extra["fp32_mixed"]["speedup_vs_fp64_single_state"] = round(updates / (ms32 / 1e3) / rate_s1, 3)
         log(f"fp32-mixed: {ms32:.1f} ms/step, speedup {ms_per_step / ms32:.2f}x, DOS L1 err {l1:.2e}")
     launch_cfg = {"fp64": H.launch_config("fp64"), "fp32": H.launch_config("fp32"), "autotuned": bool(tuned)}
+    row_order = "bisection" if H.row_order() == 1 else "caller"
     H.close()
     del H
     torch.cuda.empty_cache()
@@ -449,7 +489,8 @@ def main():
                    "chebyshev_terms": M, "launch": launch_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "alg_GBps_step": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "alg_GBps_step": round(run_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "row_order": row_order,
         "extra": extra,
     }
     print(json.dumps(rec), flush=True)

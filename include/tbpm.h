@@ -280,12 +280,12 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *               with many stored elements); wg_chunks and unroll are then unused
  *   vec         states of a row each thread holds (1, 2 or 4; capped by the
  *               padded state count)
- *   fused       1, 2 or 3: evaluate two Clenshaw orders per launch: each tile
+ *   fused       1 .. 6: evaluate two Clenshaw orders per launch: each tile
  *               stages its rows and their two-hop neighbourhood in LDS and
  *               computes the first order on its rows and their neighbours,
- *               the second on its own rows.  The value is the LDS tier: a
- *               tile uses at most 1/3, 1/4 or 1/5 of a CU's 160 KiB (bigger
- *               tiles and smaller halos, or more resident workgroups).  Two
+ *               the second on its own rows.  The value t is the LDS tier: a
+ *               tile uses at most 1/(t+2) of a CU's 160 KiB (bigger tiles and
+ *               smaller halos, or more resident workgroups).  Two
  *               extra state-sized work vectors are allocated; staged and
  *               wg_chunks are unused and unroll applies to the orders left
  *               unpaired (the last one, and a middle one when their count is

@@ -28,7 +28,7 @@ bool valid_cfg(const tbpm_launch_config &c) {
     return std::find(std::begin(ok), std::end(ok), c.wg_chunks) != std::end(ok) && (c.xcd_remap == 0 || c.xcd_remap == 1) &&
            (c.nontemporal == 0 || c.nontemporal == 1) && (c.unroll == 1 || c.unroll == 2) &&
            (c.staged == 0 || c.staged == 1) && (c.vec == 1 || c.vec == 2 || c.vec == 4) &&
-           (c.fused >= 0 && c.fused <= 3);
+           (c.fused >= 0 && c.fused <= kFusedTiers);
 }
 
 double resolve_rescale(const HostCsr &h, double rescale) {

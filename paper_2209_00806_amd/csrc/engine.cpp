@@ -76,7 +76,8 @@ void PinnedBuf::release() {
 bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
-        fused != o.fused || ckpt_every != o.ckpt_every ||
+        fused != o.fused || n_tiles != o.n_tiles || tiles_chunks != o.tiles_chunks || tiles_unit != o.tiles_unit ||
+        lds_units != o.lds_units || ckpt_every != o.ckpt_every ||
         ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
         return false;
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
@@ -405,8 +406,14 @@ tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t uni
 // two_hop_tables, then uploaded)
 // ---------------------------------------------------------------------------
 tbpm_status Engine::build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier) {
-    const int32_t key = unit_bytes * 64 + log2u + (tier << 20);
-    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) return TBPM_OK;
+    // the tables depend on the bytes of a row and the budget only (not on
+    // how a row is split into units)
+    const int32_t row_bytes = unit_bytes << log2u;
+    const int32_t key = (1 << 24) + row_bytes * 16 + tier;
+    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) {
+        fu_lds_units = (int32_t)(fu_max_rows << log2u);
+        return TBPM_OK;
+    }
     TwoHopTables t;
     if (!two_hop_tables(h_slice_off, h_col, inst_row0, log2u, unit_bytes, fused_lds_budget(tier), t))
         return fail(TBPM_E_ARG, "no two-hop tile fits the LDS budget");
@@ -433,6 +440,7 @@ tbpm_status Engine::build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit
     TRY_HIP(up(fu_hoff, t.hoff.data(), sizeof(int32_t) * nt), "upload two-hop offsets");
     TRY_HIP(up(fu_hw, t.hw.data(), sizeof(int32_t) * nt), "upload two-hop widths");
     TRY_HIP(up(fu_hidx, t.hidx.data(), sizeof(uint16_t) * t.hidx.size()), "upload two-hop halo indices");
+    fu_max_rows = t.max_xy;
     fu_lds_units = (int32_t)(t.max_xy << log2u);
     tiles_s = s_pad;
     tiles_chunks = -(int32_t)t.R;
@@ -761,14 +769,18 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.unroll = cfg.unroll;
             key.staged = staged ? 1 : 0;
             key.vec = vs;
-            key.fused = fused ? 1 : 0;
+            key.fused = fused ? cfg.fused : 0;
+            key.n_tiles = n_tiles;
+            key.tiles_chunks = tiles_chunks;
+            key.tiles_unit = tiles_unit;
+            key.lds_units = fused ? fu_lds_units : (staged ? stage_units : 0);
             key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
             key.ckpt_max = a.n_steps - 2;
             key.n_steps = a.n_steps;
             key.ckpt = a.ckpt;
-            const void *kb[14] = {v.ptr,         ba.ptr,     bb.ptr,      phi0.ptr,    partials.ptr,
-                                  coef.ptr,      tiles.ptr,  norm2_all.ptr, bc.ptr,    bd.ptr,
-                                  st_uoff.ptr,   st_ucol.ptr, st_lidx.ptr,  fu_hidx.ptr};
+            const void *kb[17] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
+                                  tiles.ptr,   norm2_all.ptr, bc.ptr,      bd.ptr,      st_uoff.ptr,  st_ucol.ptr,
+                                  st_lidx.ptr, fu_hidx.ptr, fu_n1.ptr,     fu_hoff.ptr, fu_hw.ptr};
             static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
             if (!graph_exec || !(key == graph_key)) {

@@ -261,7 +261,8 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
         std::sort(e2.begin(), e2.end());
         e2.erase(std::unique(e2.begin(), e2.end()), e2.end());
     };
-    // a tile fits if both staged arrays fit the budget (local indices are 16-bit)
+    // a tile fits if its two LDS arrays fit the budget: b_{j+1} on x rows and
+    // b_j on y rows (local indices are 16-bit)
     auto fits = [&](int64_t rows) {
         const size_t x = (size_t)rows + e1.size() + e2.size(), y = (size_t)rows + e1.size();
         return ((x + y) << log2u) * (size_t)unit_bytes <= budget && x <= 65535;
@@ -351,57 +352,8 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
 }
 
 // ---------------------------------------------------------------------------
-// locality order: rows regrouped into compact clusters grown breadth-first
+// locality order: recursive bisection of the row graph
 // ---------------------------------------------------------------------------
-std::vector<int32_t> cluster_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t cluster) {
-    std::vector<int32_t> perm;
-    perm.reserve(n);
-    std::vector<int32_t> label(n, -1);
-    std::vector<int32_t> cand;
-    int64_t scan = 0;
-    auto free_nb = [&](int32_t r) {
-        int cnt = 0;
-        for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) cnt += label[col[p]] < 0;
-        return cnt;
-    };
-    while ((int64_t)perm.size() < n) {
-        // seed: the most enclosed unassigned neighbour of the previous cluster
-        // (fills pockets before they become fragments), else the first free row
-        int32_t seed = -1;
-        int best = 1 << 30;
-        for (int32_t c : cand)
-            if (label[c] < 0) {
-                const int k = free_nb(c);
-                if (k < best) {
-                    best = k;
-                    seed = c;
-                }
-            }
-        if (seed < 0) {
-            while (label[scan] >= 0) ++scan;
-            seed = (int32_t)scan;
-        }
-        const size_t start = perm.size();
-        label[seed] = (int32_t)perm.size();
-        perm.push_back(seed);
-        for (size_t head = start; head < perm.size() && perm.size() - start < (size_t)cluster; ++head) {
-            const int32_t r = perm[head];
-            for (int64_t p = row_ptr[r]; p < row_ptr[r + 1] && perm.size() - start < (size_t)cluster; ++p) {
-                const int32_t c = col[p];
-                if (label[c] < 0) {
-                    label[c] = (int32_t)perm.size();
-                    perm.push_back(c);
-                }
-            }
-        }
-        cand.clear();
-        for (size_t k = start; k < perm.size(); ++k)
-            for (int64_t p = row_ptr[perm[k]]; p < row_ptr[perm[k] + 1]; ++p)
-                if (label[col[p]] < 0) cand.push_back(col[p]);
-    }
-    return perm;
-}
-
 std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf) {
     std::vector<int32_t> order(n), mark(n, 0), seen(n, 0), q;
     for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;

@@ -69,9 +69,11 @@ struct PinnedBuf {
 struct GraphKey {
     int32_t s_pad = 0, s_user = 0, fp32 = 0, mmax = 0, n_inst = 0;
     int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
+    // identity of the tile tables the launches were captured with
+    int32_t n_tiles = 0, tiles_chunks = 0, tiles_unit = 0, lds_units = 0;
     int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
     const void *ckpt = nullptr;
-    const void *bufs[14] = {};
+    const void *bufs[17] = {};
     bool operator==(const GraphKey &o) const;
 };
 
@@ -89,6 +91,7 @@ struct Engine {
     // two-hop tiles of the fused launch shape, and its two extra work vectors
     DevBuf fu_n1, fu_hoff, fu_hw, fu_hidx, bc, bd;
     int32_t fu_lds_units = 0;
+    size_t fu_max_rows = 0;
     int device = -1;
 
     // work buffers
@@ -100,7 +103,8 @@ struct Engine {
     hipStream_t capture_stream = nullptr;
 
     // tile tables (host) for the current (S, chunks)
-    // tiles_chunks < 0: staged tiles of -chunks rows (tiles_unit = unit bytes*64 + log2u);
+    // tiles_chunks < 0: staged or two-hop tiles of at most -chunks rows
+    // (tiles_unit = unit bytes*64 + log2u, or the two-hop key);
     // else plain tiles of chunks*256 units of tiles_unit = -vs states
     int32_t tiles_s = 0, tiles_chunks = 0, tiles_unit = 0;
     std::vector<TileDesc> h_tiles;
@@ -146,7 +150,7 @@ struct Engine {
     // TBPM_E_ARG if no tile size fits the LDS budget
     tbpm_status build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes);
     // two-hop tiles for the fused launch shape with the LDS budget of a tier
-    // (tiles_chunks = -R, tiles_unit = key + tier<<20)
+    // (tiles_chunks = -R, tiles_unit = 2^24 + 16 * row bytes + tier)
     tbpm_status build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier);
 };
 

@@ -138,7 +138,7 @@ struct FusedParams {
     const int32_t *hoff;   // [n_tiles] offset of the tile's 1-hop index block in hidx
     const int32_t *hw;     // [n_tiles] entries per 1-hop row in that block
     const uint16_t *hidx;  // local indices of the stored elements of the 1-hop rows
-    int32_t lds_units;     // LDS capacity in units: the most staged plus b_j units of a tile
+    int32_t lds_units;     // LDS capacity in units: max over tiles of n_x + n_y
 };
 
 struct InitParams {
@@ -259,19 +259,16 @@ HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *
 struct TwoHopTables {
     int64_t R = 0;                // target rows per tile
     size_t max_x = 0, max_y = 0;  // most staged rows / most rows of b_j in a tile
-    size_t max_xy = 0;            // most staged plus b_j rows in a tile (LDS size)
+    size_t max_xy = 0;            // most LDS rows of a tile: staged rows + b_j rows
     std::vector<TileDesc> tiles;
     std::vector<int32_t> inst_tile0, uoff, ucol, n1, hoff, hw;
     std::vector<uint16_t> lidx, hidx;
 };
-// LDS budget of a fused-shape tile for tier 1, 2, 3: a third, a quarter or a
-// fifth of a CU's 160 KiB, i.e. 3, 4 or 5 resident workgroups per CU
+// LDS budget of a fused-shape tile for tier t = 1 .. 6: 1/(t+2) of a CU's
+// 160 KiB, i.e. room for t+2 resident workgroups per CU
+constexpr int kFusedTiers = 6;
 inline size_t fused_lds_budget(int tier) { return (size_t)(160 * 1024 / (tier + 2)) & ~(size_t)255; }
 
-// Row order with locality: clusters of up to 'cluster' rows, each grown
-// breadth-first over the stored elements from a seed next to the previous
-// cluster.  Returns perm with perm[new row] = old row.
-std::vector<int32_t> cluster_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t cluster);
 // Row order with locality at every scale, without coordinates: recursive
 // bisection of the row graph, each part split at the middle of a
 // breadth-first order started from a pseudo-peripheral row; parts of at most

@@ -45,11 +45,12 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
     // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal);
-    // fused shapes: vec x LDS tier x (remap, non-temporal)
+    // fused shapes (sparse rows): LDS tier x vec, XCD remap and non-temporal streams
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
     while (s_pad < n_states) s_pad <<= 1;
     const int chunk_list[] = {1, 2, 4, 8, 16};
+    const bool wide_rows = eng.mat.n_rows > 0 && (double)eng.mat.ell_size > 8.0 * (double)eng.mat.n_rows;
     for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
         if (fp32 && vec == 1 && s_pad > 1) continue;  // 8-byte units are never better than 16
         for (int ch : chunk_list)
@@ -59,10 +60,14 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
                         if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec, 0});
         for (int remap = 0; remap <= 1; ++remap)
             for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec, 0});
-        for (int tier = 1; tier <= 3; ++tier)
-            for (int remap = 0; remap <= 1; ++remap)
-                for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 0, vec, tier});
     }
+    // fused shapes, tier outer (the tile tables depend on the tier only, so
+    // the vec variants of a tier share them); the two-hop halo grows with
+    // the square of the row width, so fusing pays off only for sparse rows
+    if (!wide_rows)
+        for (int tier = 1; tier <= kFusedTiers; ++tier)
+            for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2)
+                if (!(fp32 && vec == 1 && s_pad > 1)) cands.push_back(tbpm_launch_config{2, 1, 1, 1, 0, vec, tier});
     for (const tbpm_launch_config &cand : cands) {
         {
             {

@@ -131,7 +131,7 @@ def test_launch_configs_and_graph_agree():
                 H.set_launch_config(2, remap, nt, 1, staged=1, vec=vec)
                 got = tbpm.propagate(H, psi0, 40, dt, f).cpu().numpy()
                 assert _rel(got, base) < 1e-13, ("staged", remap, nt, vec)
-    for tier in (1, 2, 3):
+    for tier in (1, 2, 3, 4, 5, 6):
         for remap, nt, un in ((0, 0, 1), (1, 1, 2), (0, 1, 1)):
             for vec in (1, 2, 4):
                 H.set_launch_config(2, remap, nt, un, vec=vec, fused=tier)
@@ -442,7 +442,7 @@ def test_fused_two_order_launch_shape(case):
     ref, _, info = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
     H = tbpm.Hamiltonian.from_lattice(lat)
     kw = {"ckpt_every": 8} if case.startswith("ckpt") else {}
-    H.set_launch_config(2, 1, 1, 1, vec=min(4, 1 << (S.bit_length() - 1)), fused=1 + sum(map(ord, case)) % 3)
+    H.set_launch_config(2, 1, 1, 1, vec=min(4, 1 << (S.bit_length() - 1)), fused=1 + sum(map(ord, case)) % 6)
     got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
     H.set_launch_config(2, 1, 1, 1, fused=0)
     plain = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
@@ -459,3 +459,23 @@ def test_fused_two_order_launch_shape(case):
         _, D = tbpm.dos(_dev(got), dt)
         assert _l1(D.cpu().numpy(), Dr) < 1e-4
         assert _rel(got, plain) < 1e-5
+
+
+def test_graph_cache_follows_lds_tier():
+    """Consecutive calls that differ only in the fused shape's LDS tier build
+    different tile tables; the cached step graph must not be reused across
+    them (regression: it once was when the table buffers kept their
+    addresses)."""
+    print("case graph cache vs lds tier", flush=True)
+    rng = np.random.default_rng(71)
+    lat = inputs.graphene(48, 45, onsite=inputs.anderson(rng, 2 * 48 * 45, 1.0))
+    psi0 = _dev(inputs.random_phase_states(rng, lat.n_orb, 8))
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    f = 9.0
+    dt = math.pi / f
+    base = tbpm.propagate(H, psi0, 24, dt, f, graph=False).cpu().numpy()
+    for vec in (1, 2):
+        for tier in (1, 2, 3, 1, 6, 4, 5, 2):
+            H.set_launch_config(2, 1, 1, 1, vec=vec, fused=tier)
+            got = tbpm.propagate(H, psi0, 24, dt, f).cpu().numpy()
+            assert _rel(got, base) < 1e-13, (vec, tier)
