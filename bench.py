@@ -391,6 +391,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname,
                 "kernel_avg_ms": round(pass_ms, 5), "algorithmic_bytes_per_launch": alg,
+                # a fused launch does the work of two passes: their algorithmic bytes over its time
+                "pass_equivalent_GBps": round((2 if fused64 else 1) * pass_bytes(lat.n_orb, lat.nnz, S, 16, 8)
+                                              / (pass_ms / 1e3) / 1e9, 1),
                 "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     log(f"interior pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of peak)")
 

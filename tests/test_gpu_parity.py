@@ -442,7 +442,8 @@ def test_fused_two_order_launch_shape(case):
     ref, _, info = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
     H = tbpm.Hamiltonian.from_lattice(lat)
     kw = {"ckpt_every": 8} if case.startswith("ckpt") else {}
-    H.set_launch_config(2, 1, 1, 1, vec=min(4, 1 << (S.bit_length() - 1)), fused=1 + sum(map(ord, case)) % 6)
+    H.set_launch_config(2, 1, 1, 1 + len(case) % 2, vec=min(4, 1 << (S.bit_length() - 1)),
+                        fused=1 + sum(map(ord, case)) % 6)
     got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
     H.set_launch_config(2, 1, 1, 1, fused=0)
     plain = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, **kw)
