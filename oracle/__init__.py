@@ -13,6 +13,8 @@ Pieces:
   * :func:`n_terms` -- truncation of the Chebyshev/Bessel series;
   * :func:`propagate` -- the paper's modified Chebyshev recurrence (plain C,
     ``tbpm_oracle.c``), recording C_k = <phi0|psi_k> and ||psi_k||^2;
+  * :func:`psi_t` -- the same propagation, returning psi at chosen steps
+    (wave-packet snapshots);
   * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
     correlation, summed directly (no FFT);
   * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
@@ -55,6 +57,9 @@ def _load():
         lib.oracle_backward.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                                         P, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
         lib.oracle_backward.restype = ctypes.c_int
+        lib.oracle_psi_t.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                     P, ctypes.c_int32, P, ctypes.c_int32, P, P]
+        lib.oracle_psi_t.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -143,6 +148,25 @@ def propagate(row_ptr, col, val, onsite, psi0, n_steps: int, dt: float, rescale:
     if rc != 0:
         raise MemoryError("oracle_propagate failed")
     return corr, norm2, {"rescale": f, "z": f * dt, "M": M, "J": J}
+
+
+def psi_t(row_ptr, col, val, onsite, psi0, steps, dt: float, rescale: float, tol: float = 1e-12):
+    """psi(k dt) for each k in ``steps`` (the wave-function propagation of the
+    paper's usage section, same series as :func:`propagate`).
+
+    Returns snapshots [len(steps), n, S] complex128 and the info dict.
+    """
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    f, M, J = _scale_and_coeffs(row_ptr, val, onsite, dt, rescale, tol)
+    snaps = np.zeros((steps.shape[0], n, S), dtype=np.complex128)
+    rc = _load().oracle_psi_t(n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data, onsite.ctypes.data, f, S,
+                              psi0.ctypes.data, steps.shape[0], steps.ctypes.data, M, J.ctypes.data,
+                              snaps.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_psi_t failed (negative step or allocation failure)")
+    return snaps, {"rescale": f, "z": f * dt, "M": M, "J": J}
 
 
 def energies(n_steps: int, dt: float) -> np.ndarray:

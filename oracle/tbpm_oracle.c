@@ -141,6 +141,44 @@ int oracle_propagate(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
 }
 
 /*
+ * Snapshots of the propagated states (the wave-function propagation of the
+ * paper's usage section): snaps[(q*n + i)*S + s] = psi_s(steps[q] dt)_i for
+ * q = 0 .. n_snap-1, with the same time step as oracle_propagate.  steps must
+ * be non-negative; they need not be sorted.
+ * Returns 0 on success, -1 on allocation failure or a negative step.
+ */
+int oracle_psi_t(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_ri,
+                 const double *onsite, double f, int32_t S, const double *phi0_ri, int32_t n_snap,
+                 const int32_t *steps, int32_t M, const double *J, double *snaps_ri) {
+    const cplx *val = (const cplx *)val_ri;
+    const cplx *phi0 = (const cplx *)phi0_ri;
+    cplx *snaps = (cplx *)snaps_ri;
+    int32_t last = 0;
+    for (int32_t q = 0; q < n_snap; ++q) {
+        if (steps[q] < 0) return -1;
+        if (steps[q] > last) last = steps[q];
+    }
+    cplx *buf = malloc(sizeof(cplx) * (size_t)n * 6);
+    if (!buf) return -1;
+    cplx *psi = buf, *nxt = buf + n, *w0 = buf + 2 * n, *w1 = buf + 3 * n, *w2 = buf + 4 * n, *h = buf + 5 * n;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int64_t i = 0; i < n; ++i) psi[i] = phi0[i * S + s];
+        for (int32_t k = 0; k <= last; ++k) {
+            for (int32_t q = 0; q < n_snap; ++q)
+                if (steps[q] == k)
+                    for (int64_t i = 0; i < n; ++i) snaps[((int64_t)q * n + i) * S + s] = psi[i];
+            if (k == last) break;
+            time_step(n, row_ptr, col, val, onsite, f, M, J, psi, nxt, NULL, w0, w1, w2, h);
+            cplx *t = psi;
+            psi = nxt;
+            nxt = t;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
  * Discrete adjoint of oracle_propagate (reverse-mode differentiation of the
  * recurrence above, written out by hand).
  *

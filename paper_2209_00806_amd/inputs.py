@@ -218,6 +218,38 @@ def random_phase_states(rng: np.random.Generator, n: int, n_states: int) -> np.n
     return np.ascontiguousarray((np.exp(1j * theta) / np.sqrt(n)).T)
 
 
+def unit_states(n: int, orbitals) -> np.ndarray:
+    """One state per listed orbital, with amplitude 1 on that orbital only
+    (the initial state of the LDOS by propagation, Sec. "Local density of
+    states"); layout [n][len(orbitals)] complex128."""
+    orbitals = np.asarray(orbitals, dtype=np.int64)
+    out = np.zeros((n, orbitals.shape[0]), dtype=np.complex128)
+    out[orbitals, np.arange(orbitals.shape[0])] = 1.0
+    return out
+
+
+def local_random_states(rng: np.random.Generator, n: int, orbitals, n_states: int) -> np.ndarray:
+    """Random phases on a set of orbitals only, normalised (the LDOS averaged
+    over that set); layout [n][n_states] complex128."""
+    orbitals = np.asarray(orbitals, dtype=np.int64)
+    theta = rng.uniform(0.0, 2.0 * np.pi, size=(n_states, orbitals.shape[0]))
+    out = np.zeros((n, n_states), dtype=np.complex128)
+    out[orbitals, :] = (np.exp(1j * theta) / np.sqrt(orbitals.shape[0])).T
+    return out
+
+
+def gaussian_packet(pos: np.ndarray, center, sigma: float = 0.5, extent=(1.0, 1.0)) -> np.ndarray:
+    """Real Gaussian wave packet exp(-r^2 / (2 sigma^2)) around ``center`` in
+    the plane, with the x and y offsets scaled by ``extent`` (0 drops that
+    direction: a one-dimensional packet), normalised; the initial state of the
+    wave-function propagation example of the usage section.  Returns [n]
+    complex128."""
+    dx = (pos[:, 0] - center[0]) * extent[0]
+    dy = (pos[:, 1] - center[1]) * extent[1]
+    w = np.exp(-(dx * dx + dy * dy) / (2.0 * sigma * sigma)).astype(np.complex128)
+    return w / np.linalg.norm(w)
+
+
 def morton_order(xy: np.ndarray, cell: float) -> np.ndarray:
     """Permutation that sorts points along a Z-order (Morton) curve of their 2D
     positions quantised to ``cell``; points in the same quantum keep their order."""

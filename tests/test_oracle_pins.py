@@ -335,3 +335,79 @@ def test_backward_shift_and_homogeneity_identities():
     rhs = np.real(np.sum(np.conj(g) * dc))
     lhs = np.sum(np.real(np.conj(gval) * lat.val)) + np.sum(gons * lat.onsite)
     assert abs(lhs - rhs) < 1e-10 * max(1, abs(rhs))
+
+
+# ----------------------------------------------------------------------------
+# LDOS by propagation and wave-function snapshots (Sec. "Local density of
+# states"; the wave-packet propagation example of the usage section)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", sorted(SMALL_LATTICES))
+@pytest.mark.parametrize("tol,bound", [(1e-16, 5e-13), (1e-12, 2e-10)])
+def test_psi_t_snapshots_vs_ed(name, tol, bound):
+    """psi(k dt) = U exp(-i E k dt) U^dagger psi(0) for every requested step."""
+    lat = SMALL_LATTICES[name]()
+    h = lat.dense()
+    f = max(oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite), 1e-3) * 1.05
+    dt = math.pi / f
+    psi0 = inputs.random_phase_states(np.random.default_rng(8), lat.n_orb, 2)
+    steps = [0, 1, 7, 64, 20]
+    snaps, _ = oracle.psi_t(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, steps, dt, f, tol=tol)
+    e, u = np.linalg.eigh(h)
+    for q, k in enumerate(steps):
+        ref = u @ (np.exp(-1j * e * k * dt)[:, None] * (u.conj().T @ psi0))
+        assert np.max(np.abs(snaps[q] - ref)) < bound, (name, k)
+    assert np.array_equal(snaps[0], psi0)
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex", "square5x7_open"])
+def test_ldos_unit_state_vs_eigenvector_weights(name):
+    """With amplitude only on orbital i, C(t) = sum_j |U_ij|^2 exp(-i e_j t)
+    (Sec. "Local density of states")."""
+    lat = SMALL_LATTICES[name]()
+    e, u = np.linalg.eigh(lat.dense())
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    orbs = [0, 5, lat.n_orb - 1]
+    nt = 48
+    corr, norm2, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, inputs.unit_states(lat.n_orb, orbs),
+                                      nt, dt, f, tol=1e-16)
+    tk = np.arange(nt) * dt
+    for q, i in enumerate(orbs):
+        ref = np.exp(-1j * np.outer(tk, e)) @ (np.abs(u[i]) ** 2)
+        assert np.max(np.abs(corr[:, q] - ref)) < 5e-13
+    assert np.max(np.abs(norm2 - 1)) < 5e-13
+
+
+def test_ldos_over_all_orbitals_is_the_trace():
+    """The LDOS correlations of all orbitals average to Tr exp(-iHt) / N, so
+    their DOS is the exact DOS of the spectrum."""
+    lat = SMALL_LATTICES["graphene6x6_disorder"]()
+    e = np.linalg.eigvalsh(lat.dense())
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    nt = 64
+    corr, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite,
+                                  inputs.unit_states(lat.n_orb, np.arange(lat.n_orb)), nt, dt, f, tol=1e-16)
+    tk = np.arange(nt) * dt
+    trace = np.exp(-1j * np.outer(tk, e)).mean(axis=1)
+    assert np.max(np.abs(corr.mean(axis=1) - trace)) < 5e-13
+    _, d_ldos = oracle.dos(corr, dt)
+    _, d_exact = oracle.dos(trace[:, None], dt)
+    assert np.max(np.abs(d_ldos - d_exact)) < 1e-12 * np.max(np.abs(d_exact))
+
+
+def test_local_states_and_gaussian_packet():
+    rng = np.random.default_rng(3)
+    st = inputs.local_random_states(rng, 50, [3, 7, 11], 4)
+    assert np.allclose(np.linalg.norm(st, axis=0), 1.0)
+    assert np.count_nonzero(np.abs(st).sum(axis=1)) == 3
+    pos = inputs.graphene_positions(20, 8)
+    c = pos[:, :2].mean(axis=0)
+    g = inputs.gaussian_packet(pos, c, sigma=2.0)
+    assert abs(np.linalg.norm(g) - 1) < 1e-14
+    w = np.abs(g) ** 2
+    assert np.allclose((w[:, None] * pos[:, :2]).sum(axis=0), c, atol=0.3)
+    g1 = inputs.gaussian_packet(pos, c, sigma=2.0, extent=(1.0, 0.0))  # depends on x only
+    same_x = np.isclose(pos[:, 0], pos[0, 0])
+    assert np.allclose(g1[same_x], g1[same_x][0])
