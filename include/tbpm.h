@@ -199,6 +199,26 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
                            uint32_t flags, void *stream);
 
 /*
+ * Wave-function propagation with snapshots (the paper's usage section,
+ * propagation of a wave packet; Sec. "Tight-binding propagation method",
+ * Eq. (eq:psi_t)): propagate psi0 with the same series and time step as
+ * tbpm_propagate and store psi(k dt) for every k in steps.
+ *   steps   host, n_snap distinct step indices >= 0 (any order); step 0 is
+ *           psi0 itself.  The propagation runs to max(steps).
+ *   snaps   device, [n_snap][n_orb][n_states] complex128, written:
+ *           snaps[q] = psi(steps[q] dt), orbitals in the caller's order.
+ *   corr    device [max(steps)+1][n_states] complex128 receiving
+ *           <psi0|psi(k dt)> as in tbpm_propagate, or NULL.
+ *   prec    TBPM_FP64 or TBPM_FP32_MIXED (snapshots are stored in FP64).
+ * Other arguments, errors and the norm check as for tbpm_propagate.  The
+ * snapshot buffer is the caller's; the library keeps nothing of it.
+ */
+tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, const int32_t *steps,
+                                     int32_t n_snap, double dt, double rescale, double bessel_tol,
+                                     tbpm_precision prec, double *snaps, double *corr, uint32_t flags,
+                                     void *stream);
+
+/*
  * DOS from the correlations (paper, Eq. (dos_tbpm), with C(-t) = C(t)^*):
  *   Cbar_k = (1/S) sum_s corr[k][s],
  *   E_j = j pi / (N_t dt),  j = -N_t .. N_t - 1   (2 N_t energies),

@@ -230,6 +230,64 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
     }
 }
 
+tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, const int32_t *steps,
+                                     int32_t n_snap, double dt, double rescale, double bessel_tol,
+                                     tbpm_precision prec, double *snaps, double *corr, uint32_t flags,
+                                     void *stream) {
+    if (!H || !psi0 || !steps || !snaps) return fail(TBPM_E_ARG, "H, psi0, steps and snaps must not be NULL");
+    if (n_snap < 1) return fail(TBPM_E_ARG, "n_snap must be >= 1");
+    int32_t last = 0;
+    std::vector<int32_t> sorted(steps, steps + n_snap);
+    std::sort(sorted.begin(), sorted.end());
+    if (sorted.front() < 0) return fail(TBPM_E_ARG, "snapshot steps must be >= 0");
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(TBPM_E_ARG, "snapshot steps must be distinct");
+    last = sorted.back();
+    if (last >= (1 << 28)) return fail(TBPM_E_ARG, "snapshot step too large");
+    const int32_t n_steps = last + 1;
+    tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
+    if (st != TBPM_OK) return st;
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const double f = resolve_rescale(H->csr, rescale);
+    hipStream_t hs = (hipStream_t)stream;
+    // psi(0) is the caller's state itself
+    const size_t snap_bytes = sizeof(double) * 2 * (size_t)H->csr.n * n_states;
+    for (int32_t q = 0; q < n_snap; ++q)
+        if (steps[q] == 0) {
+            hipError_t e = hipMemcpyAsync(snaps + 2 * (size_t)q * H->csr.n * n_states, psi0, snap_bytes,
+                                          hipMemcpyDeviceToDevice, hs);
+            if (e != hipSuccess) return hip_fail(e, "copy snapshot 0");
+        }
+    double *c0 = corr;
+    if (!c0) {
+        hipError_t e = H->eng.corr_scratch.ensure(sizeof(double) * 2 * (size_t)n_steps * n_states);
+        if (e != hipSuccess) return hip_fail(e, "alloc correlation scratch");
+        c0 = (double *)H->eng.corr_scratch.ptr;
+    }
+    const double *p0 = psi0;
+    double *n0 = nullptr;
+    Engine::RunArgs a{};
+    a.psi0 = &p0;
+    a.s_user = n_states;
+    a.n_steps = n_steps;
+    a.dt = &dt;
+    a.rescale = &f;
+    a.tol = bessel_tol;
+    a.fp32 = prec == TBPM_FP32_MIXED;
+    a.corr = &c0;
+    a.norm2 = &n0;
+    a.ckpt = snaps;
+    a.snap_steps = steps;
+    a.n_snap = n_snap;
+    a.flags = flags;
+    a.stream = hs;
+    try {
+        return H->eng.run(a);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
 tbpm_status tbpm_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, tbpm_window win,
                      double *energies, double *dos, void *stream) {
     if (!corr || !energies || !dos) return fail(TBPM_E_ARG, "NULL argument");

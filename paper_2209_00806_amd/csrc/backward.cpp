@@ -122,7 +122,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     pp.phi0_ld = s_pad;
     pp.partials = (double *)eng.partials.ptr;
     pp.ckpt = nullptr;
-    pp.ckpt_every = 0;
+    pp.ckpt_slot = nullptr;
     pp.s_user = s_user;
 
     AdjParams ap{};

@@ -77,8 +77,7 @@ bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
         fused != o.fused || n_tiles != o.n_tiles || tiles_chunks != o.tiles_chunks || tiles_unit != o.tiles_unit ||
-        lds_units != o.lds_units || ckpt_every != o.ckpt_every ||
-        ckpt_max != o.ckpt_max || n_steps != o.n_steps || ckpt != o.ckpt)
+        lds_units != o.lds_units || n_steps != o.n_steps || ckpt != o.ckpt)
         return false;
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         if (bufs[i] != o.bufs[i]) return false;
@@ -265,7 +264,7 @@ void Engine::release() {
     DevBuf *bufs[] = {&v,        &ba,        &bb,      &phi0,      &partials,  &counter,  &coef,
                       &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
                       &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx, &fu_n1, &fu_hoff,
-                      &fu_hw,    &fu_hidx,  &bc,       &bd};
+                      &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -556,12 +555,17 @@ tbpm_status Engine::run(const RunArgs &a) {
     TRY_HIP(ptr_tab.ensure(sizeof(void *) * 3 * (size_t)ni), "alloc pointer table");
     TRY_HIP(inst_row0_dev.ensure(sizeof(int64_t) * (ni + 1)), "alloc inst_row0");
 
+    // slot of each stored psi(k dt): checkpoints at k = m K (k <= n_steps - 2)
+    // into slot m - 1, or the listed snapshot steps into their list position
+    const size_t slot_bytes = a.ckpt ? sizeof(int32_t) * (size_t)a.n_steps : 0;
+    if (a.ckpt) TRY_HIP(ckpt_slot.ensure(slot_bytes), "alloc checkpoint slots");
+
     // stage the small tables through pinned memory, stream-ordered
     const size_t coef_bytes = sizeof(PassCoef) * (size_t)n_passes * ni;
     const size_t tab_bytes = sizeof(void *) * 3 * (size_t)ni;
     const size_t row_bytes = sizeof(int64_t) * (ni + 1);
     TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
-    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes), "alloc staging");
+    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes + slot_bytes), "alloc staging");
     char *sp = (char *)staging.ptr;
     PassCoef *hc = (PassCoef *)sp;
     for (int p = 0; p < n_passes; ++p)
@@ -579,6 +583,17 @@ tbpm_status Engine::run(const RunArgs &a) {
     TRY_HIP(hipMemcpyAsync(inst_row0_dev.ptr, sp + coef_bytes + tab_bytes, row_bytes, hipMemcpyHostToDevice,
                            a.stream),
             "upload row offsets");
+    if (a.ckpt) {
+        int32_t *hs = (int32_t *)(sp + coef_bytes + tab_bytes + row_bytes);
+        for (int32_t k = 0; k < a.n_steps; ++k) hs[k] = -1;
+        if (a.n_snap > 0) {
+            for (int32_t q = 0; q < a.n_snap; ++q)
+                if (a.snap_steps[q] > 0 && a.snap_steps[q] < a.n_steps) hs[a.snap_steps[q]] = q;
+        } else {
+            for (int32_t k = a.ckpt_every; k <= a.n_steps - 2; k += a.ckpt_every) hs[k] = k / a.ckpt_every - 1;
+        }
+        TRY_HIP(hipMemcpyAsync(ckpt_slot.ptr, hs, slot_bytes, hipMemcpyHostToDevice, a.stream), "upload slots");
+    }
     TRY_HIP(hipEventRecord(staging_done, a.stream), "record staging");
 
     void *bufptr[5] = {v.ptr, ba.ptr, bb.ptr, bc.ptr, bd.ptr};
@@ -696,9 +711,8 @@ tbpm_status Engine::run(const RunArgs &a) {
                 pp.partials = (double *)partials.ptr;
                 pp.ckpt = a.ckpt;
                 pp.perm = mat.perm;
+                pp.ckpt_slot = a.ckpt ? (const int32_t *)ckpt_slot.ptr : nullptr;
                 pp.ckpt_stride = mat.n_rows * a.s_user;
-                pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
-                pp.ckpt_max = a.n_steps - 2;
                 pp.s_user = a.s_user;
                 hipError_t e =
                     launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs, pp, s);
@@ -732,9 +746,8 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.partials = (double *)partials.ptr;
             pp.ckpt = a.ckpt;
             pp.perm = mat.perm;
+            pp.ckpt_slot = a.ckpt ? (const int32_t *)ckpt_slot.ptr : nullptr;
             pp.ckpt_stride = mat.n_rows * a.s_user;
-            pp.ckpt_every = a.ckpt ? a.ckpt_every : 0;
-            pp.ckpt_max = a.n_steps - 2;
             pp.s_user = a.s_user;
             pp.uoff = (const int32_t *)st_uoff.ptr;
             pp.ucol = (const int32_t *)st_ucol.ptr;
@@ -774,13 +787,13 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.tiles_chunks = tiles_chunks;
             key.tiles_unit = tiles_unit;
             key.lds_units = fused ? fu_lds_units : (staged ? stage_units : 0);
-            key.ckpt_every = a.ckpt ? a.ckpt_every : 0;
-            key.ckpt_max = a.n_steps - 2;
+
             key.n_steps = a.n_steps;
             key.ckpt = a.ckpt;
-            const void *kb[17] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
+            const void *kb[18] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
                                   tiles.ptr,   norm2_all.ptr, bc.ptr,      bd.ptr,      st_uoff.ptr,  st_ucol.ptr,
-                                  st_lidx.ptr, fu_hidx.ptr, fu_n1.ptr,     fu_hoff.ptr, fu_hw.ptr};
+                                  st_lidx.ptr, fu_hidx.ptr, fu_n1.ptr,     fu_hoff.ptr, fu_hw.ptr,
+                                  a.ckpt ? ckpt_slot.ptr : nullptr};
             static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
             if (!graph_exec || !(key == graph_key)) {

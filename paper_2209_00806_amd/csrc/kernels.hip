@@ -75,10 +75,12 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
     bool do_ckpt = false;
     uint32_t ckpt_base = 0;
     if constexpr (CORR) {
-        if (p.ckpt_every > 0) {
+        if (p.ckpt_slot) {
+            // the step counter holds k of the psi(k dt) this pass produces
             const int step = *(volatile const int32_t *)p.counter;
-            do_ckpt = (step % p.ckpt_every == 0) && step <= p.ckpt_max && step > 0;
-            ckpt_base = (uint32_t)(step / p.ckpt_every - 1);
+            const int slot = p.ckpt_slot[step];
+            do_ckpt = slot >= 0;
+            ckpt_base = (uint32_t)(do_ckpt ? slot : 0);
         }
     }
 
@@ -240,10 +242,12 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     bool do_ckpt = false;
     uint32_t ckpt_base = 0;
     if constexpr (CORR) {
-        if (p.ckpt_every > 0) {
+        if (p.ckpt_slot) {
+            // the step counter holds k of the psi(k dt) this pass produces
             const int step = *(volatile const int32_t *)p.counter;
-            do_ckpt = (step % p.ckpt_every == 0) && step <= p.ckpt_max && step > 0;
-            ckpt_base = (uint32_t)(step / p.ckpt_every - 1);
+            const int slot = p.ckpt_slot[step];
+            do_ckpt = slot >= 0;
+            ckpt_base = (uint32_t)(do_ckpt ? slot : 0);
         }
     }
 

@@ -71,9 +71,9 @@ struct GraphKey {
     int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
     // identity of the tile tables the launches were captured with
     int32_t n_tiles = 0, tiles_chunks = 0, tiles_unit = 0, lds_units = 0;
-    int32_t ckpt_every = 0, ckpt_max = 0, n_steps = 0;
+    int32_t n_steps = 0;
     const void *ckpt = nullptr;
-    const void *bufs[17] = {};
+    const void *bufs[18] = {};
     bool operator==(const GraphKey &o) const;
 };
 
@@ -96,6 +96,9 @@ struct Engine {
 
     // work buffers
     DevBuf v, ba, bb, phi0, partials, counter, coef, norm2_all, tiles, inst_tile0, ptr_tab, inst_row0_dev;
+    // per-step slot of the stored states (checkpoints or snapshots), and a
+    // correlation buffer for calls that do not ask for one
+    DevBuf ckpt_slot, corr_scratch;
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
@@ -137,6 +140,11 @@ struct Engine {
         double *const *norm2;  // n_inst device pointers (entries may be null) or null
         int32_t ckpt_every;
         double *ckpt;
+        // snapshots of psi(k dt) for the listed steps (k > 0; step 0 is the
+        // caller's psi0 and is copied by the caller of run) into ckpt slots;
+        // used instead of ckpt_every when n_snap > 0
+        const int32_t *snap_steps;
+        int32_t n_snap;
         uint32_t flags;
         hipStream_t stream;
     };

@@ -91,12 +91,11 @@ struct PassParams {
     const double *phi0;    // complex128 [rows][S]
     int64_t phi0_ld;       // states per row of phi0 (>= S padded or the caller's S)
     double *partials;      // [S][3][n_tiles]
-    // checkpoints (last pass, FP64 only)
-    double *ckpt;          // complex128 [n_ckpt][rows][s_user], rows in the caller's order
-    const int32_t *perm;   // internal row -> caller's row (single member), or null
-    int64_t ckpt_stride;   // complex elements per checkpoint (rows * s_user)
-    int32_t ckpt_every;
-    int32_t ckpt_max;      // largest step index that is stored
+    // stored states (last pass): checkpoints or snapshots of psi(k dt)
+    double *ckpt;              // complex128 [n_slots][rows][s_user], rows in the caller's order
+    const int32_t *ckpt_slot;  // [n_steps]: slot of psi(k dt) in ckpt, or -1; null: none stored
+    const int32_t *perm;       // internal row -> caller's row (single member), or null
+    int64_t ckpt_stride;       // complex elements per slot (rows * s_user)
     int32_t s_user;
     // LDS staging (staged launch shape): tile t reads its own rows and the
     // external rows ucol[uoff[t] .. uoff[t+1]); lidx[slot] is the local row of

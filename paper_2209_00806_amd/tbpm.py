@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         "tbpm_num_terms": [D, D, P],
         "tbpm_bessel_j": [D, I32, P],
         "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
+        "tbpm_propagate_snapshots": [P, P, I32, P, I32, D, D, D, ctypes.c_int, P, P, U32, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
         "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
         "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
@@ -279,6 +280,53 @@ def propagate(H: Hamiltonian, psi0, n_steps: int, dt: float, rescale: float = 0.
     if ckpt_every > 0:
         res.append(ckpt)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def propagate_snapshots(H: Hamiltonian, psi0, steps, dt: float, rescale: float = 0.0, tol: float = 1e-12,
+                        precision: str = "fp64", return_corr: bool = False, stream=None):
+    """psi(k dt) for every k in ``steps`` (distinct, >= 0), for psi0 a CUDA
+    complex128 tensor [n_orb, S] (or [n_orb]).  Returns snapshots
+    [len(steps), n_orb, S] complex128 (and corr [max(steps)+1, S] if asked)."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    squeeze = psi0.dim() == 1
+    if squeeze:
+        psi0 = psi0.reshape(-1, 1)
+    n, S = psi0.shape
+    st = np.ascontiguousarray(np.asarray(steps, dtype=np.int64).reshape(-1).astype(np.int32))
+    if st.size == 0:
+        raise ValueError("steps must not be empty")
+    snaps = torch.empty((st.size, n, S), dtype=torch.complex128, device=psi0.device)
+    corr = torch.empty((int(st.max()) + 1, S), dtype=torch.complex128, device=psi0.device) if return_corr else None
+    _check(lib().tbpm_propagate_snapshots(H.handle, _ptr(psi0), S, st.ctypes.data, int(st.size), float(dt),
+                                          float(rescale), float(tol), _prec(precision), _ptr(snaps), _ptr(corr), 0,
+                                          _stream(stream)))
+    if squeeze:
+        snaps = snaps[:, :, 0]
+    return (snaps, corr) if return_corr else snaps
+
+
+def ldos(H: Hamiltonian, orbitals, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,
+         precision: str = "fp64", window: str = "hann", stream=None):
+    """Local density of states by propagation (Sec. "Local density of
+    states"): each listed orbital's unit vector is propagated, and the DOS
+    transform of the correlations, averaged over the orbitals, is returned
+    as (energies, ldos) CUDA float64 tensors.  Orbitals go 64 per launch."""
+    import torch
+
+    orbs = np.asarray(orbitals, dtype=np.int64).reshape(-1)
+    n = H.info()["n_orb"]
+    if orbs.size == 0 or orbs.min() < 0 or orbs.max() >= n:
+        raise ValueError("orbitals must be non-empty and inside [0, n_orb)")
+    corr_all = []
+    for c0 in range(0, orbs.size, 64):
+        chunk = orbs[c0:c0 + 64]
+        psi0 = torch.zeros((n, chunk.size), dtype=torch.complex128, device="cuda")
+        psi0[torch.from_numpy(chunk).cuda(), torch.arange(chunk.size, device="cuda")] = 1.0
+        corr_all.append(propagate(H, psi0, n_steps, dt, rescale, tol, precision, stream=stream))
+    corr = torch.cat(corr_all, dim=1).contiguous()
+    return dos(corr, dt, window, stream=stream)
 
 
 def dos(corr, dt: float, window: str = "hann", stream=None):
