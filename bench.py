@@ -154,6 +154,68 @@ def bench_batched(args, log):
     return out
 
 
+def bench_ldos_psi_t(args, log, cfg64=None):
+    """LDOS by propagation (8 unit-vector states on the disordered 1024^2
+    graphene of the headline, FP64) and wave-function snapshots (a Gaussian
+    packet in pristine 1024^2 graphene, 1 state, 128 steps, snapshots at 0, 16,
+    32, 64, 128 as in the usage-section example, FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_2209_00806_amd import inputs, tbpm
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    f = 9.0
+    dt = math.pi / f
+    M = tbpm.num_terms(f * dt, 1e-12)
+    lat, _ = inputs.workload_disordered_graphene(args.cells, 1)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if cfg64:  # the headline's autotuned shape (same operator and state count)
+        H.set_launch_config(precision="fp64", **cfg64)
+    orbs = np.linspace(0, lat.n_orb - 1, 8).astype(np.int64)
+    nt = args.ldos_nt
+    tbpm.ldos(H, orbs, 8, dt, f)  # warm-up (tiles, graph)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    _, D = tbpm.ldos(H, orbs, nt, dt, f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = (lat.nnz + lat.n_orb) * len(orbs) * (M - 1) * (nt - 1)
+    out["ldos"] = {"orbitals": len(orbs), "n_steps": nt, "ms": round(ms, 1), "nnz_updates_per_s": upd / (ms / 1e3),
+                   "alg_GBps": round(step_bytes(M, lat.n_orb, lat.nnz, len(orbs), 16, 8) * (nt - 1) / (ms / 1e3) / 1e9,
+                                     1),
+                   "ldos_integral": float(D.sum().item() * (2 * f / (2 * nt)))}
+    log(f"ldos: 8 orbitals, {nt} samples, {ms:.1f} ms, {upd / (ms / 1e3):.3e} nnz-updates/s")
+    H.close()
+    del H
+    lat = inputs.graphene(args.cells, args.cells)
+    pos = inputs.graphene_positions(args.cells, args.cells)
+    psi0 = torch.from_numpy(inputs.gaussian_packet(pos, pos[:, :2].mean(axis=0), sigma=5.0)).cuda()
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if cfg64:
+        H.set_launch_config(precision="fp64", **cfg64)
+    steps = [0, 16, 32, 64, 128]
+    tbpm.propagate_snapshots(H, psi0, [0, 4], dt, f)  # warm-up
+    torch.cuda.synchronize()
+    e0.record(stream)
+    snaps = tbpm.propagate_snapshots(H, psi0, steps, dt, f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = (lat.nnz + lat.n_orb) * (M - 1) * max(steps)
+    norms = [float(torch.linalg.norm(snaps[q]).item()) for q in range(len(steps))]
+    out["psi_t"] = {"n_orb": lat.n_orb, "steps": steps, "ms": round(ms, 2), "nnz_updates_per_s": upd / (ms / 1e3),
+                    "alg_GBps": round(step_bytes(M, lat.n_orb, lat.nnz, 1, 16, 8) * max(steps) / (ms / 1e3) / 1e9, 1),
+                    "max_norm_dev": max(abs(x - 1) for x in norms)}
+    log(f"psi_t: {len(steps)} snapshots over {max(steps)} steps, {ms:.1f} ms, {upd / (ms / 1e3):.3e} nnz-updates/s")
+    H.close()
+    return out
+
+
 def bench_tbg(args, log):
     """Twisted bilayer flake (two 1024^2-cell layers, 1.05 deg, ~19 stored elements per
     row, irregular rows, open boundaries): 16 states, 1024 steps, FP32-mixed, with a
@@ -284,6 +346,8 @@ def main():
     ap.add_argument("--bwd-cells", type=int, default=512)
     ap.add_argument("--bwd-nt", type=int, default=1024)
     ap.add_argument("--no-tbg", action="store_true")
+    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS and wave-function snapshot legs")
+    ap.add_argument("--ldos-nt", type=int, default=512)
     ap.add_argument("--tbg-cells", type=int, default=1024)
     ap.add_argument("--tbg-nt", type=int, default=1024)
     args = ap.parse_args()
@@ -459,6 +523,8 @@ def main():
         extra["backward"] = bench_backward(args, log)
     if not args.no_tbg:
         extra["twisted_bilayer"] = bench_tbg(args, log)
+    if not args.no_ldos:
+        extra.update(bench_ldos_psi_t(args, log, launch_cfg["fp64"] if tuned else None))
 
     cpu = None
     if not args.no_cpu_baseline:

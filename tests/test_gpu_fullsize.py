@@ -109,3 +109,32 @@ def test_batch_workload_full_size_sampled():
         ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, states[i][:, s:s + 1].copy(), nt,
                                      dts[i], fs[i])
         assert _rel(corrs[i].cpu().numpy()[:, s], ref[:, 0]) < 1e-10, (int(i), l.n_orb)
+
+
+def test_ldos_and_snapshots_full_size_prefix():
+    """The 1024x1024 lattices of the LDOS and wave-packet bench legs, on a
+    prefix of steps the oracle finishes quickly: LDOS correlations of two
+    orbitals of the disordered lattice, and snapshots of a Gaussian packet in
+    the pristine one, both through the automatic row order."""
+    print("case ldos + snapshots 1024x1024", flush=True)
+    f = 9.0
+    dt = math.pi / f
+    lat, _ = inputs.workload_disordered_graphene(1024, 1)
+    orbs = [12345, lat.n_orb - 7]
+    st = inputs.unit_states(lat.n_orb, orbs)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    assert H.row_order() == 1
+    nt = 20
+    corr = tbpm.propagate(H, _dev(st), nt, dt, f).cpu().numpy()
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, st, nt, dt, f)
+    assert _rel(corr, ref) < 1e-10
+    H.close()
+    lat = inputs.graphene(1024, 1024)
+    pos = inputs.graphene_positions(1024, 1024)
+    psi0 = inputs.gaussian_packet(pos, pos[:, :2].mean(axis=0), sigma=5.0)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    steps = [0, 5, 16]
+    got = tbpm.propagate_snapshots(H, _dev(psi0), steps, dt, f).cpu().numpy()
+    snaps, _ = oracle.psi_t(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, None], steps, dt, f)
+    for q in range(len(steps)):
+        assert _rel(got[q], snaps[q][:, 0]) < 1e-10
