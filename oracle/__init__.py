@@ -15,6 +15,8 @@ Pieces:
     ``tbpm_oracle.c``), recording C_k = <phi0|psi_k> and ||psi_k||^2;
   * :func:`psi_t` -- the same propagation, returning psi at chosen steps
     (wave-packet snapshots);
+  * :func:`quasi_eigenstates` -- windowed Fourier transform of psi(t) over
+    positive and negative times at chosen energies;
   * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
     correlation, summed directly (no FFT);
   * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
@@ -167,6 +169,35 @@ def psi_t(row_ptr, col, val, onsite, psi0, steps, dt: float, rescale: float, tol
     if rc != 0:
         raise ValueError("oracle_psi_t failed (negative step or allocation failure)")
     return snaps, {"rescale": f, "z": f * dt, "M": M, "J": J}
+
+
+def quasi_eigenstates(row_ptr, col, val, onsite, psi0, n_steps: int, dt: float, rescale: float, energies_ev,
+                      tol: float = 1e-12, kind: str = "hann"):
+    """Quasi-eigenstates (paper, Sec. "Quasieigenstates", Eq. (quasi)): the
+    windowed inverse Fourier transform of psi(t) over positive and negative
+    times,
+        Psi(E) = sum_{k=-(N_t-1)}^{N_t-1} w_|k| e^{i E k dt} psi(k dt),
+    with psi(-k dt) propagated with the time step -dt, normalised to unit norm
+    per energy and state.
+
+    Returns (states [n_E, n, S] complex128, norm2 [n_E, S] = ||Psi(E)||^2
+    before normalisation).
+    """
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    steps = np.arange(n_steps)
+    fwd, _ = psi_t(row_ptr, col, val, onsite, psi0, steps, dt, rescale, tol)
+    bwd, _ = psi_t(row_ptr, col, val, onsite, psi0, steps, -dt, rescale, tol)
+    w = window(n_steps, kind)
+    e = np.atleast_1d(np.asarray(energies_ev, dtype=np.float64))
+    out = np.zeros((e.shape[0], n, S), dtype=np.complex128)
+    norm2 = np.zeros((e.shape[0], S))
+    for j in range(e.shape[0]):
+        ph = w * np.exp(1j * e[j] * steps * dt)
+        acc = np.tensordot(ph, fwd, axes=(0, 0)) + np.tensordot(np.conj(ph[1:]), bwd[1:], axes=(0, 0))
+        norm2[j] = np.sum(np.abs(acc) ** 2, axis=0)
+        out[j] = acc / np.sqrt(norm2[j])
+    return out, norm2
 
 
 def energies(n_steps: int, dt: float) -> np.ndarray:

@@ -411,3 +411,54 @@ def test_local_states_and_gaussian_packet():
     g1 = inputs.gaussian_packet(pos, c, sigma=2.0, extent=(1.0, 0.0))  # depends on x only
     same_x = np.isclose(pos[:, 0], pos[0, 0])
     assert np.allclose(g1[same_x], g1[same_x][0])
+
+
+# ----------------------------------------------------------------------------
+# Quasi-eigenstates (Sec. "Quasieigenstates", Eq. (quasi))
+# ----------------------------------------------------------------------------
+
+def _window_kernel(x, nt, dt):
+    """W(x) = sum_{k=-(nt-1)}^{nt-1} w_|k| e^{i x k dt} = w_0 + 2 sum_{k>=1} w_k cos(x k dt)."""
+    k = np.arange(1, nt)
+    w = 0.5 * (1 + np.cos(np.pi * k / nt))
+    return 1.0 + 2.0 * np.cos(np.outer(np.atleast_1d(x), k * dt)) @ w
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex", "tbg6x6"])
+def test_quasi_eigenstates_vs_eigen_expansion(name):
+    """Psi(E) = sum_i a_i W(E - E_i) phi_i with a_i = <phi_i|psi0> and the real
+    window kernel W, then normalised."""
+    lat = SMALL_LATTICES[name]()
+    e, u = np.linalg.eigh(lat.dense())
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    nt = 40
+    psi0 = inputs.random_phase_states(np.random.default_rng(9), lat.n_orb, 2)
+    E = np.array([-2.7, -0.31, 0.0, 1.234, e[5]])
+    qe, norm2 = oracle.quasi_eigenstates(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f, E, tol=1e-16)
+    a = u.conj().T @ psi0
+    for j in range(E.shape[0]):
+        ref = u @ (_window_kernel(E[j] - e, nt, dt)[:, None] * a)
+        n2 = np.sum(np.abs(ref) ** 2, axis=0)
+        assert np.max(np.abs(norm2[j] - n2)) < 1e-10 * n2.max()
+        assert np.max(np.abs(qe[j] - ref / np.sqrt(n2))) < 1e-11
+        assert np.allclose(np.linalg.norm(qe[j], axis=0), 1.0)
+
+
+def test_quasi_eigenstate_of_the_dimer_is_its_eigenstate():
+    """For H = [[0, t], [t, 0]] and enough steps, the quasi-eigenstate at E = t
+    is the bonding state (1, 1)/sqrt(2) up to a phase."""
+    t = 1.3
+    rp = np.array([0, 1, 2])
+    col = np.array([1, 0], dtype=np.int32)
+    val = np.array([t, t], dtype=np.complex128)
+    ons = np.zeros(2)
+    psi0 = np.array([[0.8 + 0.1j], [0.2 - 0.55j]])
+    psi0 /= np.linalg.norm(psi0)
+    f = 1.5
+    dt = math.pi / f
+    qe, _ = oracle.quasi_eigenstates(rp, col, val, ons, psi0, 64, dt, f, [t, -t], tol=1e-16)
+    plus = np.array([1, 1]) / np.sqrt(2)
+    minus = np.array([1, -1]) / np.sqrt(2)
+    assert abs(abs(np.vdot(plus, qe[0][:, 0])) - 1) < 1e-6
+    assert abs(abs(np.vdot(minus, qe[1][:, 0])) - 1) < 1e-6
