@@ -219,6 +219,27 @@ tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, in
                                      void *stream);
 
 /*
+ * Quasi-eigenstates (Sec. "Quasieigenstates", Eq. (quasi)): for each energy
+ * E_j and state s,
+ *   Psi_s(E_j) = sum_{k=-(n_steps-1)}^{n_steps-1} w_|k| e^{i E_j k dt} psi_s(k dt),
+ * normalised to unit norm, where psi_s(t) propagates psi0_s with the series
+ * of tbpm_propagate (negative times with the time step -dt) and w is the
+ * window of tbpm_dos (Hann, or none).  Energies are in eV, the units of H.
+ *   energies  host, n_energies values (1 .. 256)
+ *   states    device, [n_energies][n_orb][n_states] complex128, written,
+ *             orbitals in the caller's order
+ *   norm2     device [n_energies][n_states] f64 receiving ||Psi_s(E_j)||^2
+ *             before normalisation, or NULL.  A zero norm (an energy far
+ *             outside the spectrum) leaves that state zero.
+ * The library keeps n_energies * n_orb * (n_states padded to a power of 2)
+ * complex128 accumulators.  Other arguments and errors as tbpm_propagate.
+ */
+tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                                   double dt, double rescale, double bessel_tol, tbpm_precision prec,
+                                   const double *energies, int32_t n_energies, tbpm_window win, double *states,
+                                   double *norm2, uint32_t flags, void *stream);
+
+/*
  * DOS from the correlations (paper, Eq. (dos_tbpm), with C(-t) = C(t)^*):
  *   Cbar_k = (1/S) sum_s corr[k][s],
  *   E_j = j pi / (N_t dt),  j = -N_t .. N_t - 1   (2 N_t energies),

@@ -288,6 +288,85 @@ tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, in
     }
 }
 
+tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                                   double dt, double rescale, double bessel_tol, tbpm_precision prec,
+                                   const double *energies, int32_t n_energies, tbpm_window win, double *states,
+                                   double *norm2, uint32_t flags, void *stream) {
+    if (!H || !psi0 || !energies || !states) return fail(TBPM_E_ARG, "H, psi0, energies and states must not be NULL");
+    tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
+    if (st != TBPM_OK) return st;
+    if (n_energies < 1 || n_energies > 256) return fail(TBPM_E_ARG, "n_energies must be in [1, 256]");
+    for (int32_t j = 0; j < n_energies; ++j)
+        if (!std::isfinite(energies[j])) return fail(TBPM_E_ARG, "energies must be finite");
+    if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const double f = resolve_rescale(H->csr, rescale);
+    Engine &eng = H->eng;
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < n_states) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    const int64_t n_rows = H->csr.n;
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t acc_doubles = 2 * (size_t)n_energies * n_rows * s_pad;
+    hipError_t e = eng.qe_acc.ensure(sizeof(double) * acc_doubles);
+    if (e == hipSuccess) e = eng.qe_part.ensure(sizeof(double) * 3 * (size_t)n_energies * s_pad *
+                                                qe_partial_blocks(n_rows));
+    if (e == hipSuccess) e = eng.qe_norm2.ensure(sizeof(double) * (size_t)n_energies * n_states);
+    if (e == hipSuccess) e = eng.corr_scratch.ensure(sizeof(double) * 2 * (size_t)n_steps * n_states);
+    if (e != hipSuccess) return hip_fail(e, "alloc quasi-eigenstate buffers");
+    e = launch_fill_zero((double *)eng.qe_acc.ptr, (int64_t)acc_doubles, hs);
+    if (e != hipSuccess) return hip_fail(e, "clear accumulators");
+    // coef[k][j] = w_k e^{i E_j t_k} for t_k = +k dt, then -k dt (k = 0 counted once)
+    std::vector<double> coef(2 * (size_t)n_steps * n_energies);
+    for (int pass = 0; pass < 2; ++pass) {
+        const double sgn = pass == 0 ? 1.0 : -1.0;
+        for (int32_t k = 0; k < n_steps; ++k) {
+            const double w = win == TBPM_WIN_HANN ? 0.5 * (1.0 + std::cos(M_PI * k / n_steps)) : 1.0;
+            for (int32_t j = 0; j < n_energies; ++j) {
+                const double ph = energies[j] * sgn * k * dt;
+                const bool skip = pass == 1 && k == 0;
+                coef[2 * ((size_t)k * n_energies + j)] = skip ? 0.0 : w * std::cos(ph);
+                coef[2 * ((size_t)k * n_energies + j) + 1] = skip ? 0.0 : w * std::sin(ph);
+            }
+        }
+        const double *p0 = psi0;
+        double *c0 = (double *)eng.corr_scratch.ptr;
+        double *n0 = nullptr;
+        const double dt_run = sgn * dt;
+        Engine::RunArgs a{};
+        a.psi0 = &p0;
+        a.s_user = n_states;
+        a.n_steps = n_steps;
+        a.dt = &dt_run;
+        a.rescale = &f;
+        a.tol = bessel_tol;
+        a.fp32 = prec == TBPM_FP32_MIXED;
+        a.corr = &c0;
+        a.norm2 = &n0;
+        a.qe_coef = coef.data();
+        a.n_qe = n_energies;
+        a.qe_acc = (double *)eng.qe_acc.ptr;
+        a.flags = flags & ~(uint32_t)TBPM_FLAG_ASYNC;  // the coefficient table is rewritten for the second run
+        a.stream = hs;
+        try {
+            st = eng.run(a);
+        } catch (const std::bad_alloc &) {
+            st = fail(TBPM_E_OOM, "host allocation failed");
+        }
+        if (st != TBPM_OK) return st;
+    }
+    double *n2 = norm2 ? norm2 : (double *)eng.qe_norm2.ptr;
+    e = launch_qe_finalize((const double *)eng.qe_acc.ptr, n_rows, log2s, n_states, n_energies, eng.mat.perm,
+                           (double *)eng.qe_part.ptr, n2, states, hs);
+    if (e != hipSuccess) return hip_fail(e, "launch quasi-eigenstate normalisation");
+    if (flags & TBPM_FLAG_ASYNC) return TBPM_OK;
+    e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, tbpm_window win,
                      double *energies, double *dos, void *stream) {
     if (!corr || !energies || !dos) return fail(TBPM_E_ARG, "NULL argument");

@@ -77,7 +77,7 @@ bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
         fused != o.fused || n_tiles != o.n_tiles || tiles_chunks != o.tiles_chunks || tiles_unit != o.tiles_unit ||
-        lds_units != o.lds_units || n_steps != o.n_steps || ckpt != o.ckpt)
+        lds_units != o.lds_units || n_steps != o.n_steps || n_qe != o.n_qe || ckpt != o.ckpt)
         return false;
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         if (bufs[i] != o.bufs[i]) return false;
@@ -264,7 +264,8 @@ void Engine::release() {
     DevBuf *bufs[] = {&v,        &ba,        &bb,      &phi0,      &partials,  &counter,  &coef,
                       &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
                       &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx, &fu_n1, &fu_hoff,
-                      &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch};
+                      &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
+                      &qe_acc,   &qe_part,  &qe_norm2};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -559,13 +560,15 @@ tbpm_status Engine::run(const RunArgs &a) {
     // into slot m - 1, or the listed snapshot steps into their list position
     const size_t slot_bytes = a.ckpt ? sizeof(int32_t) * (size_t)a.n_steps : 0;
     if (a.ckpt) TRY_HIP(ckpt_slot.ensure(slot_bytes), "alloc checkpoint slots");
+    const size_t qe_bytes = a.n_qe > 0 ? sizeof(double) * 2 * (size_t)a.n_steps * a.n_qe : 0;
+    if (a.n_qe > 0) TRY_HIP(qe_coef.ensure(qe_bytes), "alloc quasi-eigenstate coefficients");
 
     // stage the small tables through pinned memory, stream-ordered
     const size_t coef_bytes = sizeof(PassCoef) * (size_t)n_passes * ni;
     const size_t tab_bytes = sizeof(void *) * 3 * (size_t)ni;
     const size_t row_bytes = sizeof(int64_t) * (ni + 1);
     TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
-    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes + slot_bytes), "alloc staging");
+    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes + slot_bytes + qe_bytes), "alloc staging");
     char *sp = (char *)staging.ptr;
     PassCoef *hc = (PassCoef *)sp;
     for (int p = 0; p < n_passes; ++p)
@@ -594,6 +597,20 @@ tbpm_status Engine::run(const RunArgs &a) {
         }
         TRY_HIP(hipMemcpyAsync(ckpt_slot.ptr, hs, slot_bytes, hipMemcpyHostToDevice, a.stream), "upload slots");
     }
+    if (a.n_qe > 0) {
+        char *hq = sp + coef_bytes + tab_bytes + row_bytes + slot_bytes;
+        std::memcpy(hq, a.qe_coef, qe_bytes);
+        TRY_HIP(hipMemcpyAsync(qe_coef.ptr, hq, qe_bytes, hipMemcpyHostToDevice, a.stream),
+                "upload quasi-eigenstate coefficients");
+    }
+    const int64_t n_el_all = mat.n_rows * s_pad;
+    auto enqueue_qe = [&](hipStream_t s) -> tbpm_status {
+        if (a.n_qe <= 0) return TBPM_OK;
+        hipError_t e = launch_qe_accum(fp32, v.ptr, a.qe_acc, n_el_all, (const double *)qe_coef.ptr, a.n_qe,
+                                       (const int32_t *)counter.ptr, s);
+        if (e != hipSuccess) return hip_fail(e, "launch quasi-eigenstate accumulation");
+        return TBPM_OK;
+    };
     TRY_HIP(hipEventRecord(staging_done, a.stream), "record staging");
 
     void *bufptr[5] = {v.ptr, ba.ptr, bb.ptr, bc.ptr, bd.ptr};
@@ -627,6 +644,8 @@ tbpm_status Engine::run(const RunArgs &a) {
     rp.norm2 = d_norm2;
     rp.norm2_all = (double *)norm2_all.ptr;
     TRY_HIP(launch_reduce(ni, s_pad, rp, a.stream), "launch reduce");
+    st = enqueue_qe(a.stream);
+    if (st != TBPM_OK) return st;
 
     // Fused schedule: FIRST and NOB2 as one pair (psi -> A, B), then MID
     // orders in pairs alternating between (A, B) and (C, D), since a pair
@@ -721,7 +740,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             }
             hipError_t e = launch_reduce(ni, s_pad, rp, s);
             if (e != hipSuccess) return hip_fail(e, "launch reduce");
-            return TBPM_OK;
+            return enqueue_qe(s);
         }
         for (int p = 0; p < n_passes; ++p) {
             const PassPlan &pl = plan[p];
@@ -760,7 +779,7 @@ tbpm_status Engine::run(const RunArgs &a) {
         }
         hipError_t e = launch_reduce(ni, s_pad, rp, s);
         if (e != hipSuccess) return hip_fail(e, "launch reduce");
-        return TBPM_OK;
+        return enqueue_qe(s);
     };
 
     if (a.n_steps > 1) {
@@ -789,11 +808,13 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.lds_units = fused ? fu_lds_units : (staged ? stage_units : 0);
 
             key.n_steps = a.n_steps;
+            key.n_qe = a.n_qe;
             key.ckpt = a.ckpt;
-            const void *kb[18] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
+            const void *kb[20] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
                                   tiles.ptr,   norm2_all.ptr, bc.ptr,      bd.ptr,      st_uoff.ptr,  st_ucol.ptr,
                                   st_lidx.ptr, fu_hidx.ptr, fu_n1.ptr,     fu_hoff.ptr, fu_hw.ptr,
-                                  a.ckpt ? ckpt_slot.ptr : nullptr};
+                                  a.ckpt ? ckpt_slot.ptr : nullptr, a.n_qe > 0 ? qe_coef.ptr : nullptr,
+                                  a.n_qe > 0 ? a.qe_acc : nullptr};
             static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
             if (!graph_exec || !(key == graph_key)) {

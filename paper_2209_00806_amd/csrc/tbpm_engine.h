@@ -71,9 +71,9 @@ struct GraphKey {
     int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
     // identity of the tile tables the launches were captured with
     int32_t n_tiles = 0, tiles_chunks = 0, tiles_unit = 0, lds_units = 0;
-    int32_t n_steps = 0;
+    int32_t n_steps = 0, n_qe = 0;
     const void *ckpt = nullptr;
-    const void *bufs[18] = {};
+    const void *bufs[20] = {};
     bool operator==(const GraphKey &o) const;
 };
 
@@ -99,6 +99,8 @@ struct Engine {
     // per-step slot of the stored states (checkpoints or snapshots), and a
     // correlation buffer for calls that do not ask for one
     DevBuf ckpt_slot, corr_scratch;
+    // quasi-eigenstates: coefficient table, accumulators, partials, norms
+    DevBuf qe_coef, qe_acc, qe_part, qe_norm2;
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
@@ -145,6 +147,12 @@ struct Engine {
         // used instead of ckpt_every when n_snap > 0
         const int32_t *snap_steps;
         int32_t n_snap;
+        // quasi-eigenstate accumulation: after the initial state and after
+        // every step, qe_acc[j] += qe_coef[k][j] psi(k dt) (qe_coef host,
+        // complex [n_steps][n_qe]; qe_acc device, [n_qe][rows][S padded])
+        const double *qe_coef;
+        int32_t n_qe;
+        double *qe_acc;
         uint32_t flags;
         hipStream_t stream;
     };

@@ -224,6 +224,15 @@ struct AdjParams {
 hipError_t launch_pair(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const FusedParams &p,
                        hipStream_t st);
 
+// quasi-eigenstate launchers (quasi.hip)
+// acc[j][e] += coef[k][j] * state[e] for j < n_e, k = *counter (state at R precision)
+hipError_t launch_qe_accum(bool fp32, const void *state, double *acc, int64_t n_el, const double *coef, int32_t n_e,
+                           const int32_t *counter, hipStream_t st);
+int32_t qe_partial_blocks(int64_t n_rows);  // partials need n_e * S * 3 * blocks doubles
+// norm2[j][s] = ||acc[j][:, s]||^2 and out[j][perm[r]][s] = acc[j][r][s] / sqrt(norm2[j][s]), s < s_user
+hipError_t launch_qe_finalize(const double *acc, int64_t n_rows, int32_t log2s, int32_t s_user, int32_t n_e,
+                              const int32_t *perm, double *partials, double *norm2, double *out, hipStream_t st);
+
 // backward launchers (backward.hip)
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
 // dst[r][s] = src[perm[r]][s] (src[r][s] if perm is null), zero for s >= s_user

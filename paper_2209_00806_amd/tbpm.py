@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
         "tbpm_bessel_j": [D, I32, P],
         "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
         "tbpm_propagate_snapshots": [P, P, I32, P, I32, D, D, D, ctypes.c_int, P, P, U32, P],
+        "tbpm_quasi_eigenstates": [P, P, I32, I32, D, D, D, ctypes.c_int, P, I32, ctypes.c_int, P, P, U32, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
         "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
         "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
@@ -305,6 +306,32 @@ def propagate_snapshots(H: Hamiltonian, psi0, steps, dt: float, rescale: float =
     if squeeze:
         snaps = snaps[:, :, 0]
     return (snaps, corr) if return_corr else snaps
+
+
+def quasi_eigenstates(H: Hamiltonian, psi0, energies, n_steps: int, dt: float, rescale: float = 0.0,
+                      tol: float = 1e-12, precision: str = "fp64", window: str = "hann", return_norm: bool = False,
+                      stream=None):
+    """Quasi-eigenstates at ``energies`` (eV) from the CUDA complex128 state(s)
+    psi0 [n_orb, S] (or [n_orb]): windowed Fourier transform of psi(t) over
+    -(n_steps-1) dt .. (n_steps-1) dt, normalised.  Returns [n_E, n_orb, S]
+    (or [n_E, n_orb]) complex128, and ||Psi(E)||^2 [n_E, S] if asked."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    squeeze = psi0.dim() == 1
+    if squeeze:
+        psi0 = psi0.reshape(-1, 1)
+    n, S = psi0.shape
+    e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).reshape(-1))
+    out = torch.empty((e.size, n, S), dtype=torch.complex128, device=psi0.device)
+    n2 = torch.empty((e.size, S), dtype=torch.float64, device=psi0.device) if return_norm else None
+    _check(lib().tbpm_quasi_eigenstates(H.handle, _ptr(psi0), S, int(n_steps), float(dt), float(rescale), float(tol),
+                                        _prec(precision), e.ctypes.data, int(e.size), WIN[window], _ptr(out), _ptr(n2), 0,
+                                        _stream(stream)))
+    if squeeze:
+        out = out[:, :, 0]
+        n2 = n2[:, 0] if n2 is not None else None
+    return (out, n2) if return_norm else out
 
 
 def ldos(H: Hamiltonian, orbitals, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,
