@@ -213,6 +213,35 @@ def bench_ldos_psi_t(args, log, cfg64=None):
                     "max_norm_dev": max(abs(x - 1) for x in norms)}
     log(f"psi_t: {len(steps)} snapshots over {max(steps)} steps, {ms:.1f} ms, {upd / (ms / 1e3):.3e} nnz-updates/s")
     H.close()
+    # quasi-eigenstates: 8 energies, one random-phase state on the disordered
+    # lattice, 256 samples forward and backward
+    lat, psi_np = inputs.workload_disordered_graphene(args.cells, 1)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if cfg64:
+        H.set_launch_config(precision="fp64", **cfg64)
+    psi = torch.from_numpy(psi_np).cuda()
+    en = [-6.0, -4.0, -2.7, -1.0, 0.3, 1.0, 2.7, 5.0]
+    nq = 256
+    tbpm.quasi_eigenstates(H, psi, en, 8, dt, f)  # warm-up
+    torch.cuda.synchronize()
+    e0.record(stream)
+    qs, qn2 = tbpm.quasi_eigenstates(H, psi, en, nq, dt, f, return_norm=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_q = e0.elapsed_time(e1)
+    e0.record(stream)
+    tbpm.propagate(H, psi, nq, dt, f)
+    tbpm.propagate(H, psi, nq, dt, f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    acc_bytes = (16 + 32 * len(en)) * lat.n_orb * 2 * (nq - 1)
+    out["quasi_eigenstates"] = {"energies": len(en), "n_steps": nq, "ms": round(ms_q, 1),
+                                "ms_propagation_only": round(ms_p, 1),
+                                "accumulation_GBps": round(acc_bytes / max(ms_q - ms_p, 1e-3) / 1e6, 1),
+                                "norm2_min_max": [float(qn2.min()), float(qn2.max())]}
+    log(f"quasi-eigenstates: {len(en)} energies, 2 x {nq} samples, {ms_q:.1f} ms ({ms_p:.1f} ms propagation alone)")
+    H.close()
     return out
 
 

@@ -138,3 +138,17 @@ def test_ldos_and_snapshots_full_size_prefix():
     snaps, _ = oracle.psi_t(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, None], steps, dt, f)
     for q in range(len(steps)):
         assert _rel(got[q], snaps[q][:, 0]) < 1e-10
+
+
+def test_quasi_eigenstates_full_size_short():
+    """Quasi-eigenstates of the 1024x1024 disordered lattice (bench leg) at two
+    energies from 6 samples each way, against the oracle."""
+    print("case quasi-eigenstates 1024x1024", flush=True)
+    f = 9.0
+    dt = math.pi / f
+    lat, psi0 = inputs.workload_disordered_graphene(1024, 1)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    en = [-2.7, 0.3]
+    got = tbpm.quasi_eigenstates(H, _dev(psi0), en, 6, dt, f).cpu().numpy()
+    ref, _ = oracle.quasi_eigenstates(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 6, dt, f, en)
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
