@@ -17,6 +17,10 @@ Pieces:
     (wave-packet snapshots);
   * :func:`quasi_eigenstates` -- windowed Fourier transform of psi(t) over
     positive and negative times at chosen energies;
+  * :func:`fermi_coeffs`, :func:`apply_cheb` -- Chebyshev series of the
+    Fermi-Dirac operator (forward recurrence);
+  * :func:`ac_corr`, :func:`ac_cond` -- optical-conductivity correlation and
+    its windowed sine transform (Kubo formula);
   * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
     correlation, summed directly (no FFT);
   * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
@@ -62,6 +66,12 @@ def _load():
         lib.oracle_psi_t.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                                      P, ctypes.c_int32, P, ctypes.c_int32, P, P]
         lib.oracle_psi_t.restype = ctypes.c_int
+        lib.oracle_apply_cheb.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32, P,
+                                          ctypes.c_int32, P, P]
+        lib.oracle_apply_cheb.restype = ctypes.c_int
+        lib.oracle_ac_corr.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_int32, P, P,
+                                       ctypes.c_int32, ctypes.c_int32, P, P, P]
+        lib.oracle_ac_corr.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -198,6 +208,102 @@ def quasi_eigenstates(row_ptr, col, val, onsite, psi0, n_steps: int, dt: float, 
         norm2[j] = np.sum(np.abs(acc) ** 2, axis=0)
         out[j] = acc / np.sqrt(norm2[j])
     return out, norm2
+
+
+def fermi(x, beta: float, mu: float):
+    """Fermi-Dirac occupation 1 / (exp(beta (x - mu)) + 1), written with tanh
+    so that large |beta (x - mu)| does not overflow."""
+    return 0.5 * (1.0 - np.tanh(0.5 * beta * (np.asarray(x, dtype=np.float64) - mu)))
+
+
+def fermi_coeffs(beta: float, mu: float, rescale: float, tol: float = 1e-14, n_max: int = 1 << 16) -> np.ndarray:
+    """Chebyshev coefficients a_k with f(H) = sum_k a_k T_k(H/rescale) for the
+    Fermi-Dirac operator (Sec. "Tight-binding propagation method",
+    Eq. (ck_coef) evaluated as the discrete Fourier sum the paper gives:
+    c_k = Re[(2/N) sum_n g(cos(2 pi n/N)) e^{i 2 pi n k/N}], a_0 = c_0/2,
+    a_k = c_k), for g(x) = f(rescale * x).  Kept up to the last |a_k| >= tol."""
+    n = 1024
+    while True:
+        theta = 2.0 * np.pi * np.arange(n) / n
+        g = fermi(rescale * np.cos(theta), beta, mu)
+        c = np.real(np.fft.ifft(g) * n) * 2.0 / n  # sum_n g_n e^{+i 2 pi n k / N}
+        a = c[: n // 2].copy()
+        a[0] *= 0.5
+        big = np.flatnonzero(np.abs(a) >= tol)
+        K = int(big[-1]) + 1 if big.size else 1
+        if K < n // 8 or n >= n_max:
+            return a[:K]
+        n *= 2
+
+
+def apply_cheb(row_ptr, col, val, onsite, rescale: float, coeffs, psi):
+    """sum_k coeffs[k] T_k(H/rescale) psi (plain forward recurrence, C)."""
+    row_ptr, col, val, onsite, psi = _prep(row_ptr, col, val, onsite, psi)
+    n, S = psi.shape
+    a = np.ascontiguousarray(coeffs, dtype=np.float64)
+    out = np.zeros_like(psi)
+    rc = _load().oracle_apply_cheb(n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data, onsite.ctypes.data,
+                                   float(rescale), S, psi.ctypes.data, a.shape[0], a.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_apply_cheb failed")
+    return out
+
+
+def _sparse_apply(row_ptr, col, vals, psi):
+    n = row_ptr.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    out = np.zeros_like(psi)
+    np.add.at(out, rows, vals[:, None] * psi[col])
+    return out
+
+
+def ac_corr(row_ptr, col, val, onsite, j_alpha, j_beta, psi0, n_steps: int, dt: float, rescale: float,
+            beta: float, mu: float, tol: float = 1e-12, fermi_tol: float = 1e-14):
+    """Optical-conductivity correlation (Sec. "Optical conductivity"):
+    psi1 = [1 - f(H)] J_beta psi0, psi2 = f(H) psi0, both propagated, and
+    C_k = <psi2(k dt)| J_alpha |psi1(k dt)>.  J_alpha, J_beta: values on the
+    CSR pattern of H.  Returns (corr [n_steps, S], psi1(0), psi2(0))."""
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    ja = np.ascontiguousarray(j_alpha, dtype=np.complex128)
+    jb = np.ascontiguousarray(j_beta, dtype=np.complex128)
+    f, M, J = _scale_and_coeffs(row_ptr, val, onsite, dt, rescale, tol)
+    a = fermi_coeffs(beta, mu, f, fermi_tol)
+    one_minus = -a.copy()
+    one_minus[0] += 1.0
+    psi2 = apply_cheb(row_ptr, col, val, onsite, f, a, psi0)
+    psi1 = apply_cheb(row_ptr, col, val, onsite, f, one_minus, _sparse_apply(row_ptr, col, jb, psi0))
+    psi1 = np.ascontiguousarray(psi1)
+    psi2 = np.ascontiguousarray(psi2)
+    corr = np.zeros((n_steps, S), dtype=np.complex128)
+    rc = _load().oracle_ac_corr(n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data, onsite.ctypes.data, f, S,
+                                psi1.ctypes.data, psi2.ctypes.data, n_steps, M, J.ctypes.data, ja.ctypes.data,
+                                corr.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_ac_corr failed")
+    return corr, psi1, psi2
+
+
+def ac_cond(corr, dt: float, beta: float, area: float, kind: str = "hann"):
+    """Real part of the optical conductivity (Sec. "Optical conductivity",
+    Eq. (AC)) from the state-averaged correlation, by a rectangle rule on
+    t_k = k dt with the DOS window in place of e^{-Et}:
+        sigma(w_j) = (e^{-beta w_j} - 1) / (w_j A) * dt * sum_k w_k sin(w_j t_k) 2 Im Cbar_k,
+    on w_j = j pi / (N_t dt), j = 0 .. N_t-1 (sigma(0) = 0: the Drude part is
+    omitted).  Units e = hbar = 1 (energies in eV, lengths in A)."""
+    corr = np.asarray(corr)
+    if corr.ndim == 1:
+        corr = corr[:, None]
+    nt = corr.shape[0]
+    cbar = corr.mean(axis=1)
+    w = window(nt, kind)
+    tk = np.arange(nt) * dt
+    omega = np.arange(nt) * np.pi / (nt * dt)
+    sigma = np.zeros(nt)
+    for j in range(1, nt):
+        s = np.sum(w * np.sin(omega[j] * tk) * 2.0 * np.imag(cbar)) * dt
+        sigma[j] = (np.exp(-beta * omega[j]) - 1.0) / (omega[j] * area) * s
+    return omega, sigma
 
 
 def energies(n_steps: int, dt: float) -> np.ndarray:

@@ -179,6 +179,97 @@ int oracle_psi_t(int64_t n, const int64_t *row_ptr, const int32_t *col, const do
 }
 
 /*
+ * Chebyshev series of an operator (Sec. "Tight-binding propagation method",
+ * decomposition of other operators): out_s = sum_{k<K} a[k] T_k(H~) psi_s with
+ * H~ = H/f, by the forward recurrence T_0 psi = psi, T_1 psi = H~ psi,
+ * T_{k+1} psi = 2 H~ T_k psi - T_{k-1} psi.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_apply_cheb(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_ri,
+                      const double *onsite, double f, int32_t S, const double *psi_ri, int32_t K, const double *a,
+                      double *out_ri) {
+    const cplx *val = (const cplx *)val_ri;
+    const cplx *psi = (const cplx *)psi_ri;
+    cplx *out = (cplx *)out_ri;
+    cplx *buf = malloc(sizeof(cplx) * (size_t)n * 4);
+    if (!buf) return -1;
+    cplx *tm1 = buf, *tm = buf + n, *tp = buf + 2 * n, *h = buf + 3 * n;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int64_t i = 0; i < n; ++i) {
+            tm1[i] = psi[i * S + s];
+            out[i * S + s] = a[0] * tm1[i];
+        }
+        if (K > 1) {
+            apply_scaled_h(n, row_ptr, col, val, onsite, f, tm1, tm);
+            for (int64_t i = 0; i < n; ++i) out[i * S + s] += a[1] * tm[i];
+        }
+        for (int32_t k = 2; k < K; ++k) {
+            apply_scaled_h(n, row_ptr, col, val, onsite, f, tm, h);
+            for (int64_t i = 0; i < n; ++i) {
+                tp[i] = 2.0 * h[i] - tm1[i];
+                out[i * S + s] += a[k] * tp[i];
+            }
+            cplx *r = tm1;
+            tm1 = tm;
+            tm = tp;
+            tp = r;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
+ * Optical-conductivity correlation (Sec. "Optical conductivity"): both
+ * states are propagated with the series of oracle_propagate and
+ *   corr[k*S + s] = <psi2_s(k dt)| J_a |psi1_s(k dt)>,  k = 0 .. n_steps-1,
+ * where J_a has the sparsity pattern of H (values ja_ri, no diagonal).
+ * Returns 0, or -1 on allocation failure.
+ */
+int oracle_ac_corr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val_ri, const double *onsite,
+                   double f, int32_t S, const double *psi1_ri, const double *psi2_ri, int32_t n_steps, int32_t M,
+                   const double *J, const double *ja_ri, double *corr_ri) {
+    const cplx *val = (const cplx *)val_ri;
+    const cplx *ja = (const cplx *)ja_ri;
+    const cplx *psi1 = (const cplx *)psi1_ri, *psi2 = (const cplx *)psi2_ri;
+    cplx *corr = (cplx *)corr_ri;
+    cplx *buf = malloc(sizeof(cplx) * (size_t)n * 9);
+    if (!buf) return -1;
+    cplx *p1 = buf, *p2 = buf + n, *nx1 = buf + 2 * n, *nx2 = buf + 3 * n, *w0 = buf + 4 * n, *w1 = buf + 5 * n,
+         *w2 = buf + 6 * n, *h = buf + 7 * n, *jp = buf + 8 * n;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int64_t i = 0; i < n; ++i) {
+            p1[i] = psi1[i * S + s];
+            p2[i] = psi2[i * S + s];
+        }
+        for (int32_t k = 0; k < n_steps; ++k) {
+            for (int64_t i = 0; i < n; ++i) {
+                cplx acc = 0;
+                for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) acc += ja[q] * p1[col[q]];
+                jp[i] = acc;
+            }
+            ksum re = {0, 0}, im = {0, 0};
+            for (int64_t i = 0; i < n; ++i) {
+                const cplx c = conj(p2[i]) * jp[i];
+                ksum_add(&re, creal(c));
+                ksum_add(&im, cimag(c));
+            }
+            corr[(int64_t)k * S + s] = ksum_value(&re) + I * ksum_value(&im);
+            if (k == n_steps - 1) break;
+            time_step(n, row_ptr, col, val, onsite, f, M, J, p1, nx1, NULL, w0, w1, w2, h);
+            time_step(n, row_ptr, col, val, onsite, f, M, J, p2, nx2, NULL, w0, w1, w2, h);
+            cplx *t = p1;
+            p1 = nx1;
+            nx1 = t;
+            t = p2;
+            p2 = nx2;
+            nx2 = t;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
  * Discrete adjoint of oracle_propagate (reverse-mode differentiation of the
  * recurrence above, written out by hand).
  *

@@ -56,6 +56,10 @@ class Lattice:
     slot_ij: np.ndarray | None = None
     slot_ji: np.ndarray | None = None
     pos: np.ndarray | None = None  # optional [n_orb, 3] Cartesian positions (A)
+    # optional [nnz, 2] in-plane displacement r_j - r_i (A) of the hopping
+    # stored at each CSR entry (i, j), for the current operator
+    disp: np.ndarray | None = None
+    area: float = 0.0  # area of the sample (A^2), when known
     meta: dict = field(default_factory=dict)
 
     @property
@@ -104,8 +108,10 @@ def _csr_slots(row_ptr: np.ndarray, col: np.ndarray, i: np.ndarray, j: np.ndarra
 
 
 def from_bonds(n: int, bi: np.ndarray, bj: np.ndarray, bt: np.ndarray, onsite: np.ndarray,
-               name: str = "", keep_bonds: bool = False, pos=None) -> Lattice:
-    """Full Hermitian CSR from a half list of bonds H[i, j] = t, H[j, i] = conj(t)."""
+               name: str = "", keep_bonds: bool = False, pos=None, disp=None) -> Lattice:
+    """Full Hermitian CSR from a half list of bonds H[i, j] = t, H[j, i] = conj(t).
+    ``disp`` [n_bonds, 2]: displacement r_j - r_i of each bond (stored per
+    CSR entry, negated on (j, i)); the bonds must then not repeat an entry."""
     bi = np.asarray(bi, dtype=np.int64)
     bj = np.asarray(bj, dtype=np.int64)
     bt = np.asarray(bt)
@@ -114,6 +120,15 @@ def from_bonds(n: int, bi: np.ndarray, bj: np.ndarray, bt: np.ndarray, onsite: n
     vals = np.concatenate([bt.astype(np.complex128), np.conj(bt.astype(np.complex128))])
     row_ptr, col, val = _coo_to_csr(n, rows, cols, vals)
     lat = Lattice(n, row_ptr, col, val, np.asarray(onsite, dtype=np.float64).copy(), name=name, pos=pos)
+    if disp is not None:
+        disp = np.asarray(disp, dtype=np.float64)
+        sij = _csr_slots(row_ptr, col, bi, bj)
+        sji = _csr_slots(row_ptr, col, bj, bi)
+        if np.unique(np.concatenate([sij, sji])).size != 2 * bi.shape[0]:
+            raise ValueError("bond displacements need bonds that do not repeat a matrix entry")
+        lat.disp = np.zeros((col.shape[0], 2))
+        lat.disp[sij] = disp
+        lat.disp[sji] = -disp
     if keep_bonds:
         lat.bond_i, lat.bond_j = bi, bj
         lat.bond_t = np.asarray(bt, dtype=np.float64).copy()
@@ -171,23 +186,30 @@ def graphene_positions(nx: int, ny: int) -> np.ndarray:
 def graphene(nx: int, ny: int, t: float = -2.7, pbc: bool = True, onsite=None,
              bond_t=None, keep_bonds: bool = False, with_pos: bool = False) -> Lattice:
     """Monolayer graphene nx x ny cells, nearest-neighbour hopping ``t`` (matrix element)."""
-    bi, bj, _, _ = graphene_bonds(nx, ny, pbc)
+    bi, bj, _, kind = graphene_bonds(nx, ny, pbc)
     n = 2 * nx * ny
     bt = np.full(bi.shape[0], float(t)) if bond_t is None else np.asarray(bond_t, dtype=np.float64)
     ons = np.zeros(n) if onsite is None else np.asarray(onsite, dtype=np.float64)
     pos = graphene_positions(nx, ny) if with_pos else None
-    lat = from_bonds(n, bi, bj, bt, ons, name=f"graphene{nx}x{ny}", keep_bonds=keep_bonds, pos=pos)
+    disp = None
+    if nx > 2 and ny > 2:  # smaller periodic cells repeat matrix entries
+        lat_vec = np.stack([GRAPHENE_A1, GRAPHENE_A2])
+        d_kind = np.array([(np.array([r1, r2]) + GRAPHENE_ORB_FRAC[oj] - GRAPHENE_ORB_FRAC[oi]) @ lat_vec
+                           for (r1, r2, oi, oj) in GRAPHENE_REDUCED_HOPPINGS])
+        disp = d_kind[kind]
+    lat = from_bonds(n, bi, bj, bt, ons, name=f"graphene{nx}x{ny}", keep_bonds=keep_bonds, pos=pos, disp=disp)
+    lat.area = nx * ny * abs(float(GRAPHENE_A1[0] * GRAPHENE_A2[1] - GRAPHENE_A1[1] * GRAPHENE_A2[0]))
     lat.meta.update(kind="graphene", nx=nx, ny=ny, pbc=pbc)
     return lat
 
 
 def square(nx: int, ny: int, t: float = -2.7, pbc: bool = True, onsite=None) -> Lattice:
-    """Square lattice, one orbital per site, index ``i1*ny + i2``."""
+    """Square lattice, one orbital per site, index ``i1*ny + i2``, spacing 1 A."""
     i1, i2 = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
     i1 = i1.ravel()
     i2 = i2.ravel()
     site = i1 * ny + i2
-    bi, bj = [], []
+    bi, bj, bd = [], [], []
     for r1, r2 in ((1, 0), (0, 1)):
         t1, t2 = i1 + r1, i2 + r2
         if pbc:
@@ -198,13 +220,25 @@ def square(nx: int, ny: int, t: float = -2.7, pbc: bool = True, onsite=None) -> 
             keep = (t1 < nx) & (t2 < ny)
         bi.append(site[keep])
         bj.append((t1 * ny + t2)[keep])
+        bd.append(np.tile([float(r1), float(r2)], (int(keep.sum()), 1)))
     bi = np.concatenate(bi)
     bj = np.concatenate(bj)
     n = nx * ny
     ons = np.zeros(n) if onsite is None else np.asarray(onsite, dtype=np.float64)
-    lat = from_bonds(n, bi, bj, np.full(bi.shape[0], float(t)), ons, name=f"square{nx}x{ny}")
+    disp = np.concatenate(bd) if (not pbc or (nx > 2 and ny > 2)) else None
+    lat = from_bonds(n, bi, bj, np.full(bi.shape[0], float(t)), ons, name=f"square{nx}x{ny}", disp=disp)
+    lat.area = float(nx * ny)
     lat.meta.update(kind="square", nx=nx, ny=ny, pbc=pbc)
     return lat
+
+
+def current_values(lat: Lattice, axis: int) -> np.ndarray:
+    """Matrix elements of the current operator J_axis = -i sum_ij H_ij (r_j - r_i)_axis
+    c_i^dagger c_j (Sec. "Optical conductivity"; e = hbar = 1) on the CSR
+    pattern of ``lat``, aligned with lat.col.  Requires lat.disp."""
+    if lat.disp is None:
+        raise ValueError("the lattice carries no bond displacements")
+    return -1j * lat.val * lat.disp[:, axis]
 
 
 def anderson(rng: np.random.Generator, n: int, w: float) -> np.ndarray:

@@ -462,3 +462,92 @@ def test_quasi_eigenstate_of_the_dimer_is_its_eigenstate():
     minus = np.array([1, -1]) / np.sqrt(2)
     assert abs(abs(np.vdot(plus, qe[0][:, 0])) - 1) < 1e-6
     assert abs(abs(np.vdot(minus, qe[1][:, 0])) - 1) < 1e-6
+
+
+# ----------------------------------------------------------------------------
+# Fermi-Dirac operator and optical conductivity (Sec. "Tight-binding
+# propagation method", Chebyshev decomposition; Sec. "Optical conductivity")
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta,mu", [(5.0, 0.5), (2.0, -1.3)])
+def test_fermi_coefficients_vs_quadrature(beta, mu):
+    """a_k = (2 - delta_k0)/pi int_0^pi g(cos t) cos(k t) dt by adaptive
+    quadrature, against the discrete Fourier sum."""
+    from scipy.integrate import quad
+
+    f = 9.0
+    a = oracle.fermi_coeffs(beta, mu, f)
+    for k in (0, 1, 2, 7, 30, 60):
+        val, _ = quad(lambda t: float(oracle.fermi(f * math.cos(t), beta, mu)) * math.cos(k * t), 0.0, math.pi,
+                      limit=400, epsabs=1e-15, epsrel=1e-13)
+        ref = (1.0 if k == 0 else 2.0) / math.pi * val
+        assert abs(a[k] - ref) < 1e-12, (k, a[k], ref)
+    x = np.linspace(-1, 1, 41)
+    series = np.polynomial.chebyshev.chebval(x, a)
+    assert np.max(np.abs(series - oracle.fermi(f * x, beta, mu))) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex"])
+def test_fermi_operator_vs_ed(name):
+    lat = SMALL_LATTICES[name]()
+    e, u = np.linalg.eigh(lat.dense())
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    psi = inputs.random_phase_states(np.random.default_rng(10), lat.n_orb, 2)
+    a = oracle.fermi_coeffs(4.0, 0.3, f)
+    got = oracle.apply_cheb(lat.row_ptr, lat.col, lat.val, lat.onsite, f, a, psi)
+    ref = u @ (oracle.fermi(e, 4.0, 0.3)[:, None] * (u.conj().T @ psi))
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def _dense_of(lat, vals):
+    n = lat.n_orb
+    m = np.zeros((n, n), dtype=np.complex128)
+    m[np.repeat(np.arange(n), np.diff(lat.row_ptr)), lat.col] = vals
+    return m
+
+
+@pytest.mark.parametrize("lat_fn,axes", [(lambda: inputs.graphene(5, 4, onsite=inputs.anderson(
+    np.random.default_rng(3), 40, 1.0)), (0, 0)), (lambda: inputs.graphene(4, 3), (0, 1)),
+    (lambda: inputs.square(5, 4, pbc=False, onsite=inputs.anderson(np.random.default_rng(4), 20, 1.5)), (1, 1))])
+def test_ac_correlation_vs_ed(lat_fn, axes):
+    """C_k = <psi2(t)|J_a|psi1(t)> with psi1 = (1-f) J_b psi0, psi2 = f psi0,
+    all by exact diagonalisation."""
+    lat = lat_fn()
+    h = lat.dense()
+    e, u = np.linalg.eigh(h)
+    ja = inputs.current_values(lat, axes[0])
+    jb = inputs.current_values(lat, axes[1])
+    Ja, Jb = _dense_of(lat, ja), _dense_of(lat, jb)
+    assert np.allclose(Ja, Ja.conj().T)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    beta, mu = 3.0, 0.4
+    psi0 = inputs.random_phase_states(np.random.default_rng(11), lat.n_orb, 2)
+    nt = 24
+    corr, p1, p2 = oracle.ac_corr(lat.row_ptr, lat.col, lat.val, lat.onsite, ja, jb, psi0, nt, dt, f, beta, mu,
+                                  tol=1e-16)
+    F = oracle.fermi(e, beta, mu)
+    p1_ref = u @ ((1 - F)[:, None] * (u.conj().T @ (Jb @ psi0)))
+    p2_ref = u @ (F[:, None] * (u.conj().T @ psi0))
+    assert np.max(np.abs(p1 - p1_ref)) < 1e-11 and np.max(np.abs(p2 - p2_ref)) < 1e-11
+    for k in range(nt):
+        ph = np.exp(-1j * e * k * dt)[:, None]
+        a1 = u @ (ph * (u.conj().T @ p1_ref))
+        a2 = u @ (ph * (u.conj().T @ p2_ref))
+        ref = np.einsum("ns,ns->s", a2.conj(), Ja @ a1)
+        assert np.max(np.abs(corr[k] - ref)) < 1e-10 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_ac_conductivity_transform_vs_fft():
+    """The windowed sine sum of the Kubo formula against an FFT of length
+    2 N_t (sin(pi j k / N_t) is the imaginary part of a 2 N_t-point DFT)."""
+    rng = np.random.default_rng(12)
+    nt, dt, beta, area = 256, 0.35, 7.0, 123.4
+    corr = rng.standard_normal((nt, 3)) + 1j * rng.standard_normal((nt, 3))
+    omega, sigma = oracle.ac_cond(corr, dt, beta, area)
+    a = 0.5 * (1 + np.cos(np.pi * np.arange(nt) / nt)) * 2.0 * np.imag(corr.mean(axis=1))
+    s = np.imag(np.fft.ifft(np.concatenate([a, np.zeros(nt)])) * 2 * nt)[:nt] * dt
+    ref = np.zeros(nt)
+    ref[1:] = (np.exp(-beta * omega[1:]) - 1.0) / (omega[1:] * area) * s[1:]
+    assert np.max(np.abs(sigma - ref)) < 1e-12 * np.max(np.abs(ref))
+    assert sigma[0] == 0.0 and np.allclose(omega, np.arange(nt) * np.pi / (nt * dt))
