@@ -240,6 +240,41 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
                                    double *norm2, uint32_t flags, void *stream);
 
 /*
+ * Optical conductivity by propagation (Sec. "Optical conductivity"; the
+ * Fermi-Dirac operator by its Chebyshev series, Sec. "Tight-binding
+ * propagation method").  With f(H) = 1/(exp(beta (H - mu)) + 1),
+ *   psi1 = [1 - f(H)] J_beta psi0,   psi2 = f(H) psi0,
+ * both propagated with the series of tbpm_propagate, and
+ *   corr[k][s] = <psi2_s(k dt)| J_alpha |psi1_s(k dt)>,  k = 0 .. n_steps-1.
+ *   j_alpha, j_beta  host, 2*nnz doubles: the current operators (complex,
+ *             Hermitian; J = -i sum H_ij (r_j - r_i) c_i^+ c_j in units
+ *             e = hbar = 1) as values on H's merged pattern, in the order of
+ *             tbpm_hamiltonian_pattern; they may be the same array
+ *   n_states  1 .. 32 (both states are propagated as one block of 2 S)
+ *   beta      1/(k_B T) in 1/eV (> 0), mu the chemical potential in eV
+ *   fermi_tol truncation of the Fermi-Dirac series (last |a_k| kept >= tol)
+ *   corr      device, [n_steps][n_states] complex128, written
+ * Other arguments as tbpm_propagate.
+ */
+tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const double *j_beta, const double *psi0,
+                         int32_t n_states, int32_t n_steps, double dt, double rescale, double bessel_tol, double beta,
+                         double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags, void *stream);
+
+/*
+ * Real part of the optical conductivity (Eq. (AC)) from tbpm_ac_corr's
+ * correlation averaged over the states, by a rectangle rule on t_k = k dt
+ * with the window of tbpm_dos in place of e^{-Et}:
+ *   sigma(w_j) = (e^{-beta w_j} - 1) / (w_j area) dt sum_k w_k sin(w_j t_k) 2 Im Cbar_k
+ * on w_j = j pi / (n_steps dt), j = 0 .. n_steps-1 (sigma(0) = 0: the Drude
+ * part is omitted).  Units e = hbar = 1: energies in eV, area in the square
+ * of the length unit of the current operator.
+ *   corr          device [n_steps][n_states] complex128
+ *   omegas, sigma device [n_steps] f64, written
+ */
+tbpm_status tbpm_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
+                         tbpm_window win, double *omegas, double *sigma, void *stream);
+
+/*
  * DOS from the correlations (paper, Eq. (dos_tbpm), with C(-t) = C(t)^*):
  *   Cbar_k = (1/S) sum_s corr[k][s],
  *   E_j = j pi / (N_t dt),  j = -N_t .. N_t - 1   (2 N_t energies),

@@ -1,0 +1,159 @@
+// Optical conductivity by propagation (paper, Sec. "Optical conductivity"):
+// kernels around the Clenshaw passes.
+//
+//  * k_gather_values: the current operator J (values on H's CSR pattern) in
+//    the sliced-ELL layout of H, through the slot -> CSR-position map.
+//  * k_pack: psi1 and psi2 (internal row order, [rows][S padded]) into one
+//    block of 2S states in the caller's row order, [n][2S]: psi1 in columns
+//    0..S-1, psi2 in S..2S-1, so that one propagation carries both.
+//  * k_jcorr: per step, <psi2_s| J |psi1_s> for s < S from the propagated
+//    block: J applied to the psi1 columns of each row (gathered over the
+//    row's stored elements) and contracted with the row's psi2 columns; FP64
+//    per-tile partials in the layout of the correlation, for k_reduce.
+//  * k_ac_cond: the windowed sine transform of the Kubo formula, Eq. (AC).
+#include <hip/hip_runtime.h>
+
+#include "device_util.h"
+#include "tbpm_internal.h"
+
+namespace tbpm {
+namespace {
+
+__global__ __launch_bounds__(kWG) void k_gather_values(const int64_t *__restrict__ ell_csr, int64_t ell_size,
+                                                       const d2 *__restrict__ csr_val, d2 *__restrict__ ell_val) {
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t q = (int64_t)blockIdx.x * kWG + threadIdx.x; q < ell_size; q += stride) {
+        const int64_t pos = ell_csr[q];
+        d2 v;
+        v.x = 0.0;
+        v.y = 0.0;
+        if (pos >= 0) v = csr_val[pos];
+        ell_val[q] = v;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_pack(const d2 *__restrict__ psi1, const d2 *__restrict__ psi2, int64_t n_rows,
+                                              int log2s, int S, const int32_t *__restrict__ perm,
+                                              d2 *__restrict__ out) {
+    const int64_t total = n_rows * S;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total; i += stride) {
+        const int64_t r = i / S;
+        const int s = (int)(i % S);
+        const int64_t ro = perm ? (int64_t)perm[r] : r;
+        const int64_t src = (r << log2s) + s;
+        out[ro * 2 * S + s] = psi1[src];
+        out[ro * 2 * S + S + s] = psi2[src];
+    }
+}
+
+// state: the propagated block, [rows][2^log2s2] at precision R; thread t
+// handles state t & (SP-1) of its rows (SP = 2^log2sp >= S)
+template <typename R>
+__global__ __launch_bounds__(kWG) void k_jcorr(const TileDesc *__restrict__ tiles, int n_tiles, int log2sp, int S,
+                                               int log2s2, const void *__restrict__ state,
+                                               const uint32_t *__restrict__ soff, const int32_t *__restrict__ col,
+                                               const d2 *__restrict__ jval, double *__restrict__ partials) {
+    using C = typename CxT<R>::T;
+    const C *psi = (const C *)state;
+    const TileDesc td = tiles[blockIdx.x];
+    const uint32_t spm = (1u << log2sp) - 1u;
+    const int64_t n_u = (int64_t)td.rows << log2sp;
+    double dre = 0.0, dim = 0.0;
+    for (int64_t u = threadIdx.x; u < n_u; u += kWG) {
+        const int s = (int)(u & spm);
+        if (s >= S) continue;
+        const int64_t r = td.row0 + (u >> log2sp);
+        const int64_t sl = r / kSliceRows;
+        const uint32_t off = soff[sl];
+        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+        const int64_t base = off + r % kSliceRows;
+        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t slot = base + (int64_t)k * kSliceRows;
+            const d2 j = jval[slot];
+            const C x = psi[((int64_t)col[slot] << log2s2) + s];
+            const double xr = (double)x.x, xi = (double)x.y;
+            ar = fma(j.x, xr, fma(-j.y, xi, ar));
+            ai = fma(j.x, xi, fma(j.y, xr, ai));
+        }
+        const C y = psi[(r << log2s2) + S + s];
+        const double yr = (double)y.x, yi = (double)y.y;
+        dre = fma(yr, ar, fma(yi, ai, dre));  // conj(y) * (ar + i ai)
+        dim = fma(yr, ai, fma(-yi, ar, dim));
+    }
+    block_state_partials(dre, dim, 0.0, log2sp, partials, blockIdx.x, n_tiles);
+}
+
+// sigma(w_j) = (e^{-beta w_j} - 1) / (w_j A) dt sum_k w_k sin(w_j t_k) 2 Im Cbar_k,
+// w_j = j pi / (N_t dt), sigma(0) = 0; the phase w_j t_k = pi (j k mod 2N)/N
+// is reduced exactly in integers, the sum is compensated.
+__global__ __launch_bounds__(kWG) void k_ac_cond(const d2 *__restrict__ corr, int n_steps, int n_states, double dt,
+                                                 double beta, double area, int window, double *__restrict__ omegas,
+                                                 double *__restrict__ sigma) {
+    const int j = blockIdx.x * kWG + threadIdx.x;
+    if (j >= n_steps) return;
+    const double w_j = M_PI * j / (n_steps * dt);
+    omegas[j] = w_j;
+    if (j == 0) {
+        sigma[0] = 0.0;
+        return;
+    }
+    const int64_t two_n = 2 * (int64_t)n_steps;
+    double sum = 0.0, comp = 0.0;
+    for (int k = 1; k < n_steps; ++k) {
+        double im = 0.0;
+        for (int s = 0; s < n_states; ++s) im += corr[(int64_t)k * n_states + s].y;
+        im /= n_states;
+        const double wk = window == TBPM_WIN_HANN ? 0.5 * (1.0 + cospi((double)k / n_steps)) : 1.0;
+        const int64_t m = ((int64_t)j * k) % two_n;
+        const double term = wk * sinpi((double)m / n_steps) * 2.0 * im;
+        const double t = sum + term;  // Neumaier
+        comp += fabs(sum) >= fabs(term) ? (sum - t) + term : (term - t) + sum;
+        sum = t;
+    }
+    sigma[j] = (exp(-beta * w_j) - 1.0) / (w_j * area) * (sum + comp) * dt;
+}
+
+int64_t grid_for_n(int64_t n) {
+    int64_t b = (n + kWG - 1) / kWG;
+    if (b > 65536) b = 65536;
+    return b < 1 ? 1 : b;
+}
+
+}  // namespace
+
+hipError_t launch_gather_values(const int64_t *ell_csr, int64_t ell_size, const double *csr_val, double *ell_val,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_values, dim3((unsigned)grid_for_n(ell_size)), dim3(kWG), 0, st, ell_csr, ell_size,
+                       (const d2 *)csr_val, (d2 *)ell_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const double *psi1, const double *psi2, int64_t n_rows, int32_t log2s, int32_t S,
+                       const int32_t *perm, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)grid_for_n(n_rows * S)), dim3(kWG), 0, st, (const d2 *)psi1,
+                       (const d2 *)psi2, n_rows, log2s, S, perm, (d2 *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_jcorr(bool fp32, const TileDesc *tiles, int32_t n_tiles, int32_t log2sp, int32_t S, int32_t log2s2,
+                        const void *state, const uint32_t *slice_off, const int32_t *col, const double *jval,
+                        double *partials, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_jcorr<float>, dim3((unsigned)n_tiles), dim3(kWG), 0, st, tiles, n_tiles, log2sp, S, log2s2,
+                           state, slice_off, col, (const d2 *)jval, partials);
+    else
+        hipLaunchKernelGGL(k_jcorr<double>, dim3((unsigned)n_tiles), dim3(kWG), 0, st, tiles, n_tiles, log2sp, S,
+                           log2s2, state, slice_off, col, (const d2 *)jval, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
+                          int window, double *omegas, double *sigma, hipStream_t st) {
+    hipLaunchKernelGGL(k_ac_cond, dim3((unsigned)((n_steps + kWG - 1) / kWG)), dim3(kWG), 0, st, (const d2 *)corr,
+                       n_steps, n_states, dt, beta, area, window, omegas, sigma);
+    return hipGetLastError();
+}
+
+}  // namespace tbpm

@@ -367,6 +367,106 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
     return TBPM_OK;
 }
 
+tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const double *j_beta, const double *psi0,
+                         int32_t n_states, int32_t n_steps, double dt, double rescale, double bessel_tol, double beta,
+                         double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags,
+                         void *stream) {
+    if (!H || !j_alpha || !j_beta || !psi0 || !corr) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_states < 1 || n_states > 32) return fail(TBPM_E_ARG, "n_states must be in [1, 32]");
+    tbpm_status st = check_prop_args(2 * n_states, n_steps, dt, bessel_tol, prec);
+    if (st != TBPM_OK) return st;
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(TBPM_E_ARG, "beta must be positive and finite");
+    if (!std::isfinite(mu)) return fail(TBPM_E_ARG, "mu must be finite");
+    if (!(fermi_tol > 0.0 && fermi_tol < 1e-2)) return fail(TBPM_E_ARG, "fermi_tol must be in (0, 1e-2)");
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const int64_t nnz = H->csr.nnz(), n = H->csr.n;
+    for (int64_t p = 0; p < 2 * nnz; ++p)
+        if (!std::isfinite(j_alpha[p]) || !std::isfinite(j_beta[p])) return fail(TBPM_E_ARG, "non-finite current value");
+    const double f = resolve_rescale(H->csr, rescale);
+    const std::vector<double> a = fermi_cheb_coeffs(beta, mu, f, fermi_tol);
+    if (a.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms (beta * rescale too large)");
+    std::vector<double> one_minus(a.size());
+    for (size_t k = 0; k < a.size(); ++k) one_minus[k] = -a[k];
+    one_minus[0] += 1.0;
+    Engine &eng = H->eng;
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < n_states) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;
+    const size_t ell = sizeof(double) * 2 * (size_t)std::max<int64_t>(eng.mat.ell_size, 1);
+    hipError_t e = eng.ac_csr.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(nnz, 1));
+    if (e == hipSuccess) e = eng.ac_ja.ensure(ell);
+    if (e == hipSuccess) e = eng.ac_jb.ensure(ell);
+    if (e == hipSuccess) e = eng.ac_vec.ensure(6 * vec);
+    if (e == hipSuccess) e = eng.ac_block.ensure(sizeof(double) * 4 * (size_t)n * n_states);
+    if (e == hipSuccess) e = eng.corr_scratch.ensure(sizeof(double) * 4 * (size_t)n_steps * n_states);
+    if (e != hipSuccess) return hip_fail(e, "alloc optical-conductivity buffers");
+    // the current operators in the ELL layout of H
+    const double *jv[2] = {j_alpha, j_beta};
+    DevBuf *jd[2] = {&eng.ac_ja, &eng.ac_jb};
+    for (int q = 0; q < 2; ++q) {
+        e = hipStreamSynchronize(hs);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpy(eng.ac_csr.ptr, jv[q], sizeof(double) * 2 * (size_t)nnz, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_gather_values(eng.mat.ell_csr, eng.mat.ell_size, (const double *)eng.ac_csr.ptr,
+                                     (double *)jd[q]->ptr, hs);
+        if (e != hipSuccess) return hip_fail(e, "upload current operator");
+    }
+    char *vb = (char *)eng.ac_vec.ptr;
+    void *src = vb, *w0 = vb + vec, *w1 = vb + 2 * vec, *psi2 = vb + 3 * vec, *jpsi = vb + 4 * vec,
+         *psi1 = vb + 5 * vec;
+    e = launch_expand_states(psi0, eng.mat.perm, n_states, (double *)src, log2s, n, hs);
+    if (e != hipSuccess) return hip_fail(e, "load states");
+    try {
+        // psi2 = f(H) psi0, psi1 = (1 - f(H)) J_beta psi0
+        st = eng.apply_series(a, f, log2s, src, psi2, w0, w1, hs);
+        if (st == TBPM_OK) st = eng.apply_ell((const double *)eng.ac_jb.ptr, log2s, src, jpsi, hs);
+        if (st == TBPM_OK) st = eng.apply_series(one_minus, f, log2s, jpsi, psi1, w0, w1, hs);
+        if (st != TBPM_OK) return st;
+        e = launch_pack((const double *)psi1, (const double *)psi2, n, log2s, n_states, eng.mat.perm,
+                        (double *)eng.ac_block.ptr, hs);
+        if (e != hipSuccess) return hip_fail(e, "pack states");
+        const double *p0 = (const double *)eng.ac_block.ptr;
+        double *c0 = (double *)eng.corr_scratch.ptr;
+        double *n0 = nullptr;
+        Engine::RunArgs r{};
+        r.psi0 = &p0;
+        r.s_user = 2 * n_states;
+        r.n_steps = n_steps;
+        r.dt = &dt;
+        r.rescale = &f;
+        r.tol = bessel_tol;
+        r.fp32 = prec == TBPM_FP32_MIXED;
+        r.corr = &c0;
+        r.norm2 = &n0;
+        r.jc_val = (const double *)eng.ac_ja.ptr;
+        r.jc_states = n_states;
+        r.jc_corr = corr;
+        r.flags = flags;
+        r.stream = hs;
+        return eng.run(r);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
+                         tbpm_window win, double *omegas, double *sigma, void *stream) {
+    if (!corr || !omegas || !sigma) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_steps < 1 || n_states < 1 || n_steps > (1 << 28)) return fail(TBPM_E_ARG, "bad n_steps or n_states");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TBPM_E_ARG, "dt must be positive and finite");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(TBPM_E_ARG, "beta must be positive and finite");
+    if (!(area > 0.0) || !std::isfinite(area)) return fail(TBPM_E_ARG, "area must be positive and finite");
+    if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
+    hipError_t e = launch_ac_cond(corr, n_steps, n_states, dt, beta, area, (int)win, omegas, sigma, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch optical conductivity");
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, tbpm_window win,
                      double *energies, double *dos, void *stream) {
     if (!corr || !energies || !dos) return fail(TBPM_E_ARG, "NULL argument");

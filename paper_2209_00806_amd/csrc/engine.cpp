@@ -77,7 +77,8 @@ bool GraphKey::operator==(const GraphKey &o) const {
     if (s_pad != o.s_pad || s_user != o.s_user || fp32 != o.fp32 || mmax != o.mmax || n_inst != o.n_inst ||
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
         fused != o.fused || n_tiles != o.n_tiles || tiles_chunks != o.tiles_chunks || tiles_unit != o.tiles_unit ||
-        lds_units != o.lds_units || n_steps != o.n_steps || n_qe != o.n_qe || ckpt != o.ckpt)
+        lds_units != o.lds_units || n_steps != o.n_steps || n_qe != o.n_qe || jc_states != o.jc_states ||
+        ckpt != o.ckpt)
         return false;
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         if (bufs[i] != o.bufs[i]) return false;
@@ -265,7 +266,8 @@ void Engine::release() {
                       &norm2_all, &tiles,    &inst_tile0, &ptr_tab, &inst_row0_dev, &bwd_store, &bwd_adj,
                       &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx, &fu_n1, &fu_hoff,
                       &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
-                      &qe_acc,   &qe_part,  &qe_norm2};
+                      &qe_acc,   &qe_part,  &qe_norm2, &ac_ja,     &ac_jb,     &ac_csr,       &ac_zero,
+                      &ac_vec,   &ac_block, &jc_tab,   &jc_norm};
     for (DevBuf *b : bufs) b->release();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
@@ -562,13 +564,18 @@ tbpm_status Engine::run(const RunArgs &a) {
     if (a.ckpt) TRY_HIP(ckpt_slot.ensure(slot_bytes), "alloc checkpoint slots");
     const size_t qe_bytes = a.n_qe > 0 ? sizeof(double) * 2 * (size_t)a.n_steps * a.n_qe : 0;
     if (a.n_qe > 0) TRY_HIP(qe_coef.ensure(qe_bytes), "alloc quasi-eigenstate coefficients");
+    const size_t jc_bytes = a.jc_states > 0 ? 2 * sizeof(void *) : 0;
+    if (a.jc_states > 0) {
+        TRY_HIP(jc_tab.ensure(jc_bytes), "alloc correlation table");
+        TRY_HIP(jc_norm.ensure(sizeof(double) * (size_t)a.n_steps * a.jc_states), "alloc correlation scratch");
+    }
 
     // stage the small tables through pinned memory, stream-ordered
     const size_t coef_bytes = sizeof(PassCoef) * (size_t)n_passes * ni;
     const size_t tab_bytes = sizeof(void *) * 3 * (size_t)ni;
     const size_t row_bytes = sizeof(int64_t) * (ni + 1);
     TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
-    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes + slot_bytes + qe_bytes), "alloc staging");
+    TRY_HIP(staging.ensure(coef_bytes + tab_bytes + row_bytes + slot_bytes + qe_bytes + jc_bytes), "alloc staging");
     char *sp = (char *)staging.ptr;
     PassCoef *hc = (PassCoef *)sp;
     for (int p = 0; p < n_passes; ++p)
@@ -603,12 +610,41 @@ tbpm_status Engine::run(const RunArgs &a) {
         TRY_HIP(hipMemcpyAsync(qe_coef.ptr, hq, qe_bytes, hipMemcpyHostToDevice, a.stream),
                 "upload quasi-eigenstate coefficients");
     }
+    if (a.jc_states > 0) {
+        void **hj = (void **)(sp + coef_bytes + tab_bytes + row_bytes + slot_bytes + qe_bytes);
+        hj[0] = a.jc_corr;
+        hj[1] = nullptr;
+        TRY_HIP(hipMemcpyAsync(jc_tab.ptr, hj, jc_bytes, hipMemcpyHostToDevice, a.stream), "upload correlation table");
+    }
     const int64_t n_el_all = mat.n_rows * s_pad;
+    int32_t log2sp = 0;
+    while ((1 << log2sp) < a.jc_states) ++log2sp;
+    // per-step work after the correlation: quasi-eigenstate accumulation and
+    // the optical-conductivity correlation
     auto enqueue_qe = [&](hipStream_t s) -> tbpm_status {
-        if (a.n_qe <= 0) return TBPM_OK;
-        hipError_t e = launch_qe_accum(fp32, v.ptr, a.qe_acc, n_el_all, (const double *)qe_coef.ptr, a.n_qe,
-                                       (const int32_t *)counter.ptr, s);
-        if (e != hipSuccess) return hip_fail(e, "launch quasi-eigenstate accumulation");
+        if (a.n_qe > 0) {
+            hipError_t e = launch_qe_accum(fp32, v.ptr, a.qe_acc, n_el_all, (const double *)qe_coef.ptr, a.n_qe,
+                                           (const int32_t *)counter.ptr, s);
+            if (e != hipSuccess) return hip_fail(e, "launch quasi-eigenstate accumulation");
+        }
+        if (a.jc_states > 0) {
+            hipError_t e = launch_jcorr(fp32, (const TileDesc *)tiles.ptr, (int32_t)h_tiles.size(), log2sp, a.jc_states,
+                                        log2s, v.ptr, mat.slice_off, mat.col, a.jc_val, (double *)partials.ptr, s);
+            if (e != hipSuccess) return hip_fail(e, "launch current correlation");
+            ReduceParams jr{};
+            jr.partials = (const double *)partials.ptr;
+            jr.n_tiles = (int32_t)h_tiles.size();
+            jr.inst_tile0 = (const int32_t *)inst_tile0.ptr;
+            jr.log2s = log2sp;
+            jr.s_user = a.jc_states;
+            jr.n_steps = a.n_steps;
+            jr.counter = (const int32_t *)counter.ptr;
+            jr.corr = (double *const *)jc_tab.ptr;
+            jr.norm2 = (double *const *)jc_tab.ptr + 1;
+            jr.norm2_all = (double *)jc_norm.ptr;
+            e = launch_reduce(1, s_pad, jr, s);
+            if (e != hipSuccess) return hip_fail(e, "launch current correlation reduce");
+        }
         return TBPM_OK;
     };
     TRY_HIP(hipEventRecord(staging_done, a.stream), "record staging");
@@ -809,12 +845,14 @@ tbpm_status Engine::run(const RunArgs &a) {
 
             key.n_steps = a.n_steps;
             key.n_qe = a.n_qe;
+            key.jc_states = a.jc_states;
             key.ckpt = a.ckpt;
-            const void *kb[20] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
+            const void *kb[22] = {v.ptr,       ba.ptr,      bb.ptr,        phi0.ptr,    partials.ptr, coef.ptr,
                                   tiles.ptr,   norm2_all.ptr, bc.ptr,      bd.ptr,      st_uoff.ptr,  st_ucol.ptr,
                                   st_lidx.ptr, fu_hidx.ptr, fu_n1.ptr,     fu_hoff.ptr, fu_hw.ptr,
                                   a.ckpt ? ckpt_slot.ptr : nullptr, a.n_qe > 0 ? qe_coef.ptr : nullptr,
-                                  a.n_qe > 0 ? a.qe_acc : nullptr};
+                                  a.n_qe > 0 ? a.qe_acc : nullptr, a.jc_states > 0 ? a.jc_val : nullptr,
+                                  a.jc_states > 0 ? jc_norm.ptr : nullptr};
             static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
             if (!graph_exec || !(key == graph_key)) {
@@ -871,6 +909,107 @@ tbpm_status Engine::run(const RunArgs &a) {
             }
         }
     }
+    return TBPM_OK;
+}
+
+tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int32_t log2s, const void *src, void *dst,
+                                 void *w0, void *w1, hipStream_t st) {
+    // Clenshaw for sum_{k<K} a_k T_k(x), x = H/f (zero-padded to K >= 3):
+    //   b_{K-2} = a_{K-2} v + 2 a_{K-1} x v                       (FIRST)
+    //   b_{K-3} = (a_{K-3} - a_{K-1}) v + 2 x b_{K-2}             (NOB2)
+    //   b_k     = a_k v + 2 x b_{k+1} - b_{k+2},  k = K-4 .. 1   (MID)
+    //   out     = a_0 v + x b_1 - b_2                              (MID with beta = 1/f)
+    // and for K = 3: b_1 by FIRST, out = (a_0 - a_2) v + x b_1 (NOB2).
+    std::vector<double> a(a_in);
+    if (a.size() < 3) a.resize(3, 0.0);
+    const int32_t K = (int32_t)a.size();
+    struct Launch {
+        int kind;
+        const void *x, *b2;
+        void *out;
+        PassCoef c;
+    };
+    std::vector<Launch> seq;
+    void *w[2] = {w0, w1};
+    if (K == 3) {
+        seq.push_back({kPassFirst, src, nullptr, w[0], {a[1], 0, 2.0 * a[2] / f, 0}});
+        seq.push_back({kPassNoB2, w[0], nullptr, dst, {a[0] - a[2], 0, 1.0 / f, 0}});
+    } else {
+        seq.push_back({kPassFirst, src, nullptr, w[0], {a[K - 2], 0, 2.0 * a[K - 1] / f, 0}});
+        seq.push_back({kPassNoB2, w[0], nullptr, w[1], {a[K - 3] - a[K - 1], 0, 2.0 / f, 0}});
+        int cur = 1;  // b_{k+1} in w[cur], b_{k+2} in w[1 - cur]; MID writes over b_{k+2}
+        for (int32_t k = K - 4; k >= 1; --k) {
+            seq.push_back({kPassMid, w[cur], w[1 - cur], w[1 - cur], {a[k], 0, 2.0 / f, 0}});
+            cur = 1 - cur;
+        }
+        seq.push_back({kPassMid, w[cur], w[1 - cur], dst, {a[0], 0, 1.0 / f, 0}});
+    }
+    if (!tiles.ptr || tiles_s == 0) {
+        tbpm_status s = build_tiles(1 << log2s, cfg.wg_chunks, 1);
+        if (s != TBPM_OK) return s;
+    }
+    const size_t cb = sizeof(PassCoef) * seq.size();
+    TRY_HIP(coef.ensure(cb), "alloc series coefficients");
+    TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
+    TRY_HIP(staging.ensure(cb), "alloc staging");
+    PassCoef *hc = (PassCoef *)staging.ptr;
+    for (size_t i = 0; i < seq.size(); ++i) hc[i] = seq[i].c;
+    TRY_HIP(hipMemcpyAsync(coef.ptr, hc, cb, hipMemcpyHostToDevice, st), "upload series coefficients");
+    TRY_HIP(hipEventRecord(staging_done, st), "record staging");
+    PassParams pp{};
+    pp.tiles = (const TileDesc *)tiles.ptr;
+    pp.n_tiles = (int32_t)h_tiles.size();
+    pp.xcd_remap = cfg.xcd_remap;
+    pp.log2s = log2s;
+    pp.col = mat.col;
+    pp.val = mat.val64;
+    pp.slice_off = mat.slice_off;
+    pp.onsite = mat.onsite64;
+    pp.counter = (int32_t *)counter.ptr;
+    pp.s_user = 1 << log2s;
+    pp.v = src;
+    for (size_t i = 0; i < seq.size(); ++i) {
+        pp.x = seq[i].x;
+        pp.b2 = seq[i].b2;
+        pp.out = seq[i].out;
+        pp.coef = (const PassCoef *)coef.ptr + i;
+        hipError_t e = launch_pass(seq[i].kind, false, mat.is_complex, false, 1, 1, pp, st);
+        if (e != hipSuccess) return hip_fail(e, "launch series pass");
+    }
+    return TBPM_OK;
+}
+
+tbpm_status Engine::apply_ell(const double *jval, int32_t log2s, const void *src, void *dst, hipStream_t st) {
+    if (!tiles.ptr || tiles_s == 0) {
+        tbpm_status s = build_tiles(1 << log2s, cfg.wg_chunks, 1);
+        if (s != TBPM_OK) return s;
+    }
+    TRY_HIP(ac_zero.ensure(sizeof(double) * (size_t)std::max<int64_t>(mat.n_rows, 1)), "alloc zero on-site");
+    TRY_HIP(launch_fill_zero((double *)ac_zero.ptr, mat.n_rows, st), "clear zero on-site");
+    TRY_HIP(coef.ensure(sizeof(PassCoef)), "alloc coefficient");
+    TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
+    TRY_HIP(staging.ensure(sizeof(PassCoef)), "alloc staging");
+    PassCoef *hc = (PassCoef *)staging.ptr;
+    hc[0] = PassCoef{0.0, 0.0, 1.0, 0.0};  // out = 0 * v + 1 * (J x)
+    TRY_HIP(hipMemcpyAsync(coef.ptr, hc, sizeof(PassCoef), hipMemcpyHostToDevice, st), "upload coefficient");
+    TRY_HIP(hipEventRecord(staging_done, st), "record staging");
+    PassParams pp{};
+    pp.tiles = (const TileDesc *)tiles.ptr;
+    pp.n_tiles = (int32_t)h_tiles.size();
+    pp.xcd_remap = cfg.xcd_remap;
+    pp.log2s = log2s;
+    pp.col = mat.col;
+    pp.val = jval;
+    pp.slice_off = mat.slice_off;
+    pp.onsite = ac_zero.ptr;
+    pp.x = src;
+    pp.v = src;
+    pp.out = dst;
+    pp.coef = (const PassCoef *)coef.ptr;
+    pp.counter = (int32_t *)counter.ptr;
+    pp.s_user = 1 << log2s;
+    hipError_t e = launch_pass(kPassFirst, false, true, false, 1, 1, pp, st);
+    if (e != hipSuccess) return hip_fail(e, "launch current operator");
     return TBPM_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -401,4 +402,54 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
     return order;
 }
 
+
+// ---------------------------------------------------------------------------
+// Chebyshev coefficients of the Fermi-Dirac operator (Sec. "Tight-binding
+// propagation method", decomposition of other operators): the discrete
+// Fourier sum c_k = (2/N) Re sum_n g(cos(2 pi n/N)) e^{i 2 pi n k/N} of
+// g(x) = 1/(exp(beta (rescale x - mu)) + 1), a_0 = c_0/2, a_k = c_k, with N
+// doubled until the coefficients kept (up to the last |a_k| >= tol) use less
+// than an eighth of the sum's length.
+// ---------------------------------------------------------------------------
+static void fft_inplace(std::vector<std::complex<double>> &z, bool inverse_sign) {
+    const size_t n = z.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {  // bit reversal
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(z[i], z[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const double ang = (inverse_sign ? 2.0 : -2.0) * M_PI / (double)len;
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> w(std::cos(ang * (double)k), std::sin(ang * (double)k));
+                const std::complex<double> u = z[i + k], t = w * z[i + k + len / 2];
+                z[i + k] = u + t;
+                z[i + k + len / 2] = u - t;
+            }
+    }
+}
+
+std::vector<double> fermi_cheb_coeffs(double beta, double mu, double rescale, double tol) {
+    for (size_t n = 1024; n <= (size_t(1) << 22); n <<= 1) {
+        std::vector<std::complex<double>> z(n);
+        for (size_t q = 0; q < n; ++q) {
+            const double x = rescale * std::cos(2.0 * M_PI * (double)q / (double)n);
+            z[q] = 0.5 * (1.0 - std::tanh(0.5 * beta * (x - mu)));  // overflow-free Fermi function
+        }
+        fft_inplace(z, true);  // sum_n g_n e^{+i 2 pi n k / N}
+        std::vector<double> a(n / 2);
+        for (size_t k = 0; k < n / 2; ++k) a[k] = 2.0 * z[k].real() / (double)n;
+        a[0] *= 0.5;
+        size_t K = 1;
+        for (size_t k = 0; k < a.size(); ++k)
+            if (std::fabs(a[k]) >= tol) K = k + 1;
+        if (K < n / 8) {
+            a.resize(K);
+            return a;
+        }
+    }
+    return {};
+}
 }  // namespace tbpm

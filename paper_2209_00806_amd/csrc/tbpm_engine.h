@@ -71,9 +71,9 @@ struct GraphKey {
     int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
     // identity of the tile tables the launches were captured with
     int32_t n_tiles = 0, tiles_chunks = 0, tiles_unit = 0, lds_units = 0;
-    int32_t n_steps = 0, n_qe = 0;
+    int32_t n_steps = 0, n_qe = 0, jc_states = 0;
     const void *ckpt = nullptr;
-    const void *bufs[20] = {};
+    const void *bufs[22] = {};
     bool operator==(const GraphKey &o) const;
 };
 
@@ -101,6 +101,10 @@ struct Engine {
     DevBuf ckpt_slot, corr_scratch;
     // quasi-eigenstates: coefficient table, accumulators, partials, norms
     DevBuf qe_coef, qe_acc, qe_part, qe_norm2;
+    // optical conductivity: J_alpha / J_beta in ELL layout, their CSR upload,
+    // a zero on-site vector, preparation vectors, the packed block, and the
+    // correlation's pointer table and norm scratch
+    DevBuf ac_ja, ac_jb, ac_csr, ac_zero, ac_vec, ac_block, jc_tab, jc_norm;
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
@@ -153,10 +157,23 @@ struct Engine {
         const double *qe_coef;
         int32_t n_qe;
         double *qe_acc;
+        // optical-conductivity correlation: after the initial state and every
+        // step, jc_corr[k][s] = <block[:, S+s]| J |block[:, s]> for s < jc_states
+        // (the block holds psi1 in columns 0..S-1 and psi2 in S..2S-1; J as
+        // complex128 values in the sliced-ELL layout of H)
+        const double *jc_val;
+        int32_t jc_states;
+        double *jc_corr;
         uint32_t flags;
         hipStream_t stream;
     };
     tbpm_status run(const RunArgs &a);
+    // dst = sum_k a[k] T_k(H/f) src on [rows][2^log2s] FP64 internal blocks
+    // (Clenshaw on the plain pass kernel; w0, w1 work blocks; src kept)
+    tbpm_status apply_series(const std::vector<double> &a, double f, int32_t log2s, const void *src, void *dst,
+                             void *w0, void *w1, hipStream_t st);
+    // dst = J src for J given as complex128 values in the ELL layout of H
+    tbpm_status apply_ell(const double *jval, int32_t log2s, const void *src, void *dst, hipStream_t st);
     // back-to-back launches of the interior pass on the current buffers
     tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
     int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1;

@@ -233,6 +233,20 @@ int32_t qe_partial_blocks(int64_t n_rows);  // partials need n_e * S * 3 * block
 hipError_t launch_qe_finalize(const double *acc, int64_t n_rows, int32_t log2s, int32_t s_user, int32_t n_e,
                               const int32_t *perm, double *partials, double *norm2, double *out, hipStream_t st);
 
+// optical-conductivity launchers (ac.hip)
+hipError_t launch_gather_values(const int64_t *ell_csr, int64_t ell_size, const double *csr_val, double *ell_val,
+                                hipStream_t st);
+hipError_t launch_pack(const double *psi1, const double *psi2, int64_t n_rows, int32_t log2s, int32_t S,
+                       const int32_t *perm, double *out, hipStream_t st);
+hipError_t launch_jcorr(bool fp32, const TileDesc *tiles, int32_t n_tiles, int32_t log2sp, int32_t S, int32_t log2s2,
+                        const void *state, const uint32_t *slice_off, const int32_t *col, const double *jval,
+                        double *partials, hipStream_t st);
+hipError_t launch_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
+                          int window, double *omegas, double *sigma, hipStream_t st);
+// Chebyshev coefficients a_k of the Fermi-Dirac operator f(H) = sum_k a_k
+// T_k(H/rescale) (host); empty if they do not converge below tol
+std::vector<double> fermi_cheb_coeffs(double beta, double mu, double rescale, double tol);
+
 // backward launchers (backward.hip)
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
 // dst[r][s] = src[perm[r]][s] (src[r][s] if perm is null), zero for s >= s_user

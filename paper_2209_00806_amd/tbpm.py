@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
         "tbpm_propagate_snapshots": [P, P, I32, P, I32, D, D, D, ctypes.c_int, P, P, U32, P],
         "tbpm_quasi_eigenstates": [P, P, I32, I32, D, D, D, ctypes.c_int, P, I32, ctypes.c_int, P, P, U32, P],
+        "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
+        "tbpm_ac_cond": [P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
         "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
         "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
@@ -332,6 +334,45 @@ def quasi_eigenstates(H: Hamiltonian, psi0, energies, n_steps: int, dt: float, r
         out = out[:, :, 0]
         n2 = n2[:, 0] if n2 is not None else None
     return (out, n2) if return_norm else out
+
+
+def ac_corr(H: Hamiltonian, j_alpha, j_beta, psi0, n_steps: int, dt: float, beta: float, mu: float,
+            rescale: float = 0.0, tol: float = 1e-12, fermi_tol: float = 1e-12, precision: str = "fp64", stream=None):
+    """Optical-conductivity correlation <psi2(t)|J_alpha|psi1(t)> (numpy
+    complex128 current operators on H's merged pattern; psi0 a CUDA
+    complex128 tensor [n_orb, S], S <= 32).  Returns corr [n_steps, S]."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    if psi0.dim() == 1:
+        psi0 = psi0.reshape(-1, 1)
+    nnz = H.info()["nnz"]
+    ja = np.ascontiguousarray(j_alpha, dtype=np.complex128)
+    jb = np.ascontiguousarray(j_beta, dtype=np.complex128)
+    if ja.shape != (nnz,) or jb.shape != (nnz,):
+        raise ValueError(f"current operators must hold one value per stored element ({nnz})")
+    n, S = psi0.shape
+    corr = torch.empty((n_steps, S), dtype=torch.complex128, device=psi0.device)
+    _check(lib().tbpm_ac_corr(H.handle, ja.ctypes.data, jb.ctypes.data, _ptr(psi0), S, int(n_steps), float(dt),
+                              float(rescale), float(tol), float(beta), float(mu), float(fermi_tol), _prec(precision),
+                              _ptr(corr), 0, _stream(stream)))
+    return corr
+
+
+def ac_cond(corr, dt: float, beta: float, area: float, window: str = "hann", stream=None):
+    """(omegas, Re sigma) on w_j = j pi/(n_steps dt), j = 0..n_steps-1, from
+    ac_corr's correlation (CUDA complex128 [n_steps, S])."""
+    import torch
+
+    _require_cuda(corr, torch.complex128, "corr")
+    if corr.dim() == 1:
+        corr = corr.reshape(-1, 1)
+    nt, S = corr.shape
+    om = torch.empty(nt, dtype=torch.float64, device=corr.device)
+    sg = torch.empty(nt, dtype=torch.float64, device=corr.device)
+    _check(lib().tbpm_ac_cond(_ptr(corr), nt, S, float(dt), float(beta), float(area), WIN[window], _ptr(om), _ptr(sg),
+                              _stream(stream)))
+    return om, sg
 
 
 def ldos(H: Hamiltonian, orbitals, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,
