@@ -241,6 +241,40 @@ def bench_ldos_psi_t(args, log, cfg64=None):
                                 "accumulation_GBps": round(acc_bytes / max(ms_q - ms_p, 1e-3) / 1e6, 1),
                                 "norm2_min_max": [float(qn2.min()), float(qn2.max())]}
     log(f"quasi-eigenstates: {len(en)} energies, 2 x {nq} samples, {ms_q:.1f} ms ({ms_p:.1f} ms propagation alone)")
+    # optical conductivity sigma_xx at 300 K, mu = 0, one random-phase state on
+    # the same disordered lattice: the Fermi-Dirac series over the joined
+    # block [J psi0 | psi0], then both states propagated together
+    jx = inputs.current_values(lat, 0)
+    beta, mu = 38.68, 0.0
+    na = args.ac_nt
+    K = len(tbpm.fermi_coeffs(beta, mu, f, 1e-12))
+    tbpm.ac_corr(H, jx, jx, psi, 8, dt, beta, mu, rescale=f)  # warm-up
+    torch.cuda.synchronize()
+    e0.record(stream)
+    corr = tbpm.ac_corr(H, jx, jx, psi, na, dt, beta, mu, rescale=f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_a = e0.elapsed_time(e1)
+    psi2 = psi.repeat(1, 2).contiguous()
+    tbpm.propagate(H, psi2, 8, dt, f)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    tbpm.propagate(H, psi2, na, dt, f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_p2 = e0.elapsed_time(e1)
+    om, sg = tbpm.ac_cond(corr, dt, beta, lat.area / lat.n_orb)
+    om = om.cpu().numpy()
+    sg = sg.cpu().numpy()
+    band = (om > 0.9) & (om < 2.1)
+    series_bytes = (K - 1) * pass_bytes(lat.n_orb, lat.nnz, 2, 16, 8)
+    out["optical_conductivity"] = {
+        "n_steps": na, "beta_per_eV": beta, "fermi_terms": K, "ms": round(ms_a, 1),
+        "ms_propagation_only": round(ms_p2, 1),
+        "series_alg_GBps": round(series_bytes / max(ms_a - ms_p2, 1e-3) / 1e6, 1),
+        "sigma_xx_over_e2_8hbar_0.9_2.1eV": round(float(np.mean(sg[band]) / 0.125), 3)}
+    log(f"optical conductivity: {K} Fermi terms, {na} steps, {ms_a:.1f} ms ({ms_p2:.1f} ms propagation alone), "
+        f"sigma_xx/(e^2/8hbar) = {np.mean(sg[band]) / 0.125:.3f} at 0.9-2.1 eV")
     H.close()
     return out
 
@@ -375,8 +409,9 @@ def main():
     ap.add_argument("--bwd-cells", type=int, default=512)
     ap.add_argument("--bwd-nt", type=int, default=1024)
     ap.add_argument("--no-tbg", action="store_true")
-    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS and wave-function snapshot legs")
+    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS, snapshot, quasi-eigenstate and optical-conductivity legs")
     ap.add_argument("--ldos-nt", type=int, default=512)
+    ap.add_argument("--ac-nt", type=int, default=256, help="time steps of the optical-conductivity leg")
     ap.add_argument("--tbg-cells", type=int, default=1024)
     ap.add_argument("--tbg-nt", type=int, default=1024)
     args = ap.parse_args()

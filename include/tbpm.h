@@ -261,13 +261,30 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
                          double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags, void *stream);
 
 /*
+ * Chebyshev coefficients of the Fermi-Dirac function (Sec. "Tight-binding
+ * propagation method": the expansion of a function of H by a discrete
+ * Fourier sum over Chebyshev nodes), as tbpm_ac_corr uses them:
+ *   f(H) = sum_{k<K} a[k] T_k(H / rescale),  f(x) = 1/(exp(beta (x - mu)) + 1),
+ * kept up to the last |a[k]| >= tol.  Host call, no GPU.
+ *   a    host, capacity cap doubles: the first min(cap, K) coefficients
+ *        (cap = 0 and a = NULL query K)
+ *   K    host, written: the number of coefficients
+ * TBPM_E_ARG for beta <= 0, rescale <= 0, tol outside (0, 1e-2), or an
+ * expansion longer than 2^19 terms.
+ */
+tbpm_status tbpm_fermi_cheb(double beta, double mu, double rescale, double tol, double *a, int32_t cap, int32_t *K);
+
+/*
  * Real part of the optical conductivity (Eq. (AC)) from tbpm_ac_corr's
  * correlation averaged over the states, by a rectangle rule on t_k = k dt
  * with the window of tbpm_dos in place of e^{-Et}:
  *   sigma(w_j) = (e^{-beta w_j} - 1) / (w_j area) dt sum_k w_k sin(w_j t_k) 2 Im Cbar_k
  * on w_j = j pi / (n_steps dt), j = 0 .. n_steps-1 (sigma(0) = 0: the Drude
  * part is omitted).  Units e = hbar = 1: energies in eV, area in the square
- * of the length unit of the current operator.
+ * of the length unit of the current operator.  The state average stands for
+ * a trace: with unit-norm random states (which estimate Tr/N) pass the
+ * sample's area divided by its number of orbitals, giving the conductivity
+ * in units of e^2/hbar per spin.
  *   corr          device [n_steps][n_states] complex128
  *   omegas, sigma device [n_steps] f64, written
  */

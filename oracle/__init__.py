@@ -290,7 +290,9 @@ def ac_cond(corr, dt: float, beta: float, area: float, kind: str = "hann"):
     t_k = k dt with the DOS window in place of e^{-Et}:
         sigma(w_j) = (e^{-beta w_j} - 1) / (w_j A) * dt * sum_k w_k sin(w_j t_k) 2 Im Cbar_k,
     on w_j = j pi / (N_t dt), j = 0 .. N_t-1 (sigma(0) = 0: the Drude part is
-    omitted).  Units e = hbar = 1 (energies in eV, lengths in A)."""
+    omitted).  Units e = hbar = 1 (energies in eV, lengths in A).  With
+    unit-norm random states (an estimate of Tr/N) ``area`` is the sample's
+    area per orbital."""
     corr = np.asarray(corr)
     if corr.ndim == 1:
         corr = corr[:, None]

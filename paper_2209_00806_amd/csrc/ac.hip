@@ -3,9 +3,12 @@
 //
 //  * k_gather_values: the current operator J (values on H's CSR pattern) in
 //    the sliced-ELL layout of H, through the slot -> CSR-position map.
-//  * k_pack: psi1 and psi2 (internal row order, [rows][S padded]) into one
-//    block of 2S states in the caller's row order, [n][2S]: psi1 in columns
-//    0..S-1, psi2 in S..2S-1, so that one propagation carries both.
+//  * k_join: J psi0 and psi0 (internal row order, [rows][S padded]) side by
+//    side in one block [rows][2S padded], so that one Chebyshev series of the
+//    Fermi-Dirac operator serves both: f(H) [J psi0 | psi0].
+//  * k_pack: from that block B and F = f(H) B, psi1 = (1 - f(H)) J psi0 =
+//    B - F in columns 0..S-1 and psi2 = f(H) psi0 in S..2S-1 of one block
+//    [n][2S] in the caller's row order, so that one propagation carries both.
 //  * k_jcorr: per step, <psi2_s| J |psi1_s> for s < S from the propagated
 //    block: J applied to the psi1 columns of each row (gathered over the
 //    row's stored elements) and contracted with the row's psi2 columns; FP64
@@ -32,18 +35,42 @@ __global__ __launch_bounds__(kWG) void k_gather_values(const int64_t *__restrict
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_pack(const d2 *__restrict__ psi1, const d2 *__restrict__ psi2, int64_t n_rows,
-                                              int log2s, int S, const int32_t *__restrict__ perm,
+__global__ __launch_bounds__(kWG) void k_join(const d2 *__restrict__ jpsi, const d2 *__restrict__ psi,
+                                              int64_t n_rows, int log2s, int log2s2, int S, d2 *__restrict__ out) {
+    const int64_t total = n_rows << log2s2;
+    const int64_t stride = (int64_t)gridDim.x * kWG;
+    const int m2 = (1 << log2s2) - 1;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total; i += stride) {
+        const int64_t r = i >> log2s2;
+        const int c = (int)(i & m2);
+        d2 v;
+        v.x = 0.0;
+        v.y = 0.0;
+        if (c < S)
+            v = jpsi[(r << log2s) + c];
+        else if (c < 2 * S)
+            v = psi[(r << log2s) + c - S];
+        out[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_pack(const d2 *__restrict__ blk, const d2 *__restrict__ fblk,
+                                              int64_t n_rows, int log2s2, int S, const int32_t *__restrict__ perm,
                                               d2 *__restrict__ out) {
-    const int64_t total = n_rows * S;
+    const int64_t total = n_rows * 2 * S;
     const int64_t stride = (int64_t)gridDim.x * kWG;
     for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < total; i += stride) {
-        const int64_t r = i / S;
-        const int s = (int)(i % S);
+        const int64_t r = i / (2 * S);
+        const int c = (int)(i % (2 * S));
         const int64_t ro = perm ? (int64_t)perm[r] : r;
-        const int64_t src = (r << log2s) + s;
-        out[ro * 2 * S + s] = psi1[src];
-        out[ro * 2 * S + S + s] = psi2[src];
+        const int64_t src = (r << log2s2) + c;
+        d2 v = fblk[src];
+        if (c < S) {
+            const d2 b = blk[src];
+            v.x = b.x - v.x;
+            v.y = b.y - v.y;
+        }
+        out[ro * 2 * S + c] = v;
     }
 }
 
@@ -130,10 +157,17 @@ hipError_t launch_gather_values(const int64_t *ell_csr, int64_t ell_size, const 
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const double *psi1, const double *psi2, int64_t n_rows, int32_t log2s, int32_t S,
+hipError_t launch_join(const double *jpsi, const double *psi, int64_t n_rows, int32_t log2s, int32_t log2s2,
+                       int32_t S, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_join, dim3((unsigned)grid_for_n(n_rows << log2s2)), dim3(kWG), 0, st, (const d2 *)jpsi,
+                       (const d2 *)psi, n_rows, log2s, log2s2, S, (d2 *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const double *blk, const double *fblk, int64_t n_rows, int32_t log2s2, int32_t S,
                        const int32_t *perm, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)grid_for_n(n_rows * S)), dim3(kWG), 0, st, (const d2 *)psi1,
-                       (const d2 *)psi2, n_rows, log2s, S, perm, (d2 *)out);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)grid_for_n(n_rows * 2 * S)), dim3(kWG), 0, st, (const d2 *)blk,
+                       (const d2 *)fblk, n_rows, log2s2, S, perm, (d2 *)out);
     return hipGetLastError();
 }
 

@@ -385,22 +385,21 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     const double f = resolve_rescale(H->csr, rescale);
     const std::vector<double> a = fermi_cheb_coeffs(beta, mu, f, fermi_tol);
     if (a.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms (beta * rescale too large)");
-    std::vector<double> one_minus(a.size());
-    for (size_t k = 0; k < a.size(); ++k) one_minus[k] = -a[k];
-    one_minus[0] += 1.0;
     Engine &eng = H->eng;
     int32_t s_pad = 1, log2s = 0;
     while (s_pad < n_states) {
         s_pad <<= 1;
         ++log2s;
     }
+    const int32_t log2s2 = log2s + 1;  // the joined block [J psi0 | psi0]
     hipStream_t hs = (hipStream_t)stream;
     const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;
+    const size_t vec2 = 2 * vec;
     const size_t ell = sizeof(double) * 2 * (size_t)std::max<int64_t>(eng.mat.ell_size, 1);
     hipError_t e = eng.ac_csr.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(nnz, 1));
     if (e == hipSuccess) e = eng.ac_ja.ensure(ell);
     if (e == hipSuccess) e = eng.ac_jb.ensure(ell);
-    if (e == hipSuccess) e = eng.ac_vec.ensure(6 * vec);
+    if (e == hipSuccess) e = eng.ac_vec.ensure(2 * vec + 4 * vec2);
     if (e == hipSuccess) e = eng.ac_block.ensure(sizeof(double) * 4 * (size_t)n * n_states);
     if (e == hipSuccess) e = eng.corr_scratch.ensure(sizeof(double) * 4 * (size_t)n_steps * n_states);
     if (e != hipSuccess) return hip_fail(e, "alloc optical-conductivity buffers");
@@ -417,17 +416,20 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
         if (e != hipSuccess) return hip_fail(e, "upload current operator");
     }
     char *vb = (char *)eng.ac_vec.ptr;
-    void *src = vb, *w0 = vb + vec, *w1 = vb + 2 * vec, *psi2 = vb + 3 * vec, *jpsi = vb + 4 * vec,
-         *psi1 = vb + 5 * vec;
+    void *src = vb, *jpsi = vb + vec, *blk = vb + 2 * vec, *w0 = vb + 2 * vec + vec2, *w1 = vb + 2 * vec + 2 * vec2,
+         *fblk = vb + 2 * vec + 3 * vec2;
     e = launch_expand_states(psi0, eng.mat.perm, n_states, (double *)src, log2s, n, hs);
     if (e != hipSuccess) return hip_fail(e, "load states");
     try {
-        // psi2 = f(H) psi0, psi1 = (1 - f(H)) J_beta psi0
-        st = eng.apply_series(a, f, log2s, src, psi2, w0, w1, hs);
-        if (st == TBPM_OK) st = eng.apply_ell((const double *)eng.ac_jb.ptr, log2s, src, jpsi, hs);
-        if (st == TBPM_OK) st = eng.apply_series(one_minus, f, log2s, jpsi, psi1, w0, w1, hs);
+        // one series over [J_beta psi0 | psi0]: psi1 = J_beta psi0 - f(H) J_beta psi0,
+        // psi2 = f(H) psi0
+        st = eng.apply_ell((const double *)eng.ac_jb.ptr, log2s, src, jpsi, hs);
         if (st != TBPM_OK) return st;
-        e = launch_pack((const double *)psi1, (const double *)psi2, n, log2s, n_states, eng.mat.perm,
+        e = launch_join((const double *)jpsi, (const double *)src, n, log2s, log2s2, n_states, (double *)blk, hs);
+        if (e != hipSuccess) return hip_fail(e, "join states");
+        st = eng.apply_series(a, f, log2s2, blk, fblk, w0, w1, hs);
+        if (st != TBPM_OK) return st;
+        e = launch_pack((const double *)blk, (const double *)fblk, n, log2s2, n_states, eng.mat.perm,
                         (double *)eng.ac_block.ptr, hs);
         if (e != hipSuccess) return hip_fail(e, "pack states");
         const double *p0 = (const double *)eng.ac_block.ptr;
@@ -452,6 +454,24 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     } catch (const std::bad_alloc &) {
         return fail(TBPM_E_OOM, "host allocation failed");
     }
+}
+
+tbpm_status tbpm_fermi_cheb(double beta, double mu, double rescale, double tol, double *a, int32_t cap,
+                            int32_t *K) {
+    if (!K || (cap > 0 && !a) || cap < 0) return fail(TBPM_E_ARG, "NULL argument or negative capacity");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(TBPM_E_ARG, "beta must be positive and finite");
+    if (!std::isfinite(mu)) return fail(TBPM_E_ARG, "mu must be finite");
+    if (!(rescale > 0.0) || !std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be positive and finite");
+    if (!(tol > 0.0 && tol < 1e-2)) return fail(TBPM_E_ARG, "tol must be in (0, 1e-2)");
+    try {
+        const std::vector<double> c = fermi_cheb_coeffs(beta, mu, rescale, tol);
+        if (c.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms");
+        *K = (int32_t)c.size();
+        std::memcpy(a, c.data(), sizeof(double) * (size_t)std::min<int64_t>(cap, (int64_t)c.size()));
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+    return TBPM_OK;
 }
 
 tbpm_status tbpm_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,

@@ -236,7 +236,9 @@ hipError_t launch_qe_finalize(const double *acc, int64_t n_rows, int32_t log2s, 
 // optical-conductivity launchers (ac.hip)
 hipError_t launch_gather_values(const int64_t *ell_csr, int64_t ell_size, const double *csr_val, double *ell_val,
                                 hipStream_t st);
-hipError_t launch_pack(const double *psi1, const double *psi2, int64_t n_rows, int32_t log2s, int32_t S,
+hipError_t launch_join(const double *jpsi, const double *psi, int64_t n_rows, int32_t log2s, int32_t log2s2,
+                       int32_t S, double *out, hipStream_t st);
+hipError_t launch_pack(const double *blk, const double *fblk, int64_t n_rows, int32_t log2s2, int32_t S,
                        const int32_t *perm, double *out, hipStream_t st);
 hipError_t launch_jcorr(bool fp32, const TileDesc *tiles, int32_t n_tiles, int32_t log2sp, int32_t S, int32_t log2s2,
                         const void *state, const uint32_t *slice_off, const int32_t *col, const double *jval,

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
         "tbpm_quasi_eigenstates": [P, P, I32, I32, D, D, D, ctypes.c_int, P, I32, ctypes.c_int, P, P, U32, P],
         "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
         "tbpm_ac_cond": [P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
+        "tbpm_fermi_cheb": [D, D, D, D, P, I32, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
         "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
         "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
@@ -357,6 +358,17 @@ def ac_corr(H: Hamiltonian, j_alpha, j_beta, psi0, n_steps: int, dt: float, beta
                               float(rescale), float(tol), float(beta), float(mu), float(fermi_tol), _prec(precision),
                               _ptr(corr), 0, _stream(stream)))
     return corr
+
+
+def fermi_coeffs(beta: float, mu: float, rescale: float, tol: float = 1e-12) -> np.ndarray:
+    """Chebyshev coefficients a_k of the Fermi-Dirac function on [-rescale,
+    rescale] (f(H) = sum_k a_k T_k(H/rescale)), as ac_corr uses them."""
+    K = ctypes.c_int32(0)
+    _check(lib().tbpm_fermi_cheb(float(beta), float(mu), float(rescale), float(tol), None, 0, ctypes.byref(K)))
+    a = np.zeros(K.value, dtype=np.float64)
+    _check(lib().tbpm_fermi_cheb(float(beta), float(mu), float(rescale), float(tol), a.ctypes.data, K.value,
+                                 ctypes.byref(K)))
+    return a
 
 
 def ac_cond(corr, dt: float, beta: float, area: float, window: str = "hann", stream=None):

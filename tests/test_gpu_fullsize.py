@@ -152,3 +152,22 @@ def test_quasi_eigenstates_full_size_short():
     got = tbpm.quasi_eigenstates(H, _dev(psi0), en, 6, dt, f).cpu().numpy()
     ref, _ = oracle.quasi_eigenstates(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 6, dt, f, en)
     assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_optical_conductivity_full_size_short():
+    """The optical-conductivity correlation on the 1024x1024 disordered lattice
+    of the bench leg, in the fused launch shape, at a temperature whose
+    Fermi-Dirac series the oracle finishes quickly, on a 4-step prefix."""
+    print("case optical conductivity 1024x1024", flush=True)
+    f = 9.0
+    dt = math.pi / f
+    lat, psi0 = inputs.workload_disordered_graphene(1024, 1)
+    jx = inputs.current_values(lat, 0)
+    jy = inputs.current_values(lat, 1)
+    beta, mu = 1.5, 0.3
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, fused=2)
+    got = tbpm.ac_corr(H, jx, jy, _dev(psi0), 4, dt, beta, mu, rescale=f, fermi_tol=1e-13).cpu().numpy()
+    ref, _, _ = oracle.ac_corr(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jy, psi0, 4, dt, f, beta, mu,
+                               fermi_tol=1e-13)
+    assert _rel(got, ref) < 1e-10

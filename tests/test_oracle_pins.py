@@ -551,3 +551,32 @@ def test_ac_conductivity_transform_vs_fft():
     ref[1:] = (np.exp(-beta * omega[1:]) - 1.0) / (omega[1:] * area) * s[1:]
     assert np.max(np.abs(sigma - ref)) < 1e-12 * np.max(np.abs(ref))
     assert sigma[0] == 0.0 and np.allclose(omega, np.arange(nt) * np.pi / (nt * dt))
+
+
+def test_ac_graphene_universal_conductivity_and_isotropy():
+    """Pristine graphene (256^2 cells, one random-phase state) at beta = 10/eV,
+    mu = 0: in the linear part of the spectrum Re sigma_xx is the universal
+    value e^2/(8 hbar) per spin (1/8 in units e = hbar = 1) when the area per
+    orbital normalises a unit-norm state's estimate of the trace; the
+    hexagonal lattice makes sigma_yy equal to it and sigma_xy vanish."""
+    lat = inputs.graphene(256, 256)
+    jx = inputs.current_values(lat, 0)
+    jy = inputs.current_values(lat, 1)
+    psi0 = inputs.random_phase_states(np.random.default_rng(5), lat.n_orb, 1)
+    f = 8.3
+    dt = math.pi / f
+    nt, beta, mu = 128, 10.0, 0.0
+    area = lat.area / lat.n_orb
+    out = {}
+    for name, ja, jb in (("xx", jx, jx), ("yy", jy, jy), ("xy", jx, jy)):
+        corr, _, _ = oracle.ac_corr(lat.row_ptr, lat.col, lat.val, lat.onsite, ja, jb, psi0, nt, dt, f, beta, mu,
+                                    fermi_tol=1e-12)
+        omega, out[name] = oracle.ac_cond(corr, dt, beta, area)
+    band = (omega > 0.9) & (omega < 2.1)
+    assert abs(np.mean(out["xx"][band]) / 0.125 - 1) < 0.08
+    assert abs(np.mean(out["yy"][band]) / 0.125 - 1) < 0.08
+    # (single-state noise is a few per cent of sigma_xx point by point)
+    assert abs(np.mean(out["xy"][band])) < 0.05 * 0.125
+    assert np.max(np.abs(out["xy"][band])) < 0.25 * 0.125
+    # the van Hove singularity of interband transitions at 2|t| = 5.4 eV
+    assert abs(omega[np.argmax(out["xx"])] - 5.4) < 0.3
