@@ -21,6 +21,8 @@ Pieces:
     Fermi-Dirac operator (forward recurrence);
   * :func:`ac_corr`, :func:`ac_cond` -- optical-conductivity correlation and
     its windowed sine transform (Kubo formula);
+  * :func:`haydock`, :func:`haydock_ldos` -- the Lanczos recursion of the
+    Haydock method and the continued fraction of the Green's function;
   * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
     correlation, summed directly (no FFT);
   * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
@@ -306,6 +308,66 @@ def ac_cond(corr, dt: float, beta: float, area: float, kind: str = "hann"):
         s = np.sum(w * np.sin(omega[j] * tk) * 2.0 * np.imag(cbar)) * dt
         sigma[j] = (np.exp(-beta * omega[j]) - 1.0) / (omega[j] * area) * s
     return omega, sigma
+
+
+def haydock(row_ptr, col, val, onsite, psi0, n_iter: int, breakdown: float = 1e-11):
+    """Lanczos recursion of the Haydock method (Sec. "Local density of
+    states", the recursion method), one chain per column of psi0:
+        l_0 = psi0 / ||psi0||,  l_{-1} = 0,
+        a_i = <l_i|H|l_i>,
+        m_{i+1} = (H - a_i) l_i - b_i l_{i-1},
+        b_{i+1} = ||m_{i+1}||,  l_{i+1} = m_{i+1} / b_{i+1}.
+    Returns (a [n_iter, S], b [n_iter, S]) with b[i] = b_{i+1}.  A chain whose
+    b_{i+1} falls to ``breakdown`` times the Gershgorin bound or below has
+    reached an invariant subspace: b_{i+1} is set to 0 and the chain stays
+    zero (its continued fraction ends there).  The sparse product is SciPy's
+    CSR matrix-vector product."""
+    import scipy.sparse as sp
+
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    h = sp.csr_matrix((val, col, row_ptr), shape=(n, n)) + sp.diags(onsite)
+    thr = breakdown * gershgorin(row_ptr, val, onsite)
+    a = np.zeros((n_iter, S))
+    b = np.zeros((n_iter, S))
+    for s in range(S):
+        nrm = np.linalg.norm(psi0[:, s])
+        if nrm == 0.0:
+            continue
+        l_prev = np.zeros(n, dtype=np.complex128)
+        l_cur = psi0[:, s] / nrm
+        b_cur = 0.0
+        for i in range(n_iter):
+            hl = h @ l_cur
+            a[i, s] = np.real(np.vdot(l_cur, hl))
+            m = hl - a[i, s] * l_cur - b_cur * l_prev
+            b_next = np.linalg.norm(m)
+            if b_next <= thr:
+                break
+            b[i, s] = b_next
+            l_prev, l_cur, b_cur = l_cur, m / b_next, b_next
+    return a, b
+
+
+def haydock_ldos(a, b, energies_ev, eps: float):
+    """d(E) = -(1/pi) Im G_0(E + i eps) with the continued fraction
+    G_0(z) = 1/(z - a_0 - b_1^2/(z - a_1 - b_2^2/(... /(z - a_{n-1})))),
+    evaluated from the deepest level up (a zero terminator).  Returns
+    [n_E, S]."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    n, S = a.shape
+    out = np.zeros((len(energies_ev), S))
+    for j, e in enumerate(energies_ev):
+        z = complex(e, eps)
+        for s in range(S):
+            t = z - a[n - 1, s]
+            for i in range(n - 2, -1, -1):
+                t = z - a[i, s] - b[i, s] ** 2 / t
+            out[j, s] = -(1.0 / t).imag / math.pi
+    return out
 
 
 def energies(n_steps: int, dt: float) -> np.ndarray:

@@ -580,3 +580,80 @@ def test_ac_graphene_universal_conductivity_and_isotropy():
     assert np.max(np.abs(out["xy"][band])) < 0.25 * 0.125
     # the van Hove singularity of interband transitions at 2|t| = 5.4 eV
     assert abs(omega[np.argmax(out["xx"])] - 5.4) < 0.3
+
+
+# ----------------------------------------------------------------------------
+# Haydock recursion (Sec. "Local density of states", the recursion method)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("eps0", [0.0, 0.37])
+def test_haydock_chain_closed_form(eps0):
+    """A linear chain (on-site eps0, hopping t): from the middle site the
+    recursion gives a_i = eps0, b_1 = sqrt(2)|t|, b_i = |t| (i >= 2) until it
+    reaches an end; from an end site every b_i = |t|."""
+    L, t = 241, -2.7
+    lat = inputs.square(1, L, t=t, pbc=False, onsite=np.full(L, eps0))
+    st = inputs.unit_states(L, [L // 2, 0])
+    a, b = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, st, 100)
+    assert np.max(np.abs(a - eps0)) < 1e-13
+    assert abs(b[0, 0] - math.sqrt(2) * abs(t)) < 1e-13
+    assert np.max(np.abs(b[1:, 0] - abs(t))) < 1e-12
+    assert np.max(np.abs(b[:, 1] - abs(t))) < 1e-12
+
+
+def test_haydock_dimer_breakdown():
+    """The dimer's Krylov space from one site has dimension 2: a = (e1, e2),
+    b_1 = |t|, b_2 = 0, and the continued fraction is the exact two-level
+    Green's function."""
+    e1, e2, t = 0.4, -0.9, 1.3
+    lat = inputs.from_bonds(2, np.array([0]), np.array([1]), np.array([t]), np.array([e1, e2]))
+    a, b = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, inputs.unit_states(2, [0]), 6)
+    assert np.allclose(a[:, 0], [e1, e2, 0, 0, 0, 0], atol=1e-15)
+    assert np.allclose(b[:, 0], [abs(t), 0, 0, 0, 0, 0], atol=1e-15)
+    e, u = np.linalg.eigh(lat.dense())
+    en = np.linspace(-3, 3, 61)
+    d = oracle.haydock_ldos(a, b, en, 0.05)[:, 0]
+    ref = (np.abs(u[0]) ** 2 * (0.05 / math.pi) / ((en[:, None] - e) ** 2 + 0.05 ** 2)).sum(axis=1)
+    assert np.max(np.abs(d - ref)) < 1e-12 * np.max(ref)
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex", "square5x7_open"])
+def test_haydock_moments(name):
+    """The Jacobi matrix of n steps reproduces the moments <l0|H^k|l0> for
+    k <= 2n - 1 (brute-force powers of the dense H)."""
+    lat = SMALL_LATTICES[name]()
+    h = lat.dense()
+    rng = np.random.default_rng(13)
+    st = np.concatenate([inputs.unit_states(lat.n_orb, [3]), inputs.random_phase_states(rng, lat.n_orb, 1)], axis=1)
+    n = 9
+    a, b = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, st, n)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite)
+    for s in range(2):
+        jm = np.diag(a[:, s]) + np.diag(b[: n - 1, s], 1) + np.diag(b[: n - 1, s], -1)
+        l0 = st[:, s] / np.linalg.norm(st[:, s])
+        v = l0.copy()
+        jk = np.eye(n)
+        for k in range(1, 2 * n):
+            v = h @ v
+            jk = jk @ jm
+            mom = np.vdot(l0, v)
+            assert abs(mom.imag) < 1e-12 * f ** k
+            assert abs(jk[0, 0] - mom.real) < 1e-12 * f ** k, (s, k)
+
+
+@pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex"])
+def test_haydock_ldos_vs_ed(name):
+    """With as many steps as orbitals the recursion spans the whole Krylov
+    space and the broadened LDOS is the eigenvector-weight formula (to the
+    1e-8 level that the loss of orthogonality of finite-precision Lanczos
+    leaves)."""
+    lat = SMALL_LATTICES[name]()
+    e, u = np.linalg.eigh(lat.dense())
+    orb = 5
+    a, b = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, inputs.unit_states(lat.n_orb, [orb]),
+                          lat.n_orb)
+    en = np.linspace(-9, 9, 181)
+    eta = 0.1
+    d = oracle.haydock_ldos(a, b, en, eta)[:, 0]
+    ref = (np.abs(u[orb]) ** 2 * (eta / math.pi) / ((en[:, None] - e) ** 2 + eta ** 2)).sum(axis=1)
+    assert np.max(np.abs(d - ref)) < 1e-7 * np.max(ref)
