@@ -31,10 +31,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 KERNEL_SOURCES = ["paper_2209_00806_amd/csrc/kernels.hip", "paper_2209_00806_amd/csrc/device_util.h",
-                  "paper_2209_00806_amd/csrc/tbpm_internal.h"]
+                  "paper_2209_00806_amd/csrc/kernel_params.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pass_mid_graphene1024_s8_fp64.json")
 PAIR_SOURCES = ["paper_2209_00806_amd/csrc/fused.hip", "paper_2209_00806_amd/csrc/device_util.h",
-                "paper_2209_00806_amd/csrc/tbpm_internal.h"]
+                "paper_2209_00806_amd/csrc/kernel_params.h"]
 PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pair_mid_graphene1024_s8_fp64.json")
 
 
@@ -68,6 +68,14 @@ def step_bytes(M: int, n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
     """Algorithmic bytes of one time step, independent of the launch schedule:
     M-1 passes of pass_bytes plus the FP64 phi0 stream of the correlation."""
     return (M - 1) * pass_bytes(n_orb, nnz, S, b, v) + 16 * n_orb * S
+
+
+def hay_iter_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
+    """Algorithmic bytes of one Haydock iteration over S chains: the product
+    pass reads u_i (gathered) and u_{i-1} and writes y, the update reads y and
+    u_i and writes u_{i+1} (6 state vectors), plus the matrix and on-site
+    energies once."""
+    return 6 * b * n_orb * S + nnz * (4 + v) + n_orb * v
 
 
 def schedule_bytes(M: int, fused: bool, n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
@@ -275,6 +283,26 @@ def bench_ldos_psi_t(args, log, cfg64=None):
         "sigma_xx_over_e2_8hbar_0.9_2.1eV": round(float(np.mean(sg[band]) / 0.125), 3)}
     log(f"optical conductivity: {K} Fermi terms, {na} steps, {ms_a:.1f} ms ({ms_p2:.1f} ms propagation alone), "
         f"sigma_xx/(e^2/8hbar) = {np.mean(sg[band]) / 0.125:.3f} at 0.9-2.1 eV")
+    # LDOS by the Haydock recursion: the 8 orbitals of the LDOS leg, one
+    # Lanczos chain each, advanced together
+    st = torch.zeros((lat.n_orb, len(orbs)), dtype=torch.complex128, device="cuda")
+    st[torch.as_tensor(orbs, device="cuda"), torch.arange(len(orbs), device="cuda")] = 1.0
+    nh = args.hay_iter
+    tbpm.haydock(H, st, 8)  # warm-up (tiles, buffers)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ha, hb = tbpm.haydock(H, st, nh)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_h = e0.elapsed_time(e1)
+    en_h = torch.linspace(-10.0, 10.0, 4001, dtype=torch.float64, device="cuda")
+    dh = tbpm.haydock_ldos(ha, hb, en_h, 0.02).mean(dim=1)
+    hay_bytes = hay_iter_bytes(lat.n_orb, lat.nnz, len(orbs), 16, 8) * nh
+    out["haydock"] = {"orbitals": len(orbs), "iterations": nh, "ms": round(ms_h, 1),
+                      "us_per_iteration": round(1e3 * ms_h / nh, 1),
+                      "alg_GBps": round(hay_bytes / (ms_h / 1e3) / 1e9, 1),
+                      "ldos_integral_pm10eV": round(float(dh.sum().item() * 20.0 / 4000), 4)}
+    log(f"haydock: 8 orbitals, {nh} iterations, {ms_h:.1f} ms, {hay_bytes / (ms_h / 1e3) / 1e9:.0f} GB/s")
     H.close()
     return out
 
@@ -409,9 +437,10 @@ def main():
     ap.add_argument("--bwd-cells", type=int, default=512)
     ap.add_argument("--bwd-nt", type=int, default=1024)
     ap.add_argument("--no-tbg", action="store_true")
-    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS, snapshot, quasi-eigenstate and optical-conductivity legs")
+    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS, snapshot, quasi-eigenstate, optical-conductivity and Haydock legs")
     ap.add_argument("--ldos-nt", type=int, default=512)
     ap.add_argument("--ac-nt", type=int, default=256, help="time steps of the optical-conductivity leg")
+    ap.add_argument("--hay-iter", type=int, default=1000, help="iterations of the Haydock leg")
     ap.add_argument("--tbg-cells", type=int, default=1024)
     ap.add_argument("--tbg-nt", type=int, default=1024)
     args = ap.parse_args()

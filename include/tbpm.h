@@ -261,6 +261,39 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
                          double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags, void *stream);
 
 /*
+ * Haydock recursion (Sec. "Local density of states", the recursion method):
+ * one Lanczos chain per column of psi0, all chains advanced together,
+ *   l_0 = psi0_s / ||psi0_s||,  a_i = <l_i|H|l_i>,
+ *   m_{i+1} = (H - a_i) l_i - b_i l_{i-1},  b_{i+1} = ||m_{i+1}||,
+ *   l_{i+1} = m_{i+1} / b_{i+1}   (l_{-1} = 0),
+ * so that <l_0|(z - H)^{-1}|l_0> is the continued fraction of
+ * tbpm_haydock_ldos.  A unit vector on orbital i gives the LDOS of i.
+ *   psi0      device, [n_orb][n_states] complex128 start vectors (caller's
+ *             row order); a zero column gives zero coefficients
+ *   n_states  1 .. 64;  n_iter  1 .. 2^24
+ *   a, b      device, [n_iter][n_states] f64, written: a[i] = a_i and
+ *             b[i] = b_{i+1}.  When b_{i+1} falls to 1e-11 times the
+ *             Gershgorin bound of H or below, the chain has reached an
+ *             invariant subspace: b_{i+1} is written as 0 and every later
+ *             coefficient of that chain is 0.
+ * Unscaled H (energies in eV), FP64.  Returns after the work has finished
+ * (flags: TBPM_FLAG_NO_GRAPH launches every iteration directly).
+ */
+tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_iter, double *a,
+                         double *b, uint32_t flags, void *stream);
+
+/*
+ * LDOS from Haydock coefficients: d(E) = -(1/pi) Im G_0(E + i eps) with
+ *   G_0(z) = 1/(z - a_0 - b_1^2/(z - a_1 - b_2^2/( ... /(z - a_{n-1})))),
+ * the continued fraction cut after n_iter levels (no terminator).
+ *   a, b      device [n_iter][n_states] f64 as written by tbpm_haydock
+ *   energies  device [n_e] f64 (eV);  eps > 0 the broadening (eV)
+ *   ldos      device [n_e][n_states] f64, written (per eV)
+ */
+tbpm_status tbpm_haydock_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states,
+                              const double *energies, int64_t n_e, double eps, double *ldos, void *stream);
+
+/*
  * Chebyshev coefficients of the Fermi-Dirac function (Sec. "Tight-binding
  * propagation method": the expansion of a function of H by a discrete
  * Fourier sum over Chebyshev nodes), as tbpm_ac_corr uses them:

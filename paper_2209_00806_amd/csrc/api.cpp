@@ -456,6 +456,31 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     }
 }
 
+tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_iter, double *a,
+                         double *b, uint32_t flags, void *stream) {
+    if (!H || !psi0 || !a || !b) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    if (n_iter < 1 || n_iter > (1 << 24)) return fail(TBPM_E_ARG, "n_iter must be in [1, 2^24]");
+    if ((int64_t)H->csr.n * 64 >= ((int64_t)1 << 31)) return fail(TBPM_E_ARG, "rows * 64 states must be below 2^31");
+    const double thr = 1e-11 * H->csr.gershgorin;
+    try {
+        return H->eng.haydock(psi0, n_states, n_iter, thr, a, b, flags, (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_haydock_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states,
+                              const double *energies, int64_t n_e, double eps, double *ldos, void *stream) {
+    if (!a || !b || !energies || !ldos) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_iter < 1 || n_states < 1 || n_e < 1 || n_e * n_states > ((int64_t)1 << 40))
+        return fail(TBPM_E_ARG, "bad n_iter, n_states or n_e");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(TBPM_E_ARG, "eps must be positive and finite");
+    hipError_t e = launch_hay_ldos(a, b, n_iter, n_states, energies, n_e, eps, ldos, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch continued fraction");
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_fermi_cheb(double beta, double mu, double rescale, double tol, double *a, int32_t cap,
                             int32_t *K) {
     if (!K || (cap > 0 && !a) || cap < 0) return fail(TBPM_E_ARG, "NULL argument or negative capacity");

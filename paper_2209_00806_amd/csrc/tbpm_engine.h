@@ -105,6 +105,8 @@ struct Engine {
     // a zero on-site vector, preparation vectors, the packed block, and the
     // correlation's pointer table and norm scratch
     DevBuf ac_ja, ac_jb, ac_csr, ac_zero, ac_vec, ac_block, jc_tab, jc_norm;
+    // Haydock recursion: two Lanczos vectors, the product vector, per-state scalars
+    DevBuf hay_u, hay_y, hay_s;
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
@@ -174,6 +176,10 @@ struct Engine {
                              void *w0, void *w1, hipStream_t st);
     // dst = J src for J given as complex128 values in the ELL layout of H
     tbpm_status apply_ell(const double *jval, int32_t log2s, const void *src, void *dst, hipStream_t st);
+    // Haydock (Lanczos) recursion of every column of psi0 (device, caller's
+    // order, [rows][s_user] complex128): a_out, b_out device [n_iter][s_user]
+    tbpm_status haydock(const double *psi0, int32_t s_user, int32_t n_iter, double thr, double *a_out, double *b_out,
+                        uint32_t flags, hipStream_t st);
     // back-to-back launches of the interior pass on the current buffers
     tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
     int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1;

@@ -8,34 +8,11 @@
 #include <vector>
 
 #include "../../include/tbpm.h"
+#include "kernel_params.h"
 
 namespace tbpm {
 
-// ---------------------------------------------------------------------------
-// Device layout
-// ---------------------------------------------------------------------------
-// Off-diagonal part of H in sliced ELL: slices of kSliceRows consecutive
-// rows; slice q holds width_q = (slice_off[q+1]-slice_off[q])/kSliceRows
-// entries per row, stored column-major inside the slice, i.e. entry k of
-// row r lives at slice_off[q] + k*kSliceRows + (r % kSliceRows).  Rows
-// shorter than width_q are padded with (col = row, value = 0).
-constexpr int kSliceRows = 32;
-// Threads per workgroup of every streaming kernel (4 wave64s).
-constexpr int kWG = 256;
-
-// One workgroup's share of a Chebyshev pass: 'rows' consecutive rows of a
-// single batch member 'inst', starting at global row 'row0'.
-struct TileDesc {
-    int64_t row0;
-    int32_t rows;
-    int32_t inst;
-};
-
-// Per-member coefficients of one pass: out = alpha*v + beta*(H x) - b2.
-struct PassCoef {
-    double ar, ai, br, bi;
-};
-
+// Device image of the Hamiltonian (sliced ELL, described in kernel_params.h).
 struct DevMatrix {
     int64_t n_rows = 0;      // total rows (sum over batch members)
     int64_t n_slices = 0;
@@ -58,113 +35,6 @@ struct HostEll {
     std::vector<int64_t> slice_off;
     std::vector<int32_t> col;
     std::vector<int64_t> csr_pos;
-};
-
-// ---------------------------------------------------------------------------
-// Kernel launch parameters
-// ---------------------------------------------------------------------------
-enum PassKind : int {
-    kPassFirst = 0,   // x = v, no b2 buffer
-    kPassNoB2 = 1,    // no b2 buffer
-    kPassMid = 2,     // b2 buffer
-    kPassLast = 3,    // b2 buffer, fused correlation
-    kPassLastNoB2 = 4 // no b2 buffer, fused correlation
-};
-
-struct PassParams {
-    const TileDesc *tiles;
-    int32_t n_tiles;
-    int32_t xcd_remap;
-    int32_t log2s;  // log2 of the (padded) number of states
-    int32_t bump_counter;
-    const int32_t *col;
-    const void *val;
-    const uint32_t *slice_off;
-    const void *onsite;
-    const void *x;   // gathered vector (b_{j+1}, or v for the first pass)
-    const void *v;   // psi_k
-    const void *b2;  // b_{j+2}
-    void *out;       // b_j or psi_{k+1}; may alias b2 or v element-wise
-    const PassCoef *coef;  // [n_inst] of this pass
-    int32_t *counter;      // device step counter
-    // fused correlation (last pass)
-    const double *phi0;    // complex128 [rows][S]
-    int64_t phi0_ld;       // states per row of phi0 (>= S padded or the caller's S)
-    double *partials;      // [S][3][n_tiles]
-    // stored states (last pass): checkpoints or snapshots of psi(k dt)
-    double *ckpt;              // complex128 [n_slots][rows][s_user], rows in the caller's order
-    const int32_t *ckpt_slot;  // [n_steps]: slot of psi(k dt) in ckpt, or -1; null: none stored
-    const int32_t *perm;       // internal row -> caller's row (single member), or null
-    int64_t ckpt_stride;       // complex elements per slot (rows * s_user)
-    int32_t s_user;
-    // LDS staging (staged launch shape): tile t reads its own rows and the
-    // external rows ucol[uoff[t] .. uoff[t+1]); lidx[slot] is the local row of
-    // each ELL slot in that staged set
-    const int32_t *uoff;
-    const int32_t *ucol;
-    const uint16_t *lidx;
-    int32_t stage_units;   // LDS capacity in units (VS states)
-};
-
-// Two Clenshaw orders per launch (fused.hip).
-enum PairKind : int {
-    kPairFirst = 0,  // b_{M-2}, b_{M-3} from psi (x = psi, no b_{j+2})
-    kPairMid = 1     // b_j, b_{j-1} from b_{j+1} (x) and b_{j+2}
-};
-
-struct FusedParams {
-    const TileDesc *tiles;
-    int32_t n_tiles;
-    int32_t xcd_remap;
-    int32_t log2s;
-    int32_t bump_counter;
-    const int32_t *col;
-    const void *val;
-    const uint32_t *slice_off;
-    const void *onsite;
-    const void *x;     // b_{j+1} (or psi for kPairFirst), staged
-    const void *v;     // psi
-    const void *b2;    // b_{j+2} (kPairMid)
-    void *out1;        // b_j on own rows
-    void *out2;        // b_{j-1} on own rows
-    const PassCoef *coef1, *coef2;  // [n_inst] for orders j and j-1
-    int32_t *counter;
-    // 2-hop tiles: staged rows are own, then 1-hop (n1 of them), then 2-hop
-    const int32_t *uoff;   // [n_tiles + 1] offsets into ucol
-    const int32_t *n1;     // [n_tiles]
-    const int32_t *ucol;   // 1-hop then 2-hop global rows of every tile
-    const uint16_t *lidx;  // per ELL slot of an own row: local index (own or 1-hop)
-    const int32_t *hoff;   // [n_tiles] offset of the tile's 1-hop index block in hidx
-    const int32_t *hw;     // [n_tiles] entries per 1-hop row in that block
-    const uint16_t *hidx;  // local indices of the stored elements of the 1-hop rows
-    int32_t lds_units;     // LDS capacity in units: max over tiles of n_x + n_y
-};
-
-struct InitParams {
-    const TileDesc *tiles;
-    int32_t n_tiles;
-    int32_t log2s;
-    int32_t s_user;
-    const double *const *psi0;   // per member, [N_i][s_user] complex128
-    const int64_t *inst_row0;    // per member, first global row
-    void *v;                     // state buffer [rows][S] (R precision)
-    double *phi0;                // padded FP64 copy [rows][S], or null
-    double *partials;            // [S][3][n_tiles]
-    int32_t *counter;
-    const int32_t *perm;         // internal row -> caller's row in its member, or null
-};
-
-struct ReduceParams {
-    const double *partials;      // [S][3][n_tiles]
-    int32_t n_tiles;
-    const int32_t *inst_tile0;   // [n_inst + 1]
-    int32_t log2s;
-    int32_t s_user;
-    int32_t n_steps;
-    const int32_t *counter;
-    double *const *corr;          // per member [n_steps][s_user] complex128
-    double *const *norm2;         // per member, entries may be null
-    double *norm2_all;            // [n_inst][n_steps][s_user]
 };
 
 // launchers (kernels.hip)
@@ -250,6 +120,19 @@ hipError_t launch_ac_cond(const double *corr, int32_t n_steps, int32_t n_states,
 std::vector<double> fermi_cheb_coeffs(double beta, double mu, double rescale, double tol);
 
 // backward launchers (backward.hip)
+// Haydock recursion launchers (haydock.hip); mode: 0 a_i, 1 b_{i+1}, 2 initial norm
+hipError_t launch_hay_spmv(bool cplx, const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s,
+                           const int32_t *col, const void *val, const uint32_t *slice_off, const double *onsite,
+                           const double *u, const double *uprev, double *y, const double *hs, int32_t *counter,
+                           double *partials, hipStream_t st);
+hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s, const double *y,
+                           const double *u, double *unext, const double *hs, double *partials, hipStream_t st);
+hipError_t launch_hay_reduce(const double *partials, int32_t n_tiles, int32_t s_pad, int32_t s_user, int32_t mode,
+                             double thr, double *hs, int32_t *counter, int32_t n_iter, double *a_out, double *b_out,
+                             hipStream_t st);
+hipError_t launch_hay_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states, const double *energies,
+                           int64_t n_e, double eps, double *out, hipStream_t st);
+
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
 // dst[r][s] = src[perm[r]][s] (src[r][s] if perm is null), zero for s >= s_user
 hipError_t launch_expand_states(const double *src, const int32_t *perm, int32_t s_user, double *dst, int32_t log2s,

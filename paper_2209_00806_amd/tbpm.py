@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
         "tbpm_ac_cond": [P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
         "tbpm_fermi_cheb": [D, D, D, D, P, I32, P],
+        "tbpm_haydock": [P, P, I32, I32, P, P, U32, P],
+        "tbpm_haydock_ldos": [P, P, I32, I32, P, ctypes.c_int64, D, P, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
         "tbpm_dos_backward": [P, I32, I32, D, ctypes.c_int, P, P],
         "tbpm_backward": [P, P, I32, I32, D, D, D, P, I32, P, P, P, P],
@@ -358,6 +360,63 @@ def ac_corr(H: Hamiltonian, j_alpha, j_beta, psi0, n_steps: int, dt: float, beta
                               float(rescale), float(tol), float(beta), float(mu), float(fermi_tol), _prec(precision),
                               _ptr(corr), 0, _stream(stream)))
     return corr
+
+
+def haydock(H: Hamiltonian, psi0, n_iter: int, graph: bool = True, stream=None):
+    """Haydock (Lanczos) coefficients of every column of psi0 (CUDA
+    complex128 [n_orb, S], S <= 64): returns (a, b), each [n_iter, S] float64
+    with b[i] = b_{i+1}."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    if psi0.dim() == 1:
+        psi0 = psi0.reshape(-1, 1)
+    n, S = psi0.shape
+    a = torch.empty((n_iter, S), dtype=torch.float64, device=psi0.device)
+    b = torch.empty((n_iter, S), dtype=torch.float64, device=psi0.device)
+    _check(lib().tbpm_haydock(H.handle, _ptr(psi0), S, int(n_iter), _ptr(a), _ptr(b),
+                              0 if graph else FLAG_NO_GRAPH, _stream(stream)))
+    return a, b
+
+
+def haydock_ldos(a, b, energies, eps: float, stream=None):
+    """-(1/pi) Im G_0(E + i eps) by the continued fraction of Haydock
+    coefficients (CUDA float64 [n_iter, S]); energies a sequence or a CUDA
+    float64 tensor.  Returns [n_E, S]."""
+    import torch
+
+    _require_cuda(a, torch.float64, "a")
+    _require_cuda(b, torch.float64, "b")
+    if a.dim() == 1:
+        a, b = a.reshape(-1, 1), b.reshape(-1, 1)
+    if a.shape != b.shape:
+        raise ValueError("a and b must have the same shape")
+    en = energies if isinstance(energies, torch.Tensor) else torch.as_tensor(
+        np.asarray(energies, dtype=np.float64), device=a.device)
+    en = en.to(device=a.device, dtype=torch.float64).contiguous()
+    n_iter, S = a.shape
+    out = torch.empty((en.numel(), S), dtype=torch.float64, device=a.device)
+    _check(lib().tbpm_haydock_ldos(_ptr(a.contiguous()), _ptr(b.contiguous()), n_iter, S, _ptr(en), en.numel(),
+                                   float(eps), _ptr(out), _stream(stream)))
+    return out
+
+
+def ldos_haydock(H: Hamiltonian, orbitals, n_iter: int, energies, eps: float, stream=None):
+    """LDOS averaged over ``orbitals`` by the recursion method (unit-vector
+    start states, one Lanczos chain each, up to 64 per launch)."""
+    import torch
+
+    orbitals = np.asarray(orbitals, dtype=np.int64)
+    n = H.info()["n_orb"]
+    total = None
+    for c0 in range(0, orbitals.size, 64):
+        chunk = orbitals[c0:c0 + 64]
+        st = torch.zeros((n, chunk.size), dtype=torch.complex128, device="cuda")
+        st[torch.as_tensor(chunk, device="cuda"), torch.arange(chunk.size, device="cuda")] = 1.0
+        a, b = haydock(H, st, n_iter, stream=stream)
+        d = haydock_ldos(a, b, energies, eps, stream=stream).sum(dim=1)
+        total = d if total is None else total + d
+    return total / orbitals.size
 
 
 def fermi_coeffs(beta: float, mu: float, rescale: float, tol: float = 1e-12) -> np.ndarray:

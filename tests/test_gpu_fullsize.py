@@ -171,3 +171,19 @@ def test_optical_conductivity_full_size_short():
     ref, _, _ = oracle.ac_corr(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jy, psi0, 4, dt, f, beta, mu,
                                fermi_tol=1e-13)
     assert _rel(got, ref) < 1e-10
+
+
+def test_haydock_full_size_short():
+    """Haydock coefficients of the 8 orbitals of the bench leg on the
+    1024x1024 disordered lattice (automatic row order), first 24 iterations,
+    against the oracle."""
+    print("case haydock 1024x1024", flush=True)
+    lat, _ = inputs.workload_disordered_graphene(1024, 1)
+    orbs = np.linspace(0, lat.n_orb - 1, 8).astype(np.int64)
+    st = inputs.unit_states(lat.n_orb, orbs)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    g = H.info()["gershgorin"]
+    a, b = tbpm.haydock(H, _dev(st), 24)
+    ar, br = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, st, 24)
+    assert np.max(np.abs(a.cpu().numpy() - ar)) < 1e-11 * g
+    assert np.max(np.abs(b.cpu().numpy() - br)) < 1e-11 * g
