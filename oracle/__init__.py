@@ -23,6 +23,8 @@ Pieces:
     its windowed sine transform (Kubo formula);
   * :func:`haydock`, :func:`haydock_ldos` -- the Lanczos recursion of the
     Haydock method and the continued fraction of the Green's function;
+  * :func:`jackson`, :func:`kpm_moments`, :func:`kubo_bastin` -- the
+    Kubo-Bastin conductivity tensor by the kernel polynomial method;
   * :func:`dos` -- Hann-windowed Fourier transform of the sample-averaged
     correlation, summed directly (no FFT);
   * :func:`dos_adjoint`, :func:`backward` -- the discrete adjoints used to
@@ -368,6 +370,88 @@ def haydock_ldos(a, b, energies_ev, eps: float):
                 t = z - a[i, s] - b[i, s] ** 2 / t
             out[j, s] = -(1.0 / t).imag / math.pi
     return out
+
+
+def jackson(n_moments: int) -> np.ndarray:
+    """Jackson kernel g_m, m = 0..N-1, for N moments (the closed form of the
+    kernel polynomial method):
+    g_m = [(N - m + 1) cos(pi m/(N+1)) + sin(pi m/(N+1)) cot(pi/(N+1))]/(N+1)."""
+    N = n_moments
+    m = np.arange(N)
+    q = math.pi / (N + 1)
+    return ((N - m + 1) * np.cos(q * m) + np.sin(q * m) / math.tan(q)) / (N + 1)
+
+
+def kpm_moments(row_ptr, col, val, onsite, v_alpha, v_beta, psi0, n_moments: int, rescale: float):
+    """mu[m, n] = (1/S) sum_s <r_s| v_alpha T_m(H~) v_beta T_n(H~) |r_s>,
+    H~ = H/rescale, m, n < n_moments (Sec. "Tight-binding propagation method",
+    the Kubo-Bastin formula; no kernel factors).  v_alpha, v_beta: values on
+    the CSR pattern of H (Hermitian).  With L_m = T_m(H~) v_alpha r and
+    R_n = v_beta T_n(H~) r, mu = L^H R, a matrix product."""
+    import scipy.sparse as sp
+
+    row_ptr, col, val, onsite, psi0 = _prep(row_ptr, col, val, onsite, psi0)
+    n, S = psi0.shape
+    ht = (sp.csr_matrix((val, col, row_ptr), shape=(n, n)) + sp.diags(onsite)) / rescale
+    va = sp.csr_matrix((np.asarray(v_alpha, dtype=np.complex128), col, row_ptr), shape=(n, n))
+    vb = sp.csr_matrix((np.asarray(v_beta, dtype=np.complex128), col, row_ptr), shape=(n, n))
+    M = n_moments
+    mu = np.zeros((M, M), dtype=np.complex128)
+    for s in range(S):
+        r = psi0[:, s]
+        L = np.zeros((n, M), dtype=np.complex128)
+        R = np.zeros((n, M), dtype=np.complex128)
+        t_prev, t_cur = None, va @ r
+        for m in range(M):  # T_0 = 1, T_1 = x, T_{m+1} = 2 x T_m - T_{m-1}
+            L[:, m] = t_cur
+            t_next = ht @ t_cur if m == 0 else 2.0 * (ht @ t_cur) - t_prev
+            t_prev, t_cur = t_cur, t_next
+        t_prev, t_cur = None, r.copy()
+        for m in range(M):
+            R[:, m] = vb @ t_cur
+            t_next = ht @ t_cur if m == 0 else 2.0 * (ht @ t_cur) - t_prev
+            t_prev, t_cur = t_cur, t_next
+        mu += L.conj().T @ R
+    return mu / S
+
+
+def kubo_bastin(mu, rescale: float, e_lo: float, e_hi: float, n_energy: int, beta: float, mus, area: float):
+    """sigma_ab(mu_c, T) of the Kubo-Bastin formula by the kernel polynomial
+    method (Sec. "Tight-binding propagation method", DC conductivity tensor),
+    units e = hbar = 1:
+        sigma = 4/(pi A) (4/dE^2) int dE~ f(E~)/(1 - E~^2)^2 sum_{m,n} Gamma_nm(E~) mu~_nm
+    with dE = 2 rescale, mu~_nm = g_m g_n mu_mn / ((1 + d_n0)(1 + d_m0)) (Jackson
+    g), E~ = cos(theta),
+        Gamma_nm = T_m(E~)(E~ - i n sin theta) e^{i n theta}
+                 + T_n(E~)(E~ + i m sin theta) e^{-i m theta},
+    f the Fermi-Dirac function at chemical potential mu_c (eV) and 1/k_B T =
+    beta (1/eV).  The integral is the midpoint rule in theta over
+    E~ in [e_lo, e_hi]/rescale (the window holding the spectrum; outside it
+    the delta-function factor of the integrand vanishes), dE~ = sin theta
+    dtheta.  mu: [M, M] state averages of kpm_moments, so ``area`` is the
+    area per orbital.  Returns the real part for each mu_c."""
+    mu = np.asarray(mu, dtype=np.complex128)
+    M = mu.shape[0]
+    g = jackson(M)
+    w = g / np.where(np.arange(M) == 0, 2.0, 1.0)
+    mut = w[:, None] * w[None, :] * mu
+    th_hi = math.acos(e_lo / rescale)
+    th_lo = math.acos(e_hi / rescale)
+    dth = (th_hi - th_lo) / n_energy
+    m = np.arange(M)
+    acc = np.zeros(len(mus))
+    for k in range(n_energy):
+        th = th_lo + (k + 0.5) * dth
+        x, sn = math.cos(th), math.sin(th)
+        tm = np.cos(m * th)
+        gam = (tm[:, None] * ((x - 1j * m[None, :] * sn) * np.exp(1j * m[None, :] * th))
+               + tm[None, :] * ((x + 1j * m[:, None] * sn) * np.exp(-1j * m[:, None] * th)))
+        # gam[m, n] = Gamma_nm; the sum runs over both indices
+        val = np.sum(gam * mut).real / (1.0 - x * x) ** 2
+        e = x * rescale
+        fd = fermi(e, beta, np.asarray(mus, dtype=np.float64))
+        acc += fd * val * sn * dth
+    return 4.0 / (math.pi * area) / rescale ** 2 * acc
 
 
 def energies(n_steps: int, dt: float) -> np.ndarray:

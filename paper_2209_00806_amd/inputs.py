@@ -232,6 +232,28 @@ def square(nx: int, ny: int, t: float = -2.7, pbc: bool = True, onsite=None) -> 
     return lat
 
 
+def hofstadter(nx: int, ny: int, p: int, q: int, t: float = -1.0, onsite=None) -> Lattice:
+    """Periodic square lattice (spacing 1 A) in a uniform magnetic field of
+    p/q flux quanta per plaquette: Peierls phases in the Landau gauge
+    A = (0, B x), i.e. the bond from (i1, i2) to (i1, i2 + 1) carries
+    t exp(i 2 pi (p/q) i1).  Periodic in both directions when q divides nx.
+    Bond displacements are kept for the current operator."""
+    if nx % q != 0:
+        raise ValueError("q must divide nx for a periodic gauge")
+    lat = square(nx, ny, t=t, pbc=True, onsite=onsite)
+    if lat.disp is None:
+        raise ValueError("nx and ny must exceed 2")
+    rows = np.repeat(np.arange(lat.n_orb), np.diff(lat.row_ptr))
+    x = rows // ny
+    # the y bond out of row i (disp (0, +1)) gets e^{+i 2 pi phi x_i}; its
+    # reverse entry (disp (0, -1)) the conjugate
+    phase = np.exp(2j * np.pi * (p / q) * x * lat.disp[:, 1])
+    lat.val = lat.val * phase
+    lat.name = f"hofstadter{nx}x{ny}_{p}/{q}"
+    lat.meta.update(kind="hofstadter", flux=(p, q))
+    return lat
+
+
 def current_values(lat: Lattice, axis: int) -> np.ndarray:
     """Matrix elements of the current operator J_axis = -i sum_ij H_ij (r_j - r_i)_axis
     c_i^dagger c_j (Sec. "Optical conductivity"; e = hbar = 1) on the CSR

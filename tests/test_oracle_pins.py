@@ -657,3 +657,78 @@ def test_haydock_ldos_vs_ed(name):
     d = oracle.haydock_ldos(a, b, en, eta)[:, 0]
     ref = (np.abs(u[orb]) ** 2 * (eta / math.pi) / ((en[:, None] - e) ** 2 + eta ** 2)).sum(axis=1)
     assert np.max(np.abs(d - ref)) < 1e-7 * np.max(ref)
+
+
+# ----------------------------------------------------------------------------
+# Kubo-Bastin conductivity by the kernel polynomial method (Sec. "Tight-
+# binding propagation method", DC conductivity tensor)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 64, 257])
+def test_jackson_kernel_is_the_sine_autocorrelation(n):
+    """The closed-form Jackson coefficients equal the normalised
+    autocorrelation of a_nu = sin(pi (nu + 1)/(N + 1)), the definition of the
+    kernel as an optimal positive damping."""
+    a = np.sin(np.pi * (np.arange(n) + 1) / (n + 1))
+    ref = np.array([np.dot(a[: n - k], a[k:]) for k in range(n)])
+    assert np.max(np.abs(oracle.jackson(n) - ref / ref[0])) < 1e-14
+
+
+@pytest.mark.parametrize("axes", [(0, 1), (1, 1)])
+def test_kpm_moments_vs_dense_trace(axes):
+    """With every basis vector as a state the moments are the exact trace
+    Tr[v_a T_m(H~) v_b T_n(H~)]/N, computed here with dense matrices."""
+    lat = inputs.hofstadter(8, 6, 1, 4, t=-1.0, onsite=inputs.anderson(np.random.default_rng(7), 48, 0.8))
+    n = lat.n_orb
+    va = _dense_of(lat, inputs.current_values(lat, axes[0]))
+    vb = _dense_of(lat, inputs.current_values(lat, axes[1]))
+    f = 5.0
+    M = 12
+    mu = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, inputs.current_values(lat, axes[0]),
+                            inputs.current_values(lat, axes[1]), np.eye(n, dtype=np.complex128), M, f)
+    ht = lat.dense() / f
+    T = [np.eye(n, dtype=np.complex128), ht.copy()]
+    for _ in range(2, M):
+        T.append(2 * ht @ T[-1] - T[-2])
+    ref = np.array([[np.trace(va @ T[m] @ vb @ T[k]) / n for k in range(M)] for m in range(M)])
+    assert np.max(np.abs(mu - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_kubo_bastin_quantum_hall_plateaus():
+    """Square lattice at 1/16 flux quantum per plaquette (32 x 32, periodic;
+    Landau levels at -3.63, -2.92, -2.28 eV for t = -1 eV).  The trace is
+    exact: the system is invariant under the magnetic translations, so the
+    16 sites of one magnetic unit cell as unit-vector states give Tr/N.  In
+    the first two gaps sigma_xy = -n e^2/h (n = 1, 2; e^2/h = 1/(2 pi) in
+    units e = hbar = 1) to the finite-moment error (about 1/M), sigma_xx
+    vanishes, and the Onsager and fourfold-symmetry relations
+    sigma_xy(-B) = -sigma_xy(B), sigma_yx = -sigma_xy hold exactly."""
+    f, M = 4.2, 256
+    mus = np.array([-3.4, -2.7])
+    st = inputs.unit_states(32 * 32, [i1 * 32 for i1 in range(16)])
+
+    def sigma(p, axes):
+        lat = inputs.hofstadter(32, 32, p, 16, t=-1.0)
+        ja = inputs.current_values(lat, axes[0])
+        jb = inputs.current_values(lat, axes[1])
+        mu = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, ja, jb, st, M, f)
+        return oracle.kubo_bastin(mu, f, -4.05, 4.05, 1024, 200.0, mus, lat.area / lat.n_orb) * 2 * np.pi
+
+    sxy = sigma(1, (0, 1))
+    assert abs(sxy[0] + 1) < 0.02 and abs(sxy[1] + 2) < 0.06
+    assert np.max(np.abs(sigma(1, (0, 0)))) < 1e-3
+    assert np.max(np.abs(sigma(-1, (0, 1)) + sxy)) < 1e-10
+    assert np.max(np.abs(sigma(1, (1, 0)) + sxy)) < 1e-10
+
+
+def test_kubo_bastin_energy_grid_converges():
+    """The midpoint rule in theta has converged at 1024 energies for 64
+    moments: doubling the grid changes sigma by less than 1e-8 of its scale."""
+    lat = inputs.hofstadter(16, 16, 1, 8, t=-1.0, onsite=inputs.anderson(np.random.default_rng(8), 256, 0.5))
+    ja, jb = inputs.current_values(lat, 0), inputs.current_values(lat, 1)
+    psi0 = inputs.random_phase_states(np.random.default_rng(9), lat.n_orb, 1)
+    mu = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, ja, jb, psi0, 64, 4.6)
+    mus = np.linspace(-3.5, 3.5, 8)
+    s1 = oracle.kubo_bastin(mu, 4.6, -4.3, 4.3, 1024, 30.0, mus, 1.0)
+    s2 = oracle.kubo_bastin(mu, 4.6, -4.3, 4.3, 2048, 30.0, mus, 1.0)
+    assert np.max(np.abs(s1 - s2)) < 1e-8 * np.max(np.abs(s2))
