@@ -163,10 +163,13 @@ def bench_batched(args, log):
 
 
 def bench_ldos_psi_t(args, log, cfg64=None):
-    """LDOS by propagation (8 unit-vector states on the disordered 1024^2
-    graphene of the headline, FP64) and wave-function snapshots (a Gaussian
-    packet in pristine 1024^2 graphene, 1 state, 128 steps, snapshots at 0, 16,
-    32, 64, 128 as in the usage-section example, FP64)."""
+    """The legs beyond the DOS, all FP64 on 1024^2 graphene: LDOS by
+    propagation (8 unit-vector states on the disordered lattice of the
+    headline), wave-function snapshots (a Gaussian packet in the pristine
+    lattice, 1 state, snapshots at steps 0, 16, 32, 64, 128 as in the
+    usage-section example), quasi-eigenstates, the optical conductivity,
+    the Haydock LDOS and the Kubo-Bastin conductivity (one random-phase state
+    or the 8 orbitals on the disordered lattice)."""
     import numpy as np
     import torch
 
@@ -303,6 +306,31 @@ def bench_ldos_psi_t(args, log, cfg64=None):
                       "alg_GBps": round(hay_bytes / (ms_h / 1e3) / 1e9, 1),
                       "ldos_integral_pm10eV": round(float(dh.sum().item() * 20.0 / 4000), 4)}
     log(f"haydock: 8 orbitals, {nh} iterations, {ms_h:.1f} ms, {hay_bytes / (ms_h / 1e3) / 1e9:.0f} GB/s")
+    # Kubo-Bastin sigma_xx by the kernel polynomial method: one random-phase
+    # state on the disordered lattice, M moments; the moment product L^H R is
+    # a complex FP64 matrix product on the matrix cores
+    nm = args.kpm_moments
+    tbpm.kpm_moments(H, jx, jx, psi, 16, f)  # warm-up (handle, tiles)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    mu_k, tk = tbpm.kpm_moments(H, jx, jx, psi, nm, f, return_timing=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_k = e0.elapsed_time(e1)
+    mus_k = [-2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 2.0]
+    sk, _, _ = tbpm.kubo_bastin(mu_k, f, -0.98 * f, 0.98 * f, 2 * nm, 38.68, mus_k, lat.area / lat.n_orb)
+    gemm_flops = 8.0 * nm * nm * lat.n_orb
+    pass_b = nm * pass_bytes(lat.n_orb, lat.nnz, 1, 16, 8) * 2 + nm * pass_bytes(lat.n_orb, lat.nnz, 1, 16, 16)
+    out["kubo_bastin"] = {
+        "moments": nm, "states": 1, "ms": round(ms_k, 1), "l_recursion_ms": round(tk["l_ms"], 1),
+        "r_recursion_ms": round(tk["r_ms"], 1), "product_ms": round(tk["gemm_ms"], 1), "split_k": tk["split_k"],
+        "product_TFLOPs": round(gemm_flops / (tk["gemm_ms"] / 1e3) / 1e12, 2),
+        "product_frac_of_fp64_mfma_peak": round(gemm_flops / (tk["gemm_ms"] / 1e3) / 78.6e12, 3),
+        "recursion_alg_GBps": round(pass_b / ((tk["l_ms"] + tk["r_ms"]) / 1e3) / 1e9, 1),
+        "sigma_xx_e2_over_h": {str(m): round(float(v) * 2 * math.pi, 4) for m, v in zip(mus_k, sk.cpu().numpy())}}
+    log(f"kubo-bastin: {nm} moments, {ms_k:.1f} ms (recursions {tk['l_ms'] + tk['r_ms']:.1f} ms, product "
+        f"{tk['gemm_ms']:.1f} ms = {gemm_flops / (tk['gemm_ms'] / 1e3) / 1e12:.1f} TFLOP/s)")
+    del mu_k
     H.close()
     return out
 
@@ -437,10 +465,11 @@ def main():
     ap.add_argument("--bwd-cells", type=int, default=512)
     ap.add_argument("--bwd-nt", type=int, default=1024)
     ap.add_argument("--no-tbg", action="store_true")
-    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS, snapshot, quasi-eigenstate, optical-conductivity and Haydock legs")
+    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS, snapshot, quasi-eigenstate, optical-conductivity, Haydock and Kubo-Bastin legs")
     ap.add_argument("--ldos-nt", type=int, default=512)
     ap.add_argument("--ac-nt", type=int, default=256, help="time steps of the optical-conductivity leg")
     ap.add_argument("--hay-iter", type=int, default=1000, help="iterations of the Haydock leg")
+    ap.add_argument("--kpm-moments", type=int, default=512, help="moments of the Kubo-Bastin leg")
     ap.add_argument("--tbg-cells", type=int, default=1024)
     ap.add_argument("--tbg-nt", type=int, default=1024)
     args = ap.parse_args()

@@ -261,6 +261,54 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
                          double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags, void *stream);
 
 /*
+ * Moments of the Kubo-Bastin conductivity by the kernel polynomial method
+ * (Sec. "Tight-binding propagation method", the DC conductivity tensor):
+ *   mu_mn = (1/S) sum_s <r_s| v_alpha T_m(H/f) v_beta T_n(H/f) |r_s>,  m, n < M,
+ * with no kernel factors (tbpm_kubo_bastin applies them).  With
+ * L_m = T_m(H/f) v_alpha r and R_n = v_beta T_n(H/f) r the moments are the
+ * matrix product L^H R, computed on the matrix cores; all M vectors L_m are
+ * held in device memory (M x n_orb x S_pad x 16 bytes, S_pad the power of two
+ * >= S, plus 128 vectors of R): TBPM_E_OOM if they do not fit.
+ *   v_alpha, v_beta host, 2*nnz doubles: Hermitian operators (velocity or
+ *             current; the sign cancels in sigma) as complex values on H's
+ *             merged pattern (tbpm_hamiltonian_pattern order)
+ *   psi0      device [n_orb][n_states] complex128 random vectors (unit norm
+ *             estimates Tr/N), n_states 1 .. 64
+ *   n_moments 2 .. 16384;  rescale f > 0 must bound the spectrum of H
+ *             (<= 0: the Gershgorin bound); the moments are not checked
+ *   mu        device [M][M] complex128, written: mu[n*M + m] = mu_mn
+ *   timing_ms host [4] or NULL: milliseconds of the L recursion, the R
+ *             recursion and the products, and the number of split-K chunks
+ * Returns after the work has finished.
+ */
+tbpm_status tbpm_kpm_moments(tbpm_hamiltonian *H, const double *v_alpha, const double *v_beta, const double *psi0,
+                             int32_t n_states, int32_t n_moments, double rescale, double *mu, double *timing_ms,
+                             void *stream);
+
+/*
+ * Kubo-Bastin conductivity from the moments (Sec. "Tight-binding propagation
+ * method", the DC conductivity tensor), units e = hbar = 1:
+ *   sigma(mu_c) = 4/(pi A f^2) int dE~ f_FD(E~)/(1 - E~^2)^2 sum_{m,n} Gamma_nm(E~) g_m g_n mu_mn
+ *                 / ((1 + delta_m0)(1 + delta_n0)),
+ *   Gamma_nm = T_m(E~)(E~ - i n sin t) e^{i n t} + T_n(E~)(E~ + i m sin t) e^{-i m t},
+ * E~ = cos t, g the Jackson kernel of M moments, f_FD the Fermi-Dirac
+ * function at chemical potential mu_c (eV) and 1/k_B T = beta (1/eV).  The
+ * integral is the midpoint rule on n_energy points uniform in t over
+ * E = f E~ in [e_lo, e_hi] (a window holding the spectrum, strictly inside
+ * (-f, f); outside the spectrum the integrand's delta-function factor
+ * vanishes).  With unit-norm random vectors pass the area per orbital.
+ *   mu        device [M][M] complex128 from tbpm_kpm_moments (M <= 4096)
+ *   mus       device [n_mu] f64 chemical potentials (eV)
+ *   energies  device [n_energy] f64, written: the grid E_k (eV, descending)
+ *   weight    device [n_energy] f64, written: the real integrand times its
+ *             quadrature weight at E_k (sum_k f_FD(E_k) weight_k is the integral)
+ *   sigma     device [n_mu] f64, written (units e^2/hbar)
+ */
+tbpm_status tbpm_kubo_bastin(const double *mu, int32_t n_moments, double rescale, double e_lo, double e_hi,
+                             int32_t n_energy, double beta, const double *mus, int32_t n_mu, double area,
+                             double *energies, double *weight, double *sigma, void *stream);
+
+/*
  * Haydock recursion (Sec. "Local density of states", the recursion method):
  * one Lanczos chain per column of psi0, all chains advanced together,
  *   l_0 = psi0_s / ||psi0_s||,  a_i = <l_i|H|l_i>,

@@ -367,6 +367,32 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
     return TBPM_OK;
 }
 
+// j_alpha, j_beta (host, complex128 on H's merged pattern) -> eng.ac_ja,
+// eng.ac_jb in the ELL layout of H
+static tbpm_status upload_currents(tbpm_hamiltonian *H, const double *j_alpha, const double *j_beta, hipStream_t hs) {
+    Engine &eng = H->eng;
+    const int64_t nnz = H->csr.nnz();
+    for (int64_t p = 0; p < 2 * nnz; ++p)
+        if (!std::isfinite(j_alpha[p]) || !std::isfinite(j_beta[p])) return fail(TBPM_E_ARG, "non-finite current value");
+    const size_t ell = sizeof(double) * 2 * (size_t)std::max<int64_t>(eng.mat.ell_size, 1);
+    hipError_t e = eng.ac_csr.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(nnz, 1));
+    if (e == hipSuccess) e = eng.ac_ja.ensure(ell);
+    if (e == hipSuccess) e = eng.ac_jb.ensure(ell);
+    if (e != hipSuccess) return hip_fail(e, "alloc current operators");
+    const double *jv[2] = {j_alpha, j_beta};
+    DevBuf *jd[2] = {&eng.ac_ja, &eng.ac_jb};
+    for (int q = 0; q < 2; ++q) {
+        e = hipStreamSynchronize(hs);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpy(eng.ac_csr.ptr, jv[q], sizeof(double) * 2 * (size_t)nnz, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_gather_values(eng.mat.ell_csr, eng.mat.ell_size, (const double *)eng.ac_csr.ptr,
+                                     (double *)jd[q]->ptr, hs);
+        if (e != hipSuccess) return hip_fail(e, "upload current operator");
+    }
+    return TBPM_OK;
+}
+
 tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const double *j_beta, const double *psi0,
                          int32_t n_states, int32_t n_steps, double dt, double rescale, double bessel_tol, double beta,
                          double mu, double fermi_tol, tbpm_precision prec, double *corr, uint32_t flags,
@@ -379,9 +405,7 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     if (!std::isfinite(mu)) return fail(TBPM_E_ARG, "mu must be finite");
     if (!(fermi_tol > 0.0 && fermi_tol < 1e-2)) return fail(TBPM_E_ARG, "fermi_tol must be in (0, 1e-2)");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
-    const int64_t nnz = H->csr.nnz(), n = H->csr.n;
-    for (int64_t p = 0; p < 2 * nnz; ++p)
-        if (!std::isfinite(j_alpha[p]) || !std::isfinite(j_beta[p])) return fail(TBPM_E_ARG, "non-finite current value");
+    const int64_t n = H->csr.n;
     const double f = resolve_rescale(H->csr, rescale);
     const std::vector<double> a = fermi_cheb_coeffs(beta, mu, f, fermi_tol);
     if (a.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms (beta * rescale too large)");
@@ -395,26 +419,12 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     hipStream_t hs = (hipStream_t)stream;
     const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;
     const size_t vec2 = 2 * vec;
-    const size_t ell = sizeof(double) * 2 * (size_t)std::max<int64_t>(eng.mat.ell_size, 1);
-    hipError_t e = eng.ac_csr.ensure(sizeof(double) * 2 * (size_t)std::max<int64_t>(nnz, 1));
-    if (e == hipSuccess) e = eng.ac_ja.ensure(ell);
-    if (e == hipSuccess) e = eng.ac_jb.ensure(ell);
-    if (e == hipSuccess) e = eng.ac_vec.ensure(2 * vec + 4 * vec2);
+    hipError_t e = eng.ac_vec.ensure(2 * vec + 4 * vec2);
     if (e == hipSuccess) e = eng.ac_block.ensure(sizeof(double) * 4 * (size_t)n * n_states);
     if (e == hipSuccess) e = eng.corr_scratch.ensure(sizeof(double) * 4 * (size_t)n_steps * n_states);
     if (e != hipSuccess) return hip_fail(e, "alloc optical-conductivity buffers");
-    // the current operators in the ELL layout of H
-    const double *jv[2] = {j_alpha, j_beta};
-    DevBuf *jd[2] = {&eng.ac_ja, &eng.ac_jb};
-    for (int q = 0; q < 2; ++q) {
-        e = hipStreamSynchronize(hs);
-        if (e == hipSuccess && nnz > 0)
-            e = hipMemcpy(eng.ac_csr.ptr, jv[q], sizeof(double) * 2 * (size_t)nnz, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = launch_gather_values(eng.mat.ell_csr, eng.mat.ell_size, (const double *)eng.ac_csr.ptr,
-                                     (double *)jd[q]->ptr, hs);
-        if (e != hipSuccess) return hip_fail(e, "upload current operator");
-    }
+    st = upload_currents(H, j_alpha, j_beta, hs);
+    if (st != TBPM_OK) return st;
     char *vb = (char *)eng.ac_vec.ptr;
     void *src = vb, *jpsi = vb + vec, *blk = vb + 2 * vec, *w0 = vb + 2 * vec + vec2, *w1 = vb + 2 * vec + 2 * vec2,
          *fblk = vb + 2 * vec + 3 * vec2;
@@ -454,6 +464,55 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     } catch (const std::bad_alloc &) {
         return fail(TBPM_E_OOM, "host allocation failed");
     }
+}
+
+tbpm_status tbpm_kpm_moments(tbpm_hamiltonian *H, const double *v_alpha, const double *v_beta, const double *psi0,
+                             int32_t n_states, int32_t n_moments, double rescale, double *mu, double *timing_ms,
+                             void *stream) {
+    if (!H || !v_alpha || !v_beta || !psi0 || !mu) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    if (n_moments < 2 || n_moments > 16384) return fail(TBPM_E_ARG, "n_moments must be in [2, 16384]");
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    if ((int64_t)H->csr.n * 64 >= ((int64_t)1 << 31)) return fail(TBPM_E_ARG, "rows * 64 states must be below 2^31");
+    const double f = resolve_rescale(H->csr, rescale);
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        tbpm_status st = upload_currents(H, v_alpha, v_beta, hs);
+        if (st != TBPM_OK) return st;
+        Engine::KpmTiming t;
+        st = H->eng.kpm_moments((const double *)H->eng.ac_ja.ptr, (const double *)H->eng.ac_jb.ptr, psi0, n_states,
+                                n_moments, f, mu, hs, timing_ms ? &t : nullptr);
+        if (st == TBPM_OK && timing_ms) {
+            timing_ms[0] = t.l_ms;
+            timing_ms[1] = t.r_ms;
+            timing_ms[2] = t.gemm_ms;
+            timing_ms[3] = t.n_parts;
+        }
+        return st;
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
+tbpm_status tbpm_kubo_bastin(const double *mu, int32_t n_moments, double rescale, double e_lo, double e_hi,
+                             int32_t n_energy, double beta, const double *mus, int32_t n_mu, double area,
+                             double *energies, double *weight, double *sigma, void *stream) {
+    if (!mu || !mus || !energies || !weight || !sigma) return fail(TBPM_E_ARG, "NULL argument");
+    if (n_moments < 2 || n_moments > kpm_max_moments_lds())
+        return fail(TBPM_E_ARG, "n_moments must be in [2, " + std::to_string(kpm_max_moments_lds()) + "]");
+    if (!(rescale > 0.0) || !std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be positive and finite");
+    if (!(e_lo > -rescale && e_lo < e_hi && e_hi < rescale))
+        return fail(TBPM_E_ARG, "need -rescale < e_lo < e_hi < rescale");
+    if (n_energy < 1 || n_mu < 1) return fail(TBPM_E_ARG, "n_energy and n_mu must be positive");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(TBPM_E_ARG, "beta must be positive and finite");
+    if (!(area > 0.0) || !std::isfinite(area)) return fail(TBPM_E_ARG, "area must be positive and finite");
+    const double th_lo = std::acos(e_hi / rescale), th_hi = std::acos(e_lo / rescale);
+    const double dth = (th_hi - th_lo) / n_energy;
+    const double scale = 4.0 / (M_PI * area * rescale * rescale);
+    hipError_t e = launch_kubo_bastin(mu, n_moments, rescale, th_lo, dth, n_energy, mus, n_mu, beta, scale, energies,
+                                      weight, sigma, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch Kubo-Bastin integral");
+    return TBPM_OK;
 }
 
 tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_iter, double *a,

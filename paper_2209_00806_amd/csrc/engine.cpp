@@ -267,8 +267,10 @@ void Engine::release() {
                       &bwd_gacc, &bwd_gdiag, &bwd_coef, &st_uoff, &st_ucol, &st_lidx, &fu_n1, &fu_hoff,
                       &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
                       &qe_acc,   &qe_part,  &qe_norm2, &ac_ja,     &ac_jb,     &ac_csr,       &ac_zero,
-                      &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s};
+                      &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s,
+                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts};
     for (DevBuf *b : bufs) b->release();
+    release_blas();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
     staging_done = nullptr;

@@ -1,0 +1,211 @@
+// Host driver of the kernel-polynomial moments of the Kubo-Bastin formula
+// (paper, Sec. "Tight-binding propagation method", the DC conductivity
+// tensor):
+//     mu_mn = (1/S) sum_s <r_s| v_a T_m(H~) v_b T_n(H~) |r_s>,   m, n < M.
+// With L_m = T_m(H~) v_a r and R_n = v_b T_n(H~) r (H~ and v Hermitian),
+// mu_mn = <L_m|R_n>: the moments are one complex matrix product L^H R with
+// an inner dimension of rows x states.  All M vectors L_m are kept in HBM
+// (the Chebyshev recursion writes them in place); R is produced in blocks of
+// moments, and each block's product runs as a split-K batched ZGEMM on the
+// matrix cores (rocBLAS) whose per-chunk results are summed in a fixed order.
+#define ROCM_MATHLIBS_API_USE_HIP_COMPLEX 1
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "tbpm_engine.h"
+
+namespace tbpm {
+
+#define TRY_HIP(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+#define TRY_BLAS(expr, what)                                                                        \
+    do {                                                                                            \
+        rocblas_status b_ = (expr);                                                                 \
+        if (b_ != rocblas_status_success)                                                           \
+            return fail(TBPM_E_DEVICE, std::string(what) + ": rocBLAS status " + std::to_string((int)b_)); \
+    } while (0)
+
+void Engine::release_blas() {
+    if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
+    blas = nullptr;
+}
+
+tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double *psi0, int32_t s_user, int32_t n_mom,
+                                double f, double *mu, hipStream_t st, KpmTiming *timing) {
+    int32_t s_pad = 1, log2s = 0;
+    while (s_pad < s_user) {
+        s_pad <<= 1;
+        ++log2s;
+    }
+    const int64_t n = mat.n_rows;
+    const int64_t K = n * s_pad;  // inner dimension of the moment product
+    const int32_t nb = std::min<int32_t>(n_mom, 128);
+    const size_t vec = sizeof(double) * 2 * (size_t)K;
+    // split-K: chunks of at least 4096 rows x states, at most 64 of them
+    const int64_t n_parts = std::max<int64_t>(1, std::min<int64_t>(64, K / 4096));
+    const int64_t kc = K / n_parts, k_rest = K - kc * n_parts;
+    const size_t part_bytes = sizeof(double) * 2 * (size_t)n_mom * nb;
+    const size_t need = vec * ((size_t)n_mom + nb + 3) + part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0));
+    size_t free_b = 0, total_b = 0;
+    TRY_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const size_t have = kp_store.bytes + kp_rblk.bytes + kp_vec.bytes + kp_parts.bytes;
+    if (need > free_b + have)
+        return fail(TBPM_E_OOM, "the moment vectors need " + std::to_string(need >> 20) + " MiB of device memory");
+
+    tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
+    if (s0 != TBPM_OK) return s0;
+    TRY_HIP(kp_store.ensure(vec * (size_t)n_mom), "alloc moment vectors L");
+    TRY_HIP(kp_rblk.ensure(vec * (size_t)nb), "alloc moment vectors R");
+    TRY_HIP(kp_vec.ensure(3 * vec), "alloc Chebyshev vectors");
+    TRY_HIP(kp_parts.ensure(part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0))), "alloc split-K parts");
+    TRY_HIP(counter.ensure(sizeof(int32_t)), "alloc counter");
+    TRY_HIP(ac_zero.ensure(sizeof(double) * (size_t)std::max<int64_t>(n, 1)), "alloc zero on-site");
+    TRY_HIP(launch_fill_zero((double *)ac_zero.ptr, n, st), "clear zero on-site");
+    if (!blas) {
+        rocblas_handle h = nullptr;
+        TRY_BLAS(rocblas_create_handle(&h), "rocblas_create_handle");
+        blas = h;
+    }
+    rocblas_handle bh = (rocblas_handle)blas;
+    TRY_BLAS(rocblas_set_stream(bh, st), "rocblas_set_stream");
+
+    // pass coefficients: out = 0 v + beta (op x) - b2 with op = J (beta 1), H~ (1/f) or 2 H~ (2/f)
+    TRY_HIP(coef.ensure(3 * sizeof(PassCoef)), "alloc coefficients");
+    TRY_HIP(hipEventSynchronize(staging_done), "wait for staging");
+    TRY_HIP(staging.ensure(3 * sizeof(PassCoef)), "alloc staging");
+    PassCoef *hc = (PassCoef *)staging.ptr;
+    hc[0] = PassCoef{0.0, 0.0, 1.0, 0.0};
+    hc[1] = PassCoef{0.0, 0.0, 1.0 / f, 0.0};
+    hc[2] = PassCoef{0.0, 0.0, 2.0 / f, 0.0};
+    TRY_HIP(hipMemcpyAsync(coef.ptr, hc, 3 * sizeof(PassCoef), hipMemcpyHostToDevice, st), "upload coefficients");
+    TRY_HIP(hipEventRecord(staging_done, st), "record staging");
+    const PassCoef *c_j = (const PassCoef *)coef.ptr, *c_1 = c_j + 1, *c_2 = c_j + 2;
+
+    auto pass = [&](int kind, bool jop, const double *jval, const void *x, const void *b2, void *out,
+                    const PassCoef *c) -> hipError_t {
+        PassParams pp{};
+        pp.tiles = (const TileDesc *)tiles.ptr;
+        pp.n_tiles = (int32_t)h_tiles.size();
+        pp.xcd_remap = cfg.xcd_remap;
+        pp.log2s = log2s;
+        pp.col = mat.col;
+        pp.val = jop ? (const void *)jval : mat.val64;
+        pp.slice_off = mat.slice_off;
+        pp.onsite = jop ? ac_zero.ptr : (const void *)mat.onsite64;
+        pp.x = x;
+        pp.v = x;
+        pp.b2 = b2;
+        pp.out = out;
+        pp.coef = c;
+        pp.counter = (int32_t *)counter.ptr;
+        pp.s_user = s_pad;
+        return launch_pass(kind, false, jop ? true : mat.is_complex, false, 1, 1, pp, st);
+    };
+
+    char *Ls = (char *)kp_store.ptr;
+    char *Rb = (char *)kp_rblk.ptr;
+    char *vb = (char *)kp_vec.ptr;
+    void *r = vb, *t0 = vb + vec, *t1 = vb + 2 * vec;
+    TRY_HIP(launch_expand_states(psi0, mat.perm, s_user, (double *)r, log2s, n, st), "load random vectors");
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (timing)
+        for (auto &e : ev) TRY_HIP(hipEventCreate(&e), "hipEventCreate");
+    if (timing) TRY_HIP(hipEventRecord(ev[0], st), "record");
+
+    // L_0 = v_a r, L_1 = H~ L_0, L_{m+1} = 2 H~ L_m - L_{m-1}, in place in the store
+    TRY_HIP(pass(kPassFirst, true, ja, r, nullptr, Ls, c_j), "launch current operator");
+    for (int32_t m = 1; m < n_mom; ++m) {
+        void *out = Ls + vec * (size_t)m;
+        const void *x = Ls + vec * (size_t)(m - 1);
+        if (m == 1)
+            TRY_HIP(pass(kPassFirst, false, nullptr, x, nullptr, out, c_1), "launch Chebyshev pass");
+        else
+            TRY_HIP(pass(kPassMid, false, nullptr, x, Ls + vec * (size_t)(m - 2), out, c_2), "launch Chebyshev pass");
+    }
+    if (timing) TRY_HIP(hipEventRecord(ev[1], st), "record");
+
+    // R_n = v_b T_n(H~) r in blocks of nb moments; T_n in (t0, t1), the
+    // interior order written over T_{n-1}
+    const rocblas_double_complex alpha = make_hipDoubleComplex(1.0 / s_user, 0.0);
+    const rocblas_double_complex zero = make_hipDoubleComplex(0.0, 0.0);
+    const void *tc = r;  // T_n
+    void *tn[2] = {t0, t1};
+    float gemm_ms = 0.0f;
+    for (int32_t n0 = 0; n0 < n_mom; n0 += nb) {
+        const int32_t cnt = std::min(nb, n_mom - n0);
+        for (int32_t j = 0; j < cnt; ++j) {
+            const int32_t nn = n0 + j;
+            if (nn == 1) {
+                TRY_HIP(pass(kPassFirst, false, nullptr, r, nullptr, t0, c_1), "launch Chebyshev pass");
+                tc = t0;
+            } else if (nn == 2) {
+                TRY_HIP(pass(kPassMid, false, nullptr, t0, r, t1, c_2), "launch Chebyshev pass");
+                tc = t1;
+            } else if (nn > 2) {
+                // T_k lives in tn[(k - 1) & 1]: T_nn = 2 H~ T_{nn-1} - T_{nn-2} is
+                // written over T_{nn-2}
+                void *prev = tn[(nn - 1) & 1];
+                TRY_HIP(pass(kPassMid, false, nullptr, tn[nn & 1], prev, prev, c_2), "launch Chebyshev pass");
+                tc = prev;
+            }
+            TRY_HIP(pass(kPassFirst, true, jb, tc, nullptr, Rb + vec * (size_t)j, c_j), "launch current operator");
+        }
+        hipEvent_t g0 = nullptr, g1 = nullptr;
+        if (timing) {
+            TRY_HIP(hipEventCreate(&g0), "hipEventCreate");
+            TRY_HIP(hipEventCreate(&g1), "hipEventCreate");
+            TRY_HIP(hipEventRecord(g0, st), "record");
+        }
+        // parts[p] = L[chunk p]^H R[chunk p] (M x cnt), then summed into mu[:, n0 : n0 + cnt]
+        const rocblas_double_complex *A = (const rocblas_double_complex *)Ls;
+        const rocblas_double_complex *B = (const rocblas_double_complex *)Rb;
+        rocblas_double_complex *P = (rocblas_double_complex *)kp_parts.ptr;
+        const int64_t pstride = (int64_t)n_mom * cnt;
+        TRY_BLAS(rocblas_zgemm_strided_batched_64(bh, rocblas_operation_conjugate_transpose, rocblas_operation_none,
+                                                  n_mom, cnt, kc, &alpha, A, K, kc, B, K, kc, &zero, P, n_mom,
+                                                  pstride, n_parts),
+                 "moment product");
+        if (k_rest)
+            TRY_BLAS(rocblas_zgemm_strided_batched_64(bh, rocblas_operation_conjugate_transpose,
+                                                      rocblas_operation_none, n_mom, cnt, k_rest, &alpha,
+                                                      A + kc * n_parts, K, 0, B + kc * n_parts, K, 0, &zero,
+                                                      P + pstride * n_parts, n_mom, pstride, 1),
+                     "moment product (rest)");
+        TRY_HIP(launch_kpm_sum_parts((const double *)P, pstride, (int32_t)(n_parts + (k_rest ? 1 : 0)), pstride,
+                                     mu + 2 * (size_t)n0 * n_mom, st),
+                "sum moment parts");
+        if (timing) {
+            TRY_HIP(hipEventRecord(g1, st), "record");
+            TRY_HIP(hipEventSynchronize(g1), "sync");
+            float ms = 0.0f;
+            TRY_HIP(hipEventElapsedTime(&ms, g0, g1), "elapsed");
+            gemm_ms += ms;
+            (void)hipEventDestroy(g0);
+            (void)hipEventDestroy(g1);
+        }
+    }
+    if (timing) {
+        TRY_HIP(hipEventRecord(ev[2], st), "record");
+        TRY_HIP(hipEventSynchronize(ev[2]), "sync");
+        float a = 0.0f, b = 0.0f;
+        TRY_HIP(hipEventElapsedTime(&a, ev[0], ev[1]), "elapsed");
+        TRY_HIP(hipEventElapsedTime(&b, ev[1], ev[2]), "elapsed");
+        timing->l_ms = a;
+        timing->r_ms = b - gemm_ms;
+        timing->gemm_ms = gemm_ms;
+        timing->n_parts = (int32_t)n_parts;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
+    TRY_HIP(hipGetLastError(), "kernel execution");
+    return TBPM_OK;
+}
+
+}  // namespace tbpm

@@ -107,6 +107,11 @@ struct Engine {
     DevBuf ac_ja, ac_jb, ac_csr, ac_zero, ac_vec, ac_block, jc_tab, jc_norm;
     // Haydock recursion: two Lanczos vectors, the product vector, per-state scalars
     DevBuf hay_u, hay_y, hay_s;
+    // kernel-polynomial moments: the L store, a block of R, Chebyshev vectors,
+    // split-K partial products; the rocBLAS handle (created on first use)
+    DevBuf kp_store, kp_rblk, kp_vec, kp_parts;
+    void *blas = nullptr;
+    void release_blas();
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;
@@ -180,6 +185,14 @@ struct Engine {
     // order, [rows][s_user] complex128): a_out, b_out device [n_iter][s_user]
     tbpm_status haydock(const double *psi0, int32_t s_user, int32_t n_iter, double thr, double *a_out, double *b_out,
                         uint32_t flags, hipStream_t st);
+    // mu[n][m] (complex128, m contiguous) = (1/S) sum_s <r_s| v_a T_m(H/f) v_b T_n(H/f) |r_s>
+    // for m, n < n_mom; ja, jb: complex128 values in the ELL layout of H
+    struct KpmTiming {
+        float l_ms = 0, r_ms = 0, gemm_ms = 0;
+        int32_t n_parts = 0;
+    };
+    tbpm_status kpm_moments(const double *ja, const double *jb, const double *psi0, int32_t s_user, int32_t n_mom,
+                            double f, double *mu, hipStream_t st, KpmTiming *timing);
     // back-to-back launches of the interior pass on the current buffers
     tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
     int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1;

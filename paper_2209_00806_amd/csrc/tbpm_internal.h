@@ -133,6 +133,14 @@ hipError_t launch_hay_reduce(const double *partials, int32_t n_tiles, int32_t s_
 hipError_t launch_hay_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states, const double *energies,
                            int64_t n_e, double eps, double *out, hipStream_t st);
 
+// kernel-polynomial method (kpm.hip)
+int32_t kpm_max_moments_lds();
+hipError_t launch_kpm_sum_parts(const double *parts, int64_t n_el, int32_t n_parts, int64_t part_stride, double *out,
+                                hipStream_t st);
+hipError_t launch_kubo_bastin(const double *mu, int32_t n_mom, double rescale, double th_lo, double dth,
+                              int32_t n_energy, const double *mus, int32_t n_mu, double beta, double scale,
+                              double *energies, double *weight, double *sigma, hipStream_t st);
+
 hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStream_t st);
 // dst[r][s] = src[perm[r]][s] (src[r][s] if perm is null), zero for s >= s_user
 hipError_t launch_expand_states(const double *src, const int32_t *perm, int32_t s_user, double *dst, int32_t log2s,

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
         "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
         "tbpm_ac_cond": [P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
         "tbpm_fermi_cheb": [D, D, D, D, P, I32, P],
+        "tbpm_kpm_moments": [P, P, P, P, I32, I32, D, P, P, P],
+        "tbpm_kubo_bastin": [P, I32, D, D, D, I32, D, P, I32, D, P, P, P, P],
         "tbpm_haydock": [P, P, I32, I32, P, P, U32, P],
         "tbpm_haydock_ldos": [P, P, I32, I32, P, ctypes.c_int64, D, P, P],
         "tbpm_dos": [P, I32, I32, D, ctypes.c_int, P, P, P],
@@ -360,6 +362,56 @@ def ac_corr(H: Hamiltonian, j_alpha, j_beta, psi0, n_steps: int, dt: float, beta
                               float(rescale), float(tol), float(beta), float(mu), float(fermi_tol), _prec(precision),
                               _ptr(corr), 0, _stream(stream)))
     return corr
+
+
+def kpm_moments(H: Hamiltonian, v_alpha, v_beta, psi0, n_moments: int, rescale: float = 0.0,
+                return_timing: bool = False, stream=None):
+    """Kubo-Bastin moments mu[m, n] = (1/S) sum_s <r_s| v_alpha T_m(H/f) v_beta
+    T_n(H/f) |r_s> (numpy complex128 operators on H's merged pattern; psi0 a
+    CUDA complex128 tensor [n_orb, S], S <= 64).  Returns a CUDA complex128
+    [M, M] tensor indexed [m, n] (a transposed view of the library's layout),
+    and the timing dict if asked."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    if psi0.dim() == 1:
+        psi0 = psi0.reshape(-1, 1)
+    nnz = H.info()["nnz"]
+    va = np.ascontiguousarray(v_alpha, dtype=np.complex128)
+    vb = np.ascontiguousarray(v_beta, dtype=np.complex128)
+    if va.shape != (nnz,) or vb.shape != (nnz,):
+        raise ValueError(f"operators must hold one value per stored element ({nnz})")
+    n, S = psi0.shape
+    M = int(n_moments)
+    out = torch.empty((M, M), dtype=torch.complex128, device=psi0.device)  # [n][m]
+    t = np.zeros(4, dtype=np.float64)
+    _check(lib().tbpm_kpm_moments(H.handle, va.ctypes.data, vb.ctypes.data, _ptr(psi0), S, M, float(rescale),
+                                  _ptr(out), t.ctypes.data if return_timing else None, _stream(stream)))
+    mu = out.transpose(0, 1)
+    if return_timing:
+        return mu, {"l_ms": float(t[0]), "r_ms": float(t[1]), "gemm_ms": float(t[2]), "split_k": int(t[3])}
+    return mu
+
+
+def kubo_bastin(mu, rescale: float, e_lo: float, e_hi: float, n_energy: int, beta: float, mus, area: float,
+                stream=None):
+    """sigma(mu_c) of the Kubo-Bastin formula from kpm_moments' mu (indexed
+    [m, n]); returns (sigma [n_mu], energies [n_energy], weight [n_energy]) as
+    CUDA float64 tensors."""
+    import torch
+
+    if not isinstance(mu, torch.Tensor) or not mu.is_cuda or mu.dtype != torch.complex128 or mu.dim() != 2:
+        raise TypeError("mu must be a CUDA complex128 [M, M] tensor")
+    M = mu.shape[0]
+    mc = mu.transpose(0, 1).contiguous()  # the library's layout [n][m]
+    m_t = mus if isinstance(mus, torch.Tensor) else torch.as_tensor(np.asarray(mus, dtype=np.float64))
+    m_t = m_t.to(device=mu.device, dtype=torch.float64).contiguous().reshape(-1)
+    en = torch.empty(int(n_energy), dtype=torch.float64, device=mu.device)
+    w = torch.empty(int(n_energy), dtype=torch.float64, device=mu.device)
+    sg = torch.empty(m_t.numel(), dtype=torch.float64, device=mu.device)
+    _check(lib().tbpm_kubo_bastin(_ptr(mc), M, float(rescale), float(e_lo), float(e_hi), int(n_energy), float(beta),
+                                  _ptr(m_t), m_t.numel(), float(area), _ptr(en), _ptr(w), _ptr(sg), _stream(stream)))
+    return sg, en, w
 
 
 def haydock(H: Hamiltonian, psi0, n_iter: int, graph: bool = True, stream=None):
