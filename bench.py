@@ -320,7 +320,12 @@ def bench_ldos_psi_t(args, log, cfg64=None):
     mus_k = [-2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 2.0]
     sk, _, _ = tbpm.kubo_bastin(mu_k, f, -0.98 * f, 0.98 * f, 2 * nm, 38.68, mus_k, lat.area / lat.n_orb)
     gemm_flops = 8.0 * nm * nm * lat.n_orb
-    pass_b = nm * pass_bytes(lat.n_orb, lat.nnz, 1, 16, 8) * 2 + nm * pass_bytes(lat.n_orb, lat.nnz, 1, 16, 16)
+    # a Chebyshev order reads the gathered T_m and T_{m-1} and writes T_{m+1}
+    # (3 streams); the current operator reads its input and writes its output
+    # (2 streams) with complex values
+    cheb_b = 3 * 16 * lat.n_orb + lat.nnz * 12 + lat.n_orb * 8
+    cur_b = 2 * 16 * lat.n_orb + lat.nnz * 20 + lat.n_orb * 8
+    pass_b = nm * cheb_b * 2 + nm * cur_b
     out["kubo_bastin"] = {
         "moments": nm, "states": 1, "ms": round(ms_k, 1), "l_recursion_ms": round(tk["l_ms"], 1),
         "r_recursion_ms": round(tk["r_ms"], 1), "product_ms": round(tk["gemm_ms"], 1), "split_k": tk["split_k"],

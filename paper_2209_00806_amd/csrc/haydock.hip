@@ -112,9 +112,15 @@ __global__ __launch_bounds__(kWG) void k_hay_reduce(const double *__restrict__ p
     __shared__ double red[kWG];
     const int s = blockIdx.x;
     const double *p = partials + (int64_t)s * 3 * n_tiles + (mode == kHayA ? 0 : 2 * (int64_t)n_tiles);
-    double v = 0.0;
-    for (int t = threadIdx.x; t < n_tiles; t += kWG) v += p[t];
-    red[threadIdx.x] = v;
+    // eight independent accumulators keep loads in flight; the order is fixed
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int t = threadIdx.x;
+    for (; t + 7 * kWG < n_tiles; t += 8 * kWG) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] += p[t + q * kWG];
+    }
+    for (; t < n_tiles; t += kWG) v[0] += p[t];
+    red[threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     __syncthreads();
     for (int h = kWG / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
