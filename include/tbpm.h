@@ -335,7 +335,7 @@ tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_stat
  *   G_0(z) = 1/(z - a_0 - b_1^2/(z - a_1 - b_2^2/( ... /(z - a_{n-1})))),
  * the continued fraction cut after n_iter levels (no terminator).
  *   a, b      device [n_iter][n_states] f64 as written by tbpm_haydock
- *   energies  device [n_e] f64 (eV);  eps > 0 the broadening (eV)
+ *   energies  device [n_e] f64 (eV), n_e * n_states <= 2^31;  eps > 0 the broadening (eV)
  *   ldos      device [n_e][n_states] f64, written (per eV)
  */
 tbpm_status tbpm_haydock_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states,

@@ -532,7 +532,7 @@ tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_stat
 tbpm_status tbpm_haydock_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states,
                               const double *energies, int64_t n_e, double eps, double *ldos, void *stream) {
     if (!a || !b || !energies || !ldos) return fail(TBPM_E_ARG, "NULL argument");
-    if (n_iter < 1 || n_states < 1 || n_e < 1 || n_e * n_states > ((int64_t)1 << 40))
+    if (n_iter < 1 || n_states < 1 || n_e < 1 || n_e * n_states > ((int64_t)1 << 31))
         return fail(TBPM_E_ARG, "bad n_iter, n_states or n_e");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(TBPM_E_ARG, "eps must be positive and finite");
     hipError_t e = launch_hay_ldos(a, b, n_iter, n_states, energies, n_e, eps, ldos, (hipStream_t)stream);
