@@ -137,3 +137,25 @@ def test_ac_argument_errors():
     corr = _dev(np.zeros((8, 1), np.complex128))
     with pytest.raises(tbpm.TBPMError):
         tbpm.ac_cond(corr, 0.3, 10.0, 0.0)
+
+
+def test_ac_edge_cases():
+    """32 states (a joined block of 64, the maximum), one and five time steps,
+    and a chemical potential far below the spectrum (f(H) = 0 to rounding,
+    so psi2 and the correlation vanish)."""
+    print("case ac edge cases", flush=True)
+    rng = np.random.default_rng(98)
+    lat = inputs.graphene(8, 7, onsite=inputs.anderson(rng, 112, 1.0))
+    jx, jy = inputs.current_values(lat, 0), inputs.current_values(lat, 1)
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, 32)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.02
+    dt = math.pi / f
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    for nt in (1, 5):
+        ref, _, _ = oracle.ac_corr(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jy, psi0, nt, dt, f, 12.0, 0.4,
+                                   fermi_tol=1e-13)
+        got = tbpm.ac_corr(H, jx, jy, _dev(psi0), nt, dt, 12.0, 0.4, rescale=f, fermi_tol=1e-13).cpu().numpy()
+        assert got.shape == (nt, 32)
+        assert _rel(got, ref) < 1e-10
+    got = tbpm.ac_corr(H, jx, jx, _dev(psi0[:, :2]), 6, dt, 10.0, -40.0, rescale=f, fermi_tol=1e-13).cpu().numpy()
+    assert np.max(np.abs(got)) < 1e-12

@@ -159,3 +159,19 @@ def test_haydock_argument_errors():
     a, b = tbpm.haydock(H, psi0, 4)
     with pytest.raises(tbpm.TBPMError):
         tbpm.haydock_ldos(a, b, [0.0], 0.0)
+
+
+def test_haydock_64_chains():
+    """The maximum of 64 chains at once (unit vectors on every other orbital
+    and random states) against the oracle."""
+    print("case haydock 64 chains", flush=True)
+    rng = np.random.default_rng(104)
+    lat = inputs.graphene(10, 9, onsite=inputs.anderson(rng, 180, 1.2))
+    st = inputs.unit_states(lat.n_orb, np.arange(0, 128, 2))
+    st[:, 40:] = inputs.random_phase_states(rng, lat.n_orb, 24)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    g = H.info()["gershgorin"]
+    a, b = tbpm.haydock(H, _dev(st), 12)
+    ar, br = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, st, 12)
+    assert np.max(np.abs(a.cpu().numpy() - ar)) < 1e-11 * g
+    assert np.max(np.abs(b.cpu().numpy() - br)) < 1e-11 * g

@@ -113,3 +113,18 @@ def test_kpm_argument_errors():
         tbpm.kubo_bastin(mu, 4.5, -5.0, 4.0, 64, 10.0, [0.0], 1.0)  # window outside (-f, f)
     with pytest.raises(tbpm.TBPMError):
         tbpm.kubo_bastin(mu, 4.5, -4.0, 4.0, 64, 10.0, [0.0], 0.0)
+
+
+@pytest.mark.parametrize("M", [2, 24])
+def test_kpm_64_states_and_fewest_moments(M):
+    """64 random vectors (the maximum) and the smallest moment count."""
+    print(f"case kpm 64 states M={M}", flush=True)
+    rng = np.random.default_rng(12)
+    lat = inputs.square(12, 12, t=-1.0, onsite=inputs.anderson(rng, 144, 0.8))
+    jx, jy = inputs.current_values(lat, 0), inputs.current_values(lat, 1)
+    st = inputs.random_phase_states(rng, lat.n_orb, 64)
+    f = 5.0
+    ref = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jy, st, M, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    got = tbpm.kpm_moments(H, jx, jy, _dev(st), M, f).cpu().numpy()
+    assert _rel(got, ref) < 1e-11

@@ -121,3 +121,36 @@ def test_entry_points_reject_null_and_bad_arguments():
     assert L.tbpm_batch_create(None, 0, ctypes.byref(ctypes.c_void_p())) == 1
     assert L.tbpm_stream_copy(None, None, 16, None) == 1
     assert b"NULL" in L.tbpm_last_error() or len(L.tbpm_last_error()) > 0
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host():
+    """The entry points beyond the DOS validate their arguments before any
+    device call (dummy non-NULL pointers are never dereferenced here)."""
+    L = tbpm.lib()
+    d = ctypes.c_void_p(64)
+    assert L.tbpm_ac_cond(None, 8, 1, 0.1, 10.0, 1.0, 0, None, None, None) == 1
+    assert L.tbpm_ac_cond(d, 8, 1, 0.1, 10.0, 0.0, 0, d, d, None) == 1          # area 0
+    assert L.tbpm_ac_cond(d, 8, 1, 0.1, -1.0, 1.0, 0, d, d, None) == 1         # beta < 0
+    assert L.tbpm_ac_corr(None, None, None, None, 1, 8, 0.1, 9.0, 1e-12, 10.0, 0.0, 1e-12, 0, None, 0, None) == 1
+    assert L.tbpm_haydock(None, None, 1, 8, None, None, 0, None) == 1
+    assert L.tbpm_haydock_ldos(d, d, 0, 1, d, 4, 0.1, d, None) == 1              # n_iter 0
+    assert L.tbpm_haydock_ldos(d, d, 4, 1, d, 4, 0.0, d, None) == 1              # eps 0
+    assert L.tbpm_kpm_moments(None, None, None, None, 1, 8, 4.0, None, None, None) == 1
+    assert L.tbpm_kubo_bastin(d, 1, 4.0, -3.0, 3.0, 64, 10.0, d, 1, 1.0, d, d, d, None) == 1   # M < 2
+    assert L.tbpm_kubo_bastin(d, 4097, 4.0, -3.0, 3.0, 64, 10.0, d, 1, 1.0, d, d, d, None) == 1  # M > LDS cap
+    assert L.tbpm_kubo_bastin(d, 16, 4.0, -5.0, 3.0, 64, 10.0, d, 1, 1.0, d, d, d, None) == 1  # window
+    assert L.tbpm_kubo_bastin(d, 16, 4.0, 3.0, -3.0, 64, 10.0, d, 1, 1.0, d, d, d, None) == 1  # e_lo > e_hi
+    K = ctypes.c_int32()
+    assert L.tbpm_fermi_cheb(-1.0, 0.0, 9.0, 1e-12, None, 0, ctypes.byref(K)) == 1
+    assert L.tbpm_fermi_cheb(10.0, 0.0, 9.0, 0.5, None, 0, ctypes.byref(K)) == 1
+
+
+@pytest.mark.parametrize("beta,mu", [(38.68, 0.0), (5.0, -1.2)])
+def test_library_fermi_coefficients_vs_oracle(beta, mu):
+    """tbpm_fermi_cheb (host; the library's own FFT) against the oracle's
+    coefficients (NumPy's FFT) under the same truncation reading."""
+    a = tbpm.fermi_coeffs(beta, mu, 9.0, 1e-13)
+    ref = oracle.fermi_coeffs(beta, mu, 9.0, 1e-13, n_max=1 << 20)
+    k = min(a.size, ref.size)
+    assert abs(a.size - ref.size) <= 2
+    assert np.max(np.abs(a[:k] - ref[:k])) < 1e-13
