@@ -411,6 +411,9 @@ def bench_backward(args, log):
     _, target = tbpm.dos(tbpm.propagate(Ht, psi0, nt, dt, f), dt)
     Ht.close()
     H = tbpm.Hamiltonian.from_lattice(lat)
+    # the autotuned FP64 shape serves the forward, the segment replay and the
+    # adjoint (two orders per launch when the fused shape wins)
+    cfg, _, _ = tbpm.autotune_cached(H, 4, "fp64", args.tune_cache)
     slot_ij = torch.from_numpy(lat.slot_ij).cuda()
     slot_ji = torch.from_numpy(lat.slot_ji).cuda()
     sel = torch.arange(0, 2 * nt, 8, device="cuda")  # 256 energies
@@ -440,7 +443,8 @@ def bench_backward(args, log):
     bwd = e1.elapsed_time(e2)
     g = t_param.grad
     out = {"n_orb": lat.n_orb, "bond_params": int(lat.bond_t.shape[0]), "n_states": 4, "n_steps": nt,
-           "ckpt_every": K, "loss": L.item(), "forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+           "ckpt_every": K, "launch": cfg, "loss": L.item(), "forward_ms": round(fwd, 2),
+           "backward_ms": round(bwd, 2),
            "backward_over_forward": round(bwd / fwd, 3), "grad_norm": float(torch.linalg.norm(g).item())}
     log(f"backward: fwd {fwd:.1f} ms, bwd {bwd:.1f} ms, ratio {bwd / fwd:.2f}")
     H.close()

@@ -47,10 +47,17 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     const int n_passes = (int)plan.size();
 
     eng.cfg = eng.cfgs[0];
-    eng.cfg.staged = 0;  // the replay and the adjoint use plain tiles of single-state units
+    eng.cfg.staged = 0;  // the replay and the adjoint use single-state units
     eng.cfg.vec = 1;
     eng.cfg.fused = 0;
-    tbpm_status s = eng.build_tiles(s_pad, eng.cfg.wg_chunks, 1);
+    // With the fused shape in the FP64 launch configuration the replay takes
+    // two Clenshaw orders per launch (when the two-hop tile tables fit): every
+    // order's output has a slot of its own in the segment store, so a pair's
+    // outputs never alias what its tiles read.  The adjoint passes run on the
+    // same tiles (any tiling of the rows serves them).
+    bool pairs = eng.cfgs[0].fused > 0 && M - 2 >= 2;
+    if (pairs && eng.build_fused_tiles(s_pad, log2s, 16, eng.cfgs[0].fused) != TBPM_OK) pairs = false;
+    tbpm_status s = pairs ? TBPM_OK : eng.build_tiles(s_pad, eng.cfg.wg_chunks, 1);
     if (s != TBPM_OK) return s;
     const int32_t n_tiles = (int32_t)eng.h_tiles.size();
     const int64_t n_el = n_rows * s_pad;
@@ -67,7 +74,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     const int32_t n_b = M - 2;  // stored b_1 .. b_{M-2} per step
     const size_t n_store = (size_t)(seg_len + 1) + (size_t)seg_len * n_b;
     TRY_HIP(eng.bwd_store.ensure(vb * n_store), "alloc segment store (reduce ckpt_every)");
-    TRY_HIP(eng.bwd_adj.ensure(vb * 4), "alloc adjoint vectors");
+    TRY_HIP(eng.bwd_adj.ensure(vb * (pairs ? 5 : 4)), "alloc adjoint vectors");
     TRY_HIP(eng.phi0.ensure(vb), "alloc phi0");
     TRY_HIP(eng.bwd_gacc.ensure((cplx ? 16 : 8) * (size_t)std::max<int64_t>(eng.mat.ell_size, 1)), "alloc gradient");
     TRY_HIP(eng.bwd_gdiag.ensure(8 * (size_t)n_rows), "alloc gradient");
@@ -88,6 +95,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     double *adj = (double *)eng.bwd_adj.ptr;
     double *lam = adj, *acc = adj + 2 * n_el;
     double *rot[3] = {lam, adj + 4 * n_el, adj + 6 * n_el};
+    double *rot4 = pairs ? adj + 8 * n_el : nullptr;  // the fourth alpha buffer of the paired sweep
     double *phi0p = (double *)eng.phi0.ptr;
 
     TRY_HIP(launch_expand_states(psi0, eng.mat.perm, s_user, phi0p, log2s, n_rows, st), "expand psi0");
@@ -140,6 +148,152 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     ap.gdiag = (double *)eng.bwd_gdiag.ptr;
     ap.phi0 = phi0p;
 
+    // one step of the replay in the fused shape: orders (M-2, M-3) from psi,
+    // then (j, j-1) pairs, a leftover order alone, and the last pass alone
+    FusedParams fp{};
+    fp.tiles = (const TileDesc *)eng.tiles.ptr;
+    fp.n_tiles = n_tiles;
+    fp.xcd_remap = eng.cfg.xcd_remap;
+    fp.log2s = log2s;
+    fp.bump_counter = 0;
+    fp.col = eng.mat.col;
+    fp.val = eng.mat.val64;
+    fp.slice_off = eng.mat.slice_off;
+    fp.onsite = eng.mat.onsite64;
+    fp.counter = (int32_t *)eng.counter.ptr;
+    fp.uoff = (const int32_t *)eng.st_uoff.ptr;
+    fp.n1 = (const int32_t *)eng.fu_n1.ptr;
+    fp.ucol = (const int32_t *)eng.st_ucol.ptr;
+    fp.lidx = (const uint16_t *)eng.st_lidx.ptr;
+    fp.hoff = (const int32_t *)eng.fu_hoff.ptr;
+    fp.hw = (const int32_t *)eng.fu_hw.ptr;
+    fp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
+    fp.lds_units = eng.fu_lds_units;
+    const PassCoef *coefs = (const PassCoef *)eng.bwd_coef.ptr;
+    auto replay_step_pairs = [&](int32_t t) -> hipError_t {
+        // plan entry p evaluates order pass_j[p]: 0 FIRST (M-2), 1 NOB2 (M-3),
+        // 2 .. n_passes-2 MID (M-4 .. 1), n_passes-1 LAST (0)
+        fp.v = psi_slot(t);
+        fp.x = psi_slot(t);
+        fp.b2 = nullptr;
+        fp.out1 = b_slot(t, M - 2);
+        fp.out2 = b_slot(t, M - 3);
+        fp.coef1 = coefs;
+        fp.coef2 = coefs + 1;
+        hipError_t e = launch_pair(kPairFirst, false, cplx, false, 1, fp, st);
+        int p = 2;
+        for (; e == hipSuccess && p + 1 < n_passes - 1; p += 2) {
+            const int j = pass_j[p];
+            fp.x = b_slot(t, j + 1);
+            fp.b2 = b_slot(t, j + 2);
+            fp.out1 = b_slot(t, j);
+            fp.out2 = b_slot(t, j - 1);
+            fp.coef1 = coefs + p;
+            fp.coef2 = coefs + p + 1;
+            e = launch_pair(kPairMid, false, cplx, false, 1, fp, st);
+        }
+        for (; e == hipSuccess && p < n_passes; ++p) {  // a leftover MID, then LAST
+            const int j = pass_j[p];
+            pp.v = psi_slot(t);
+            pp.x = b_slot(t, j + 1);
+            pp.b2 = b_slot(t, j + 2);
+            pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
+            pp.coef = coefs + p;
+            e = launch_pass(plan[p].kind, false, cplx, false, eng.cfg.unroll, 1, pp, st);
+        }
+        return e;
+    };
+
+    // one step of the adjoint with two orders per launch: (0, 1), then
+    // (j, j+1) while j + 2 <= M - 2, the remaining orders with the single-order
+    // kernel (the last one, j = M - 2, with b_{M-1} = c_{M-1} psi_l).  The
+    // alpha vectors rotate over four buffers: a pair reads alpha_j on other
+    // tiles' rows and alpha_{j-1} on its 1-hop rows, so its outputs go to the
+    // two buffers it does not read.  lambda_l ends in 'acc'.
+    AdjPairParams qp{};
+    qp.tiles = (const TileDesc *)eng.tiles.ptr;
+    qp.n_tiles = n_tiles;
+    qp.xcd_remap = eng.cfg.xcd_remap;
+    qp.log2s = log2s;
+    qp.col = eng.mat.col;
+    qp.val = eng.mat.val64;
+    qp.slice_off = eng.mat.slice_off;
+    qp.onsite = eng.mat.onsite64;
+    qp.inv_f = 1.0 / f;
+    qp.gacc = eng.bwd_gacc.ptr;
+    qp.gdiag = (double *)eng.bwd_gdiag.ptr;
+    qp.uoff = (const int32_t *)eng.st_uoff.ptr;
+    qp.n1 = (const int32_t *)eng.fu_n1.ptr;
+    qp.ucol = (const int32_t *)eng.st_ucol.ptr;
+    qp.lidx = (const uint16_t *)eng.st_lidx.ptr;
+    qp.hoff = (const int32_t *)eng.fu_hoff.ptr;
+    qp.hw = (const int32_t *)eng.fu_hw.ptr;
+    qp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
+    qp.lds_units = eng.fu_lds_units;
+    qp.cc0_re = c[0].real();
+    qp.cc0_im = -c[0].imag();
+    auto adjoint_step_pairs = [&](int32_t t, int32_t l) -> hipError_t {
+        double *X = rot[0];  // alpha_0 = lambda_{l+1}
+        double *P = nullptr;
+        double *fr[2] = {rot[1], rot[2]};  // buffers no launch of this order reads
+        double *spare = rot4;
+        int j = 0;
+        hipError_t e = hipSuccess;
+        for (; e == hipSuccess && j + 2 <= M - 2; j += 2) {
+            qp.x = X;
+            qp.a_prev = P;
+            qp.out1 = fr[0];
+            qp.out2 = fr[1];
+            qp.lam_acc = acc;
+            qp.bq1 = b_slot(t, j + 1);
+            qp.bq2 = b_slot(t, j + 2);
+            qp.w1 = j == 0 ? 1.0 : 2.0;
+            qp.w2 = 2.0;
+            qp.cc1_re = c[j + 1].real();
+            qp.cc1_im = -c[j + 1].imag();
+            qp.cc2_re = c[j + 2].real();
+            qp.cc2_im = -c[j + 2].imag();
+            e = launch_adjoint_pair(j == 0 ? kAdjPairFirst : kAdjPairMid, cplx, qp, st);
+            // alpha_{j+2} is the next x, alpha_{j+1} the next prev; the old x and
+            // prev (or the spare buffer after the first pair) take the outputs
+            double *nx = fr[1], *np = fr[0];
+            fr[0] = X;
+            fr[1] = P ? P : spare;
+            X = nx;
+            P = np;
+        }
+        for (; e == hipSuccess && j <= M - 2; ++j) {
+            const int kind = (j == M - 2) ? kAdjFinal : kAdjMid;
+            ap.a_cur = X;
+            ap.a_prev = P;
+            ap.a_next = fr[0];
+            ap.lam_acc = acc;
+            if (j + 1 <= M - 2) {
+                ap.bq = b_slot(t, j + 1);
+                ap.bs_re = 1.0;
+                ap.bs_im = 0.0;
+            } else {  // b_{M-1} = c_{M-1} psi_l
+                ap.bq = psi_slot(t);
+                ap.bs_re = c[M - 1].real();
+                ap.bs_im = c[M - 1].imag();
+            }
+            ap.gw = 2.0;
+            ap.cc0_re = c[0].real();
+            ap.cc0_im = -c[0].imag();
+            ap.ccn_re = c[j + 1].real();
+            ap.ccn_im = -c[j + 1].imag();
+            ap.gcorr_l = gcorr + 2 * (size_t)l * s_user;
+            e = launch_adjoint_pass(kind, cplx, ap, st);
+            double *nx = fr[0];
+            fr[0] = P;
+            P = X;
+            X = nx;
+        }
+        // lambda_l is in acc: it becomes alpha_0 of the next step
+        std::swap(rot[0], acc);
+        return e;
+    };
+
     const int32_t n_seg = (N - 1 + K - 1) / K;
     for (int32_t seg = n_seg - 1; seg >= 0; --seg) {
         const int32_t l0 = seg * K;
@@ -152,6 +306,10 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
                     "segment start");
         // forward replay, keeping b_1 .. b_{M-2} of every step
         for (int32_t t = 0; t < len; ++t) {
+            if (pairs) {
+                TRY_HIP(replay_step_pairs(t), "replay pair");
+                continue;
+            }
             for (int p = 0; p < n_passes; ++p) {
                 const int j = pass_j[p];
                 const PassPlan &pl = plan[p];
@@ -169,6 +327,10 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
         // adjoint sweep through the segment
         for (int32_t t = len - 1; t >= 0; --t) {
             const int32_t l = l0 + t;
+            if (pairs) {
+                TRY_HIP(adjoint_step_pairs(t, l), "adjoint pair");
+                continue;
+            }
             for (int j = 0; j <= M - 2; ++j) {
                 const int kind = (j == 0) ? kAdjFirst : (j == M - 2 ? kAdjFinal : kAdjMid);
                 ap.a_cur = rot[j % 3];

@@ -151,6 +151,193 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
     }
 }
 
+// Two adjoint orders per launch.  With alpha_j staged on the tile's own,
+// 1-hop and 2-hop rows (xs), alpha_{j+1} = 2 H~ alpha_j - alpha_{j-1} (H~
+// alpha_0 for the first pair) is evaluated on own and 1-hop rows (ys), then
+// alpha_{j+2} = 2 H~ alpha_{j+1} - alpha_j on own rows.  On own rows the
+// gradient slots take w1 alpha_j[p] conj(b_{j+1}[q]) + w2 alpha_{j+1}[p]
+// conj(b_{j+2}[q]) summed over states in one read-modify-write, and lambda
+// gains conj(c_{j+1}) alpha_{j+1} + conj(c_{j+2}) alpha_{j+2}.  Indexing of the
+// staged rows is that of k_pair with single-state units.
+template <bool CH, int KIND>
+__global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
+    extern __shared__ __align__(16) unsigned char adj_mem[];
+    using HV = std::conditional_t<CH, d2, double>;
+    using GV = std::conditional_t<CH, d2, double>;
+    constexpr int KG = 4;
+    constexpr bool FIRST = (KIND == kAdjPairFirst);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const TileDesc td = p.tiles[tile];
+    const int log2s = p.log2s;
+    const uint32_t smask = (1u << log2s) - 1u;
+    const uint32_t s = threadIdx.x & smask;
+    const uint32_t n_own = (uint32_t)td.rows;
+    const uint32_t row0 = (uint32_t)td.row0;
+    const int32_t e_beg = p.uoff[tile], e_end = p.uoff[tile + 1];
+    const uint32_t n1 = (uint32_t)p.n1[tile];
+    const uint32_t n_x = (n_own + (uint32_t)(e_end - e_beg)) << log2s;
+    const uint32_t n_y = (n_own + n1) << log2s;
+    const int32_t hoff = p.hoff[tile], hw = p.hw[tile];
+    d2 *xs = reinterpret_cast<d2 *>(adj_mem);
+    d2 *ys = xs + n_x;
+    const d2 *__restrict__ x = (const d2 *)p.x;
+    const d2 *__restrict__ bq1 = (const d2 *)p.bq1;
+    const d2 *__restrict__ bq2 = (const d2 *)p.bq2;
+    const HV *__restrict__ val = (const HV *)p.val;
+    const uint32_t *__restrict__ soff = p.slice_off;
+    const int32_t *__restrict__ ucol = p.ucol + e_beg;
+    GV *gacc = (GV *)p.gacc;
+    const double inv_f = p.inv_f;
+    auto grow_of = [&](uint32_t lr) -> uint32_t { return lr < n_own ? row0 + lr : (uint32_t)ucol[lr - n_own]; };
+
+    // stage alpha_j: four loads in flight per thread
+    for (uint32_t i0 = threadIdx.x; i0 < n_x; i0 += 4 * kWG) {
+        d2 t[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * kWG;
+            if (i < n_x) t[q] = x[(grow_of(i >> log2s) << log2s) + (i & smask)];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * kWG;
+            if (i < n_x) xs[i] = t[q];
+        }
+    }
+    __syncthreads();
+
+    // alpha_{j+1} on own + 1-hop rows
+    for (uint32_t u = threadIdx.x; u < n_y; u += kWG) {
+        const uint32_t lr = u >> log2s;
+        const uint32_t grow = grow_of(lr);
+        const uint32_t gu = (grow << log2s) + s;
+        const uint32_t sl = grow / kSliceRows;
+        const uint32_t off = soff[sl];
+        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+        const uint32_t base = off + grow % kSliceRows;
+        d2 ap;
+        if constexpr (!FIRST) ap = ((const d2 *)p.a_prev)[gu];
+        const d2 xo = xs[u];
+        d2 acc;
+        acc.x = p.onsite[grow] * xo.x;
+        acc.y = p.onsite[grow] * xo.y;
+        const bool own = lr < n_own;
+        const uint16_t *hrow = p.hidx + hoff + (int64_t)(own ? 0 : (lr - n_own)) * hw;
+        for (int k = 0; k < w; k += KG) {
+            uint32_t li[KG];
+            HV h[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const uint32_t l = valid ? (own ? (uint32_t)p.lidx[slot] : (uint32_t)hrow[k + i]) : lr;
+                const HV hv = val[slot];
+                li[i] = (l << log2s) + s;
+                h[i] = valid ? hv : HV{};
+            }
+#pragma unroll
+            for (int i = 0; i < KG; ++i) acc = hmad(h[i], xs[li[i]], acc);
+        }
+        d2 an;
+        if constexpr (FIRST) {
+            an = acc * inv_f;
+        } else {
+            an.x = fma(2.0 * inv_f, acc.x, -ap.x);
+            an.y = fma(2.0 * inv_f, acc.y, -ap.y);
+        }
+        ys[u] = an;
+        if (own) ((d2 *)p.out1)[gu] = an;
+    }
+    __syncthreads();
+
+    // alpha_{j+2}, lambda and the gradient on own rows
+    d2 cc0, cc1, cc2;
+    cc0.x = p.cc0_re;
+    cc0.y = p.cc0_im;
+    cc1.x = p.cc1_re;
+    cc1.y = p.cc1_im;
+    cc2.x = p.cc2_re;
+    cc2.y = p.cc2_im;
+    const double w1 = p.w1, w2 = p.w2;
+    const uint32_t n_u = n_own << log2s;
+    // n_u is a multiple of S and the S lanes of a row are consecutive lanes of
+    // one wave, so the lanes of a row take the same trip counts
+    for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
+        const uint32_t lr = u >> log2s;
+        const uint32_t row = row0 + lr;
+        const uint32_t gu = (row << log2s) + s;
+        const uint32_t sl = row / kSliceRows;
+        const uint32_t off = soff[sl];
+        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+        const uint32_t base = off + row % kSliceRows;
+        const d2 aj = xs[u], aj1 = ys[u];
+        const d2 ga1 = aj * w1, ga2 = aj1 * w2;
+        d2 lam;
+        if constexpr (!FIRST) lam = ((const d2 *)p.lam_acc)[gu];
+        {
+            const d2 b1 = bq1[gu], b2 = bq2[gu];
+            const double dg = row_sum(ga1.x * b1.x + ga1.y * b1.y + ga2.x * b2.x + ga2.y * b2.y, log2s);
+            if (s == 0) p.gdiag[row] += dg;
+        }
+        d2 acc;
+        acc.x = p.onsite[row] * aj1.x;
+        acc.y = p.onsite[row] * aj1.y;
+        for (int k = 0; k < w; k += KG) {
+            uint32_t slot[KG], li[KG], gc[KG];
+            HV h[KG];
+            bool valid[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                valid[i] = k + i < w;
+                slot[i] = valid[i] ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const uint32_t l = valid[i] ? (uint32_t)p.lidx[slot[i]] : lr;
+                const int32_t c = p.col[slot[i]];
+                const HV hv = val[slot[i]];
+                li[i] = (l << log2s) + s;
+                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2s) + s;
+                h[i] = valid[i] ? hv : HV{};
+            }
+            d2 xb1[KG], xb2[KG];
+            GV gold[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                xb1[i] = bq1[gc[i]];
+                xb2[i] = bq2[gc[i]];
+                gold[i] = gacc[slot[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                acc = hmad(h[i], ys[li[i]], acc);
+                const double gr = row_sum(ga1.x * xb1[i].x + ga1.y * xb1[i].y + ga2.x * xb2[i].x +
+                                              ga2.y * xb2[i].y,
+                                          log2s);
+                if constexpr (CH) {
+                    const double gi = row_sum(ga1.y * xb1[i].x - ga1.x * xb1[i].y + ga2.y * xb2[i].x -
+                                                  ga2.x * xb2[i].y,
+                                              log2s);
+                    if (s == 0 && valid[i]) {
+                        d2 nv = gold[i];
+                        nv.x += gr;
+                        nv.y += gi;
+                        gacc[slot[i]] = nv;
+                    }
+                } else {
+                    if (s == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
+                }
+            }
+        }
+        d2 an2;
+        an2.x = fma(2.0 * inv_f, acc.x, -aj.x);
+        an2.y = fma(2.0 * inv_f, acc.y, -aj.y);
+        ((d2 *)p.out2)[gu] = an2;
+        if constexpr (FIRST)
+            lam = cmul(cc0, aj) + cmul(cc1, aj1) + cmul(cc2, an2);
+        else
+            lam = lam + cmul(cc1, aj1) + cmul(cc2, an2);
+        ((d2 *)p.lam_acc)[gu] = lam;
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_expand(const d2 *__restrict__ src, const int32_t *__restrict__ perm,
                                                 int s_user, d2 *__restrict__ dst, int log2s, int64_t n_el) {
     const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -234,6 +421,25 @@ hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStrea
             TBPM_ADJ(false, kAdjFinal);
     }
 #undef TBPM_ADJ
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_pair(int kind, bool cplx, const AdjPairParams &p, hipStream_t st) {
+    if (p.n_tiles <= 0) return hipSuccess;
+    const dim3 grid(p.n_tiles), block(kWG);
+    const size_t lds = (size_t)p.lds_units * sizeof(d2);
+    if (kind != kAdjPairFirst && kind != kAdjPairMid) return hipErrorInvalidValue;
+    if (cplx) {
+        if (kind == kAdjPairFirst)
+            hipLaunchKernelGGL((k_adj_pair<true, kAdjPairFirst>), grid, block, lds, st, p);
+        else
+            hipLaunchKernelGGL((k_adj_pair<true, kAdjPairMid>), grid, block, lds, st, p);
+    } else {
+        if (kind == kAdjPairFirst)
+            hipLaunchKernelGGL((k_adj_pair<false, kAdjPairFirst>), grid, block, lds, st, p);
+        else
+            hipLaunchKernelGGL((k_adj_pair<false, kAdjPairMid>), grid, block, lds, st, p);
+    }
     return hipGetLastError();
 }
 

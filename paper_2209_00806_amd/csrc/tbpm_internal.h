@@ -91,6 +91,50 @@ struct AdjParams {
     const double *gcorr_l;  // complex [s_user]: dL/dC at this step (final pass)
 };
 
+// Two adjoint orders per launch (backward.hip), on the two-hop tiles of the
+// fused shape with single-state units: alpha_j staged, alpha_{j+1} on own and
+// 1-hop rows, alpha_{j+2} on own rows, both orders' gradient contributions
+// and lambda terms in one read-modify-write.
+enum AdjPairKind : int {
+    kAdjPairFirst = 0,  // orders 0, 1: alpha_1 = H~ alpha_0, lambda initialised
+    kAdjPairMid = 1     // orders j, j+1 (1 <= j, j+2 <= M-2)
+};
+
+struct AdjPairParams {
+    const TileDesc *tiles;
+    int32_t n_tiles;
+    int32_t xcd_remap;
+    int32_t log2s;
+    const int32_t *col;
+    const void *val;        // double or double2 (FP64)
+    const uint32_t *slice_off;
+    const double *onsite;
+    double inv_f;
+    const double *x;        // alpha_j, complex [rows][S], staged
+    const double *a_prev;   // alpha_{j-1} (own and 1-hop rows; null for the first pair)
+    double *out1;           // alpha_{j+1}, own rows
+    double *out2;           // alpha_{j+2}, own rows
+    double *lam_acc;        // lambda accumulator (written by the first pair, else read-modify-write)
+    const double *bq1;      // b_{j+1} (gathered)
+    const double *bq2;      // b_{j+2} (gathered)
+    double w1, w2;          // gradient weights of orders j and j+1
+    double cc0_re, cc0_im;  // conj(c_0) (first pair)
+    double cc1_re, cc1_im;  // conj(c_{j+1})
+    double cc2_re, cc2_im;  // conj(c_{j+2})
+    void *gacc;             // per ELL slot: double (real H) or double2
+    double *gdiag;          // [rows]
+    // two-hop tile tables (as FusedParams)
+    const int32_t *uoff;
+    const int32_t *n1;
+    const int32_t *ucol;
+    const uint16_t *lidx;
+    const int32_t *hoff;
+    const int32_t *hw;
+    const uint16_t *hidx;
+    int32_t lds_units;
+};
+hipError_t launch_adjoint_pair(int kind, bool cplx, const AdjPairParams &p, hipStream_t st);
+
 hipError_t launch_pair(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const FusedParams &p,
                        hipStream_t st);
 

@@ -159,3 +159,44 @@ def test_shift_identity_medium():
     rhs = float(np.real(np.sum(np.conj(g) * (-1j * k * dt) * c)))
     lhs = float(gons.sum().item())
     assert abs(lhs - rhs) < 1e-9 * max(1.0, abs(rhs))
+
+
+@pytest.mark.parametrize("M_dt", [1.0, 0.25, 0.12])
+@pytest.mark.parametrize("tier", [1, 2, 3])
+@pytest.mark.parametrize("name", ["graphene9x8_disorder", "graphene6x5_complex", "square9x7_open"])
+def test_backward_fused_shape_vs_oracle(name, tier, M_dt):
+    """The backward with the fused shape in the launch configuration: the
+    segment replay two Clenshaw orders per launch and the adjoint two orders
+    per launch (first pair, middle pairs, leftover single orders and the last
+    order), against the oracle's adjoint and the plain shape.  Time steps of
+    pi/f, pi/(4f) and 0.12 pi/f give series of 18, 11 and 9 terms: 17, 10 and
+    8 adjoint orders, with and without single orders left after the pairs."""
+    print(f"case backward fused {name} tier={tier} dt={M_dt}", flush=True)
+    rng = np.random.default_rng(23)
+    lats = {
+        "graphene9x8_disorder": lambda: inputs.graphene(9, 8, onsite=inputs.anderson(rng, 144, 1.0)),
+        "graphene6x5_complex": lambda: _complex_graphene(6, 5, 4),
+        "square9x7_open": lambda: inputs.square(9, 7, pbc=False, onsite=inputs.anderson(rng, 63, 1.0)),
+    }
+    lat = lats[name]()
+    S = 3
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    nt = 19
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = M_dt * math.pi / f
+    g = rng.standard_normal((nt, S)) + 1j * rng.standard_normal((nt, S))
+    gval_r, gons_r = oracle.backward(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f, g)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    p0 = _dev(psi0)
+    out = {}
+    for fused in (0, tier):
+        H.set_launch_config(2, 1, 1, 1, fused=fused)
+        corr, ckpt = tbpm.propagate(H, p0, nt, dt, f, ckpt_every=5)
+        gval, gons = tbpm.backward(H, p0, nt, dt, f, _dev(g), 5, ckpt)
+        out[fused] = (gval.cpu().numpy(), gons.cpu().numpy())
+    gval, gons = out[tier]
+    cmp = gval if H.info()["is_complex"] else gval.real
+    ref = gval_r if H.info()["is_complex"] else gval_r.real
+    assert _rel(cmp, ref) < 1e-10
+    assert _rel(gons, gons_r) < 1e-10
+    assert _rel(gval, out[0][0]) < 1e-12 and _rel(gons, out[0][1]) < 1e-12
