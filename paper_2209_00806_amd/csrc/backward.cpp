@@ -55,8 +55,19 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     // order's output has a slot of its own in the segment store, so a pair's
     // outputs never alias what its tiles read.  The adjoint passes run on the
     // same tiles (any tiling of the rows serves them).
+    // Those launches take the configuration's states per thread (vs) and
+    // non-temporal streaming; the single-order adjoint keeps one state per
+    // thread.  The two-hop tables depend on the bytes of a row only, so one
+    // set serves every unit width (the LDS size in units follows the width).
     bool pairs = eng.cfgs[0].fused > 0 && M - 2 >= 2;
-    if (pairs && eng.build_fused_tiles(s_pad, log2s, 16, eng.cfgs[0].fused) != TBPM_OK) pairs = false;
+    int32_t pvs = 1, log2pvs = 0;
+    while (pvs < eng.cfgs[0].vec && pvs < s_pad && pvs < 4) {
+        pvs <<= 1;
+        ++log2pvs;
+    }
+    const bool pnt = eng.cfgs[0].nontemporal != 0;
+    if (pairs && eng.build_fused_tiles(s_pad, log2s - log2pvs, 16 * pvs, eng.cfgs[0].fused) != TBPM_OK)
+        pairs = false;
     tbpm_status s = pairs ? TBPM_OK : eng.build_tiles(s_pad, eng.cfg.wg_chunks, 1);
     if (s != TBPM_OK) return s;
     const int32_t n_tiles = (int32_t)eng.h_tiles.size();
@@ -168,7 +179,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     fp.hoff = (const int32_t *)eng.fu_hoff.ptr;
     fp.hw = (const int32_t *)eng.fu_hw.ptr;
     fp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
-    fp.lds_units = eng.fu_lds_units;
+    fp.lds_units = (int32_t)(eng.fu_max_rows << (log2s - log2pvs));
     const PassCoef *coefs = (const PassCoef *)eng.bwd_coef.ptr;
     auto replay_step_pairs = [&](int32_t t) -> hipError_t {
         // plan entry p evaluates order pass_j[p]: 0 FIRST (M-2), 1 NOB2 (M-3),
@@ -180,7 +191,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
         fp.out2 = b_slot(t, M - 3);
         fp.coef1 = coefs;
         fp.coef2 = coefs + 1;
-        hipError_t e = launch_pair(kPairFirst, false, cplx, false, 1, fp, st);
+        hipError_t e = launch_pair(kPairFirst, false, cplx, pnt, pvs, fp, st);
         int p = 2;
         for (; e == hipSuccess && p + 1 < n_passes - 1; p += 2) {
             const int j = pass_j[p];
@@ -190,7 +201,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             fp.out2 = b_slot(t, j - 1);
             fp.coef1 = coefs + p;
             fp.coef2 = coefs + p + 1;
-            e = launch_pair(kPairMid, false, cplx, false, 1, fp, st);
+            e = launch_pair(kPairMid, false, cplx, pnt, pvs, fp, st);
         }
         for (; e == hipSuccess && p < n_passes; ++p) {  // a leftover MID, then LAST
             const int j = pass_j[p];
@@ -199,7 +210,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             pp.b2 = b_slot(t, j + 2);
             pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
             pp.coef = coefs + p;
-            e = launch_pass(plan[p].kind, false, cplx, false, eng.cfg.unroll, 1, pp, st);
+            e = launch_pass(plan[p].kind, false, cplx, pnt, eng.cfg.unroll, pvs, pp, st);
         }
         return e;
     };
@@ -229,7 +240,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     qp.hoff = (const int32_t *)eng.fu_hoff.ptr;
     qp.hw = (const int32_t *)eng.fu_hw.ptr;
     qp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
-    qp.lds_units = eng.fu_lds_units;
+    qp.lds_units = (int32_t)(eng.fu_max_rows << (log2s - log2pvs));
     qp.cc0_re = c[0].real();
     qp.cc0_im = -c[0].imag();
     auto adjoint_step_pairs = [&](int32_t t, int32_t l) -> hipError_t {
@@ -253,7 +264,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             qp.cc1_im = -c[j + 1].imag();
             qp.cc2_re = c[j + 2].real();
             qp.cc2_im = -c[j + 2].imag();
-            e = launch_adjoint_pair(j == 0 ? kAdjPairFirst : kAdjPairMid, cplx, qp, st);
+            e = launch_adjoint_pair(j == 0 ? kAdjPairFirst : kAdjPairMid, cplx, pvs, qp, st);
             // alpha_{j+2} is the next x, alpha_{j+1} the next prev; the old x and
             // prev (or the spare buffer after the first pair) take the outputs
             double *nx = fr[1], *np = fr[0];

@@ -157,32 +157,62 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
 // alpha_{j+2} = 2 H~ alpha_{j+1} - alpha_j on own rows.  On own rows the
 // gradient slots take w1 alpha_j[p] conj(b_{j+1}[q]) + w2 alpha_{j+1}[p]
 // conj(b_{j+2}[q]) summed over states in one read-modify-write, and lambda
-// gains conj(c_{j+1}) alpha_{j+1} + conj(c_{j+2}) alpha_{j+2}.  Indexing of the
-// staged rows is that of k_pair with single-state units.
-template <bool CH, int KIND>
+// gains conj(c_{j+1}) alpha_{j+1} + conj(c_{j+2}) alpha_{j+2}.  A thread
+// handles units of VS states; the staged-row indexing is that of k_pair.
+
+// sum over the U consecutive lanes that hold the units of one row
+__device__ __forceinline__ double unit_row_sum(double x, int log2u) {
+    for (int off = 1; off < (1 << log2u); off <<= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// sum over the VS states of a unit of Re(a_i conj(b_i)) (im = false) or
+// Im(a_i conj(b_i)) (im = true)
+template <int VS>
+__device__ __forceinline__ double unit_dot(const VecT<double, VS> &a, const VecT<double, VS> &b, bool im) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < VS; ++i)
+        r += im ? (a[2 * i + 1] * b[2 * i] - a[2 * i] * b[2 * i + 1]) : (a[2 * i] * b[2 * i] + a[2 * i + 1] * b[2 * i + 1]);
+    return r;
+}
+
+// acc += c * x for a complex scalar c and the VS components of x
+template <int VS>
+__device__ __forceinline__ void unit_cmad(d2 c, const VecT<double, VS> &x, VecT<double, VS> &acc) {
+#pragma unroll
+    for (int i = 0; i < VS; ++i) {
+        acc[2 * i] = fma(c.x, x[2 * i], fma(-c.y, x[2 * i + 1], acc[2 * i]));
+        acc[2 * i + 1] = fma(c.x, x[2 * i + 1], fma(c.y, x[2 * i], acc[2 * i + 1]));
+    }
+}
+
+template <bool CH, int KIND, int VS>
 __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
     extern __shared__ __align__(16) unsigned char adj_mem[];
+    using V = VecT<double, VS>;
     using HV = std::conditional_t<CH, d2, double>;
     using GV = std::conditional_t<CH, d2, double>;
     constexpr int KG = 4;
     constexpr bool FIRST = (KIND == kAdjPairFirst);
+    constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
     const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
     const TileDesc td = p.tiles[tile];
-    const int log2s = p.log2s;
-    const uint32_t smask = (1u << log2s) - 1u;
-    const uint32_t s = threadIdx.x & smask;
+    const int log2u = p.log2s - LOG2VS;
+    const uint32_t umask = (1u << log2u) - 1u;
+    const uint32_t usub = threadIdx.x & umask;
     const uint32_t n_own = (uint32_t)td.rows;
     const uint32_t row0 = (uint32_t)td.row0;
     const int32_t e_beg = p.uoff[tile], e_end = p.uoff[tile + 1];
     const uint32_t n1 = (uint32_t)p.n1[tile];
-    const uint32_t n_x = (n_own + (uint32_t)(e_end - e_beg)) << log2s;
-    const uint32_t n_y = (n_own + n1) << log2s;
+    const uint32_t n_x = (n_own + (uint32_t)(e_end - e_beg)) << log2u;
+    const uint32_t n_y = (n_own + n1) << log2u;
     const int32_t hoff = p.hoff[tile], hw = p.hw[tile];
-    d2 *xs = reinterpret_cast<d2 *>(adj_mem);
-    d2 *ys = xs + n_x;
-    const d2 *__restrict__ x = (const d2 *)p.x;
-    const d2 *__restrict__ bq1 = (const d2 *)p.bq1;
-    const d2 *__restrict__ bq2 = (const d2 *)p.bq2;
+    V *xs = reinterpret_cast<V *>(adj_mem);
+    V *ys = xs + n_x;
+    const V *__restrict__ x = (const V *)p.x;
+    const V *__restrict__ bq1 = (const V *)p.bq1;
+    const V *__restrict__ bq2 = (const V *)p.bq2;
     const HV *__restrict__ val = (const HV *)p.val;
     const uint32_t *__restrict__ soff = p.slice_off;
     const int32_t *__restrict__ ucol = p.ucol + e_beg;
@@ -192,11 +222,11 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
 
     // stage alpha_j: four loads in flight per thread
     for (uint32_t i0 = threadIdx.x; i0 < n_x; i0 += 4 * kWG) {
-        d2 t[4];
+        V t[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t i = i0 + (uint32_t)q * kWG;
-            if (i < n_x) t[q] = x[(grow_of(i >> log2s) << log2s) + (i & smask)];
+            if (i < n_x) t[q] = x[(grow_of(i >> log2u) << log2u) + (i & umask)];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -208,19 +238,16 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
 
     // alpha_{j+1} on own + 1-hop rows
     for (uint32_t u = threadIdx.x; u < n_y; u += kWG) {
-        const uint32_t lr = u >> log2s;
+        const uint32_t lr = u >> log2u;
         const uint32_t grow = grow_of(lr);
-        const uint32_t gu = (grow << log2s) + s;
+        const uint32_t gu = (grow << log2u) + usub;
         const uint32_t sl = grow / kSliceRows;
         const uint32_t off = soff[sl];
         const int w = (int)((soff[sl + 1] - off) / kSliceRows);
         const uint32_t base = off + grow % kSliceRows;
-        d2 ap;
-        if constexpr (!FIRST) ap = ((const d2 *)p.a_prev)[gu];
-        const d2 xo = xs[u];
-        d2 acc;
-        acc.x = p.onsite[grow] * xo.x;
-        acc.y = p.onsite[grow] * xo.y;
+        V ap;
+        if constexpr (!FIRST) ap = ((const V *)p.a_prev)[gu];
+        V acc = p.onsite[grow] * xs[u];
         const bool own = lr < n_own;
         const uint16_t *hrow = p.hidx + hoff + (int64_t)(own ? 0 : (lr - n_own)) * hw;
         for (int k = 0; k < w; k += KG) {
@@ -232,21 +259,24 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
                 const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
                 const uint32_t l = valid ? (own ? (uint32_t)p.lidx[slot] : (uint32_t)hrow[k + i]) : lr;
                 const HV hv = val[slot];
-                li[i] = (l << log2s) + s;
+                li[i] = (l << log2u) + usub;
                 h[i] = valid ? hv : HV{};
             }
 #pragma unroll
-            for (int i = 0; i < KG; ++i) acc = hmad(h[i], xs[li[i]], acc);
+            for (int i = 0; i < KG; ++i) {
+                if constexpr (CH)
+                    unit_mad_cplx<double, VS>(h[i], xs[li[i]], acc);
+                else
+                    unit_mad_real<double, VS>(h[i], xs[li[i]], acc);
+            }
         }
-        d2 an;
-        if constexpr (FIRST) {
+        V an;
+        if constexpr (FIRST)
             an = acc * inv_f;
-        } else {
-            an.x = fma(2.0 * inv_f, acc.x, -ap.x);
-            an.y = fma(2.0 * inv_f, acc.y, -ap.y);
-        }
+        else
+            an = (2.0 * inv_f) * acc - ap;
         ys[u] = an;
-        if (own) ((d2 *)p.out1)[gu] = an;
+        if (own) ((V *)p.out1)[gu] = an;
     }
     __syncthreads();
 
@@ -259,29 +289,28 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
     cc2.x = p.cc2_re;
     cc2.y = p.cc2_im;
     const double w1 = p.w1, w2 = p.w2;
-    const uint32_t n_u = n_own << log2s;
-    // n_u is a multiple of S and the S lanes of a row are consecutive lanes of
-    // one wave, so the lanes of a row take the same trip counts
+    const uint32_t n_u = n_own << log2u;
+    // n_u is a multiple of the units per row and the units of a row are
+    // consecutive lanes of one wave, so the lanes of a row take the same trip
+    // counts
     for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
-        const uint32_t lr = u >> log2s;
+        const uint32_t lr = u >> log2u;
         const uint32_t row = row0 + lr;
-        const uint32_t gu = (row << log2s) + s;
+        const uint32_t gu = (row << log2u) + usub;
         const uint32_t sl = row / kSliceRows;
         const uint32_t off = soff[sl];
         const int w = (int)((soff[sl + 1] - off) / kSliceRows);
         const uint32_t base = off + row % kSliceRows;
-        const d2 aj = xs[u], aj1 = ys[u];
-        const d2 ga1 = aj * w1, ga2 = aj1 * w2;
-        d2 lam;
-        if constexpr (!FIRST) lam = ((const d2 *)p.lam_acc)[gu];
+        const V aj = xs[u], aj1 = ys[u];
+        const V ga1 = aj * w1, ga2 = aj1 * w2;
+        V lam;
+        if constexpr (!FIRST) lam = ((const V *)p.lam_acc)[gu];
         {
-            const d2 b1 = bq1[gu], b2 = bq2[gu];
-            const double dg = row_sum(ga1.x * b1.x + ga1.y * b1.y + ga2.x * b2.x + ga2.y * b2.y, log2s);
-            if (s == 0) p.gdiag[row] += dg;
+            const V b1 = bq1[gu], b2 = bq2[gu];
+            const double dg = unit_row_sum(unit_dot<VS>(ga1, b1, false) + unit_dot<VS>(ga2, b2, false), log2u);
+            if (usub == 0) p.gdiag[row] += dg;
         }
-        d2 acc;
-        acc.x = p.onsite[row] * aj1.x;
-        acc.y = p.onsite[row] * aj1.y;
+        V acc = p.onsite[row] * aj1;
         for (int k = 0; k < w; k += KG) {
             uint32_t slot[KG], li[KG], gc[KG];
             HV h[KG];
@@ -293,11 +322,11 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
                 const uint32_t l = valid[i] ? (uint32_t)p.lidx[slot[i]] : lr;
                 const int32_t c = p.col[slot[i]];
                 const HV hv = val[slot[i]];
-                li[i] = (l << log2s) + s;
-                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2s) + s;
+                li[i] = (l << log2u) + usub;
+                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2u) + usub;
                 h[i] = valid[i] ? hv : HV{};
             }
-            d2 xb1[KG], xb2[KG];
+            V xb1[KG], xb2[KG];
             GV gold[KG];
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
@@ -307,34 +336,35 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
             }
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
-                acc = hmad(h[i], ys[li[i]], acc);
-                const double gr = row_sum(ga1.x * xb1[i].x + ga1.y * xb1[i].y + ga2.x * xb2[i].x +
-                                              ga2.y * xb2[i].y,
-                                          log2s);
+                if constexpr (CH)
+                    unit_mad_cplx<double, VS>(h[i], ys[li[i]], acc);
+                else
+                    unit_mad_real<double, VS>(h[i], ys[li[i]], acc);
+                const double gr =
+                    unit_row_sum(unit_dot<VS>(ga1, xb1[i], false) + unit_dot<VS>(ga2, xb2[i], false), log2u);
                 if constexpr (CH) {
-                    const double gi = row_sum(ga1.y * xb1[i].x - ga1.x * xb1[i].y + ga2.y * xb2[i].x -
-                                                  ga2.x * xb2[i].y,
-                                              log2s);
-                    if (s == 0 && valid[i]) {
+                    const double gi =
+                        unit_row_sum(unit_dot<VS>(ga1, xb1[i], true) + unit_dot<VS>(ga2, xb2[i], true), log2u);
+                    if (usub == 0 && valid[i]) {
                         d2 nv = gold[i];
                         nv.x += gr;
                         nv.y += gi;
                         gacc[slot[i]] = nv;
                     }
                 } else {
-                    if (s == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
+                    if (usub == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
                 }
             }
         }
-        d2 an2;
-        an2.x = fma(2.0 * inv_f, acc.x, -aj.x);
-        an2.y = fma(2.0 * inv_f, acc.y, -aj.y);
-        ((d2 *)p.out2)[gu] = an2;
-        if constexpr (FIRST)
-            lam = cmul(cc0, aj) + cmul(cc1, aj1) + cmul(cc2, an2);
-        else
-            lam = lam + cmul(cc1, aj1) + cmul(cc2, an2);
-        ((d2 *)p.lam_acc)[gu] = lam;
+        const V an2 = (2.0 * inv_f) * acc - aj;
+        ((V *)p.out2)[gu] = an2;
+        if constexpr (FIRST) {
+            lam = V{};
+            unit_cmad<VS>(cc0, aj, lam);
+        }
+        unit_cmad<VS>(cc1, aj1, lam);
+        unit_cmad<VS>(cc2, an2, lam);
+        ((V *)p.lam_acc)[gu] = lam;
     }
 }
 
@@ -424,23 +454,28 @@ hipError_t launch_adjoint_pass(int kind, bool cplx, const AdjParams &p, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_pair(int kind, bool cplx, const AdjPairParams &p, hipStream_t st) {
-    if (p.n_tiles <= 0) return hipSuccess;
+template <bool CH, int VS>
+hipError_t launch_adj_pair_t(int kind, const AdjPairParams &p, hipStream_t st) {
     const dim3 grid(p.n_tiles), block(kWG);
-    const size_t lds = (size_t)p.lds_units * sizeof(d2);
+    const size_t lds = (size_t)p.lds_units * sizeof(VecT<double, VS>);
+    if (kind == kAdjPairFirst)
+        hipLaunchKernelGGL((k_adj_pair<CH, kAdjPairFirst, VS>), grid, block, lds, st, p);
+    else
+        hipLaunchKernelGGL((k_adj_pair<CH, kAdjPairMid, VS>), grid, block, lds, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_pair(int kind, bool cplx, int vs, const AdjPairParams &p, hipStream_t st) {
+    if (p.n_tiles <= 0) return hipSuccess;
     if (kind != kAdjPairFirst && kind != kAdjPairMid) return hipErrorInvalidValue;
     if (cplx) {
-        if (kind == kAdjPairFirst)
-            hipLaunchKernelGGL((k_adj_pair<true, kAdjPairFirst>), grid, block, lds, st, p);
-        else
-            hipLaunchKernelGGL((k_adj_pair<true, kAdjPairMid>), grid, block, lds, st, p);
-    } else {
-        if (kind == kAdjPairFirst)
-            hipLaunchKernelGGL((k_adj_pair<false, kAdjPairFirst>), grid, block, lds, st, p);
-        else
-            hipLaunchKernelGGL((k_adj_pair<false, kAdjPairMid>), grid, block, lds, st, p);
+        if (vs == 4) return launch_adj_pair_t<true, 4>(kind, p, st);
+        if (vs == 2) return launch_adj_pair_t<true, 2>(kind, p, st);
+        return launch_adj_pair_t<true, 1>(kind, p, st);
     }
-    return hipGetLastError();
+    if (vs == 4) return launch_adj_pair_t<false, 4>(kind, p, st);
+    if (vs == 2) return launch_adj_pair_t<false, 2>(kind, p, st);
+    return launch_adj_pair_t<false, 1>(kind, p, st);
 }
 
 hipError_t launch_expand_states(const double *src, const int32_t *perm, int32_t s_user, double *dst, int32_t log2s,

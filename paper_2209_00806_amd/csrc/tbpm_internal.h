@@ -133,7 +133,9 @@ struct AdjPairParams {
     const uint16_t *hidx;
     int32_t lds_units;
 };
-hipError_t launch_adjoint_pair(int kind, bool cplx, const AdjPairParams &p, hipStream_t st);
+// vs: states per thread (1, 2 or 4; at most the padded state count);
+// lds_units counts units of vs states
+hipError_t launch_adjoint_pair(int kind, bool cplx, int vs, const AdjPairParams &p, hipStream_t st);
 
 hipError_t launch_pair(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const FusedParams &p,
                        hipStream_t st);

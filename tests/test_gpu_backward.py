@@ -162,16 +162,17 @@ def test_shift_identity_medium():
 
 
 @pytest.mark.parametrize("M_dt", [1.0, 0.25, 0.12])
-@pytest.mark.parametrize("tier", [1, 2, 3])
+@pytest.mark.parametrize("tier,vec", [(1, 1), (2, 2), (4, 4), (3, 2)])
 @pytest.mark.parametrize("name", ["graphene9x8_disorder", "graphene6x5_complex", "square9x7_open"])
-def test_backward_fused_shape_vs_oracle(name, tier, M_dt):
+def test_backward_fused_shape_vs_oracle(name, tier, vec, M_dt):
     """The backward with the fused shape in the launch configuration: the
     segment replay two Clenshaw orders per launch and the adjoint two orders
     per launch (first pair, middle pairs, leftover single orders and the last
-    order), against the oracle's adjoint and the plain shape.  Time steps of
+    order) with 1, 2 or 4 states per thread, against the oracle's adjoint and
+    the plain shape.  Time steps of
     pi/f, pi/(4f) and 0.12 pi/f give series of 18, 11 and 9 terms: 17, 10 and
     8 adjoint orders, with and without single orders left after the pairs."""
-    print(f"case backward fused {name} tier={tier} dt={M_dt}", flush=True)
+    print(f"case backward fused {name} tier={tier} vec={vec} dt={M_dt}", flush=True)
     rng = np.random.default_rng(23)
     lats = {
         "graphene9x8_disorder": lambda: inputs.graphene(9, 8, onsite=inputs.anderson(rng, 144, 1.0)),
@@ -179,7 +180,7 @@ def test_backward_fused_shape_vs_oracle(name, tier, M_dt):
         "square9x7_open": lambda: inputs.square(9, 7, pbc=False, onsite=inputs.anderson(rng, 63, 1.0)),
     }
     lat = lats[name]()
-    S = 3
+    S = 5  # padded to 8: with 4 states per thread, two units per row
     psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
     nt = 19
     f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
@@ -190,7 +191,7 @@ def test_backward_fused_shape_vs_oracle(name, tier, M_dt):
     p0 = _dev(psi0)
     out = {}
     for fused in (0, tier):
-        H.set_launch_config(2, 1, 1, 1, fused=fused)
+        H.set_launch_config(2, 1, 1, 1, vec=vec if fused else 1, precision="fp64", fused=fused)
         corr, ckpt = tbpm.propagate(H, p0, nt, dt, f, ckpt_every=5)
         gval, gons = tbpm.backward(H, p0, nt, dt, f, _dev(g), 5, ckpt)
         out[fused] = (gval.cpu().numpy(), gons.cpu().numpy())
