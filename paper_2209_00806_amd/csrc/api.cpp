@@ -419,7 +419,7 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     hipStream_t hs = (hipStream_t)stream;
     const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;
     const size_t vec2 = 2 * vec;
-    hipError_t e = eng.ac_vec.ensure(2 * vec + 4 * vec2);
+    hipError_t e = eng.ac_vec.ensure(2 * vec + 6 * vec2);
     if (e == hipSuccess) e = eng.ac_block.ensure(sizeof(double) * 4 * (size_t)n * n_states);
     if (e == hipSuccess) e = eng.corr_scratch.ensure(sizeof(double) * 4 * (size_t)n_steps * n_states);
     if (e != hipSuccess) return hip_fail(e, "alloc optical-conductivity buffers");
@@ -427,7 +427,7 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     if (st != TBPM_OK) return st;
     char *vb = (char *)eng.ac_vec.ptr;
     void *src = vb, *jpsi = vb + vec, *blk = vb + 2 * vec, *w0 = vb + 2 * vec + vec2, *w1 = vb + 2 * vec + 2 * vec2,
-         *fblk = vb + 2 * vec + 3 * vec2;
+         *fblk = vb + 2 * vec + 3 * vec2, *w2 = vb + 2 * vec + 4 * vec2, *w3 = vb + 2 * vec + 5 * vec2;
     e = launch_expand_states(psi0, eng.mat.perm, n_states, (double *)src, log2s, n, hs);
     if (e != hipSuccess) return hip_fail(e, "load states");
     try {
@@ -437,7 +437,7 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
         if (st != TBPM_OK) return st;
         e = launch_join((const double *)jpsi, (const double *)src, n, log2s, log2s2, n_states, (double *)blk, hs);
         if (e != hipSuccess) return hip_fail(e, "join states");
-        st = eng.apply_series(a, f, log2s2, blk, fblk, w0, w1, hs);
+        st = eng.apply_series(a, f, log2s2, blk, fblk, w0, w1, hs, w2, w3);
         if (st != TBPM_OK) return st;
         e = launch_pack((const double *)blk, (const double *)fblk, n, log2s2, n_states, eng.mat.perm,
                         (double *)eng.ac_block.ptr, hs);

@@ -915,7 +915,7 @@ tbpm_status Engine::run(const RunArgs &a) {
 }
 
 tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int32_t log2s, const void *src, void *dst,
-                                 void *w0, void *w1, hipStream_t st) {
+                                 void *w0, void *w1, hipStream_t st, void *w2, void *w3) {
     // Clenshaw for sum_{k<K} a_k T_k(x), x = H/f (zero-padded to K >= 3):
     //   b_{K-2} = a_{K-2} v + 2 a_{K-1} x v                       (FIRST)
     //   b_{K-3} = (a_{K-3} - a_{K-1}) v + 2 x b_{K-2}             (NOB2)
@@ -946,8 +946,20 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
         }
         seq.push_back({kPassMid, w[cur], w[1 - cur], dst, {a[0], 0, 1.0 / f, 0}});
     }
-    if (!tiles.ptr || tiles_s == 0) {
-        tbpm_status s = build_tiles(1 << log2s, cfg.wg_chunks, 1);
+    // With the fused shape configured (and two more work blocks), the orders
+    // run two per launch: (K-2, K-3) from the input, then (k, k-1) pairs over
+    // four rotating blocks (a pair's outputs go to the two blocks it does not
+    // read), the last pair writing the result; an order left over runs alone.
+    const int32_t s_pad = 1 << log2s;
+    bool pairs = w2 && w3 && K >= 4 && cfgs[0].fused > 0;
+    int32_t pvs = 1, log2pvs = 0;
+    while (pvs < cfgs[0].vec && pvs < s_pad && pvs < 4) {
+        pvs <<= 1;
+        ++log2pvs;
+    }
+    if (pairs && build_fused_tiles(s_pad, log2s - log2pvs, 16 * pvs, cfgs[0].fused) != TBPM_OK) pairs = false;
+    if (!pairs && (!tiles.ptr || tiles_s == 0)) {
+        tbpm_status s = build_tiles(s_pad, cfg.wg_chunks, 1);
         if (s != TBPM_OK) return s;
     }
     const size_t cb = sizeof(PassCoef) * seq.size();
@@ -970,6 +982,66 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
     pp.counter = (int32_t *)counter.ptr;
     pp.s_user = 1 << log2s;
     pp.v = src;
+    if (pairs) {
+        // seq holds the orders K-2, K-3, ..., 0 in evaluation order with
+        // their coefficients; only the coefficients are taken from it here
+        const bool nt = cfgs[0].nontemporal != 0;
+        FusedParams fp{};
+        fp.tiles = (const TileDesc *)tiles.ptr;
+        fp.n_tiles = (int32_t)h_tiles.size();
+        fp.xcd_remap = cfg.xcd_remap;
+        fp.log2s = log2s;
+        fp.col = mat.col;
+        fp.val = mat.val64;
+        fp.slice_off = mat.slice_off;
+        fp.onsite = mat.onsite64;
+        fp.counter = (int32_t *)counter.ptr;
+        fp.uoff = (const int32_t *)st_uoff.ptr;
+        fp.n1 = (const int32_t *)fu_n1.ptr;
+        fp.ucol = (const int32_t *)st_ucol.ptr;
+        fp.lidx = (const uint16_t *)st_lidx.ptr;
+        fp.hoff = (const int32_t *)fu_hoff.ptr;
+        fp.hw = (const int32_t *)fu_hw.ptr;
+        fp.hidx = (const uint16_t *)fu_hidx.ptr;
+        fp.lds_units = (int32_t)(fu_max_rows << (log2s - log2pvs));
+        fp.v = src;
+        void *wb[4] = {w0, w1, w2, w3};
+        const PassCoef *cf = (const PassCoef *)coef.ptr;
+        const size_t n_ord = seq.size();  // K - 1 orders, the last one the result
+        // (K-2, K-3) from the input into wb[0], wb[1]
+        fp.x = src;
+        fp.b2 = nullptr;
+        fp.out1 = wb[0];
+        fp.out2 = n_ord == 2 ? dst : wb[1];
+        fp.coef1 = cf;
+        fp.coef2 = cf + 1;
+        hipError_t e = launch_pair(kPairFirst, false, mat.is_complex, nt, pvs, fp, st);
+        int x = 1, b2 = 0;  // b_{k+1} in wb[x], b_{k+2} in wb[b2]
+        size_t i = 2;
+        for (; e == hipSuccess && i + 1 < n_ord; i += 2) {
+            int free_[2], nf = 0;
+            for (int q = 0; q < 4 && nf < 2; ++q)
+                if (q != x && q != b2) free_[nf++] = q;
+            fp.x = wb[x];
+            fp.b2 = wb[b2];
+            fp.out1 = wb[free_[0]];
+            fp.out2 = (i + 1 == n_ord - 1) ? dst : wb[free_[1]];
+            fp.coef1 = cf + i;
+            fp.coef2 = cf + i + 1;
+            e = launch_pair(kPairMid, false, mat.is_complex, nt, pvs, fp, st);
+            b2 = free_[0];
+            x = free_[1];
+        }
+        if (e == hipSuccess && i < n_ord) {  // the result alone: out = a_0 v + H~ b_1 - b_2
+            pp.x = wb[x];
+            pp.b2 = wb[b2];
+            pp.out = dst;
+            pp.coef = cf + i;
+            e = launch_pass(kPassMid, false, mat.is_complex, nt, 1, pvs, pp, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "launch series pair");
+        return TBPM_OK;
+    }
     for (size_t i = 0; i < seq.size(); ++i) {
         pp.x = seq[i].x;
         pp.b2 = seq[i].b2;

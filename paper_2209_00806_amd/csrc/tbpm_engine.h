@@ -176,9 +176,10 @@ struct Engine {
     };
     tbpm_status run(const RunArgs &a);
     // dst = sum_k a[k] T_k(H/f) src on [rows][2^log2s] FP64 internal blocks
-    // (Clenshaw on the plain pass kernel; w0, w1 work blocks; src kept)
+    // (Clenshaw; w0, w1 work blocks, and w2, w3 for two orders per launch
+    // when the fused shape is configured; src kept)
     tbpm_status apply_series(const std::vector<double> &a, double f, int32_t log2s, const void *src, void *dst,
-                             void *w0, void *w1, hipStream_t st);
+                             void *w0, void *w1, hipStream_t st, void *w2 = nullptr, void *w3 = nullptr);
     // dst = J src for J given as complex128 values in the ELL layout of H
     tbpm_status apply_ell(const double *jval, int32_t log2s, const void *src, void *dst, hipStream_t st);
     // Haydock (Lanczos) recursion of every column of psi0 (device, caller's

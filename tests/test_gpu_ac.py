@@ -69,6 +69,8 @@ def test_ac_corr_vs_oracle(case, order, fused, precision):
     assert np.array_equal(rp, lat.row_ptr) and np.array_equal(ci, lat.col)
     H.set_row_order(order)
     H.set_launch_config(2, 1, 1, 1, fused=fused)
+    if fused:  # the Fermi-Dirac series and the FP64 propagation with 2 states per thread
+        H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=fused)
     got = tbpm.ac_corr(H, ja, jb, _dev(psi0), nt, dt, beta, mu, rescale=f, fermi_tol=1e-13, precision=precision)
     got = got.cpu().numpy()
     assert got.shape == (nt, S)
