@@ -59,11 +59,25 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     if (need > free_b + have)
         return fail(TBPM_E_OOM, "the moment vectors need " + std::to_string(need >> 20) + " MiB of device memory");
 
-    tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
-    if (s0 != TBPM_OK) return s0;
+    // With the fused shape configured, the Chebyshev orders run two per launch
+    // (the Clenshaw pair with alpha = 0 is the three-term recursion: the second
+    // order subtracts the first's input): L_m straight into the store, T_n
+    // over four rotating blocks.
+    bool pairs = cfgs[0].fused > 0 && n_mom >= 4;
+    int32_t pvs = 1, log2pvs = 0;
+    while (pvs < cfgs[0].vec && pvs < s_pad && pvs < 4) {
+        pvs <<= 1;
+        ++log2pvs;
+    }
+    const bool pnt = cfgs[0].nontemporal != 0;
+    if (pairs && build_fused_tiles(s_pad, log2s - log2pvs, 16 * pvs, cfgs[0].fused) != TBPM_OK) pairs = false;
+    if (!pairs) {
+        tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
+        if (s0 != TBPM_OK) return s0;
+    }
     TRY_HIP(kp_store.ensure(vec * (size_t)n_mom), "alloc moment vectors L");
     TRY_HIP(kp_rblk.ensure(vec * (size_t)nb), "alloc moment vectors R");
-    TRY_HIP(kp_vec.ensure(3 * vec), "alloc Chebyshev vectors");
+    TRY_HIP(kp_vec.ensure(5 * vec), "alloc Chebyshev vectors");
     TRY_HIP(kp_parts.ensure(part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0))), "alloc split-K parts");
     TRY_HIP(counter.ensure(sizeof(int32_t)), "alloc counter");
     TRY_HIP(ac_zero.ensure(sizeof(double) * (size_t)std::max<int64_t>(n, 1)), "alloc zero on-site");
@@ -106,7 +120,36 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
         pp.coef = c;
         pp.counter = (int32_t *)counter.ptr;
         pp.s_user = s_pad;
-        return launch_pass(kind, false, jop ? true : mat.is_complex, false, 1, 1, pp, st);
+        return launch_pass(kind, false, jop ? true : mat.is_complex, pairs && pnt, 1, pairs ? pvs : 1, pp, st);
+    };
+
+    FusedParams fp{};
+    fp.tiles = (const TileDesc *)tiles.ptr;
+    fp.n_tiles = (int32_t)h_tiles.size();
+    fp.xcd_remap = cfg.xcd_remap;
+    fp.log2s = log2s;
+    fp.col = mat.col;
+    fp.val = mat.val64;
+    fp.slice_off = mat.slice_off;
+    fp.onsite = mat.onsite64;
+    fp.counter = (int32_t *)counter.ptr;
+    fp.uoff = (const int32_t *)st_uoff.ptr;
+    fp.n1 = (const int32_t *)fu_n1.ptr;
+    fp.ucol = (const int32_t *)st_ucol.ptr;
+    fp.lidx = (const uint16_t *)st_lidx.ptr;
+    fp.hoff = (const int32_t *)fu_hoff.ptr;
+    fp.hw = (const int32_t *)fu_hw.ptr;
+    fp.hidx = (const uint16_t *)fu_hidx.ptr;
+    fp.lds_units = (int32_t)(fu_max_rows << (log2s - log2pvs));
+    fp.coef1 = fp.coef2 = c_2;
+    // T_{k+1}, T_{k+2} = 2 H~ T_k - T_{k-1}, 2 H~ T_{k+1} - T_k
+    auto pair = [&](const void *tk, const void *tkm1, void *o1, void *o2) -> hipError_t {
+        fp.x = tk;
+        fp.v = tk;
+        fp.b2 = tkm1;
+        fp.out1 = o1;
+        fp.out2 = o2;
+        return launch_pair(kPairMid, false, mat.is_complex, pnt, pvs, fp, st);
     };
 
     char *Ls = (char *)kp_store.ptr;
@@ -121,7 +164,16 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
 
     // L_0 = v_a r, L_1 = H~ L_0, L_{m+1} = 2 H~ L_m - L_{m-1}, in place in the store
     TRY_HIP(pass(kPassFirst, true, ja, r, nullptr, Ls, c_j), "launch current operator");
-    for (int32_t m = 1; m < n_mom; ++m) {
+    int32_t m_done = 1;  // orders written so far
+    if (pairs) {
+        TRY_HIP(pass(kPassFirst, false, nullptr, Ls, nullptr, Ls + vec, c_1), "launch Chebyshev pass");
+        m_done = 2;
+        for (; m_done + 1 < n_mom; m_done += 2)
+            TRY_HIP(pair(Ls + vec * (size_t)(m_done - 1), Ls + vec * (size_t)(m_done - 2), Ls + vec * (size_t)m_done,
+                         Ls + vec * (size_t)(m_done + 1)),
+                    "launch Chebyshev pair");
+    }
+    for (int32_t m = m_done; m < n_mom; ++m) {
         void *out = Ls + vec * (size_t)m;
         const void *x = Ls + vec * (size_t)(m - 1);
         if (m == 1)
@@ -137,10 +189,37 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     const rocblas_double_complex zero = make_hipDoubleComplex(0.0, 0.0);
     const void *tc = r;  // T_n
     void *tn[2] = {t0, t1};
+    // paired T recursion: T_n (n >= 1) lives in tq[n & 3]; orders are produced
+    // when first needed, two per launch while the series allows (a pair writes
+    // over T_{n-4} and T_{n-3}, whose current-operator passes are done)
+    void *tq[4] = {vb + 3 * vec, t0, t1, vb + 4 * vec};
+    int32_t produced = 0;  // T_0 = r
     float gemm_ms = 0.0f;
     for (int32_t n0 = 0; n0 < n_mom; n0 += nb) {
         const int32_t cnt = std::min(nb, n_mom - n0);
-        for (int32_t j = 0; j < cnt; ++j) {
+        for (int32_t j = 0; pairs && j < cnt; ++j) {
+            const int32_t nn = n0 + j;
+            while (produced < nn) {
+                const int32_t k = produced + 1;
+                if (k == 1) {
+                    TRY_HIP(pass(kPassFirst, false, nullptr, r, nullptr, tq[1], c_1), "launch Chebyshev pass");
+                    produced = 1;
+                } else if (k == 2) {
+                    TRY_HIP(pass(kPassMid, false, nullptr, tq[1], r, tq[2], c_2), "launch Chebyshev pass");
+                    produced = 2;
+                } else if (k + 1 < n_mom) {
+                    TRY_HIP(pair(tq[(k - 1) & 3], tq[(k - 2) & 3], tq[k & 3], tq[(k + 1) & 3]), "launch Chebyshev pair");
+                    produced = k + 1;
+                } else {
+                    TRY_HIP(pass(kPassMid, false, nullptr, tq[(k - 1) & 3], tq[(k - 2) & 3], tq[k & 3], c_2),
+                            "launch Chebyshev pass");
+                    produced = k;
+                }
+            }
+            const void *tcur = nn == 0 ? r : tq[nn & 3];
+            TRY_HIP(pass(kPassFirst, true, jb, tcur, nullptr, Rb + vec * (size_t)j, c_j), "launch current operator");
+        }
+        for (int32_t j = 0; !pairs && j < cnt; ++j) {
             const int32_t nn = n0 + j;
             if (nn == 1) {
                 TRY_HIP(pass(kPassFirst, false, nullptr, r, nullptr, t0, c_1), "launch Chebyshev pass");

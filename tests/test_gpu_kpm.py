@@ -51,10 +51,10 @@ def _states(lat, spec):
     return inputs.random_phase_states(np.random.default_rng(11), lat.n_orb, spec)
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order,fused", [(0, 0), (1, 0), (1, 2)])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_kpm_moments_vs_oracle(case, order):
-    print(f"case kpm {case} order={order}", flush=True)
+def test_kpm_moments_vs_oracle(case, order, fused):
+    print(f"case kpm {case} order={order} fused={fused}", flush=True)
     make, spec, M, (ax_a, ax_b) = CASES[case]
     lat = make()
     va = inputs.current_values(lat, ax_a)
@@ -64,6 +64,8 @@ def test_kpm_moments_vs_oracle(case, order):
     ref = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, va, vb, st, M, f)
     H = tbpm.Hamiltonian.from_lattice(lat)
     H.set_row_order(order)
+    if fused:  # Chebyshev orders two per launch, 2 states per thread
+        H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=fused)
     mu, t = tbpm.kpm_moments(H, va, vb, _dev(st), M, f, return_timing=True)
     got = mu.cpu().numpy()
     assert got.shape == (M, M)
