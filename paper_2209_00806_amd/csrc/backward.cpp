@@ -98,6 +98,11 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     TRY_HIP(hipMemcpy(eng.bwd_coef.ptr, hc.data(), sizeof(PassCoef) * n_passes, hipMemcpyHostToDevice),
             "upload coefficients");
 
+    // the replay needs psi_{l+1} but not its correlation: the last pass runs
+    // as the same combination without the correlation stream
+    auto replay_kind = [](int kind) {
+        return kind == kPassLast ? (int)kPassMid : (kind == kPassLastNoB2 ? (int)kPassNoB2 : kind);
+    };
     double *store = (double *)eng.bwd_store.ptr;
     auto psi_slot = [&](int t) { return store + (size_t)t * 2 * n_el; };
     auto b_slot = [&](int t, int j) {  // b_j, j = 1 .. M-2, of local step t
@@ -210,7 +215,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             pp.b2 = b_slot(t, j + 2);
             pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
             pp.coef = coefs + p;
-            e = launch_pass(plan[p].kind, false, cplx, pnt, eng.cfg.unroll, pvs, pp, st);
+            e = launch_pass(replay_kind(plan[p].kind), false, cplx, pnt, eng.cfg.unroll, pvs, pp, st);
         }
         return e;
     };
@@ -332,7 +337,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
                 pp.b2 = (pl.kind == kPassMid || pl.kind == kPassLast) ? b_slot(t, j + 2) : nullptr;
                 pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
                 pp.coef = (const PassCoef *)eng.bwd_coef.ptr + p;
-                TRY_HIP(launch_pass(pl.kind, false, cplx, false, eng.cfg.unroll, 1, pp, st), "replay pass");
+                TRY_HIP(launch_pass(replay_kind(pl.kind), false, cplx, false, eng.cfg.unroll, 1, pp, st), "replay pass");
             }
         }
         // adjoint sweep through the segment
