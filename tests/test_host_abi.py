@@ -154,3 +154,38 @@ def test_library_fermi_coefficients_vs_oracle(beta, mu):
     k = min(a.size, ref.size)
     assert abs(a.size - ref.size) <= 2
     assert np.max(np.abs(a[:k] - ref[:k])) < 1e-13
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/tbpm.h is a C header: a C99 program (-pedantic, no C++)
+    compiles against it, links libtbpm.so, and calls host-only entry points
+    (version, Bessel coefficients, argument rejection) without a GPU."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    tbpm.lib()  # built
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "tbpm.h"\n#include <math.h>\n#include <stdio.h>\n'
+        "int main(void) {\n"
+        "    double J[4];\n"
+        "    int32_t M = 0;\n"
+        "    if (!tbpm_version()) return 1;\n"
+        "    if (tbpm_bessel_j(3.14159265358979, 4, J) != TBPM_OK) return 2;\n"
+        "    if (tbpm_num_terms(3.14159265358979, 1e-12, &M) != TBPM_OK || M != 18) return 3;\n"
+        "    if (tbpm_dos(0, 4, 1, 0.1, TBPM_WIN_HANN, 0, 0, 0) != TBPM_E_ARG) return 4;\n"
+        '    printf("%.15f %d\\n", J[0], (int)M);\n'
+        "    return 0;\n"
+        "}\n")
+    lib_dir = os.path.join(ROOT, "paper_2209_00806_amd")
+    exe = str(tmp_path / "abi")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", f"-I{os.path.join(ROOT, 'include')}",
+                    str(src), f"-L{lib_dir}", "-ltbpm", f"-Wl,-rpath,{lib_dir}", "-lm", "-o", exe],
+                   check=True, capture_output=True, timeout=120)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    j0, m = r.stdout.split()
+    assert abs(float(j0) - oracle.bessel_j(0, math.pi)) < 1e-14 and int(m) == 18
