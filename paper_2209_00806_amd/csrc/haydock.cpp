@@ -24,10 +24,7 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
         ++log2s;
     }
     const int64_t n = mat.n_rows;
-    // tiles of at least 2048 state elements: every iteration reduces one
-    // partial per tile and state twice, so fewer, larger tiles shorten the
-    // reductions
-    tbpm_status s0 = build_tiles(s_pad, std::max(cfg.wg_chunks, 8), 1);
+    tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
     if (s0 != TBPM_OK) return s0;
     const int32_t n_tiles = (int32_t)h_tiles.size();
     const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;

@@ -41,35 +41,49 @@ __global__ __launch_bounds__(kWG) void k_hay_spmv(const TileDesc *__restrict__ t
                                                   const double *__restrict__ hs, int32_t *counter,
                                                   double *__restrict__ partials) {
     using HV = typename std::conditional<CH, d2, double>::type;
-    const HV *hv = (const HV *)val;
+    const HV *hvp = (const HV *)val;
+    auto hv_ = [&](uint32_t slot) { return hvp[slot]; };
     const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap);
     const TileDesc td = tiles[tile];
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(counter, 1);
-    const int smask = (1 << log2s) - 1;
-    const int s = threadIdx.x & smask;
+    const uint32_t smask = (1u << log2s) - 1u;
+    const uint32_t s = threadIdx.x & smask;
     const double inv = hs[4 * s], cprev = hs[4 * s + 1];
-    const int64_t n_u = (int64_t)td.rows << log2s;
+    // 32-bit element indices: rows * S < 2^31 (checked by the entry point)
+    const uint32_t n_u = (uint32_t)td.rows << log2s;
+    const uint32_t row0 = (uint32_t)td.row0;
+    constexpr int KG = 4;  // stored elements gathered per batch
     double dre = 0.0;
-    for (int64_t q = threadIdx.x; q < n_u; q += kWG) {
-        const int64_t r = td.row0 + (q >> log2s);
-        const int64_t sl = r / kSliceRows;
+    for (uint32_t q = threadIdx.x; q < n_u; q += kWG) {
+        const uint32_t r = row0 + (q >> log2s);
+        const uint32_t sl = r / kSliceRows;
         const uint32_t off = soff[sl];
         const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const int64_t base = off + r % kSliceRows;
-        const int64_t e = (r << log2s) + s;
+        const uint32_t base = off + r % kSliceRows;
+        const uint32_t e = (r << log2s) + s;
+        const d2 up = __builtin_nontemporal_load(uprev + e);  // read once
         const d2 ur = u[e];
         d2 acc;
         acc.x = onsite[r] * ur.x;
         acc.y = onsite[r] * ur.y;
-        for (int k = 0; k < w; ++k) {
-            const int64_t slot = base + (int64_t)k * kSliceRows;
-            acc = hmad(hv[slot], u[((int64_t)col[slot] << log2s) + s], acc);
+        for (int k = 0; k < w; k += KG) {
+            HV h[KG];
+            uint32_t g[KG];
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : base;
+                const HV hv = hv_(slot);
+                g[i] = ((valid ? (uint32_t)col[slot] : r) << log2s) + s;
+                h[i] = valid ? hv : HV{};
+            }
+#pragma unroll
+            for (int i = 0; i < KG; ++i) acc = hmad(h[i], u[g[i]], acc);
         }
-        const d2 up = uprev[e];
         d2 yv;
         yv.x = fma(inv, acc.x, -cprev * up.x);
         yv.y = fma(inv, acc.y, -cprev * up.y);
-        y[e] = yv;
+        __builtin_nontemporal_store(yv, y + e);
         dre = fma(ur.x * inv, yv.x, fma(ur.y * inv, yv.y, dre));
     }
     block_state_partials(dre, 0.0, 0.0, log2s, partials, tile, n_tiles);
@@ -82,15 +96,15 @@ __global__ __launch_bounds__(kWG) void k_hay_axpy(const TileDesc *__restrict__ t
                                                   const double *__restrict__ hs, double *__restrict__ partials) {
     const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap);
     const TileDesc td = tiles[tile];
-    const int smask = (1 << log2s) - 1;
-    const int s = threadIdx.x & smask;
+    const uint32_t smask = (1u << log2s) - 1u;
+    const uint32_t s = threadIdx.x & smask;
     const double c = unext ? hs[4 * s + 2] : 0.0;
-    const int64_t n_u = (int64_t)td.rows << log2s;
-    const int64_t u0 = td.row0 << log2s;
+    const uint32_t n_u = (uint32_t)td.rows << log2s;
+    const uint32_t u0 = (uint32_t)td.row0 << log2s;
     double nrm = 0.0;
-    for (int64_t q = threadIdx.x; q < n_u; q += kWG) {
-        const int64_t e = u0 + q;
-        d2 v = y[e];
+    for (uint32_t q = threadIdx.x; q < n_u; q += kWG) {
+        const uint32_t e = u0 + q;
+        d2 v = __builtin_nontemporal_load(y + e);  // read once
         if (unext) {
             const d2 ui = u[e];
             v.x = fma(-c, ui.x, v.x);
