@@ -250,11 +250,17 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
  *             Hermitian; J = -i sum H_ij (r_j - r_i) c_i^+ c_j in units
  *             e = hbar = 1) as values on H's merged pattern, in the order of
  *             tbpm_hamiltonian_pattern; they may be the same array
+ *   psi0      device, [n_orb][n_states] complex128 (caller's row order)
  *   n_states  1 .. 32 (both states are propagated as one block of 2 S)
  *   beta      1/(k_B T) in 1/eV (> 0), mu the chemical potential in eV
- *   fermi_tol truncation of the Fermi-Dirac series (last |a_k| kept >= tol)
+ *   fermi_tol truncation of the Fermi-Dirac series (last |a_k| kept >= tol),
+ *             in (0, 1e-2); the series (coefficients of tbpm_fermi_cheb) is
+ *             evaluated once, in FP64, on the block [J_beta psi0 | psi0], and
+ *             psi1 = J_beta psi0 - f(H) J_beta psi0; prec applies to the
+ *             propagation only
  *   corr      device, [n_steps][n_states] complex128, written
- * Other arguments as tbpm_propagate.
+ * Other arguments as tbpm_propagate.  TBPM_E_ARG also when the series needs
+ * more than 2^19 terms (beta times the rescale factor too large).
  */
 tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const double *j_beta, const double *psi0,
                          int32_t n_states, int32_t n_steps, double dt, double rescale, double bessel_tol, double beta,
