@@ -356,27 +356,33 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
 // locality order: recursive bisection of the row graph
 // ---------------------------------------------------------------------------
 std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf) {
-    std::vector<int32_t> order(n), mark(n, 0), seen(n, 0), q;
+    std::vector<int32_t> order(n), mark(n, 0), seen(n, 0), q, du(n, 0), dv(n, 0);
     for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
     int32_t stamp = 0, visit = 0;
     // breadth-first order of the part (rows with mark == stamp) from s, then
-    // from the first unvisited row of each remaining piece; returns the last row
-    auto bfs = [&](int32_t s, int64_t lo, int64_t hi) {
+    // from the first unvisited row of each remaining piece, with the level of
+    // every row in dist (pieces after the first continue the level count);
+    // returns the last row
+    auto bfs = [&](int32_t s, int64_t lo, int64_t hi, std::vector<int32_t> &dist) {
         ++visit;
         q.clear();
         int64_t next = lo;
+        int32_t base = 0;
         while ((int64_t)q.size() < hi - lo) {
             if (q.size() > 0 || seen[s] == visit) {
                 while (seen[order[next]] == visit) ++next;
                 s = order[next];
+                base = dist[q.back()] + 1;
             }
             seen[s] = visit;
+            dist[s] = base;
             q.push_back(s);
             for (size_t h = q.size() - 1; h < q.size(); ++h)
                 for (int64_t p = row_ptr[q[h]]; p < row_ptr[q[h] + 1]; ++p) {
                     const int32_t c = col[p];
                     if (mark[c] == stamp && seen[c] != visit) {
                         seen[c] = visit;
+                        dist[c] = dist[q[h]] + 1;
                         q.push_back(c);
                     }
                 }
@@ -384,17 +390,37 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
         return q.back();
     };
     std::vector<std::pair<int64_t, int64_t>> stack{{0, n}};
+    std::vector<int32_t> rank;
     while (!stack.empty()) {
         const auto [lo, hi] = stack.back();
         stack.pop_back();
         if (hi - lo < 2) continue;
         ++stamp;
         for (int64_t k = lo; k < hi; ++k) mark[order[k]] = stamp;
-        // a pseudo-peripheral start: the row reached last from the first row
-        const int32_t far = bfs(order[lo], lo, hi);
-        bfs(far, lo, hi);
+        // pseudo-peripheral rows u (reached last from the first row) and v
+        // (reached last from u)
+        const int32_t u = bfs(order[lo], lo, hi, du);
+        const int32_t v = bfs(u, lo, hi, du);
         std::copy(q.begin(), q.end(), order.begin() + lo);
         if (hi - lo <= std::max<int64_t>(leaf, 2)) continue;
+        // split along the bisector of u and v: rows ordered by
+        // d(u, r) - d(v, r) (ties in breadth-first order from u), so the cut
+        // runs straight across the part rather than along a level of one
+        // breadth-first search
+        bfs(v, lo, hi, dv);
+        // counting sort on the integer key (stable, so ties keep the order from u)
+        int32_t kmin = INT32_MAX, kmax = INT32_MIN;
+        for (int64_t k = lo; k < hi; ++k) {
+            const int32_t key = du[order[k]] - dv[order[k]];
+            kmin = std::min(kmin, key);
+            kmax = std::max(kmax, key);
+        }
+        rank.assign((size_t)(kmax - kmin) + 2, 0);
+        for (int64_t k = lo; k < hi; ++k) ++rank[(size_t)(du[order[k]] - dv[order[k]] - kmin) + 1];
+        for (size_t b = 1; b < rank.size(); ++b) rank[b] += rank[b - 1];
+        q.assign(hi - lo, 0);
+        for (int64_t k = lo; k < hi; ++k) q[rank[(size_t)(du[order[k]] - dv[order[k]] - kmin)]++] = order[k];
+        std::copy(q.begin(), q.end(), order.begin() + lo);
         const int64_t mid = lo + (hi - lo) / 2;
         stack.push_back({mid, hi});
         stack.push_back({lo, mid});

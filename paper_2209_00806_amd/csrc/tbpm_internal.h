@@ -231,9 +231,10 @@ constexpr int kFusedTiers = 6;
 inline size_t fused_lds_budget(int tier) { return (size_t)(160 * 1024 / (tier + 2)) & ~(size_t)255; }
 
 // Row order with locality at every scale, without coordinates: recursive
-// bisection of the row graph, each part split at the middle of a
-// breadth-first order started from a pseudo-peripheral row; parts of at most
-// 'leaf' rows keep that breadth-first order.  perm[new row] = old row.
+// bisection of the row graph; each part is split at the median of
+// d(u, r) - d(v, r) for two pseudo-peripheral rows u, v (graph distances), a
+// cut across the middle of the part; parts of at most 'leaf' rows keep the
+// breadth-first order from u.  perm[new row] = old row.
 std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf);
 // false if no R fits the LDS budget of budget bytes (units of unit_bytes,
 // 2^log2u units per row)
