@@ -52,7 +52,7 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     const int64_t n_parts = std::max<int64_t>(1, std::min<int64_t>(64, K / 4096));
     const int64_t kc = K / n_parts, k_rest = K - kc * n_parts;
     const size_t part_bytes = sizeof(double) * 2 * (size_t)n_mom * nb;
-    const size_t need = vec * ((size_t)n_mom + nb + 3) + part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0));
+    const size_t need = vec * ((size_t)n_mom + nb + 5) + part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0));
     size_t free_b = 0, total_b = 0;
     TRY_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     const size_t have = kp_store.bytes + kp_rblk.bytes + kp_vec.bytes + kp_parts.bytes;
