@@ -187,3 +187,18 @@ def test_haydock_full_size_short():
     ar, br = oracle.haydock(lat.row_ptr, lat.col, lat.val, lat.onsite, st, 24)
     assert np.max(np.abs(a.cpu().numpy() - ar)) < 1e-11 * g
     assert np.max(np.abs(b.cpu().numpy() - br)) < 1e-11 * g
+
+
+def test_kpm_moments_full_size_short():
+    """Kubo-Bastin moments of the 1024x1024 disordered lattice of the bench
+    leg (one random-phase state, J_x twice) in the fused shape the bench
+    autotunes to, for the first 16 moments, against the oracle."""
+    print("case kpm moments 1024x1024", flush=True)
+    f = 9.0
+    lat, psi0 = inputs.workload_disordered_graphene(1024, 1)
+    jx = inputs.current_values(lat, 0)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=2)
+    got = tbpm.kpm_moments(H, jx, jx, _dev(psi0), 16, f).cpu().numpy()
+    ref = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jx, psi0, 16, f)
+    assert _rel(got, ref) < 1e-11
