@@ -31,12 +31,14 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
     TRY_HIP(hay_u.ensure(2 * vec), "alloc Lanczos vectors");
     TRY_HIP(hay_y.ensure(vec), "alloc Lanczos product");
     TRY_HIP(hay_s.ensure(sizeof(double) * 4 * (size_t)s_pad), "alloc Lanczos scalars");
-    TRY_HIP(partials.ensure(sizeof(double) * 3 * (size_t)n_tiles * s_pad), "alloc partials");
+    const size_t n_part = 3 * (size_t)n_tiles * s_pad;
+    TRY_HIP(partials.ensure(sizeof(double) * (n_part + (size_t)hay_fold_count(n_tiles) * s_pad)), "alloc partials");
     TRY_HIP(counter.ensure(sizeof(int32_t)), "alloc counter");
     double *u[2] = {(double *)hay_u.ptr, (double *)((char *)hay_u.ptr + vec)};
     double *y = (double *)hay_y.ptr;
     double *hs = (double *)hay_s.ptr;
     double *part = (double *)partials.ptr;
+    double *fold = part + n_part;
     int32_t *cnt = (int32_t *)counter.ptr;
     const TileDesc *td = (const TileDesc *)tiles.ptr;
     const void *val = mat.val64;  // double or complex128 per stored element
@@ -45,16 +47,18 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
     TRY_HIP(launch_expand_states(psi0, mat.perm, s_user, u[0], log2s, n, st), "load start vectors");
     TRY_HIP(launch_fill_zero(u[1], 2 * n * s_pad, st), "clear Lanczos vector");
     TRY_HIP(launch_hay_axpy(td, n_tiles, cfg.xcd_remap, log2s, u[0], nullptr, nullptr, hs, part, st), "start norm");
-    TRY_HIP(launch_hay_reduce(part, n_tiles, s_pad, s_user, 2, thr, hs, cnt, n_iter, a_out, b_out, st),
+    TRY_HIP(launch_hay_reduce(part, n_tiles, s_pad, s_user, 2, thr, hs, cnt, n_iter, a_out, b_out, fold, st),
             "start norm reduce");
 
     auto iteration = [&](int par, hipStream_t s) -> hipError_t {
         double *cur = u[par], *prev = u[1 - par];
         hipError_t e = launch_hay_spmv(mat.is_complex, td, n_tiles, cfg.xcd_remap, log2s, mat.col, val,
                                        mat.slice_off, mat.onsite64, cur, prev, y, hs, cnt, part, s);
-        if (e == hipSuccess) e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 0, thr, hs, cnt, n_iter, a_out, b_out, s);
+        if (e == hipSuccess)
+            e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 0, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
         if (e == hipSuccess) e = launch_hay_axpy(td, n_tiles, cfg.xcd_remap, log2s, y, cur, prev, hs, part, s);
-        if (e == hipSuccess) e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 1, thr, hs, cnt, n_iter, a_out, b_out, s);
+        if (e == hipSuccess)
+            e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 1, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
         return e;
     };
 

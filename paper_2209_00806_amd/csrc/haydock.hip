@@ -119,21 +119,51 @@ __global__ __launch_bounds__(kWG) void k_hay_axpy(const TileDesc *__restrict__ t
 // One workgroup per state: the fixed-order sum of the per-tile partials and
 // the scalar update.  The iteration index is the device counter minus one
 // (k_hay_spmv bumps it).
-__global__ __launch_bounds__(kWG) void k_hay_reduce(const double *__restrict__ partials, int n_tiles, int s_user,
-                                                    int mode, double thr, double *__restrict__ hs,
+// First stage of a per-state sum over many per-tile partials: workgroup
+// (g, s) adds values [g kFold, (g+1) kFold) of state s (row s of `in`, stride
+// in_stride) in a fixed order and writes out[s n_fold + g].  One pass with
+// all loads in flight, instead of one workgroup per state walking the whole
+// row with dependent rounds of loads.
+constexpr int kFold = 4 * kWG;
+
+__global__ __launch_bounds__(kWG) void k_hay_fold(const double *__restrict__ in, int64_t in_stride, int n,
+                                                  double *__restrict__ out, int n_fold) {
+    __shared__ double red[kWG];
+    const int g = blockIdx.x, s = blockIdx.y;
+    const double *p = in + (int64_t)s * in_stride + (int64_t)g * kFold;
+    const int m = min(kFold, n - g * kFold);
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = (int)threadIdx.x + q * kWG;
+        v[q] = i < m ? p[i] : 0.0;
+    }
+    red[threadIdx.x] = (v[0] + v[1]) + (v[2] + v[3]);
+    __syncthreads();
+    for (int h = kWG / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)s * n_fold + g] = red[0];
+}
+
+// Final stage: workgroup s sums row s of `in` (n values, stride in_stride)
+// and applies the Lanczos scalar update of `mode`.
+__global__ __launch_bounds__(kWG) void k_hay_reduce(const double *__restrict__ in, int64_t in_stride, int n,
+                                                    int s_user, int mode, double thr, double *__restrict__ hs,
                                                     int32_t *counter, int n_iter, double *__restrict__ a_out,
                                                     double *__restrict__ b_out) {
     __shared__ double red[kWG];
     const int s = blockIdx.x;
-    const double *p = partials + (int64_t)s * 3 * n_tiles + (mode == kHayA ? 0 : 2 * (int64_t)n_tiles);
+    const double *p = in + (int64_t)s * in_stride;
     // eight independent accumulators keep loads in flight; the order is fixed
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int t = threadIdx.x;
-    for (; t + 7 * kWG < n_tiles; t += 8 * kWG) {
+    for (; t + 7 * kWG < n; t += 8 * kWG) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] += p[t + q * kWG];
     }
-    for (; t < n_tiles; t += kWG) v[0] += p[t];
+    for (; t < n; t += kWG) v[0] += p[t];
     red[threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
     __syncthreads();
     for (int h = kWG / 2; h > 0; h >>= 1) {
@@ -214,11 +244,26 @@ hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_r
     return hipGetLastError();
 }
 
+int32_t hay_fold_count(int32_t n_tiles) { return n_tiles > kFold ? (n_tiles + kFold - 1) / kFold : 0; }
+
 hipError_t launch_hay_reduce(const double *partials, int32_t n_tiles, int32_t s_pad, int32_t s_user, int32_t mode,
                              double thr, double *hs, int32_t *counter, int32_t n_iter, double *a_out, double *b_out,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_hay_reduce, dim3((unsigned)s_pad), dim3(kWG), 0, st, partials, n_tiles, s_user, (int)mode,
-                       thr, hs, counter, n_iter, a_out, b_out);
+                             double *fold, hipStream_t st) {
+    const double *in = partials + (mode == kHayA ? 0 : 2 * (int64_t)n_tiles);
+    int64_t stride = 3 * (int64_t)n_tiles;
+    int n = n_tiles;
+    const int32_t n_fold = hay_fold_count(n_tiles);
+    if (n_fold > 0) {
+        hipLaunchKernelGGL(k_hay_fold, dim3((unsigned)n_fold, (unsigned)s_pad), dim3(kWG), 0, st, in, stride, n_tiles,
+                           fold, n_fold);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        in = fold;
+        stride = n_fold;
+        n = n_fold;
+    }
+    hipLaunchKernelGGL(k_hay_reduce, dim3((unsigned)s_pad), dim3(kWG), 0, st, in, stride, n, s_user, (int)mode, thr,
+                       hs, counter, n_iter, a_out, b_out);
     return hipGetLastError();
 }
 

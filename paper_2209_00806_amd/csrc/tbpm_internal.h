@@ -173,9 +173,13 @@ hipError_t launch_hay_spmv(bool cplx, const TileDesc *tiles, int32_t n_tiles, in
                            double *partials, hipStream_t st);
 hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s, const double *y,
                            const double *u, double *unext, const double *hs, double *partials, hipStream_t st);
+// Per-state sum of the tile partials and the scalar update of `mode`; above
+// 4 kWG tiles the sum runs in two stages through `fold`, which must hold
+// hay_fold_count(n_tiles) * s_pad doubles (0: unused).
+int32_t hay_fold_count(int32_t n_tiles);
 hipError_t launch_hay_reduce(const double *partials, int32_t n_tiles, int32_t s_pad, int32_t s_user, int32_t mode,
                              double thr, double *hs, int32_t *counter, int32_t n_iter, double *a_out, double *b_out,
-                             hipStream_t st);
+                             double *fold, hipStream_t st);
 hipError_t launch_hay_ldos(const double *a, const double *b, int32_t n_iter, int32_t n_states, const double *energies,
                            int64_t n_e, double eps, double *out, hipStream_t st);
 
