@@ -24,6 +24,9 @@
  *   - "device" pointers are HIP device memory on the current device;
  *     "host" pointers are ordinary host memory.  The caller owns every
  *     buffer it passes in; the library owns only what its handles hold.
+ *   - A handle lives on the device that was current when it was created;
+ *     every call that uses it must be made with that device current
+ *     (TBPM_E_ARG otherwise, before any work is enqueued).
  *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
  *     void*; NULL means the default stream).
  *   - Inputs are validated on the host before any device work.

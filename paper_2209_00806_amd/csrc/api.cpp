@@ -47,6 +47,15 @@ tbpm_status check_prop_args(int32_t n_states, int32_t n_steps, double dt, double
 
 }  // namespace
 
+// every call on a handle runs on the device the handle was created on
+tbpm_status check_device(const Engine &eng) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != eng.device) return fail(TBPM_E_ARG, "handle was created on another device");
+    return TBPM_OK;
+}
+
 extern "C" {
 
 const char *tbpm_version(void) { return "libtbpm 0.1 (gfx950)"; }
@@ -87,6 +96,7 @@ tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, 
     if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
     const int64_t nnz = H->csr.nnz(), n = H->csr.n;
     if ((nnz > 0 && !val) || !onsite) return fail(TBPM_E_ARG, "val and onsite must not be NULL");
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     hipStream_t st = (hipStream_t)stream;
     if (flags & TBPM_FLAG_DEVICE_PTRS) {
         hipError_t e = launch_convert_values(H->eng.mat, val, onsite, n, st);
@@ -248,6 +258,7 @@ tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, in
     tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
     if (st != TBPM_OK) return st;
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     const double f = resolve_rescale(H->csr, rescale);
     hipStream_t hs = (hipStream_t)stream;
     // psi(0) is the caller's state itself
@@ -308,6 +319,7 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
         ++log2s;
     }
     const int64_t n_rows = H->csr.n;
+    if (tbpm_status d = check_device(eng); d != TBPM_OK) return d;
     hipStream_t hs = (hipStream_t)stream;
     const size_t acc_doubles = 2 * (size_t)n_energies * n_rows * s_pad;
     hipError_t e = eng.qe_acc.ensure(sizeof(double) * acc_doubles);
@@ -406,6 +418,7 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     if (!(fermi_tol > 0.0 && fermi_tol < 1e-2)) return fail(TBPM_E_ARG, "fermi_tol must be in (0, 1e-2)");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
     const int64_t n = H->csr.n;
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     const double f = resolve_rescale(H->csr, rescale);
     const std::vector<double> a = fermi_cheb_coeffs(beta, mu, f, fermi_tol);
     if (a.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms (beta * rescale too large)");
@@ -475,6 +488,7 @@ tbpm_status tbpm_kpm_moments(tbpm_hamiltonian *H, const double *v_alpha, const d
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
     if ((int64_t)H->csr.n * 64 >= ((int64_t)1 << 31)) return fail(TBPM_E_ARG, "rows * 64 states must be below 2^31");
     const double f = resolve_rescale(H->csr, rescale);
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     hipStream_t hs = (hipStream_t)stream;
     try {
         tbpm_status st = upload_currents(H, v_alpha, v_beta, hs);
@@ -522,6 +536,7 @@ tbpm_status tbpm_haydock(tbpm_hamiltonian *H, const double *psi0, int32_t n_stat
     if (n_iter < 1 || n_iter > (1 << 24)) return fail(TBPM_E_ARG, "n_iter must be in [1, 2^24]");
     if ((int64_t)H->csr.n * 64 >= ((int64_t)1 << 31)) return fail(TBPM_E_ARG, "rows * 64 states must be below 2^31");
     const double thr = 1e-11 * H->csr.gershgorin;
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     try {
         return H->eng.haydock(psi0, n_states, n_iter, thr, a, b, flags, (hipStream_t)stream);
     } catch (const std::bad_alloc &) {
@@ -720,6 +735,7 @@ tbpm_status tbpm_autotune(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision 
                           double *best_ms, void *stream) {
     if (!H) return fail(TBPM_E_ARG, "H must not be NULL");
     if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     std::vector<double> f{resolve_rescale(H->csr, 0.0)};
     return autotune_impl(H->eng, f, n_states, prec == TBPM_FP32_MIXED, best, best_ms, (hipStream_t)stream);
 }
@@ -728,6 +744,7 @@ tbpm_status tbpm_batch_autotune(tbpm_batch *B, int32_t n_states, tbpm_precision 
                                 double *best_ms, void *stream) {
     if (!B) return fail(TBPM_E_ARG, "B must not be NULL");
     if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
+    if (tbpm_status d = check_device(B->eng); d != TBPM_OK) return d;
     std::vector<double> f;
     for (auto *h : B->members) f.push_back(resolve_rescale(h->csr, 0.0));
     return autotune_impl(B->eng, f, n_states, prec == TBPM_FP32_MIXED, best, best_ms, (hipStream_t)stream);
@@ -743,6 +760,7 @@ tbpm_status tbpm_stream_copy(const void *src, void *dst, size_t bytes, void *str
 tbpm_status tbpm_bench_pass(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec, int32_t n_launch,
                             void *stream) {
     if (!H || n_launch < 0) return fail(TBPM_E_ARG, "bad argument");
+    if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     return H->eng.bench_pass(n_states, prec == TBPM_FP32_MIXED, n_launch, (hipStream_t)stream);
 }
 
