@@ -222,6 +222,9 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n, const std::
     mat.n_rows = N;
     mat.n_slices = (int64_t)e.slice_off.size() - 1;
     mat.ell_size = S;
+    mat.max_width = 0;
+    for (int64_t q = 0; q < mat.n_slices; ++q)
+        mat.max_width = std::max<int32_t>(mat.max_width, (int32_t)((e.slice_off[q + 1] - e.slice_off[q]) / kSliceRows));
     mat.is_complex = cplx;
     const size_t vb = (cplx ? 2 : 1) * (size_t)std::max<int64_t>(S, 1);
     if (S >= (int64_t)UINT32_MAX) return fail(TBPM_E_ARG, "sliced-ELL size must be < 2^32 entries");
@@ -810,7 +813,8 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.ucol = (const int32_t *)st_ucol.ptr;
             pp.lidx = (const uint16_t *)st_lidx.ptr;
             pp.stage_units = stage_units;
-            hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, pp, s)
+            hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs,
+                                                  mat.max_width > kStagedWide, pp, s)
                                   : launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs,
                                                 pp, s);
             if (e != hipSuccess) return hip_fail(e, "launch pass");
@@ -1152,7 +1156,8 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     }
     for (int32_t i = 0; i < n_launch; ++i) {
         hipError_t e = last_staged
-                           ? launch_pass_staged(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, pp, stream)
+                           ? launch_pass_staged(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs,
+                                                mat.max_width > kStagedWide, pp, stream)
                            : launch_pass(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, last_vs, pp,
                                          stream);
         if (e != hipSuccess) return hip_fail(e, "launch pass");

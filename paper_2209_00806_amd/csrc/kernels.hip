@@ -189,14 +189,16 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
 // global memory once per tile instead of once per stored element that
 // references it), then evaluates the pass with every neighbour read from
 // LDS through the slot's precomputed local index.  Same arithmetic as
-// k_pass, so results are identical.
+// k_pass, so results are identical.  A row's stored elements are taken KG at
+// a time (indices and values loaded together, then the LDS reads): 4 for
+// narrow rows, 12 for wide ones, where fewer dependent rounds of loads per
+// row matter more than the padded slots of the last batch.
 // ---------------------------------------------------------------------------
-template <typename R, bool CH, int KIND, bool NT, int VS>
+template <typename R, bool CH, int KIND, bool NT, int VS, int KG>
 __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     extern __shared__ __align__(16) unsigned char stage_mem[];
     using V = VecT<R, VS>;
     using HV = typename HValT<R, CH>::T;
-    constexpr int KG = 4;
     constexpr bool X_IS_V = (KIND == kPassFirst);
     constexpr bool HAS_B2 = (KIND == kPassMid || KIND == kPassLast);
     constexpr bool CORR = (KIND == kPassLast || KIND == kPassLastNoB2);
@@ -594,25 +596,25 @@ hipError_t launch_pass_r(int kind, bool cplx, bool nt, int ne, const PassParams 
     return nt ? launch_pass_ne<R, false, true, VS>(kind, ne, p, st) : launch_pass_ne<R, false, false, VS>(kind, ne, p, st);
 }
 
-template <typename R, bool CH, bool NT, int VS>
+template <typename R, bool CH, bool NT, int VS, int KG>
 hipError_t launch_staged_t(int kind, const PassParams &p, hipStream_t st) {
     const dim3 grid(p.n_tiles), block(kWG);
     const size_t lds = (size_t)p.stage_units * sizeof(VecT<R, VS>);
     switch (kind) {
         case kPassFirst:
-            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassFirst, NT, VS>), grid, block, lds, st, p);
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassFirst, NT, VS, KG>), grid, block, lds, st, p);
             break;
         case kPassNoB2:
-            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassNoB2, NT, VS>), grid, block, lds, st, p);
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassNoB2, NT, VS, KG>), grid, block, lds, st, p);
             break;
         case kPassMid:
-            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassMid, NT, VS>), grid, block, lds, st, p);
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassMid, NT, VS, KG>), grid, block, lds, st, p);
             break;
         case kPassLast:
-            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLast, NT, VS>), grid, block, lds, st, p);
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLast, NT, VS, KG>), grid, block, lds, st, p);
             break;
         case kPassLastNoB2:
-            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLastNoB2, NT, VS>), grid, block, lds, st, p);
+            hipLaunchKernelGGL((k_pass_staged<R, CH, kPassLastNoB2, NT, VS, KG>), grid, block, lds, st, p);
             break;
         default:
             return hipErrorInvalidValue;
@@ -620,10 +622,17 @@ hipError_t launch_staged_t(int kind, const PassParams &p, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename R, int VS, int KG>
+hipError_t launch_staged_k(int kind, bool cplx, bool nt, const PassParams &p, hipStream_t st) {
+    if (cplx)
+        return nt ? launch_staged_t<R, true, true, VS, KG>(kind, p, st)
+                  : launch_staged_t<R, true, false, VS, KG>(kind, p, st);
+    return nt ? launch_staged_t<R, false, true, VS, KG>(kind, p, st) : launch_staged_t<R, false, false, VS, KG>(kind, p, st);
+}
+
 template <typename R, int VS>
-hipError_t launch_staged_r(int kind, bool cplx, bool nt, const PassParams &p, hipStream_t st) {
-    if (cplx) return nt ? launch_staged_t<R, true, true, VS>(kind, p, st) : launch_staged_t<R, true, false, VS>(kind, p, st);
-    return nt ? launch_staged_t<R, false, true, VS>(kind, p, st) : launch_staged_t<R, false, false, VS>(kind, p, st);
+hipError_t launch_staged_r(int kind, bool cplx, bool nt, bool wide, const PassParams &p, hipStream_t st) {
+    return wide ? launch_staged_k<R, VS, 12>(kind, cplx, nt, p, st) : launch_staged_k<R, VS, 4>(kind, cplx, nt, p, st);
 }
 
 }  // namespace
@@ -641,17 +650,17 @@ hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne,
     return launch_pass_r<double, 1>(kind, cplx, nontemporal, ne, p, st);
 }
 
-hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const PassParams &p,
-                              hipStream_t st) {
+hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, bool wide,
+                              const PassParams &p, hipStream_t st) {
     if (p.n_tiles <= 0) return hipSuccess;
     if (fp32) {
-        if (vs == 4) return launch_staged_r<float, 4>(kind, cplx, nontemporal, p, st);
-        if (vs == 2) return launch_staged_r<float, 2>(kind, cplx, nontemporal, p, st);
-        return launch_staged_r<float, 1>(kind, cplx, nontemporal, p, st);
+        if (vs == 4) return launch_staged_r<float, 4>(kind, cplx, nontemporal, wide, p, st);
+        if (vs == 2) return launch_staged_r<float, 2>(kind, cplx, nontemporal, wide, p, st);
+        return launch_staged_r<float, 1>(kind, cplx, nontemporal, wide, p, st);
     }
-    if (vs == 4) return launch_staged_r<double, 4>(kind, cplx, nontemporal, p, st);
-    if (vs == 2) return launch_staged_r<double, 2>(kind, cplx, nontemporal, p, st);
-    return launch_staged_r<double, 1>(kind, cplx, nontemporal, p, st);
+    if (vs == 4) return launch_staged_r<double, 4>(kind, cplx, nontemporal, wide, p, st);
+    if (vs == 2) return launch_staged_r<double, 2>(kind, cplx, nontemporal, wide, p, st);
+    return launch_staged_r<double, 1>(kind, cplx, nontemporal, wide, p, st);
 }
 
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st) {

@@ -17,6 +17,7 @@ struct DevMatrix {
     int64_t n_rows = 0;      // total rows (sum over batch members)
     int64_t n_slices = 0;
     int64_t ell_size = 0;    // slots incl. padding
+    int32_t max_width = 0;   // stored elements per row of the widest slice
     bool is_complex = false;
     uint32_t *slice_off = nullptr; // [n_slices + 1]
     int32_t *col = nullptr;        // [ell_size]
@@ -41,8 +42,11 @@ struct HostEll {
 // vs = states per thread (1, 2 or 4; at most the padded state count)
 hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne, int vs, const PassParams &p,
                        hipStream_t st);
-hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, const PassParams &p,
-                              hipStream_t st);
+// wide: the matrix has slices wider than kStagedWide stored elements per row
+// (the staged pass then walks a row's elements in batches of 12, else of 4)
+constexpr int32_t kStagedWide = 8;
+hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, bool wide,
+                              const PassParams &p, hipStream_t st);
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st);
 hipError_t launch_reduce(int n_inst, int s_pad, const ReduceParams &p, hipStream_t st);
 hipError_t launch_dos(const double *corr, int32_t n_steps, int32_t n_states, double dt, int window,

@@ -334,8 +334,8 @@ def test_batched_async_and_plain_launches():
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
 
 
-@pytest.mark.parametrize("case", ["tbg_s16_fp64", "tbg_s16_fp32", "graphene_s64_fp64", "graphene_s1_fp32",
-                                  "batch_s4_fp64"])
+@pytest.mark.parametrize("case", ["tbg_s16_fp64", "tbg_s16_fp32", "tbg_complex_s3_fp64", "graphene_s64_fp64",
+                                  "graphene_s1_fp32", "batch_s4_fp64"])
 def test_lds_staged_launch_shape(case):
     """The LDS-staged pass (every tile copies the rows of x it reads into LDS
     first) against the oracle, on wide irregular rows, the largest state count,
@@ -356,7 +356,14 @@ def test_lds_staged_launch_shape(case):
             ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 48, dt, f)
             assert _rel(c.cpu().numpy(), ref) < 1e-10
         return
-    if case.startswith("tbg"):
+    if case.startswith("tbg_complex"):
+        # wide rows with complex elements: a gauge transform of the bilayer,
+        # H_ij e^{i (theta_i - theta_j)}, stays Hermitian; 3 states padded to 4
+        lat, S = inputs.twisted_bilayer(16, 16, angle_deg=3.0), 3
+        th = rng.uniform(0, 2 * np.pi, lat.n_orb)
+        rows = np.repeat(np.arange(lat.n_orb), np.diff(lat.row_ptr))
+        lat.val = lat.val * np.exp(1j * (th[rows] - th[lat.col]))
+    elif case.startswith("tbg"):
         lat, S = inputs.twisted_bilayer(32, 32, angle_deg=1.05), 16
     elif "s64" in case:
         lat, S = inputs.graphene(12, 10, onsite=inputs.anderson(rng, 240, 1.0)), 64
@@ -368,7 +375,7 @@ def test_lds_staged_launch_shape(case):
     nt = 96
     ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
     H = tbpm.Hamiltonian.from_lattice(lat)
-    H.set_launch_config(2, 1, 1, 1, staged=1, vec=min(4, S))
+    H.set_launch_config(2, 1, 1, 1, staged=1, vec=2 if S == 3 else min(4, S))
     got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec).cpu().numpy()
     H.set_launch_config(2, 1, 1, 1, staged=0)
     plain = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec).cpu().numpy()
@@ -418,7 +425,14 @@ def test_fused_two_order_launch_shape(case):
             ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 48, dt, f)
             assert _rel(c.cpu().numpy(), ref) < 1e-10
         return
-    if case.startswith("tbg"):
+    if case.startswith("tbg_complex"):
+        # wide rows with complex elements: a gauge transform of the bilayer,
+        # H_ij e^{i (theta_i - theta_j)}, stays Hermitian; 3 states padded to 4
+        lat, S = inputs.twisted_bilayer(16, 16, angle_deg=3.0), 3
+        th = rng.uniform(0, 2 * np.pi, lat.n_orb)
+        rows = np.repeat(np.arange(lat.n_orb), np.diff(lat.row_ptr))
+        lat.val = lat.val * np.exp(1j * (th[rows] - th[lat.col]))
+    elif case.startswith("tbg"):
         lat, S = inputs.twisted_bilayer(32, 32, angle_deg=1.05), 16
     elif "s64" in case:
         lat, S = inputs.graphene(12, 10, onsite=inputs.anderson(rng, 240, 1.0)), 64
