@@ -458,9 +458,12 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *   xcd_remap   1: give each of the 8 XCDs a contiguous range of tiles
  *   nontemporal 1: stream the read-once vectors with non-temporal hints
  *   unroll      elements each thread handles at once (1 or 2)
- *   staged      1: each workgroup first copies the distinct rows of x that its
- *               tile reads into LDS and gathers from there (pays off for rows
- *               with many stored elements); wg_chunks and unroll are then unused
+ *   staged      1 .. 6: each workgroup first copies the distinct rows of x
+ *               that its tile reads into LDS and gathers from there (pays off
+ *               for rows with many stored elements); the value t is the LDS
+ *               tier, as for fused below: a tile's staged rows use at most
+ *               1/(t+2) of a CU's 160 KiB.  wg_chunks and unroll are then
+ *               unused.  0: gather from global memory
  *   vec         states of a row each thread holds (1, 2 or 4; capped by the
  *               padded state count)
  *   fused       1 .. 6: evaluate two Clenshaw orders per launch: each tile

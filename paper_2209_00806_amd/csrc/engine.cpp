@@ -318,12 +318,13 @@ tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks, int32_t vs) {
 // ---------------------------------------------------------------------------
 // staged tiles: R consecutive rows of one member; the rows of x a tile reads
 // are its own rows plus a sorted list of external rows.  R is the largest
-// power of two (<= 256) whose biggest staged set fits the LDS budget.
+// power of two (<= 256) whose biggest staged set fits the LDS budget of the
+// tier (the fused shape's tiers: 1/(tier+2) of a CU's 160 KiB).
 // ---------------------------------------------------------------------------
-tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes) {
-    const int32_t key = unit_bytes * 64 + log2u;
+tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier) {
+    const int32_t key = (unit_bytes * 64 + log2u) * 8 + tier;
     if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) return TBPM_OK;
-    const size_t budget = 48 * 1024;
+    const size_t budget = fused_lds_budget(tier);
     const int64_t SR = kSliceRows;
     std::vector<int32_t> ext;
     auto collect = [&](int64_t r0, int64_t rows) {
@@ -541,7 +542,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     bool staged = cfg.staged != 0 && !fused;
     tbpm_status st = TBPM_OK;
     if (fused && build_fused_tiles(s_pad, log2u, unit_bytes, cfg.fused) != TBPM_OK) fused = false;  // fall back
-    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes) != TBPM_OK) staged = false;
+    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes, cfg.staged) != TBPM_OK) staged = false;
     if (!staged && !fused) st = build_tiles(s_pad, chunks, vs);
     if (st != TBPM_OK) return st;
     const int32_t n_tiles = (int32_t)h_tiles.size();
@@ -841,7 +842,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             key.remap = cfg.xcd_remap;
             key.nt = cfg.nontemporal;
             key.unroll = cfg.unroll;
-            key.staged = staged ? 1 : 0;
+            key.staged = staged ? cfg.staged : 0;
             key.vec = vs;
             key.fused = fused ? cfg.fused : 0;
             key.n_tiles = n_tiles;

@@ -201,7 +201,7 @@ struct Engine {
     tbpm_status build_tiles(int32_t s_pad, int32_t chunks, int32_t vs);
     // staged tiles for s_pad states of unit_bytes per VS states (log2u units per row);
     // TBPM_E_ARG if no tile size fits the LDS budget
-    tbpm_status build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes);
+    tbpm_status build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier);
     // two-hop tiles for the fused launch shape with the LDS budget of a tier
     // (tiles_chunks = -R, tiles_unit = 2^24 + 16 * row bytes + tier)
     tbpm_status build_fused_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier);

@@ -44,7 +44,8 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
-    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal);
+    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal),
+    // and for wide rows vec x LDS tier 2-4 x remap;
     // fused shapes (sparse rows): LDS tier x vec, XCD remap and non-temporal streams
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
@@ -60,6 +61,11 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
                         if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec, 0});
         for (int remap = 0; remap <= 1; ++remap)
             for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec, 0});
+        // other LDS tiers of the staged shape for wide rows, where the halo
+        // sets the trade between tile size and resident workgroups
+        if (wide_rows)
+            for (int tier = 2; tier <= 4; ++tier)
+                for (int remap = 0; remap <= 1; ++remap) cands.push_back(tbpm_launch_config{2, remap, 0, 1, tier, vec, 0});
     }
     // fused shapes, tier outer (the tile tables depend on the tier only, so
     // the vec variants of a tier share them); the two-hop halo grows with

@@ -389,6 +389,27 @@ def test_lds_staged_launch_shape(case):
         assert _rel(got, plain) < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_staged_lds_tiers(precision):
+    """Every LDS tier of the staged shape (smaller tiles, more resident
+    workgroups) gives the plain pass's result on wide irregular rows."""
+    print(f"case staged tiers {precision}", flush=True)
+    rng = np.random.default_rng(43)
+    lat = inputs.twisted_bilayer(24, 24, angle_deg=2.0)
+    S = 8
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    dt = math.pi / f
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, staged=0, precision=precision)
+    plain = tbpm.propagate(H, _dev(psi0), 24, dt, f, precision=precision).cpu().numpy()
+    for tier in (1, 2, 3, 4, 6):
+        for vec in (2, 4):
+            H.set_launch_config(2, tier % 2, 0, 1, staged=tier, vec=vec, precision=precision)
+            got = tbpm.propagate(H, _dev(psi0), 24, dt, f, precision=precision).cpu().numpy()
+            assert _rel(got, plain) < (1e-13 if precision == "fp64" else 1e-6), (tier, vec)
+
+
 def _dt_for_terms(f, parity):
     """A time step whose Bessel series has M terms of the given parity (M >= 5),
     so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
