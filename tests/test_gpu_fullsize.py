@@ -202,3 +202,26 @@ def test_kpm_moments_full_size_short():
     got = tbpm.kpm_moments(H, jx, jx, _dev(psi0), 16, f).cpu().numpy()
     ref = oracle.kpm_moments(lat.row_ptr, lat.col, lat.val, lat.onsite, jx, jx, psi0, 16, f)
     assert _rel(got, ref) < 1e-11
+
+
+def test_twisted_bilayer_full_size_sampled():
+    """The 4,194,304-orbital twisted bilayer of the bench leg, 16 states, in
+    the LDS-staged shapes the bench's tuner picks (FP32: tier 2, 4 states per
+    thread; FP64: tier 1, 4 states per thread; rows walked 12 elements at a
+    time): a 3-step prefix of two sampled states against the oracle.  FP64 to
+    1e-10; FP32-mixed to 1e-5 of max |C| (storage rounding of about 6e-8 per
+    pass over 51 passes)."""
+    print("case twisted bilayer 4M", flush=True)
+    lat, psi0 = inputs.workload_twisted_bilayer(1024, 16)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite)
+    dt = math.pi / f
+    nt = 4
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, [0, 15]].copy(), nt, dt, f)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    p = _dev(psi0)
+    for prec, tier, bar in (("fp64", 1, 1e-10), ("fp32", 2, 1e-5)):
+        H.set_launch_config(2, 0, 0, 1, staged=tier, vec=4, precision=prec)
+        corr, n2 = tbpm.propagate(H, p, nt, dt, f, precision=prec, return_norm=True)
+        corr = corr.cpu().numpy()
+        assert _rel(corr[:, [0, 15]], ref) < bar, prec
+        assert np.max(np.abs(n2.cpu().numpy() - 1)) < (1e-10 if prec == "fp64" else 1e-5), prec
