@@ -257,22 +257,28 @@ def test_gershgorin_default_rescale_and_set_values():
 
 
 def test_config2_full_size_sampled_states():
-    """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, FP64, the
-    bench launch shape: a prefix of steps for two sampled states against the
-    oracle, and at every step the norm and C_0 = ||psi0||^2."""
+    """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, FP64, in
+    the default launch shape and in the shape the bench's tuner picks (two
+    orders per launch, LDS tier 2, 2 states per thread): a prefix of steps for
+    two sampled states against the oracle, and at every step the norm and
+    C_0 = ||psi0||^2."""
     print("case config2 full size", flush=True)
     lat, psi0 = inputs.workload_disordered_graphene(1024, 8)
     f = 9.0
     dt = math.pi / f
     H = tbpm.Hamiltonian.from_lattice(lat)
     nt = 24
-    corr, n2 = tbpm.propagate(H, _dev(psi0), nt, dt, f, return_norm=True)
-    corr = corr.cpu().numpy()
-    n2 = n2.cpu().numpy()
-    assert np.max(np.abs(n2 - 1)) < 1e-10
-    for s in (0, 5):
-        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), nt, dt, f)
-        assert _rel(corr[:, s], ref[:, 0]) < 1e-10
+    refs = {s: oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), nt, dt, f)[0]
+            for s in (0, 5)}
+    for shape in ("default", "bench"):
+        if shape == "bench":
+            H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=2)
+        corr, n2 = tbpm.propagate(H, _dev(psi0), nt, dt, f, return_norm=True)
+        corr = corr.cpu().numpy()
+        n2 = n2.cpu().numpy()
+        assert np.max(np.abs(n2 - 1)) < 1e-10, shape
+        for s, ref in refs.items():
+            assert _rel(corr[:, s], ref[:, 0]) < 1e-10, (shape, s)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
