@@ -26,8 +26,10 @@ def _rel(a, b):
 def test_differentiable_workload_full_size_fd():
     """512x512 graphene with 786,432 bond parameters and 524,288 on-site
     energies, 4 states; a 64-step prefix keeps the finite differences cheap.
-    Central FD of the GPU forward on 32 seeded bonds and along one random
-    direction of all bonds, and the shift identity for the on-site gradient."""
+    The gradients in the default shape and in the bench's tuned fused shape
+    agree; central FD of the GPU forward on 32 seeded bonds and along one
+    random direction of all bonds, and the shift identity for the on-site
+    gradient."""
     print("case differentiable 512x512 FD", flush=True)
     from paper_2209_00806_amd import autograd as ag
 
@@ -58,6 +60,17 @@ def test_differentiable_workload_full_size_fd():
     ge = e_p.grad.detach().clone()
     gmax = float(g.abs().max())
     assert gmax > 0
+    # the shape the bench's tuner picks (two orders per launch in the forward,
+    # the replay and the adjoint; LDS tier 2, 2 states per thread): the same
+    # loss and gradients; the finite differences below then run in it
+    H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=2)
+    t_f = t_p.detach().clone().requires_grad_(True)
+    e_f = torch.zeros_like(e_p).requires_grad_(True)
+    L_f = loss(t_f, e_f)
+    L_f.backward()
+    assert abs(L_f.item() - L.item()) < 1e-10 * abs(L.item())
+    assert float((t_f.grad - g).abs().max()) < 1e-10 * gmax
+    assert float((e_f.grad - ge).abs().max()) < 1e-10 * float(ge.abs().max())
     rng = np.random.default_rng(77)
     h = 1e-4
     with torch.no_grad():
