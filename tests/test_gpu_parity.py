@@ -415,6 +415,14 @@ def test_staged_lds_tiers(precision):
             H.set_launch_config(2, tier % 2, 0, 1, staged=tier, vec=vec, precision=precision)
             got = tbpm.propagate(H, _dev(psi0), 24, dt, f, precision=precision).cpu().numpy()
             assert _rel(got, plain) < (1e-13 if precision == "fp64" else 1e-6), (tier, vec)
+    # out-of-range shapes are rejected on the host, the handle keeps its shape
+    before = H.launch_config(precision)
+    for bad in (dict(staged=7), dict(staged=-1), dict(fused=7), dict(vec=3), dict(unroll=3),
+                dict(wg_chunks=3), dict(xcd_remap=2)):
+        with pytest.raises(tbpm.TBPMError):
+            H.set_launch_config(**dict(dict(wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1), **bad),
+                                precision=precision)
+    assert H.launch_config(precision) == before
 
 
 def _dt_for_terms(f, parity):
