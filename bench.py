@@ -678,7 +678,7 @@ def main():
         log(f"cpu oracle: {cpu['value']:.3e} nnz-updates/s on {threads} threads ({tcpu:.1f}s)")
 
     rec = {
-        "metric": "TBPM propagation nnz-updates/s (FP64), with HBM GB/s vs peak and FP32-mixed vs FP64",
+        "metric": "TBPM propagation nnz-updates/s + HBM GB/s vs peak; FP32/batched vs FP64",
         "value": value,
         "unit": "nnz-updates/s",
         "n_gpus": 1,
