@@ -50,6 +50,13 @@ def kernel_hash(sources=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
+def nnz_updates(n_orb: int, nnz: int, S: int, M: int, nt: int) -> int:
+    """Work of a run in the metric's unit: one stored element (off-diagonal or
+    on-site) x one state x one sparse pass, over M-1 passes per time step and
+    nt-1 time steps."""
+    return (nnz + n_orb) * S * (M - 1) * (nt - 1)
+
+
 def pass_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
     """Algorithmic HBM bytes of one Clenshaw pass: 4 state streams (read the
     gathered b_{j+1}, b_{j+2} and psi once, write b_j), the sliced-ELL matrix
@@ -360,7 +367,7 @@ def bench_tbg(args, log):
     del psi0_np
     log(f"twisted bilayer built: N={lat.n_orb}, nnz={lat.nnz} ({lat.nnz / lat.n_orb:.1f}/row), "
         f"f={f:.3f} eV in {time.time() - t0:.1f}s")
-    updates = (lat.nnz + lat.n_orb) * 16 * (M - 1) * (nt - 1)
+    updates = nnz_updates(lat.n_orb, lat.nnz, 16, M, nt)
     stream = torch.cuda.current_stream()
     out = {"n_orb": lat.n_orb, "nnz_offdiag": lat.nnz, "nnz_per_row": round(lat.nnz / lat.n_orb, 2),
            "max_row": H.info()["max_row"], "n_states": 16, "n_steps": nt, "rescale_eV": f}
@@ -555,7 +562,7 @@ def main():
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms_per_step = ev0.elapsed_time(ev1) / max(args.steps, 1)
-    updates = (lat.nnz + lat.n_orb) * S * n_pass * (nt - 1)
+    updates = nnz_updates(lat.n_orb, lat.nnz, S, n_pass + 1, nt)
     value = updates / (ms_per_step / 1e3)
     fused64 = H.launch_config("fp64").get("fused", 0) > 0
     run_bytes = step_bytes(M, lat.n_orb, lat.nnz, S, 16, 8) * (nt - 1)

@@ -1,0 +1,50 @@
+"""CPU checks of the byte and work model behind the benchmark's roofline
+figures, against hand-computed values for the benchmark workloads (the
+disordered 1024x1024 graphene: N = 2,097,152, 6,291,456 stored off-diagonal
+elements, S = 8, M = 18 terms at z = pi; the twisted bilayer: N = 4,194,304,
+80,955,560 elements, S = 16), and that the committed HBM-traffic records
+still match the kernel sources they were taken for."""
+import json
+import os
+
+import bench
+
+N, NNZ, S = 2_097_152, 6_291_456, 8
+VEC64 = 16 * N * S                      # one FP64 state block: 268,435,456 B
+MAT64 = NNZ * (4 + 8) + N * 8           # int32 columns, FP64 values, on-site: 92,274,688 B
+
+
+def test_pass_bytes_fp64_and_fp32():
+    assert bench.pass_bytes(N, NNZ, S, 16, 8) == 4 * VEC64 + MAT64 == 1_166_016_512
+    assert bench.pass_bytes(N, NNZ, S, 8, 4) == 4 * (VEC64 // 2) + NNZ * 8 + N * 4 == 595_591_168
+
+
+def test_pair_and_step_bytes():
+    assert bench.pair_bytes(N, NNZ, S, 16, 8) == 5 * VEC64 + MAT64 == 1_434_451_968
+    # 17 passes plus the FP64 phi0 stream of the correlation
+    assert bench.step_bytes(18, N, NNZ, S, 16, 8) == 17 * 1_166_016_512 + VEC64
+    # fused schedule: FIRST+NOB2 (psi in, two vectors out), 7 middle pairs, LAST alone, phi0
+    fused = (3 * VEC64 + MAT64) + 7 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(18, True, N, NNZ, S, 16, 8) == fused == 12_373_196_800
+    assert bench.schedule_bytes(18, False, N, NNZ, S, 16, 8) == bench.step_bytes(18, N, NNZ, S, 16, 8)
+    # an odd number of middle orders leaves one single middle pass
+    odd = (3 * VEC64 + MAT64) + 6 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(17, True, N, NNZ, S, 16, 8) == odd
+
+
+def test_haydock_and_wide_row_bytes():
+    assert bench.hay_iter_bytes(N, NNZ, S, 16, 8) == 6 * VEC64 + MAT64
+    assert bench.pass_bytes(4_194_304, 80_955_560, 16, 8, 4) == 2_811_905_344
+
+
+def test_nnz_update_count_of_the_headline_run():
+    # (nnz + N) * S * (M - 1) * (N_t - 1) for 2048 samples
+    assert bench.nnz_updates(N, NNZ, S, 18, 2048) == 8_388_608 * 8 * 17 * 2047 == 2_335_321_358_336
+
+
+def test_traffic_records_match_their_sources():
+    for path, sources in ((bench.TRAFFIC_FILE, bench.KERNEL_SOURCES), (bench.PAIR_TRAFFIC_FILE, bench.PAIR_SOURCES)):
+        with open(path) as f:
+            rec = json.load(f)
+        assert rec["kernel_hash"] == bench.kernel_hash(sources), os.path.basename(path)
+        assert rec["bytes_per_launch"] > 0
