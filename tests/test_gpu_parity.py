@@ -425,6 +425,32 @@ def test_staged_lds_tiers(precision):
     assert H.launch_config(precision) == before
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_staged_tiers_on_a_mixed_width_batch(precision):
+    """A batch whose widest member has wide rows (so every member's rows are
+    walked 12 elements at a time, the narrow ones with padded batches) in the
+    staged shape at LDS tiers 1-4, against the plain shape and the oracle."""
+    print(f"case staged tiers batch {precision}", flush=True)
+    rng = np.random.default_rng(47)
+    lats = [inputs.graphene(13, 11, onsite=inputs.anderson(rng, 286, 1.0)), inputs.twisted_bilayer(14, 14, angle_deg=3.5),
+            inputs.square(9, 23, pbc=False)]
+    psis = [inputs.random_phase_states(rng, l.n_orb, 4) for l in lats]
+    fs = [oracle.gershgorin(l.row_ptr, l.val, l.onsite) * 1.02 for l in lats]
+    dts = [math.pi / f for f in fs]
+    B = tbpm.Batch([tbpm.Hamiltonian.from_lattice(l) for l in lats])
+    nt = 32
+    B.set_launch_config(2, 1, 1, 1, staged=0, precision=precision)
+    plain = [c.cpu().numpy() for c in B.propagate([_dev(p) for p in psis], nt, dts, fs, precision=precision)]
+    for l, p, f, dt, c in zip(lats, psis, fs, dts, plain):
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, nt, dt, f)
+        assert _rel(c, ref) < (1e-10 if precision == "fp64" else 1e-5)
+    for tier in (1, 2, 3, 4):
+        B.set_launch_config(2, tier % 2, 0, 1, staged=tier, vec=4, precision=precision)
+        got = B.propagate([_dev(p) for p in psis], nt, dts, fs, precision=precision)
+        for g, c in zip(got, plain):
+            assert _rel(g.cpu().numpy(), c) < (1e-13 if precision == "fp64" else 1e-6), tier
+
+
 def _dt_for_terms(f, parity):
     """A time step whose Bessel series has M terms of the given parity (M >= 5),
     so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
