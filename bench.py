@@ -38,8 +38,11 @@ PAIR_SOURCES = ["paper_2209_00806_amd/csrc/fused.hip", "paper_2209_00806_amd/csr
 PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pair_mid_graphene1024_s8_fp64.json")
 
 
+T_START = time.time()
+
+
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash(sources=KERNEL_SOURCES) -> str:

@@ -322,8 +322,13 @@ tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks, int32_t vs) {
 // tier (the fused shape's tiers: 1/(tier+2) of a CU's 160 KiB).
 // ---------------------------------------------------------------------------
 tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier) {
-    const int32_t key = (unit_bytes * 64 + log2u) * 8 + tier;
-    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) return TBPM_OK;
+    // the tables depend on the bytes of a row and the tier only (not on how a
+    // row is split into units)
+    const int32_t key = (unit_bytes << log2u) * 8 + tier;
+    if (tiles_s == s_pad && tiles_chunks < 0 && tiles_unit == key && tiles.ptr) {
+        stage_units = (int32_t)(stage_max_rows << log2u);
+        return TBPM_OK;
+    }
     const size_t budget = fused_lds_budget(tier);
     const int64_t SR = kSliceRows;
     std::vector<int32_t> ext;
@@ -402,6 +407,7 @@ tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t uni
                 "upload staged rows");
     TRY_HIP(hipMemcpy(st_lidx.ptr, lidx.data(), sizeof(uint16_t) * lidx.size(), hipMemcpyHostToDevice),
             "upload staged indices");
+    stage_max_rows = max_stage;
     stage_units = (int32_t)(max_stage << log2u);
     tiles_s = s_pad;
     tiles_chunks = -(int32_t)R;

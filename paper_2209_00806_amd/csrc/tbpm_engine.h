@@ -88,6 +88,7 @@ struct Engine {
     // staged tiles: external-row lists and per-slot local indices
     DevBuf st_uoff, st_ucol, st_lidx;
     int32_t stage_units = 0;
+    size_t stage_max_rows = 0;  // most staged rows of a tile (units = rows << log2u)
     // two-hop tiles of the fused launch shape, and its two extra work vectors
     DevBuf fu_n1, fu_hoff, fu_hw, fu_hidx, bc, bd;
     int32_t fu_lds_units = 0;

@@ -44,32 +44,35 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
-    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes: vec x (remap, non-temporal),
-    // and for wide rows vec x LDS tier 2-4 x remap;
-    // fused shapes (sparse rows): LDS tier x vec, XCD remap and non-temporal streams
+    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes, tier outer: LDS tier 1 x vec x
+    // (remap, non-temporal), and for wide rows tiers 2-4 x vec x remap; fused shapes (sparse rows): LDS tier x vec,
+    // XCD remap and non-temporal streams.  Staged and fused tile tables depend on the row bytes and the tier only,
+    // so the vec variants of a tier share them when they are tried one after the other.
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
     while (s_pad < n_states) s_pad <<= 1;
     const int chunk_list[] = {1, 2, 4, 8, 16};
     const bool wide_rows = eng.mat.n_rows > 0 && (double)eng.mat.ell_size > 8.0 * (double)eng.mat.n_rows;
+    auto vec_ok = [&](int vec) { return !(fp32 && vec == 1 && s_pad > 1); };  // 8-byte units never beat 16
     for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
-        if (fp32 && vec == 1 && s_pad > 1) continue;  // 8-byte units are never better than 16
+        if (!vec_ok(vec)) continue;
         for (int ch : chunk_list)
             for (int un = 1; un <= 2; ++un)
                 for (int remap = 0; remap <= 1; ++remap)
                     for (int nt = 0; nt <= 1; ++nt)
                         if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec, 0});
-        for (int remap = 0; remap <= 1; ++remap)
-            for (int nt = 0; nt <= 1; ++nt) cands.push_back(tbpm_launch_config{2, remap, nt, 1, 1, vec, 0});
-        // other LDS tiers of the staged shape for wide rows, where the halo
-        // sets the trade between tile size and resident workgroups
-        if (wide_rows)
-            for (int tier = 2; tier <= 4; ++tier)
-                for (int remap = 0; remap <= 1; ++remap) cands.push_back(tbpm_launch_config{2, remap, 0, 1, tier, vec, 0});
     }
-    // fused shapes, tier outer (the tile tables depend on the tier only, so
-    // the vec variants of a tier share them); the two-hop halo grows with
-    // the square of the row width, so fusing pays off only for sparse rows
+    // the staged shape; for wide rows also the smaller LDS tiers, where the
+    // halo sets the trade between tile size and resident workgroups
+    for (int tier = 1; tier <= (wide_rows ? 4 : 1); ++tier)
+        for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
+            if (!vec_ok(vec)) continue;
+            for (int remap = 0; remap <= 1; ++remap)
+                for (int nt = 0; nt <= (tier == 1 ? 1 : 0); ++nt)
+                    cands.push_back(tbpm_launch_config{2, remap, nt, 1, tier, vec, 0});
+        }
+    // fused shapes, tier outer; the two-hop halo grows with the square of
+    // the row width, so fusing pays off only for sparse rows
     if (!wide_rows)
         for (int tier = 1; tier <= kFusedTiers; ++tier)
             for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2)
