@@ -451,6 +451,33 @@ def test_staged_tiers_on_a_mixed_width_batch(precision):
             assert _rel(g.cpu().numpy(), c) < (1e-13 if precision == "fp64" else 1e-6), tier
 
 
+@pytest.mark.parametrize("fused", [0, 2])
+def test_shortest_runs_and_series(fused):
+    """Degenerate lengths in the plain and the fused shape: 1 sample (C_0 =
+    ||psi0||^2, no propagation) and 2 samples, and the shortest series, M = 3
+    (the fused shape falls back to one order per launch) and M = 4 (one pair
+    and the last order), against the oracle."""
+    print(f"case shortest runs fused={fused}", flush=True)
+    rng = np.random.default_rng(53)
+    lat = inputs.graphene(9, 7, onsite=inputs.anderson(rng, 126, 1.0))
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, 3)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=fused)
+    dt = math.pi / f
+    for nt in (1, 2):
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+        got = tbpm.propagate(H, _dev(psi0), nt, dt, f).cpu().numpy()
+        assert got.shape == (nt, 3)
+        assert _rel(got, ref) < 1e-12, nt
+    assert np.allclose(got[0], np.sum(np.abs(psi0) ** 2, axis=0), rtol=0, atol=1e-14)
+    for M in (3, 4):
+        z = next(z for z in np.geomspace(1e-6, 1.0, 400) if tbpm.num_terms(z) == M)
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 24, z / f, f)
+        got = tbpm.propagate(H, _dev(psi0), 24, z / f, f).cpu().numpy()
+        assert _rel(got, ref) < 1e-12, M
+
+
 def _dt_for_terms(f, parity):
     """A time step whose Bessel series has M terms of the given parity (M >= 5),
     so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
