@@ -92,6 +92,10 @@ def test_haydock_graph_direct_and_odd_lengths_agree():
     a3, b3 = tbpm.haydock(H, st, 16)
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
     assert torch.equal(a1[:16], a3) and torch.equal(b1[:16], b3)
+    # the shortest runs: one and two iterations (direct launches only)
+    for n in (1, 2):
+        an, bn = tbpm.haydock(H, st, n)
+        assert an.shape == (n, 4) and torch.equal(a1[:n], an) and torch.equal(b1[:n], bn)
 
 
 def test_haydock_chain_and_breakdown():
