@@ -271,7 +271,7 @@ void Engine::release() {
                       &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
                       &qe_acc,   &qe_part,  &qe_norm2, &ac_ja,     &ac_jb,     &ac_csr,       &ac_zero,
                       &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s,
-                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts};
+                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &blk_psi,   &blk_corr,     &blk_norm};
     for (DevBuf *b : bufs) b->release();
     release_blas();
     staging.release();
@@ -509,6 +509,47 @@ int32_t cheb_coeffs(double z, double tol, std::vector<cd> &c) {
     static const cd mi[4] = {cd(1, 0), cd(0, -1), cd(-1, 0), cd(0, 1)};  // (-i)^m
     for (int32_t m = 0; m < M; ++m) c[m] = (m == 0 ? 1.0 : 2.0) * J[m] * mi[m & 3];
     return M;
+}
+
+tbpm_status Engine::run_states(const RunArgs &a) {
+    const tbpm_launch_config &c = cfgs[a.fp32 ? 1 : 0];
+    const int32_t esize = a.fp32 ? 8 : 16;  // bytes per state element of the recursion
+    const int32_t blk = kStagedRowBytes / esize;
+    int32_t s_pad = 1;
+    while (s_pad < a.s_user) s_pad <<= 1;
+    const bool plain = a.ckpt == nullptr && a.ckpt_every == 0 && a.n_snap == 0 && a.n_qe == 0 && a.jc_val == nullptr;
+    if (!(plain && n_inst() == 1 && c.staged != 0 && c.fused == 0 && s_pad > blk)) return run(a);
+    const int64_t n = inst_row0[1] - inst_row0[0];
+    const bool want_norm = a.norm2 && a.norm2[0];
+    TRY_HIP(blk_psi.ensure(sizeof(double) * 2 * (size_t)n * blk), "alloc state block");
+    TRY_HIP(blk_corr.ensure(sizeof(double) * 2 * (size_t)a.n_steps * blk), "alloc block correlation");
+    if (want_norm) TRY_HIP(blk_norm.ensure(sizeof(double) * (size_t)a.n_steps * blk), "alloc block norms");
+    const size_t row_in = sizeof(double) * 2 * (size_t)a.s_user;  // bytes per row of the caller's arrays
+    for (int32_t s0 = 0; s0 < a.s_user; s0 += blk) {
+        const int32_t nb = std::min(blk, a.s_user - s0);
+        const size_t w = sizeof(double) * 2 * (size_t)nb;
+        TRY_HIP(hipMemcpy2DAsync(blk_psi.ptr, w, a.psi0[0] + 2 * (size_t)s0, row_in, w, (size_t)n,
+                                 hipMemcpyDeviceToDevice, a.stream),
+                "gather state block");
+        const double *p0 = (const double *)blk_psi.ptr;
+        double *c0 = (double *)blk_corr.ptr;
+        double *n0 = want_norm ? (double *)blk_norm.ptr : nullptr;
+        RunArgs b = a;
+        b.psi0 = &p0;
+        b.s_user = nb;
+        b.corr = &c0;
+        b.norm2 = want_norm ? &n0 : nullptr;
+        const tbpm_status st = run(b);
+        if (st != TBPM_OK) return st;
+        TRY_HIP(hipMemcpy2DAsync(a.corr[0] + 2 * (size_t)s0, row_in, c0, w, w, (size_t)a.n_steps,
+                                 hipMemcpyDeviceToDevice, a.stream),
+                "scatter block correlation");
+        if (want_norm)
+            TRY_HIP(hipMemcpy2DAsync(a.norm2[0] + s0, sizeof(double) * (size_t)a.s_user, n0, sizeof(double) * nb,
+                                     sizeof(double) * nb, (size_t)a.n_steps, hipMemcpyDeviceToDevice, a.stream),
+                    "scatter block norms");
+    }
+    return TBPM_OK;
 }
 
 tbpm_status Engine::run(const RunArgs &a) {

@@ -111,6 +111,9 @@ struct Engine {
     // kernel-polynomial moments: the L store, a block of R, Chebyshev vectors,
     // split-K partial products; the rocBLAS handle (created on first use)
     DevBuf kp_store, kp_rblk, kp_vec, kp_parts;
+    // state blocks of the staged shape: one block of states, its correlation
+    // and norms, in the caller's order
+    DevBuf blk_psi, blk_corr, blk_norm;
     void *blas = nullptr;
     void release_blas();
     // adjoint: segment store, four adjoint vectors, gradient accumulators
@@ -142,6 +145,13 @@ struct Engine {
     void release();
 
     // the propagation driver (shared by single and batched entry points)
+    // run() for the plain propagation, except that the staged shape keeps
+    // rows of at most kStagedRowBytes: wider state blocks are propagated in
+    // blocks of that many bytes (states are independent; the matrix is read
+    // once per block, the staged tiles hold more rows and re-fetch fewer
+    // halo rows).  Falls back to run() for everything else.
+    struct RunArgs;
+    tbpm_status run_states(const RunArgs &a);
     struct RunArgs {
         const double *const *psi0;  // n_inst device pointers
         int32_t s_user;

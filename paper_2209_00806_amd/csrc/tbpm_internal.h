@@ -45,6 +45,8 @@ hipError_t launch_pass(int kind, bool fp32, bool cplx, bool nontemporal, int ne,
 // wide: the matrix has slices wider than kStagedWide stored elements per row
 // (the staged pass then walks a row's elements in batches of 12, else of 4)
 constexpr int32_t kStagedWide = 8;
+// widest state row the staged shape propagates at once (bytes per row)
+constexpr int32_t kStagedRowBytes = 128;
 hipError_t launch_pass_staged(int kind, bool fp32, bool cplx, bool nontemporal, int vs, bool wide,
                               const PassParams &p, hipStream_t st);
 hipError_t launch_init(bool fp32, const InitParams &p, hipStream_t st);

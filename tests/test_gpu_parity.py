@@ -478,6 +478,35 @@ def test_shortest_runs_and_series(fused):
         assert _rel(got, ref) < 1e-12, M
 
 
+@pytest.mark.parametrize("precision,S", [("fp64", 13), ("fp32", 24)])
+def test_staged_state_blocks(precision, S):
+    """The staged shape propagates rows wider than 128 B in state blocks
+    (FP64: 8 states, FP32: 16): 13 FP64 states run as 8 + 5 and 24 FP32
+    states as 16 + 8.  Correlations and norms land in the caller's columns and
+    match the unblocked plain shape and the oracle."""
+    print(f"case staged state blocks {precision} S={S}", flush=True)
+    rng = np.random.default_rng(59)
+    lat = inputs.twisted_bilayer(20, 20, angle_deg=2.5)
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    dt = math.pi / f
+    nt = 40
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(2, 1, 1, 1, staged=0, precision=precision)
+    plain, pn = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True)
+    for tier, vec in ((1, 4), (2, 2)):
+        H.set_launch_config(2, 0, 0, 1, staged=tier, vec=vec, precision=precision)
+        got, gn = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True)
+        assert got.shape == (nt, S) and gn.shape == (nt, S)
+        bar = 1e-13 if precision == "fp64" else 1e-6
+        assert _rel(got.cpu().numpy(), plain.cpu().numpy()) < bar, (tier, vec)
+        assert float((gn - pn).abs().max()) < bar, (tier, vec)
+    ref, ref_n2, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    if precision == "fp64":
+        assert _rel(got.cpu().numpy(), ref) < 1e-10
+        assert np.max(np.abs(gn.cpu().numpy() - ref_n2)) < 1e-10
+
+
 def _dt_for_terms(f, parity):
     """A time step whose Bessel series has M terms of the given parity (M >= 5),
     so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
