@@ -202,6 +202,31 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
                            uint32_t flags, void *stream);
 
 /*
+ * tbpm_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same propagation and correlation, corr[k][s] = <psi0_s|psi_s(k dt)> and
+ * norm2[k][s] = ||psi_s(k dt)||^2, with the same kernels in the plain launch
+ * shape (one Clenshaw order per launch, the handle's configuration for prec;
+ * the fused and staged shapes are not used), launched directly.
+ *   Arguments as tbpm_propagate (no checkpoints, no flags); norm2 may be NULL.
+ * Work memory: every work buffer lives in one fixed device array of 64 MiB
+ * per device, reserved by the library when its code is loaded onto the
+ * device and held until the process ends.  A call needs about
+ * 4096 + (3 b + 16) n_orb S_pad + 32 n_orb bytes (b = 16 for TBPM_FP64,
+ * 8 for TBPM_FP32_MIXED; S_pad = n_states rounded up to a power of two);
+ * beyond 64 MiB it returns TBPM_E_ARG before any work is enqueued, and the
+ * series may have at most 65 terms.  All calls on one device share that
+ * array: calls that overlap on one device race (serialise them, e.g. on one
+ * stream).  The call allocates nothing, copies nothing from the host and
+ * never synchronises: it only enqueues kernels on 'stream' and returns, so
+ * it performs no norm check (read norm2 to check).  The caller's buffers
+ * must stay valid until the work has finished.
+ */
+tbpm_status tbpm_propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                                   double dt, double rescale, double bessel_tol, tbpm_precision prec, double *corr,
+                                   double *norm2, void *stream);
+
+/*
  * Wave-function propagation with snapshots (the paper's usage section,
  * propagation of a wave packet; Sec. "Tight-binding propagation method",
  * Eq. (eq:psi_t)): propagate psi0 with the same series and time step as

@@ -240,6 +240,22 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
     }
 }
 
+tbpm_status tbpm_propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, int32_t n_steps,
+                                   double dt, double rescale, double bessel_tol, tbpm_precision prec, double *corr,
+                                   double *norm2, void *stream) {
+    if (!H || !psi0 || !corr) return fail(TBPM_E_ARG, "H, psi0 and corr must not be NULL");
+    tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
+    if (st != TBPM_OK) return st;
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    const double f = resolve_rescale(H->csr, rescale);
+    try {
+        return propagate_noalloc(H, psi0, n_states, n_steps, dt, f, bessel_tol, prec == TBPM_FP32_MIXED, corr, norm2,
+                                 (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+        return fail(TBPM_E_OOM, "host allocation failed");
+    }
+}
+
 tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, int32_t n_states, const int32_t *steps,
                                      int32_t n_snap, double dt, double rescale, double bessel_tol,
                                      tbpm_precision prec, double *snaps, double *corr, uint32_t flags,

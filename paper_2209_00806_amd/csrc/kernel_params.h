@@ -137,7 +137,7 @@ struct ReduceParams {
     const int32_t *counter;
     double *const *corr;          // per member [n_steps][s_user] complex128
     double *const *norm2;         // per member, entries may be null
-    double *norm2_all;            // [n_inst][n_steps][s_user]
+    double *norm2_all;            // [n_inst][n_steps][s_user], or null
 };
 
 }  // namespace tbpm

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kWG) void k_reduce(const ReduceParams p) {
             cc.y = red[1][0];
             ((d2 *)p.corr[inst])[o] = cc;
             if (p.norm2[inst]) p.norm2[inst][o] = red[2][0];
-            p.norm2_all[(int64_t)inst * p.n_steps * p.s_user + o] = red[2][0];
+            if (p.norm2_all) p.norm2_all[(int64_t)inst * p.n_steps * p.s_user + o] = red[2][0];
         }
     }
 }

@@ -229,3 +229,11 @@ struct tbpm_batch {
     std::vector<tbpm_hamiltonian *> members;
     tbpm::Engine eng;
 };
+
+namespace tbpm {
+// tbpm_propagate in the plain launch shape with every work buffer in a fixed
+// per-device scratch array (noalloc.hip): enqueues kernels only, no norm check
+tbpm_status propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int32_t s_user, int32_t n_steps, double dt,
+                              double f, double tol, bool fp32, double *corr, double *norm2, hipStream_t st);
+size_t noalloc_scratch_bytes();
+}  // namespace tbpm

@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         "tbpm_num_terms": [D, D, P],
         "tbpm_bessel_j": [D, I32, P],
         "tbpm_propagate": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, I32, P, U32, P],
+        "tbpm_propagate_noalloc": [P, P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
         "tbpm_propagate_snapshots": [P, P, I32, P, I32, D, D, D, ctypes.c_int, P, P, U32, P],
         "tbpm_quasi_eigenstates": [P, P, I32, I32, D, D, D, ctypes.c_int, P, I32, ctypes.c_int, P, P, U32, P],
         "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
@@ -288,6 +289,32 @@ def propagate(H: Hamiltonian, psi0, n_steps: int, dt: float, rescale: float = 0.
     if ckpt_every > 0:
         res.append(ckpt)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def propagate_noalloc(H: Hamiltonian, psi0, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,
+                      precision: str = "fp64", corr=None, norm2=None, stream=None):
+    """tbpm_propagate_noalloc: C_k = <psi0|psi(k dt)> into the caller's CUDA
+    tensors corr [n_steps, S] complex128 (and norm2 [n_steps, S] float64 if
+    given), with no device allocation by the library; enqueued on the stream
+    and not synchronised.  Returns corr (allocated here if not given)."""
+    import torch
+
+    _require_cuda(psi0, torch.complex128, "psi0")
+    if psi0.dim() == 1:
+        psi0 = psi0.reshape(-1, 1)
+    n, S = psi0.shape
+    if corr is None:
+        corr = torch.empty((n_steps, S), dtype=torch.complex128, device=psi0.device)
+    _require_cuda(corr, torch.complex128, "corr")
+    if tuple(corr.shape) != (n_steps, S):
+        raise ValueError(f"corr must have shape {(n_steps, S)}")
+    if norm2 is not None:
+        _require_cuda(norm2, torch.float64, "norm2")
+        if tuple(norm2.shape) != (n_steps, S):
+            raise ValueError(f"norm2 must have shape {(n_steps, S)}")
+    _check(lib().tbpm_propagate_noalloc(H.handle, _ptr(psi0), S, int(n_steps), float(dt), float(rescale),
+                                        float(tol), _prec(precision), _ptr(corr), _ptr(norm2), _stream(stream)))
+    return corr
 
 
 def propagate_snapshots(H: Hamiltonian, psi0, steps, dt: float, rescale: float = 0.0, tol: float = 1e-12,
