@@ -106,7 +106,12 @@ tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const
  * TBPM_FLAG_DEVICE_PTRS both are device pointers, the copy is enqueued on
  * 'stream' and Hermiticity is NOT re-checked; otherwise host pointers,
  * validated like create.  A real H stays real: the imaginary parts of val
- * are ignored unless H was created complex.
+ * are ignored unless H was created complex.  Values set from device pointers
+ * never reach the host, so the Gershgorin bound of the new values is not
+ * known: until host values are set again (or the row order is set, which
+ * re-uploads the last host values), every call on H that would take that
+ * bound (rescale <= 0) returns TBPM_E_ARG, and tbpm_hamiltonian_info reports
+ * the bound of the last host values.
  */
 tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, const double *onsite,
                                         uint32_t flags, void *stream);
@@ -312,7 +317,8 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
  *             (<= 0: the Gershgorin bound); the moments are not checked
  *   mu        device [M][M] complex128, written: mu[n*M + m] = mu_mn
  *   timing_ms host [4] or NULL: milliseconds of the L recursion, the R
- *             recursion and the products, and the number of split-K chunks
+ *             recursion and the products, and the number of chunks the product's
+ *             inner dimension is split into
  * Returns after the work has finished.
  */
 tbpm_status tbpm_kpm_moments(tbpm_hamiltonian *H, const double *v_alpha, const double *v_beta, const double *psi0,

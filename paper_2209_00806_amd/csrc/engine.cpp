@@ -273,7 +273,6 @@ void Engine::release() {
                       &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s,
                       &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &blk_psi,   &blk_corr,     &blk_norm};
     for (DevBuf *b : bufs) b->release();
-    release_blas();
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
     staging_done = nullptr;

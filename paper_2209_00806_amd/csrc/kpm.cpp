@@ -6,11 +6,10 @@
 // mu_mn = <L_m|R_n>: the moments are one complex matrix product L^H R with
 // an inner dimension of rows x states.  All M vectors L_m are kept in HBM
 // (the Chebyshev recursion writes them in place); R is produced in blocks of
-// moments, and each block's product runs as a split-K batched ZGEMM on the
-// matrix cores (rocBLAS) whose per-chunk results are summed in a fixed order.
-#define ROCM_MATHLIBS_API_USE_HIP_COMPLEX 1
+// moments, and each block's product runs on the FP64 matrix cores
+// (k_kpm_product), split into chunks of the long inner dimension whose
+// results are summed in a fixed order.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cstring>
@@ -25,18 +24,6 @@ namespace tbpm {
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
-#define TRY_BLAS(expr, what)                                                                        \
-    do {                                                                                            \
-        rocblas_status b_ = (expr);                                                                 \
-        if (b_ != rocblas_status_success)                                                           \
-            return fail(TBPM_E_DEVICE, std::string(what) + ": rocBLAS status " + std::to_string((int)b_)); \
-    } while (0)
-
-void Engine::release_blas() {
-    if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
-    blas = nullptr;
-}
-
 tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double *psi0, int32_t s_user, int32_t n_mom,
                                 double f, double *mu, hipStream_t st, KpmTiming *timing) {
     int32_t s_pad = 1, log2s = 0;
@@ -48,11 +35,23 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     const int64_t K = n * s_pad;  // inner dimension of the moment product
     const int32_t nb = std::min<int32_t>(n_mom, 128);
     const size_t vec = sizeof(double) * 2 * (size_t)K;
-    // split-K: chunks of at least 4096 rows x states, at most 64 of them
-    const int64_t n_parts = std::max<int64_t>(1, std::min<int64_t>(64, K / 4096));
-    const int64_t kc = K / n_parts, k_rest = K - kc * n_parts;
+    // vectors of the L store and the R block lie vstride bytes apart: a pad
+    // of 768 bytes keeps the rows the product reads at once off the same
+    // offset of a large power-of-two stride (measured: their loads run 12%
+    // faster than at the bare stride)
+    const size_t vstride = vec + 768;
+    // product split: the inner dimension (ld = 2K doubles) in chunks of a
+    // multiple of 32 doubles, enough of them that the product's workgroups
+    // (tiles of one chunk) fill the chip about 16 times over (two per CU)
+    const int64_t ld = 2 * K;
+    const KpmProductShape sh = kpm_product_shape(kpm_shape);
+    const int64_t tiles_m = (n_mom + sh.wm * sh.tm * 16 - 1) / (sh.wm * sh.tm * 16);
+    const int64_t tiles_n = (nb + (4 / sh.wm) * sh.tn * 16 - 1) / ((4 / sh.wm) * sh.tn * 16);
+    const int64_t want = std::max<int64_t>(1, 4096 / (tiles_m * tiles_n));
+    const int64_t kchunk = std::max<int64_t>(512, ((ld + want - 1) / want + 31) & ~(int64_t)31);
+    const int64_t n_parts = (ld + kchunk - 1) / kchunk;
     const size_t part_bytes = sizeof(double) * 2 * (size_t)n_mom * nb;
-    const size_t need = vec * ((size_t)n_mom + nb + 5) + part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0));
+    const size_t need = vstride * ((size_t)n_mom + nb) + vec * 5 + part_bytes * (size_t)n_parts;
     size_t free_b = 0, total_b = 0;
     TRY_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     const size_t have = kp_store.bytes + kp_rblk.bytes + kp_vec.bytes + kp_parts.bytes;
@@ -75,20 +74,13 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
         tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
         if (s0 != TBPM_OK) return s0;
     }
-    TRY_HIP(kp_store.ensure(vec * (size_t)n_mom), "alloc moment vectors L");
-    TRY_HIP(kp_rblk.ensure(vec * (size_t)nb), "alloc moment vectors R");
+    TRY_HIP(kp_store.ensure(vstride * (size_t)n_mom), "alloc moment vectors L");
+    TRY_HIP(kp_rblk.ensure(vstride * (size_t)nb), "alloc moment vectors R");
     TRY_HIP(kp_vec.ensure(5 * vec), "alloc Chebyshev vectors");
-    TRY_HIP(kp_parts.ensure(part_bytes * (size_t)(n_parts + (k_rest ? 1 : 0))), "alloc split-K parts");
+    TRY_HIP(kp_parts.ensure(part_bytes * (size_t)n_parts), "alloc product parts");
     TRY_HIP(counter.ensure(sizeof(int32_t)), "alloc counter");
     TRY_HIP(ac_zero.ensure(sizeof(double) * (size_t)std::max<int64_t>(n, 1)), "alloc zero on-site");
     TRY_HIP(launch_fill_zero((double *)ac_zero.ptr, n, st), "clear zero on-site");
-    if (!blas) {
-        rocblas_handle h = nullptr;
-        TRY_BLAS(rocblas_create_handle(&h), "rocblas_create_handle");
-        blas = h;
-    }
-    rocblas_handle bh = (rocblas_handle)blas;
-    TRY_BLAS(rocblas_set_stream(bh, st), "rocblas_set_stream");
 
     // pass coefficients: out = 0 v + beta (op x) - b2 with op = J (beta 1), H~ (1/f) or 2 H~ (2/f)
     TRY_HIP(coef.ensure(3 * sizeof(PassCoef)), "alloc coefficients");
@@ -166,27 +158,25 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     TRY_HIP(pass(kPassFirst, true, ja, r, nullptr, Ls, c_j), "launch current operator");
     int32_t m_done = 1;  // orders written so far
     if (pairs) {
-        TRY_HIP(pass(kPassFirst, false, nullptr, Ls, nullptr, Ls + vec, c_1), "launch Chebyshev pass");
+        TRY_HIP(pass(kPassFirst, false, nullptr, Ls, nullptr, Ls + vstride, c_1), "launch Chebyshev pass");
         m_done = 2;
         for (; m_done + 1 < n_mom; m_done += 2)
-            TRY_HIP(pair(Ls + vec * (size_t)(m_done - 1), Ls + vec * (size_t)(m_done - 2), Ls + vec * (size_t)m_done,
-                         Ls + vec * (size_t)(m_done + 1)),
+            TRY_HIP(pair(Ls + vstride * (size_t)(m_done - 1), Ls + vstride * (size_t)(m_done - 2), Ls + vstride * (size_t)m_done,
+                         Ls + vstride * (size_t)(m_done + 1)),
                     "launch Chebyshev pair");
     }
     for (int32_t m = m_done; m < n_mom; ++m) {
-        void *out = Ls + vec * (size_t)m;
-        const void *x = Ls + vec * (size_t)(m - 1);
+        void *out = Ls + vstride * (size_t)m;
+        const void *x = Ls + vstride * (size_t)(m - 1);
         if (m == 1)
             TRY_HIP(pass(kPassFirst, false, nullptr, x, nullptr, out, c_1), "launch Chebyshev pass");
         else
-            TRY_HIP(pass(kPassMid, false, nullptr, x, Ls + vec * (size_t)(m - 2), out, c_2), "launch Chebyshev pass");
+            TRY_HIP(pass(kPassMid, false, nullptr, x, Ls + vstride * (size_t)(m - 2), out, c_2), "launch Chebyshev pass");
     }
     if (timing) TRY_HIP(hipEventRecord(ev[1], st), "record");
 
     // R_n = v_b T_n(H~) r in blocks of nb moments; T_n in (t0, t1), the
     // interior order written over T_{n-1}
-    const rocblas_double_complex alpha = make_hipDoubleComplex(1.0 / s_user, 0.0);
-    const rocblas_double_complex zero = make_hipDoubleComplex(0.0, 0.0);
     const void *tc = r;  // T_n
     void *tn[2] = {t0, t1};
     // paired T recursion: T_n (n >= 1) lives in tq[n & 3]; orders are produced
@@ -217,7 +207,7 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
                 }
             }
             const void *tcur = nn == 0 ? r : tq[nn & 3];
-            TRY_HIP(pass(kPassFirst, true, jb, tcur, nullptr, Rb + vec * (size_t)j, c_j), "launch current operator");
+            TRY_HIP(pass(kPassFirst, true, jb, tcur, nullptr, Rb + vstride * (size_t)j, c_j), "launch current operator");
         }
         for (int32_t j = 0; !pairs && j < cnt; ++j) {
             const int32_t nn = n0 + j;
@@ -234,7 +224,7 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
                 TRY_HIP(pass(kPassMid, false, nullptr, tn[nn & 1], prev, prev, c_2), "launch Chebyshev pass");
                 tc = prev;
             }
-            TRY_HIP(pass(kPassFirst, true, jb, tc, nullptr, Rb + vec * (size_t)j, c_j), "launch current operator");
+            TRY_HIP(pass(kPassFirst, true, jb, tc, nullptr, Rb + vstride * (size_t)j, c_j), "launch current operator");
         }
         hipEvent_t g0 = nullptr, g1 = nullptr;
         if (timing) {
@@ -242,22 +232,14 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
             TRY_HIP(hipEventCreate(&g1), "hipEventCreate");
             TRY_HIP(hipEventRecord(g0, st), "record");
         }
-        // parts[p] = L[chunk p]^H R[chunk p] (M x cnt), then summed into mu[:, n0 : n0 + cnt]
-        const rocblas_double_complex *A = (const rocblas_double_complex *)Ls;
-        const rocblas_double_complex *B = (const rocblas_double_complex *)Rb;
-        rocblas_double_complex *P = (rocblas_double_complex *)kp_parts.ptr;
+        // parts[p][n][m] = sum over chunk p of conj(L_m) R_{n0+n}, then
+        // mu[:, n0 : n0 + cnt] = (1/S) sum_p parts[p] in order
+        double *P = (double *)kp_parts.ptr;
         const int64_t pstride = (int64_t)n_mom * cnt;
-        TRY_BLAS(rocblas_zgemm_strided_batched_64(bh, rocblas_operation_conjugate_transpose, rocblas_operation_none,
-                                                  n_mom, cnt, kc, &alpha, A, K, kc, B, K, kc, &zero, P, n_mom,
-                                                  pstride, n_parts),
-                 "moment product");
-        if (k_rest)
-            TRY_BLAS(rocblas_zgemm_strided_batched_64(bh, rocblas_operation_conjugate_transpose,
-                                                      rocblas_operation_none, n_mom, cnt, k_rest, &alpha,
-                                                      A + kc * n_parts, K, 0, B + kc * n_parts, K, 0, &zero,
-                                                      P + pstride * n_parts, n_mom, pstride, 1),
-                     "moment product (rest)");
-        TRY_HIP(launch_kpm_sum_parts((const double *)P, pstride, (int32_t)(n_parts + (k_rest ? 1 : 0)), pstride,
+        TRY_HIP(launch_kpm_product(kpm_shape, (const double *)Ls, (const double *)Rb, (int64_t)(vstride / 8), ld,
+                                   n_mom, cnt, kchunk, (int32_t)n_parts, P, st),
+                "launch moment product");
+        TRY_HIP(launch_kpm_sum_parts(P, pstride, (int32_t)n_parts, pstride, 1.0 / s_user,
                                      mu + 2 * (size_t)n0 * n_mom, st),
                 "sum moment parts");
         if (timing) {

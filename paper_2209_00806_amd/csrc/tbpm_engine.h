@@ -26,6 +26,9 @@ struct HostCsr {
     std::vector<double> onsite;
     bool is_complex = false;
     double gershgorin = 0.0;
+    // the device values were last replaced from device pointers: gershgorin
+    // (and val, onsite) describe the last host values, not the device copy
+    bool bound_stale = false;
     int64_t max_row = 0;
     int64_t nnz() const { return (int64_t)col.size(); }
 };
@@ -109,13 +112,12 @@ struct Engine {
     // Haydock recursion: two Lanczos vectors, the product vector, per-state scalars
     DevBuf hay_u, hay_y, hay_s;
     // kernel-polynomial moments: the L store, a block of R, Chebyshev vectors,
-    // split-K partial products; the rocBLAS handle (created on first use)
+    // per-chunk partial products; the product's workgroup tiling (kpm_product_shape)
     DevBuf kp_store, kp_rblk, kp_vec, kp_parts;
+    int32_t kpm_shape = 0;
     // state blocks of the staged shape: one block of states, its correlation
     // and norms, in the caller's order
     DevBuf blk_psi, blk_corr, blk_norm;
-    void *blas = nullptr;
-    void release_blas();
     // adjoint: segment store, four adjoint vectors, gradient accumulators
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
     PinnedBuf staging;

@@ -191,8 +191,22 @@ hipError_t launch_hay_ldos(const double *a, const double *b, int32_t n_iter, int
 
 // kernel-polynomial method (kpm.hip)
 int32_t kpm_max_moments_lds();
-hipError_t launch_kpm_sum_parts(const double *parts, int64_t n_el, int32_t n_parts, int64_t part_stride, double *out,
-                                hipStream_t st);
+// Moment product parts[c][n][m] = sum over chunk c of conj(L_m) R_n (complex128)
+// for L [n_mom], R [cnt] complex128 vectors of ld doubles (even) whose rows
+// are stride doubles apart (even, >= ld), chunks of kchunk doubles (a
+// multiple of 32), n_chunks = ceil(ld / kchunk).
+// shape selects the workgroup tiling (kpm_product_shape): 0 is the default.
+struct KpmProductShape {
+    int tm, tn, wm;  // 16x16 tiles per wave along m and n; waves along m (of 4)
+    int prefetch;    // 1: the next step's operands are loaded before the current products
+};
+KpmProductShape kpm_product_shape(int32_t shape);
+hipError_t launch_kpm_product(int32_t shape, const double *L, const double *R, int64_t stride, int64_t ld,
+                              int32_t n_mom, int32_t cnt, int64_t kchunk, int32_t n_chunks, double *parts,
+                              hipStream_t st);
+// out[i] = scale sum_{p < n_parts} parts[p * part_stride + i] (complex128), p in order
+hipError_t launch_kpm_sum_parts(const double *parts, int64_t n_el, int32_t n_parts, int64_t part_stride, double scale,
+                                double *out, hipStream_t st);
 hipError_t launch_kubo_bastin(const double *mu, int32_t n_mom, double rescale, double th_lo, double dth,
                               int32_t n_energy, const double *mus, int32_t n_mu, double beta, double scale,
                               double *energies, double *weight, double *sigma, hipStream_t st);

@@ -416,7 +416,7 @@ def kpm_moments(H: Hamiltonian, v_alpha, v_beta, psi0, n_moments: int, rescale: 
                                   _ptr(out), t.ctypes.data if return_timing else None, _stream(stream)))
     mu = out.transpose(0, 1)
     if return_timing:
-        return mu, {"l_ms": float(t[0]), "r_ms": float(t[1]), "gemm_ms": float(t[2]), "split_k": int(t[3])}
+        return mu, {"l_ms": float(t[0]), "r_ms": float(t[1]), "product_ms": float(t[2]), "chunks": int(t[3])}
     return mu
 
 
