@@ -45,7 +45,12 @@ class TBPMDos(torch.autograd.Function):
 
 def tbpm_dos(H: "tbpm.Hamiltonian", val, onsite, psi0, n_steps: int, dt: float, rescale: float,
              ckpt_every: int = 64, tol: float = 1e-12, window: str = "hann"):
-    """Differentiable (energies, dos) of H with values (val, onsite)."""
+    """Differentiable (energies, dos) of H with values (val, onsite).  The
+    rescale factor f must be given (> 0) and bound the spectrum for every
+    value the optimiser visits: the values reach the library as device
+    tensors, whose Gershgorin bound it never sees."""
+    if not rescale > 0:
+        raise ValueError("rescale must be positive: the values are set from device tensors, whose bound is unknown")
     return TBPMDos.apply(val, onsite, H, psi0, n_steps, dt, rescale, ckpt_every, tol, window)
 
 

@@ -36,6 +36,18 @@ double resolve_rescale(const HostCsr &h, double rescale) {
     return h.gershgorin > 0 ? h.gershgorin : 1.0;
 }
 
+// rescale <= 0 selects the Gershgorin bound, which is only known for values
+// given on the host: after a device-pointer set_values the caller must pass f
+tbpm_status pick_rescale(const HostCsr &h, double rescale, double *f) {
+    if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
+    if (rescale <= 0 && h.bound_stale)
+        return fail(TBPM_E_ARG,
+                    "rescale <= 0 selects the Gershgorin bound, which is not known after values were set from "
+                    "device pointers: pass rescale > 0");
+    *f = resolve_rescale(h, rescale);
+    return TBPM_OK;
+}
+
 tbpm_status check_prop_args(int32_t n_states, int32_t n_steps, double dt, double tol, tbpm_precision prec) {
     if (n_states < 1 || n_states > 64) return fail(TBPM_E_ARG, "n_states must be in [1, 64]");
     if (n_steps < 1) return fail(TBPM_E_ARG, "n_steps must be >= 1");
@@ -101,6 +113,7 @@ tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, 
     if (flags & TBPM_FLAG_DEVICE_PTRS) {
         hipError_t e = launch_convert_values(H->eng.mat, val, onsite, n, st);
         if (e != hipSuccess) return hip_fail(e, "launch value conversion");
+        H->csr.bound_stale = true;
         return TBPM_OK;
     }
     HostCsr copy = H->csr;
@@ -117,6 +130,7 @@ tbpm_status tbpm_hamiltonian_set_values(tbpm_hamiltonian *H, const double *val, 
     tbpm_status s = check_values(copy, hmax);
     if (s != TBPM_OK) return s;
     copy.is_complex = was_complex;
+    copy.bound_stale = false;
     // stage through device scratch and convert with the device path
     double *dval = nullptr, *dons = nullptr;
     hipError_t e = hipMalloc(&dval, sizeof(double) * std::max<int64_t>(2 * nnz, 1));
@@ -149,6 +163,7 @@ tbpm_status tbpm_hamiltonian_set_row_order(tbpm_hamiltonian *H, int32_t order) {
     if (e != hipSuccess) return hip_fail(e, "synchronize before re-upload");
     H->eng.release();
     H->eng.row_order = order;
+    H->csr.bound_stale = false;  // the device copy is rebuilt from the host values
     const HostCsr *m = &H->csr;
     try {
         return H->eng.upload(&m, 1);
@@ -215,7 +230,8 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
         return fail(TBPM_E_ARG, "ckpt_every must be >= 0 and ckpt non-NULL when checkpoints are due");
     if (ckpt_every > 0 && prec != TBPM_FP64) return fail(TBPM_E_ARG, "checkpoints require TBPM_FP64");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     const double *p0 = psi0;
     double *c0 = corr;
     double *n0 = norm2;
@@ -247,7 +263,8 @@ tbpm_status tbpm_propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int3
     tbpm_status st = check_prop_args(n_states, n_steps, dt, bessel_tol, prec);
     if (st != TBPM_OK) return st;
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     try {
         return propagate_noalloc(H, psi0, n_states, n_steps, dt, f, bessel_tol, prec == TBPM_FP32_MIXED, corr, norm2,
                                  (hipStream_t)stream);
@@ -275,7 +292,8 @@ tbpm_status tbpm_propagate_snapshots(tbpm_hamiltonian *H, const double *psi0, in
     if (st != TBPM_OK) return st;
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
     if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     hipStream_t hs = (hipStream_t)stream;
     // psi(0) is the caller's state itself
     const size_t snap_bytes = sizeof(double) * 2 * (size_t)H->csr.n * n_states;
@@ -327,7 +345,8 @@ tbpm_status tbpm_quasi_eigenstates(tbpm_hamiltonian *H, const double *psi0, int3
         if (!std::isfinite(energies[j])) return fail(TBPM_E_ARG, "energies must be finite");
     if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     Engine &eng = H->eng;
     int32_t s_pad = 1, log2s = 0;
     while (s_pad < n_states) {
@@ -435,7 +454,8 @@ tbpm_status tbpm_ac_corr(tbpm_hamiltonian *H, const double *j_alpha, const doubl
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
     const int64_t n = H->csr.n;
     if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     const std::vector<double> a = fermi_cheb_coeffs(beta, mu, f, fermi_tol);
     if (a.empty()) return fail(TBPM_E_ARG, "the Fermi-Dirac expansion needs more than 2^19 terms (beta * rescale too large)");
     Engine &eng = H->eng;
@@ -503,7 +523,8 @@ tbpm_status tbpm_kpm_moments(tbpm_hamiltonian *H, const double *v_alpha, const d
     if (n_moments < 2 || n_moments > 16384) return fail(TBPM_E_ARG, "n_moments must be in [2, 16384]");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
     if ((int64_t)H->csr.n * 64 >= ((int64_t)1 << 31)) return fail(TBPM_E_ARG, "rows * 64 states must be below 2^31");
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     if (tbpm_status d = check_device(H->eng); d != TBPM_OK) return d;
     hipStream_t hs = (hipStream_t)stream;
     try {
@@ -636,7 +657,8 @@ tbpm_status tbpm_backward(tbpm_hamiltonian *H, const double *psi0, int32_t n_sta
     if (ckpt_every < 1) return fail(TBPM_E_ARG, "ckpt_every must be >= 1");
     if (!ckpt && n_steps > ckpt_every + 1) return fail(TBPM_E_ARG, "ckpt must not be NULL");
     if (!std::isfinite(rescale)) return fail(TBPM_E_ARG, "rescale must be finite");
-    const double f = resolve_rescale(H->csr, rescale);
+    double f = 0.0;
+    if (tbpm_status rs = pick_rescale(H->csr, rescale, &f); rs != TBPM_OK) return rs;
     try {
         return backward_impl(H, psi0, n_states, n_steps, dt, f, bessel_tol, grad_corr, ckpt_every, ckpt, grad_val,
                              grad_onsite, (hipStream_t)stream);
@@ -697,6 +719,7 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
         if (!std::isfinite(rescale[i])) return fail(TBPM_E_ARG, "rescale must be finite");
     }
     std::vector<double> f(n);
+    // the batch holds each member's host values as of tbpm_batch_create, whose bound is known
     for (int32_t i = 0; i < n; ++i) f[i] = resolve_rescale(B->members[i]->csr, rescale[i]);
     Engine::RunArgs a{};
     a.psi0 = psi0;

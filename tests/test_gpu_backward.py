@@ -201,3 +201,84 @@ def test_backward_fused_shape_vs_oracle(name, tier, vec, M_dt):
     assert _rel(cmp, ref) < 1e-10
     assert _rel(gons, gons_r) < 1e-10
     assert _rel(gval, out[0][0]) < 1e-12 and _rel(gons, out[0][1]) < 1e-12
+
+
+@pytest.mark.parametrize("fused", [0, 2])
+@pytest.mark.parametrize("name", ["graphene24x20_disorder", "graphene10x9_complex"])
+def test_backward_bench_segmentation_k64(name, fused):
+    """Checkpoints every K = 64 steps, as the differentiable bench leg takes
+    them: 130 samples (checkpoints at steps 64 and 128: three segments, the
+    last of one step) and 1024 samples (15 checkpoints: the 16 segments of
+    the bench leg), 4 states, in the default shape and in the bench's tuned
+    fused shape (LDS tier 2, 2 states per thread), against the oracle's
+    discrete adjoint (which stores every step and takes no checkpoints)."""
+    print(f"case backward K=64 {name} fused={fused}", flush=True)
+    rng = np.random.default_rng(29)
+    lat = {"graphene24x20_disorder": lambda: inputs.graphene(24, 20, onsite=inputs.anderson(rng, 960, 1.0)),
+           "graphene10x9_complex": lambda: _complex_graphene(10, 9, 8)}[name]()
+    S, K = 4, 64
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if fused:
+        H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=fused)
+    p0 = _dev(psi0)
+    cplx = H.info()["is_complex"]
+    for nt in (130, 1024):
+        g = rng.standard_normal((nt, S)) + 1j * rng.standard_normal((nt, S))
+        gval_r, gons_r = oracle.backward(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f, g)
+        corr, ckpt = tbpm.propagate(H, p0, nt, dt, f, ckpt_every=K)
+        assert ckpt.shape[0] == (nt - 2) // K
+        gval, gons = tbpm.backward(H, p0, nt, dt, f, _dev(g), K, ckpt)
+        gval = gval.cpu().numpy()
+        gons = gons.cpu().numpy()
+        assert _rel(gval if cplx else gval.real, gval_r if cplx else gval_r.real) < 1e-10, nt
+        assert _rel(gons, gons_r) < 1e-10, nt
+
+
+@pytest.mark.parametrize("fused", [0, 2])
+def test_dos_loss_bench_segmentation_vs_oracle_chain(fused):
+    """The differentiable bench leg's chain at a small size: per-bond
+    hoppings -2.7 (1 + 0.05 N(0,1)), 4 states, 1024 samples, checkpoints
+    every 64 steps, the loss on every 8th energy (256 energies) against a
+    uniform-hopping target, through the torch.autograd.Function; the bond
+    and on-site gradients against the oracle chain (DOS adjoint, then the
+    discrete adjoint of the propagation)."""
+    print(f"case dos loss K=64 1024 samples fused={fused}", flush=True)
+    from paper_2209_00806_amd import autograd as ag
+
+    rng = np.random.default_rng(41)
+    nx, ny, S, nt, K, f = 12, 10, 4, 1024, 64, 9.0
+    n_b = 3 * nx * ny
+    bt = -2.7 * (1 + 0.05 * rng.standard_normal(n_b))
+    lat = inputs.graphene(nx, ny, bond_t=bt, keep_bonds=True)
+    tgt = inputs.graphene(nx, ny, keep_bonds=True)
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    dt = math.pi / f
+    ref_corr, _, _ = oracle.propagate(tgt.row_ptr, tgt.col, tgt.val, tgt.onsite, psi0, nt, dt, f)
+    _, target = oracle.dos(ref_corr, dt)
+    sel = np.arange(0, 2 * nt, 8)
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    if fused:
+        H.set_launch_config(2, 1, 1, 1, vec=2, precision="fp64", fused=fused)
+    p0 = _dev(psi0)
+    t_param = _dev(bt).requires_grad_(True)
+    e_param = _dev(lat.onsite.copy()).requires_grad_(True)
+    val = ag.bond_values(lat.nnz, _dev(lat.slot_ij), _dev(lat.slot_ji), t_param)
+    _, D = ag.tbpm_dos(H, val, e_param, p0, nt, dt, f, ckpt_every=K)
+    sel_t = _dev(sel)
+    L = torch.sum((D[sel_t] - _dev(target)[sel_t]) ** 2)
+    L.backward()
+    gt = t_param.grad.cpu().numpy()
+    ge = e_param.grad.cpu().numpy()
+    corr_o, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    _, D_o = oracle.dos(corr_o, dt)
+    gD = np.zeros_like(D_o)
+    gD[sel] = 2 * (D_o[sel] - target[sel])
+    gc = oracle.dos_adjoint(gD, nt, S, dt)
+    gval_o, gons_o = oracle.backward(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f, gc)
+    gt_o = (gval_o[lat.slot_ij] + gval_o[lat.slot_ji]).real
+    assert abs(L.item() - float(np.sum((D_o[sel] - target[sel]) ** 2))) < 1e-10 * max(L.item(), 1e-300)
+    assert _rel(gt, gt_o) < 1e-9
+    assert _rel(ge, gons_o) < 1e-9

@@ -224,24 +224,39 @@ def test_kpm_moments_full_size_short():
     assert _rel(got, ref) < 1e-11
 
 
+@pytest.mark.timeout(600)
 def test_twisted_bilayer_full_size_sampled():
     """The 4,194,304-orbital twisted bilayer of the bench leg, 16 states, in
     the LDS-staged shapes the bench's tuner picks (FP32: tier 2, 4 states per
-    thread; FP64: tier 1, 4 states per thread; rows walked 12 elements at a
-    time): a 3-step prefix of two sampled states against the oracle.  FP64 to
-    1e-10; FP32-mixed to 1e-5 of max |C| (storage rounding of about 6e-8 per
-    pass over 51 passes)."""
+    thread; FP64: tier 1, 2 states per thread, in state blocks of 8; rows
+    walked 12 elements at a time): a 33-sample prefix (32 time steps, 544
+    sparse passes) of two sampled states against the oracle.  FP64 to 1e-10;
+    FP32-mixed to 1e-5 of max |C| (storage rounding of about 6e-8 per pass)
+    and its prefix DOS to 1e-4 (L1) of the FP64 oracle's; the norm at every
+    sample."""
     print("case twisted bilayer 4M", flush=True)
     lat, psi0 = inputs.workload_twisted_bilayer(1024, 16)
     f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite)
     dt = math.pi / f
-    nt = 4
-    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, [0, 15]].copy(), nt, dt, f)
+    nt = 33
     H = tbpm.Hamiltonian.from_lattice(lat)
     p = _dev(psi0)
-    for prec, tier, bar in (("fp64", 1, 1e-10), ("fp32", 2, 1e-5)):
-        H.set_launch_config(2, 0, 0, 1, staged=tier, vec=4, precision=prec)
+    runs = {}
+    for prec, tier, vec in (("fp64", 1, 2), ("fp32", 2, 4)):
+        H.set_launch_config(2, 0, 0, 1, staged=tier, vec=vec, precision=prec)
         corr, n2 = tbpm.propagate(H, p, nt, dt, f, precision=prec, return_norm=True)
-        corr = corr.cpu().numpy()
-        assert _rel(corr[:, [0, 15]], ref) < bar, prec
-        assert np.max(np.abs(n2.cpu().numpy() - 1)) < (1e-10 if prec == "fp64" else 1e-5), prec
+        runs[prec] = (corr.cpu().numpy(), n2.cpu().numpy())
+    H.close()
+    del p
+    print("case twisted bilayer 4M: oracle", flush=True)
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, [0, 15]].copy(), nt, dt, f)
+    for prec, (corr, n2) in runs.items():
+        bar = 1e-10 if prec == "fp64" else 1e-5
+        assert _rel(corr[:, [0, 15]], ref) < bar, (prec, _rel(corr[:, [0, 15]], ref))
+        assert np.max(np.abs(n2 - 1)) < bar, prec
+        if prec == "fp32":
+            for q, s in enumerate((0, 15)):
+                _, Dr = oracle.dos(ref[:, q:q + 1].copy(), dt)
+                _, D = tbpm.dos(_dev(corr[:, s:s + 1].copy()), dt)
+                D = D.cpu().numpy()
+                assert np.sum(np.abs(D - Dr)) / np.sum(np.abs(Dr)) < 1e-4, s

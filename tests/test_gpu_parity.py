@@ -253,33 +253,67 @@ def test_gershgorin_default_rescale_and_set_values():
     H.set_values(_dev(val2), _dev(ons2))
     got3 = tbpm.propagate(H, _dev(psi0), 64, dt, 11.0).cpu().numpy()
     assert _rel(got3, ref2) < 1e-10
+    # values from device pointers: their Gershgorin bound is unknown, so a
+    # call that would take it (rescale <= 0) is refused until host values
+    # are set again
+    with pytest.raises(tbpm.TBPMError) as e:
+        tbpm.propagate(H, _dev(psi0), 8, dt, 0.0)
+    assert e.value.name == "TBPM_E_ARG" and "device pointers" in str(e.value)
+    H.set_values(val2, ons2)
+    got4 = tbpm.propagate(H, _dev(psi0), 64, dt, 0.0).cpu().numpy()
+    ref4, _, _ = oracle.propagate(lat.row_ptr, lat.col, val2, ons2, psi0, 64, dt,
+                                  oracle.gershgorin(lat.row_ptr, val2, ons2))
+    assert _rel(got4, ref4) < 1e-10
     del lat2
 
 
-def test_config2_full_size_sampled_states():
-    """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, FP64 in
-    the default launch shape and in the shape the bench's tuner picks (two
-    orders per launch, LDS tier 2, 2 states per thread), and FP32-mixed in its
-    tuned shape (4 states per thread): a prefix of steps for two sampled
-    states against the oracle (FP64 to 1e-10, FP32 to 1e-5 of max |C|), and
-    at every step the norm."""
-    print("case config2 full size", flush=True)
+C2_STEPS = 256
+
+
+@pytest.fixture(scope="module")
+def config2_runs():
+    """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, the first
+    256 correlation samples on the GPU: FP64 in the default launch shape and
+    in the shape the bench's tuner picks (two orders per launch, LDS tier 2,
+    2 states per thread), and FP32-mixed in its tuned shape (4 states per
+    thread)."""
+    print("case config2 full size: GPU runs", flush=True)
     lat, psi0 = inputs.workload_disordered_graphene(1024, 8)
     f = 9.0
     dt = math.pi / f
     H = tbpm.Hamiltonian.from_lattice(lat)
-    nt = 24
-    refs = {s: oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), nt, dt, f)[0]
-            for s in (0, 5)}
-    for shape, prec, bar in (("default", "fp64", 1e-10), ("bench", "fp64", 1e-10), ("bench", "fp32", 1e-5)):
+    runs = {}
+    for shape, prec in (("default", "fp64"), ("bench", "fp64"), ("bench", "fp32")):
         if shape == "bench":
             H.set_launch_config(2, 1, 1, 1, vec=2 if prec == "fp64" else 4, precision=prec, fused=2)
-        corr, n2 = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=prec, return_norm=True)
-        corr = corr.cpu().numpy()
-        n2 = n2.cpu().numpy()
-        assert np.max(np.abs(n2 - 1)) < bar, (shape, prec)
-        for s, ref in refs.items():
-            assert _rel(corr[:, s], ref[:, 0]) < bar, (shape, prec, s)
+        corr, n2 = tbpm.propagate(H, _dev(psi0), C2_STEPS, dt, f, precision=prec, return_norm=True)
+        runs[(shape, prec)] = (corr.cpu().numpy(), n2.cpu().numpy())
+    H.close()
+    return lat, psi0, f, dt, runs
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("s", [0, 5])
+def test_config2_full_size_256_steps(config2_runs, s):
+    """A 256-sample prefix (255 time steps, 4335 sparse passes) of one sampled
+    state of the disordered 1024x1024 workload against the oracle, in every
+    launch shape the bench times: FP64 to 1e-10 of max |C|; FP32-mixed to
+    1e-5 of max |C| and its prefix DOS to 1e-4 (L1) of the FP64 oracle's;
+    the norm at every sample."""
+    lat, psi0, f, dt, runs = config2_runs
+    print(f"case config2 full size: oracle state {s}", flush=True)
+    ref = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), C2_STEPS, dt, f)[0]
+    _, Dr = oracle.dos(ref, dt)
+    for (shape, prec), (corr, n2) in runs.items():
+        bar = 1e-10 if prec == "fp64" else 1e-5
+        assert np.max(np.abs(n2[:, s] - 1)) < bar, (shape, prec)
+        assert _rel(corr[:, s], ref[:, 0]) < bar, (shape, prec, _rel(corr[:, s], ref[:, 0]))
+        _, D = tbpm.dos(_dev(corr[:, s:s + 1].copy()), dt)
+        D = D.cpu().numpy()
+        if prec == "fp64":
+            assert _rel(D, Dr) < 1e-10, (shape, prec)
+        else:
+            assert _l1(D, Dr) < 1e-4, (shape, prec, _l1(D, Dr))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
