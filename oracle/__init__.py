@@ -21,6 +21,8 @@ Pieces:
     Fermi-Dirac operator (forward recurrence);
   * :func:`ac_corr`, :func:`ac_cond` -- optical-conductivity correlation and
     its windowed sine transform (Kubo formula);
+  * :func:`ac_cond_imag` -- the imaginary part of the optical conductivity
+    from the real part by the Kramers-Kronig relation;
   * :func:`haydock`, :func:`haydock_ldos` -- the Lanczos recursion of the
     Haydock method and the continued fraction of the Green's function;
   * :func:`jackson`, :func:`kpm_moments`, :func:`kubo_bastin` -- the
@@ -310,6 +312,40 @@ def ac_cond(corr, dt: float, beta: float, area: float, kind: str = "hann"):
         s = np.sum(w * np.sin(omega[j] * tk) * 2.0 * np.imag(cbar)) * dt
         sigma[j] = (np.exp(-beta * omega[j]) - 1.0) / (omega[j] * area) * s
     return omega, sigma
+
+
+def ac_cond_imag(re_sigma):
+    """Imaginary part of the optical conductivity by the Kramers-Kronig
+    relation (Sec. "Optical conductivity"):
+        Im sigma(w) = -(1/pi) P int_{-inf}^{inf} Re sigma(w') / (w' - w) dw',
+    on the uniform grid w_k = k dw of ``re_sigma`` (the grid of ac_cond;
+    the spacing cancels).  Readings: Re sigma(-w) = Re sigma(w), since
+    sigma(-w) = sigma(w)^* for a real response; Re sigma is piecewise linear
+    between grid points and falls linearly to zero one spacing past the last
+    one.  The principal value is the exact integral of that function,
+    segment by segment over the whole line: on a segment [x0, x1] with
+    Re sigma = y(x) linear,
+        int y(x)/(x - w) dx = y(w) (ln|x1 - w| - ln|x0 - w|) + (y1 - y0),
+    where y(w) extends the segment's line; at w = x0 or x1 the logarithm of
+    zero is left out, since the two segments that meet at w contribute it
+    with opposite signs and the same y(w)."""
+    y = np.asarray(re_sigma, dtype=np.float64)
+    n = y.shape[0]
+    # nodes on the whole line in units of the spacing: -n .. n, value 0 at +-n
+    xs = np.arange(-n, n + 1, dtype=np.float64)
+    ys = np.concatenate([[0.0], y[:0:-1], y, [0.0]])
+    x0, x1, y0, y1 = xs[:-1], xs[1:], ys[:-1], ys[1:]
+    slope = y1 - y0  # segments have unit length
+    out = np.zeros(n)
+    for k in range(n):
+        w = float(k)
+        yw = y0 + slope * (w - x0)
+        d1 = np.abs(x1 - w)
+        d0 = np.abs(x0 - w)
+        l1 = np.where(d1 > 0, np.log(np.where(d1 > 0, d1, 1.0)), 0.0)
+        l0 = np.where(d0 > 0, np.log(np.where(d0 > 0, d0, 1.0)), 0.0)
+        out[k] = -np.sum(yw * (l1 - l0) + slope) / np.pi
+    return out
 
 
 def haydock(row_ptr, col, val, onsite, psi0, n_iter: int, breakdown: float = 1e-11):

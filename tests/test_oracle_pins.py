@@ -553,6 +553,57 @@ def test_ac_conductivity_transform_vs_fft():
     assert sigma[0] == 0.0 and np.allclose(omega, np.arange(nt) * np.pi / (nt * dt))
 
 
+def _kk_pair(omega, a, eta):
+    """sigma(w) = -i [1/(a - w - i eta) + 1/(-a - w - i eta)]: two causal
+    poles (analytic for Im w > 0) placed so that sigma(-w) = sigma(w)^*."""
+    return -1j * (1.0 / (a - omega - 1j * eta) + 1.0 / (-a - omega - 1j * eta))
+
+
+def test_kramers_kronig_closed_form_pair():
+    """The Kramers-Kronig transform of Re sigma of a closed-form causal pair
+    gives its Im sigma: within the interpolation error of the grid (spacing
+    eta/20: about 1e-3 of the peak) and the truncated tail (1e-5)."""
+    a, eta, dw = 2.0, 0.2, 0.01
+    omega = np.arange(2000) * dw  # up to 20 = 10 a
+    sig = _kk_pair(omega, a, eta)
+    assert np.allclose(_kk_pair(-omega, a, eta), np.conj(sig))
+    im = oracle.ac_cond_imag(sig.real)
+    err = np.max(np.abs(im - sig.imag)) / np.max(np.abs(sig.imag))
+    assert err < 2e-3, err
+    # the transform is linear and odd in its data's sign, and zero for zero
+    assert np.array_equal(oracle.ac_cond_imag(np.zeros(50)), np.zeros(50))
+    assert np.allclose(oracle.ac_cond_imag(-3.0 * sig.real), -3.0 * im)
+
+
+def test_kramers_kronig_vs_exact_diagonalisation():
+    """Eq. (ac_diag) of the paper evaluated by exact diagonalisation of a
+    small disordered graphene flake (one k-point, Omega_c the sample's area,
+    v = -J, e = hbar = 1) with w -> w + i eta is analytic for Im w > 0 and
+    satisfies sigma(-w) = sigma(w)^*: the Kramers-Kronig transform of its
+    real part on a fine grid gives its imaginary part.  xx and xy."""
+    lat = inputs.graphene(4, 3, onsite=inputs.anderson(np.random.default_rng(7), 24, 1.0))
+    e, u = np.linalg.eigh(lat.dense())
+    beta, mu, eta = 4.0, 0.3, 0.15
+    F = oracle.fermi(e, beta, mu)
+    dE = e[:, None] - e[None, :]  # eps_m - eps_n
+    same = np.abs(dE) < 1e-9  # degenerate pairs: the Drude part, left out
+    w_mn = np.where(same, 0.0, (F[:, None] - F[None, :]) / np.where(same, 1.0, dE))
+    area = lat.area
+    dw = 0.0125
+    omega = np.arange(4000) * dw  # up to 50 eV, three times the widest transition
+    for axes in ((0, 0), (0, 1)):
+        va = -(u.conj().T @ _dense_of(lat, inputs.current_values(lat, axes[0])) @ u)  # <m|v_a|n>
+        vb = -(u.conj().T @ _dense_of(lat, inputs.current_values(lat, axes[1])) @ u)
+        # <n|v_a|m><m|v_b|n> for each (m, n)
+        M = va.T * vb
+        sig = np.array([1j / area * np.sum(w_mn * M / (dE - (w + 1j * eta))) for w in omega])
+        sig_neg = np.array([1j / area * np.sum(w_mn * M / (dE - (-w + 1j * eta))) for w in omega[:50]])
+        assert np.allclose(sig_neg, np.conj(sig[:50]), atol=1e-12 * np.max(np.abs(sig)))
+        im = oracle.ac_cond_imag(sig.real)
+        err = np.max(np.abs(im - sig.imag)) / np.max(np.abs(sig.imag))
+        assert err < 5e-3, (axes, err)
+
+
 def test_ac_graphene_universal_conductivity_and_isotropy():
     """Pristine graphene (256^2 cells, one random-phase state) at beta = 10/eV,
     mu = 0: in the linear part of the spectrum Re sigma_xx is the universal
