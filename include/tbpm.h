@@ -66,7 +66,8 @@ typedef enum {
 } tbpm_window;
 
 /* flags */
-#define TBPM_FLAG_DEVICE_PTRS 0x1u /* set_values: val/onsite are device pointers */
+#define TBPM_FLAG_HOST_PTRS 0x0u   /* create, set_values: the arrays are host memory (the default) */
+#define TBPM_FLAG_DEVICE_PTRS 0x1u /* create, set_values: the arrays are device memory of the current device */
 #define TBPM_FLAG_ASYNC 0x2u       /* propagate: do not synchronise; skip the norm check */
 #define TBPM_FLAG_NO_GRAPH 0x4u    /* propagate: plain kernel launches instead of a replayed HIP graph */
 
@@ -80,22 +81,30 @@ typedef enum {
  * Eq. (hal) and Eq. (eq:ham_mat_finite)).
  *
  *   n_orb    number of orbitals (rows), 1 <= n_orb < 2^31.
- *   row_ptr  host, [n_orb + 1], row_ptr[0] = 0, non-decreasing; nnz = row_ptr[n_orb].
- *   col_idx  host, [nnz], column of each stored off-diagonal element, in [0, n_orb),
+ *   row_ptr  [n_orb + 1], row_ptr[0] = 0, non-decreasing; nnz = row_ptr[n_orb].
+ *   col_idx  [nnz], column of each stored off-diagonal element, in [0, n_orb),
  *            never equal to its row.  Order inside a row is free; repeated
  *            (row, col) pairs are summed.
- *   val      host, [2 * nnz] doubles, the complex matrix elements H_ij (not -t_ij:
+ *   val      [2 * nnz] doubles, the complex matrix elements H_ij (not -t_ij:
  *            a hopping written "t = -2.7 eV" is passed as -2.7).  The FULL Hermitian
  *            pattern is required (both (i,j) and (j,i)); the paper's half list with
  *            t_ij(R) = t_ji(-R)^* must be expanded by the caller.
- *   onsite   host, [n_orb], real on-site energies eps_i (eV).
+ *   onsite   [n_orb], real on-site energies eps_i (eV).
+ *   flags    TBPM_FLAG_HOST_PTRS (0): the four arrays are host memory.
+ *            TBPM_FLAG_DEVICE_PTRS: they are device memory of the current
+ *            device (TBPM_E_ARG otherwise); the library reads them into its
+ *            own host copy (row_ptr first, then the rest; synchronous), so
+ *            the caller keeps no host copy.  Every check below then runs on
+ *            that copy, exactly as for host pointers.
  *   out      receives the handle; release with tbpm_hamiltonian_destroy.
+ * The caller keeps ownership of the arrays; the library copies them.
  * Errors: TBPM_E_ARG, TBPM_E_CSR, TBPM_E_NOT_HERMITIAN (checked on the host
- * before any device call), TBPM_E_OOM, TBPM_E_DEVICE.  On error *out is NULL.
- * If every stored element has zero imaginary part the device copy is real.
+ * before the device copy of H is built), TBPM_E_OOM, TBPM_E_DEVICE.  On
+ * error *out is NULL.  If every stored element has zero imaginary part the
+ * device copy is real.
  */
 tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const int32_t *col_idx,
-                                    const double *val, const double *onsite,
+                                    const double *val, const double *onsite, uint32_t flags,
                                     tbpm_hamiltonian **out);
 
 /*
@@ -411,6 +420,23 @@ tbpm_status tbpm_fermi_cheb(double beta, double mu, double rescale, double tol, 
  */
 tbpm_status tbpm_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
                          tbpm_window win, double *omegas, double *sigma, void *stream);
+
+/*
+ * Imaginary part of the optical conductivity from its real part by the
+ * Kramers-Kronig relation (Sec. "Optical conductivity"):
+ *   Im sigma(w) = -(1/pi) P int_{-inf}^{inf} Re sigma(w') / (w' - w) dw',
+ * on the uniform grid w_j = j dw, j = 0 .. n-1, that tbpm_ac_cond writes (the
+ * spacing drops out).  Re sigma(-w) = Re sigma(w) (sigma(-w) = sigma(w)^* for
+ * a real response); between grid points Re sigma is taken linear, and it
+ * falls linearly to zero one spacing past the last point; the principal
+ * value of that function is integrated exactly (closed-form weights per
+ * grid point, a direct O(n^2) sum in FP64 with compensation, fixed order).
+ * Like the real part it omits the Drude weight at w = 0.
+ *   re_sigma  device [n] f64 (e.g. the sigma of tbpm_ac_cond)
+ *   n         1 .. 2^17
+ *   im_sigma  device [n] f64, written; must not alias re_sigma
+ */
+tbpm_status tbpm_ac_cond_imag(const double *re_sigma, int32_t n, double *im_sigma, void *stream);
 
 /*
  * DOS from the correlations (paper, Eq. (dos_tbpm), with C(-t) = C(t)^*):

@@ -14,6 +14,9 @@
 //    row's stored elements) and contracted with the row's psi2 columns; FP64
 //    per-tile partials in the layout of the correlation, for k_reduce.
 //  * k_ac_cond: the windowed sine transform of the Kubo formula, Eq. (AC).
+//  * k_ac_kk: the imaginary part from the real part by the Kramers-Kronig
+//    relation (the principal-value integral of the piecewise-linear,
+//    even extension of Re sigma, as closed-form weights per grid point).
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -142,6 +145,41 @@ __global__ __launch_bounds__(kWG) void k_ac_cond(const d2 *__restrict__ corr, in
     sigma[j] = (exp(-beta * w_j) - 1.0) / (w_j * area) * (sum + comp) * dt;
 }
 
+// P int phi(u) / (u - m) du for the unit hat phi(u) = max(0, 1 - |u|):
+//   g(m) = (1 - m) ln|1 - m| - (1 + m) ln|1 + m| + 2 m ln|m|   (0 ln 0 = 0),
+// odd in m; for |m| >= 2 in the form -|m| log1p(-1/m^2) - log1p(2/(|m| - 1)),
+// which has no cancellation between terms of size |m| ln|m|.
+__device__ __forceinline__ double kk_hat(int64_t m) {
+    const double a = (double)(m < 0 ? -m : m);
+    double g;
+    if (a < 2.0) {
+        const double t1 = a == 1.0 ? 0.0 : (1.0 - a) * log(fabs(1.0 - a));
+        const double t3 = a == 0.0 ? 0.0 : 2.0 * a * log(a);
+        g = t1 - (1.0 + a) * log(1.0 + a) + t3;
+    } else {
+        g = -a * log1p(-1.0 / (a * a)) - log1p(2.0 / (a - 1.0));
+    }
+    return m < 0 ? -g : g;
+}
+
+// Im sigma_k = -(1/pi) P int Re sigma(|w|)/(w - w_k) dw on the grid w_j = j dw
+// with Re sigma = sum_j y_j phi(w/dw - j) (linear between grid points, zero
+// one spacing past the last) and its mirror image for w < 0: node 0 gives
+// y_0 g(k), node j >= 1 gives y_j (g(k - j) + g(k + j)).  One thread per k;
+// the sum over j is compensated (Neumaier) and runs in a fixed order.
+__global__ __launch_bounds__(kWG) void k_ac_kk(const double *__restrict__ re, int n, double *__restrict__ im) {
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k >= n) return;
+    double sum = re[0] * kk_hat(k), comp = 0.0;
+    for (int j = 1; j < n; ++j) {
+        const double term = re[j] * (kk_hat((int64_t)k - j) + kk_hat((int64_t)k + j));
+        const double t = sum + term;
+        comp += fabs(sum) >= fabs(term) ? (sum - t) + term : (term - t) + sum;
+        sum = t;
+    }
+    im[k] = -(sum + comp) / M_PI;
+}
+
 int64_t grid_for_n(int64_t n) {
     int64_t b = (n + kWG - 1) / kWG;
     if (b > 65536) b = 65536;
@@ -180,6 +218,11 @@ hipError_t launch_jcorr(bool fp32, const TileDesc *tiles, int32_t n_tiles, int32
     else
         hipLaunchKernelGGL(k_jcorr<double>, dim3((unsigned)n_tiles), dim3(kWG), 0, st, tiles, n_tiles, log2sp, S,
                            log2s2, state, slice_off, col, (const d2 *)jval, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_ac_kk(const double *re, int32_t n, double *im, hipStream_t st) {
+    hipLaunchKernelGGL(k_ac_kk, dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG), 0, st, re, n, im);
     return hipGetLastError();
 }
 

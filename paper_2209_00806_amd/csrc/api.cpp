@@ -68,19 +68,76 @@ tbpm_status check_device(const Engine &eng) {
     return TBPM_OK;
 }
 
+namespace {
+
+// memory of the current device (hipMalloc'd, or a view into it)
+bool on_current_device(const void *p) {
+    if (!p) return false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice && a.device == dev;
+}
+
+// The CSR arrays given as device pointers, read into host memory: row_ptr
+// first (its last entry sizes the rest), checked before the other reads.
+tbpm_status read_device_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                            const double *onsite, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
+                            std::vector<double> &va, std::vector<double> &on) {
+    if (n < 1 || n >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb must be in [1, 2^31)");
+    if (!on_current_device(row_ptr) || !on_current_device(onsite))
+        return fail(TBPM_E_ARG, "TBPM_FLAG_DEVICE_PTRS: row_ptr and onsite must be device memory of the current device");
+    rp.resize(n + 1);
+    on.resize(n);
+    hipError_t e = hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(on.data(), onsite, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read device CSR");
+    if (rp[0] != 0) return fail(TBPM_E_CSR, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(TBPM_E_CSR, "row_ptr must be non-decreasing");
+    const int64_t nnz = rp[n];
+    ci.resize(nnz);
+    va.resize(2 * nnz);
+    if (nnz > 0) {
+        if (!on_current_device(col) || !on_current_device(val))
+            return fail(TBPM_E_ARG, "TBPM_FLAG_DEVICE_PTRS: col_idx and val must be device memory of the current device");
+        e = hipMemcpy(ci.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(va.data(), val, sizeof(double) * 2 * nnz, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "read device CSR");
+    }
+    return TBPM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *tbpm_version(void) { return "libtbpm 0.1 (gfx950)"; }
 
 tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const int32_t *col_idx,
-                                    const double *val, const double *onsite, tbpm_hamiltonian **out) {
+                                    const double *val, const double *onsite, uint32_t flags,
+                                    tbpm_hamiltonian **out) {
     if (!out) return fail(TBPM_E_ARG, "out must not be NULL");
     *out = nullptr;
+    if (flags & ~TBPM_FLAG_DEVICE_PTRS) return fail(TBPM_E_ARG, "unknown flags");
     tbpm_hamiltonian *H = new (std::nothrow) tbpm_hamiltonian();
     if (!H) return fail(TBPM_E_OOM, "host allocation failed");
     tbpm_status st;
     try {
-        st = canonical_csr(n_orb, row_ptr, col_idx, val, onsite, H->csr);
+        if (flags & TBPM_FLAG_DEVICE_PTRS) {
+            std::vector<int64_t> rp;
+            std::vector<int32_t> ci;
+            std::vector<double> va, on;
+            st = read_device_csr(n_orb, row_ptr, col_idx, val, onsite, rp, ci, va, on);
+            if (st == TBPM_OK)
+                st = canonical_csr(n_orb, rp.data(), ci.data(), va.data(), on.data(), H->csr);
+        } else {
+            st = canonical_csr(n_orb, row_ptr, col_idx, val, onsite, H->csr);
+        }
     } catch (const std::bad_alloc &) {
         st = fail(TBPM_E_OOM, "host allocation failed");
     }
@@ -620,6 +677,15 @@ tbpm_status tbpm_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, 
     if (win != TBPM_WIN_HANN && win != TBPM_WIN_NONE) return fail(TBPM_E_ARG, "unknown window");
     hipError_t e = launch_ac_cond(corr, n_steps, n_states, dt, beta, area, (int)win, omegas, sigma, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "launch optical conductivity");
+    return TBPM_OK;
+}
+
+tbpm_status tbpm_ac_cond_imag(const double *re_sigma, int32_t n, double *im_sigma, void *stream) {
+    if (!re_sigma || !im_sigma) return fail(TBPM_E_ARG, "NULL argument");
+    if (n < 1 || n > (1 << 17)) return fail(TBPM_E_ARG, "n must be in [1, 2^17] (the transform is a direct O(n^2) sum)");
+    if (re_sigma == im_sigma) return fail(TBPM_E_ARG, "re_sigma and im_sigma must not be the same array");
+    hipError_t e = launch_ac_kk(re_sigma, n, im_sigma, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch Kramers-Kronig transform");
     return TBPM_OK;
 }
 

@@ -167,6 +167,8 @@ hipError_t launch_jcorr(bool fp32, const TileDesc *tiles, int32_t n_tiles, int32
                         double *partials, hipStream_t st);
 hipError_t launch_ac_cond(const double *corr, int32_t n_steps, int32_t n_states, double dt, double beta, double area,
                           int window, double *omegas, double *sigma, hipStream_t st);
+// im[k] = Kramers-Kronig transform of re[0 .. n) on a uniform grid from 0
+hipError_t launch_ac_kk(const double *re, int32_t n, double *im, hipStream_t st);
 // Chebyshev coefficients a_k of the Fermi-Dirac operator f(H) = sum_k a_k
 // T_k(H/rescale) (host); empty if they do not converge below tol
 std::vector<double> fermi_cheb_coeffs(double beta, double mu, double rescale, double tol);

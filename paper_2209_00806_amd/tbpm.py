@@ -61,7 +61,7 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_uint32, ctypes.c_size_t)
     PP = ctypes.POINTER(ctypes.c_void_p)
     sig = {
-        "tbpm_hamiltonian_create": [I64, P, P, P, P, PP],
+        "tbpm_hamiltonian_create": [I64, P, P, P, P, U32, PP],
         "tbpm_hamiltonian_set_values": [P, P, P, U32, P],
         "tbpm_hamiltonian_info": [P, P, P, P, P, P],
         "tbpm_hamiltonian_pattern": [P, P, P],
@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         "tbpm_quasi_eigenstates": [P, P, I32, I32, D, D, D, ctypes.c_int, P, I32, ctypes.c_int, P, P, U32, P],
         "tbpm_ac_corr": [P, P, P, P, I32, I32, D, D, D, D, D, D, ctypes.c_int, P, U32, P],
         "tbpm_ac_cond": [P, I32, I32, D, D, D, ctypes.c_int, P, P, P],
+        "tbpm_ac_cond_imag": [P, I32, P, P],
         "tbpm_fermi_cheb": [D, D, D, D, P, I32, P],
         "tbpm_kpm_moments": [P, P, P, P, I32, I32, D, P, P, P],
         "tbpm_kubo_bastin": [P, I32, D, D, D, I32, D, P, I32, D, P, P, P, P],
@@ -164,13 +165,25 @@ class Hamiltonian:
     """Library-owned device copy of a tight-binding Hamiltonian."""
 
     def __init__(self, n_orb: int, row_ptr, col, val, onsite):
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col, dtype=np.int32)
-        va = np.ascontiguousarray(val, dtype=np.complex128)
-        on = np.ascontiguousarray(onsite, dtype=np.float64)
+        """CSR arrays as numpy arrays (host), or all four as CUDA tensors on the
+        current device (int64, int32, complex128, float64), which the library
+        reads from device memory (TBPM_FLAG_DEVICE_PTRS)."""
         h = ctypes.c_void_p()
-        _check(lib().tbpm_hamiltonian_create(int(n_orb), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
-                                             on.ctypes.data, ctypes.byref(h)))
+        if hasattr(row_ptr, "is_cuda") and row_ptr.is_cuda:
+            import torch
+
+            for t, dt, name in ((row_ptr, torch.int64, "row_ptr"), (col, torch.int32, "col"),
+                                (val, torch.complex128, "val"), (onsite, torch.float64, "onsite")):
+                _require_cuda(t, dt, name)
+            _check(lib().tbpm_hamiltonian_create(int(n_orb), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(onsite),
+                                                 FLAG_DEVICE_PTRS, ctypes.byref(h)))
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(col, dtype=np.int32)
+            va = np.ascontiguousarray(val, dtype=np.complex128)
+            on = np.ascontiguousarray(onsite, dtype=np.float64)
+            _check(lib().tbpm_hamiltonian_create(int(n_orb), rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                                                 on.ctypes.data, 0, ctypes.byref(h)))
         self._h = h
 
     @classmethod
@@ -523,6 +536,19 @@ def ac_cond(corr, dt: float, beta: float, area: float, window: str = "hann", str
     _check(lib().tbpm_ac_cond(_ptr(corr), nt, S, float(dt), float(beta), float(area), WIN[window], _ptr(om), _ptr(sg),
                               _stream(stream)))
     return om, sg
+
+
+def ac_cond_imag(re_sigma, stream=None):
+    """Im sigma on the same grid from Re sigma (a CUDA float64 tensor [n], e.g.
+    ac_cond's second output) by the Kramers-Kronig relation."""
+    import torch
+
+    _require_cuda(re_sigma, torch.float64, "re_sigma")
+    if re_sigma.dim() != 1:
+        raise ValueError("re_sigma must be one-dimensional")
+    im = torch.empty_like(re_sigma)
+    _check(lib().tbpm_ac_cond_imag(_ptr(re_sigma), int(re_sigma.shape[0]), _ptr(im), _stream(stream)))
+    return im
 
 
 def ldos(H: Hamiltonian, orbitals, n_steps: int, dt: float, rescale: float = 0.0, tol: float = 1e-12,

@@ -76,12 +76,23 @@ def test_ac_corr_vs_oracle(case, order, fused, precision):
     assert got.shape == (nt, S)
     bar = 1e-10 if precision == "fp64" else 2e-5
     assert _rel(got, ref) < bar, _rel(got, ref)
-    # the transform of the library's correlation equals the oracle's transform of it
+    # the library's chain (its correlation -> Re sigma -> Im sigma by the
+    # Kramers-Kronig relation) against the oracle's chain; both transforms
+    # are linear, so the correlation's difference bounds theirs
     area = lat.area if lat.area > 0 else float(lat.n_orb)
     om, sg = tbpm.ac_cond(_dev(got), dt, beta, area)
-    om_r, sg_r = oracle.ac_cond(got, dt, beta, area)
-    assert np.max(np.abs(om.cpu().numpy() - om_r)) < 1e-12 * om_r[-1]
-    assert _rel(sg.cpu().numpy(), sg_r) < 1e-12
+    om_r, sg_r = oracle.ac_cond(ref, dt, beta, area)
+    om = om.cpu().numpy()
+    assert np.max(np.abs(om - om_r)) < 1e-12 * om_r[-1]
+    dc = np.max(np.abs(got.mean(axis=1) - ref.mean(axis=1)))
+    bound = np.zeros(nt)
+    bound[1:] = np.abs((np.exp(-beta * om_r[1:]) - 1.0) / (om_r[1:] * area)) * dt * np.sum(oracle.window(nt)) * 2 * dc
+    d_sg = np.abs(sg.cpu().numpy() - sg_r)
+    assert np.all(d_sg <= 1.01 * bound + 1e-13 * np.max(np.abs(sg_r))), np.max(d_sg - bound)
+    im = tbpm.ac_cond_imag(sg).cpu().numpy()
+    im_r = oracle.ac_cond_imag(sg_r)
+    kk_gain = 2.0 / math.pi * (2 * math.log(2.0) + math.log(2.0 * nt) + 1.0)
+    assert np.max(np.abs(im - im_r)) <= kk_gain * np.max(d_sg) + 1e-10 * np.max(np.abs(im_r))
 
 
 def test_ac_repeat_calls_share_the_handle():
@@ -104,6 +115,57 @@ def test_ac_repeat_calls_share_the_handle():
         assert _rel(c, c_ref) < 1e-10
         a = tbpm.ac_corr(H, jx, jx, _dev(psi0), 40, dt, 15.0, 0.3, rescale=f, fermi_tol=1e-13).cpu().numpy()
         assert _rel(a, a_ref) < 1e-10
+
+
+def test_ac_transform_alone_vs_oracle():
+    """tbpm_ac_cond on seeded synthetic correlations (the same input for both
+    sides), Hann window, against the oracle's transform."""
+    print("case ac transform alone", flush=True)
+    rng = np.random.default_rng(98)
+    corr = rng.standard_normal((300, 2)) + 1j * rng.standard_normal((300, 2))
+    om, sg = tbpm.ac_cond(_dev(corr), 0.31, 20.0, 3.5)
+    om_r, sg_r = oracle.ac_cond(corr, 0.31, 20.0, 3.5)
+    assert np.max(np.abs(om.cpu().numpy() - om_r)) < 1e-12 * om_r[-1]
+    assert _rel(sg.cpu().numpy(), sg_r) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 300, 2048])
+def test_ac_cond_imag_vs_oracle(n):
+    """The Kramers-Kronig kernel on seeded synthetic Re sigma (the same input
+    for both sides; a smooth part plus noise, with the first value zero as
+    tbpm_ac_cond writes it and without) against the oracle: within 1e-10 of
+    the largest |Im sigma|."""
+    print(f"case kk n={n}", flush=True)
+    rng = np.random.default_rng(99 + n)
+    x = np.arange(n) / max(n, 1)
+    re = np.exp(-((x - 0.3) / 0.1) ** 2) + 0.2 * rng.standard_normal(n)
+    for first in (re[0], 0.0):
+        re[0] = first
+        im = tbpm.ac_cond_imag(_dev(re)).cpu().numpy()
+        im_r = oracle.ac_cond_imag(re)
+        assert np.max(np.abs(im - im_r)) <= 1e-10 * max(np.max(np.abs(im_r)), 1e-300), n
+
+
+def test_ac_cond_imag_closed_form_pair():
+    """Through the GPU kernel: the transform of the real part of the causal
+    pole pair sigma(w) = -i [1/(a - w - i eta) + 1/(-a - w - i eta)] gives its
+    imaginary part within the grid's interpolation error (1e-3 of the peak
+    at a spacing of eta/20)."""
+    print("case kk closed form", flush=True)
+    a, eta, dw = 2.0, 0.2, 0.01
+    omega = np.arange(2000) * dw
+    sig = -1j * (1.0 / (a - omega - 1j * eta) + 1.0 / (-a - omega - 1j * eta))
+    im = tbpm.ac_cond_imag(_dev(sig.real)).cpu().numpy()
+    assert np.max(np.abs(im - sig.imag)) < 2e-3 * np.max(np.abs(sig.imag))
+
+
+def test_ac_cond_imag_argument_errors():
+    x = torch.zeros(16, dtype=torch.float64, device="cuda")  # x + 64 bytes is its second half
+    L = tbpm.lib()
+    assert L.tbpm_ac_cond_imag(None, 8, x.data_ptr(), None) == 1
+    assert L.tbpm_ac_cond_imag(x.data_ptr(), 0, x.data_ptr() + 64, None) == 1
+    assert L.tbpm_ac_cond_imag(x.data_ptr(), (1 << 17) + 1, x.data_ptr() + 64, None) == 1
+    assert L.tbpm_ac_cond_imag(x.data_ptr(), 8, x.data_ptr(), None) == 1  # in place
 
 
 def test_ac_no_window():

@@ -72,12 +72,16 @@ def test_kpm_moments_vs_oracle(case, order, fused):
     assert got.shape == (M, M)
     assert _rel(got, ref) < 1e-11, _rel(got, ref)
     assert t["chunks"] >= 1 and t["product_ms"] >= 0.0
-    # the energy integral on the library's moments against the oracle's
+    # the energy integral alone: the library's kernel on the oracle's moments
     mus = np.linspace(-0.8 * f, 0.8 * f, 9)
     e_lo, e_hi = -0.98 * f, 0.98 * f
-    sg, en, w = tbpm.kubo_bastin(mu, f, e_lo, e_hi, 512, 40.0, mus, 1.0)
-    sg_ref = oracle.kubo_bastin(got, f, e_lo, e_hi, 512, 40.0, mus, 1.0)
-    assert np.max(np.abs(sg.cpu().numpy() - sg_ref)) < 1e-10 * max(np.max(np.abs(sg_ref)), 1e-300)
+    sg, en, w = tbpm.kubo_bastin(_dev(ref), f, e_lo, e_hi, 512, 40.0, mus, 1.0)
+    sg_ref = oracle.kubo_bastin(ref, f, e_lo, e_hi, 512, 40.0, mus, 1.0)
+    scale = max(np.max(np.abs(sg_ref)), 1e-300)
+    assert np.max(np.abs(sg.cpu().numpy() - sg_ref)) < 1e-10 * scale
+    # and the library's whole chain (its own moments) against the oracle's
+    sg2, _, _ = tbpm.kubo_bastin(mu, f, e_lo, e_hi, 512, 40.0, mus, 1.0)
+    assert np.max(np.abs(sg2.cpu().numpy() - sg_ref)) < 1e-8 * scale
     en = en.cpu().numpy()
     assert np.all(np.diff(en) < 0) and e_lo < en[-1] < en[0] < e_hi
 

@@ -646,3 +646,59 @@ def test_graph_cache_follows_lds_tier():
             H.set_launch_config(2, 1, 1, 1, vec=vec, fused=tier)
             got = tbpm.propagate(H, psi0, 24, dt, f).cpu().numpy()
             assert _rel(got, base) < 1e-13, (vec, tier)
+
+
+def test_create_from_device_pointers():
+    """tbpm_hamiltonian_create with TBPM_FLAG_DEVICE_PTRS: the CSR given as
+    CUDA tensors (unsorted rows with a duplicate entry, complex hoppings)
+    gives the handle a host CSR would (same merged pattern, bit-identical
+    correlations) and matches the oracle; malformed and non-Hermitian device
+    CSRs get the host path's errors; arrays on the host with the device flag
+    are refused."""
+    print("case create from device pointers", flush=True)
+    lat = _complex_graphene(9, 7, 12)
+    # shuffle every row and split one entry into two summed parts
+    rng = np.random.default_rng(3)
+    rp, col, val = lat.row_ptr.copy(), lat.col.copy(), lat.val.copy()
+    for i in range(lat.n_orb):
+        a, b = rp[i], rp[i + 1]
+        p = rng.permutation(b - a)
+        col[a:b] = col[a:b][p]
+        val[a:b] = val[a:b][p]
+    dup_col = np.insert(col, rp[1], col[0])
+    dup_val = np.insert(val, rp[1], 0.25 * val[0])
+    dup_val[0] *= 0.75
+    dup_rp = rp.copy()
+    dup_rp[1:] += 1
+    H_host = tbpm.Hamiltonian(lat.n_orb, dup_rp, dup_col, dup_val, lat.onsite)
+    H_dev = tbpm.Hamiltonian(lat.n_orb, _dev(dup_rp), _dev(dup_col), _dev(dup_val), _dev(lat.onsite))
+    for a, b in zip(H_host.pattern(), H_dev.pattern()):
+        assert np.array_equal(a, b)
+    assert H_host.info() == H_dev.info()
+    S, nt = 3, 64
+    psi0 = inputs.random_phase_states(np.random.default_rng(4), lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.05
+    dt = math.pi / f
+    c_host = tbpm.propagate(H_host, _dev(psi0), nt, dt, f).cpu().numpy()
+    c_dev = tbpm.propagate(H_dev, _dev(psi0), nt, dt, f).cpu().numpy()
+    assert np.array_equal(c_host, c_dev)
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    assert _rel(c_dev, ref) < 1e-10
+    bad_rp = dup_rp.copy()
+    bad_rp[3] = bad_rp[4] + 1  # not monotone
+    with pytest.raises(tbpm.TBPMError) as e:
+        tbpm.Hamiltonian(lat.n_orb, _dev(bad_rp), _dev(dup_col), _dev(dup_val), _dev(lat.onsite))
+    assert e.value.name == "TBPM_E_CSR"
+    nh_val = dup_val.copy()
+    nh_val[5] += 0.1  # breaks H_ij = conj(H_ji)
+    with pytest.raises(tbpm.TBPMError) as e:
+        tbpm.Hamiltonian(lat.n_orb, _dev(dup_rp), _dev(dup_col), _dev(nh_val), _dev(lat.onsite))
+    assert e.value.name == "TBPM_E_NOT_HERMITIAN"
+    L = tbpm.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    st = L.tbpm_hamiltonian_create(lat.n_orb, dup_rp.ctypes.data, dup_col.ctypes.data, dup_val.ctypes.data,
+                                   lat.onsite.ctypes.data, tbpm.FLAG_DEVICE_PTRS, ctypes.byref(h))
+    assert st == 1 and not h.value
+    H_host.close()
+    H_dev.close()

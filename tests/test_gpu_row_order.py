@@ -92,8 +92,10 @@ def test_renumbered_rows_backward_and_device_values():
     noise = sp.csr_matrix((rng.standard_normal(lat.nnz) + 1j * rng.standard_normal(lat.nnz), lat.col, lat.row_ptr),
                           shape=(n, n))
     herm = (noise + noise.conj().T) * 0.5
-    new_val = _dev(lat.val + 0.02 * np.asarray(herm[rows, lat.col]).ravel())
-    new_ons = _dev(lat.onsite + 0.05 * rng.standard_normal(n))
+    new_val_h = lat.val + 0.02 * np.asarray(herm[rows, lat.col]).ravel()
+    new_ons_h = lat.onsite + 0.05 * rng.standard_normal(n)
+    new_val = _dev(new_val_h)
+    new_ons = _dev(new_ons_h)
     out = {}
     for order in (0, 1):
         H = tbpm.Hamiltonian.from_lattice(lat)
@@ -108,7 +110,7 @@ def test_renumbered_rows_backward_and_device_values():
     for a, b in zip(out[1], out[0]):
         assert _rel(a, b) < 1e-12
     rp, col = lat.row_ptr, lat.col
-    ref2, _, _ = oracle.propagate(rp, col, new_val.cpu().numpy(), new_ons.cpu().numpy(), psi0, nt, dt, f)
+    ref2, _, _ = oracle.propagate(rp, col, new_val_h, new_ons_h, psi0, nt, dt, f)
     assert _rel(out[1][3], ref2) < 1e-10
 
 

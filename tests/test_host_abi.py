@@ -105,9 +105,22 @@ def test_create_rejects_non_finite_and_bad_sizes():
     _expect("TBPM_E_ARG", lat.n_orb, lat.row_ptr, lat.col, lat.val, ons)
     L = tbpm.lib()
     h = ctypes.c_void_p()
-    assert L.tbpm_hamiltonian_create(0, None, None, None, None, ctypes.byref(h)) == 1
-    assert L.tbpm_hamiltonian_create(-5, None, None, None, None, ctypes.byref(h)) == 1
-    assert L.tbpm_hamiltonian_create(4, None, None, None, None, None) == 1
+    assert L.tbpm_hamiltonian_create(0, None, None, None, None, 0, ctypes.byref(h)) == 1
+    assert L.tbpm_hamiltonian_create(-5, None, None, None, None, 0, ctypes.byref(h)) == 1
+    assert L.tbpm_hamiltonian_create(4, None, None, None, None, 0, None) == 1
+    # unknown flags, and device pointers that are not device memory (host
+    # arrays, NULL): refused on the host before any copy
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    ci = np.array([1, 0], dtype=np.int32)
+    va = np.array([1.0, 0.0, 1.0, 0.0])
+    on = np.zeros(2)
+    assert L.tbpm_hamiltonian_create(2, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, on.ctypes.data, 0x80,
+                                     ctypes.byref(h)) == 1
+    assert L.tbpm_hamiltonian_create(2, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, on.ctypes.data, 1,
+                                     ctypes.byref(h)) == 1
+    assert "device memory" in L.tbpm_last_error().decode()
+    assert L.tbpm_hamiltonian_create(2, None, None, None, None, 1, ctypes.byref(h)) == 1
+    assert not h.value
 
 
 def test_entry_points_reject_null_and_bad_arguments():
