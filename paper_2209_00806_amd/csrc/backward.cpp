@@ -90,6 +90,15 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     TRY_HIP(eng.bwd_gacc.ensure((cplx ? 16 : 8) * (size_t)std::max<int64_t>(eng.mat.ell_size, 1)), "alloc gradient");
     TRY_HIP(eng.bwd_gdiag.ensure(8 * (size_t)n_rows), "alloc gradient");
     TRY_HIP(eng.bwd_coef.ensure(sizeof(PassCoef) * n_passes), "alloc coefficients");
+    if (pairs && !eng.partner_ready) {
+        const std::vector<int32_t> part = ell_partner_slots(n_rows, eng.h_slice_off, eng.h_col);
+        if (part.empty()) return fail(TBPM_E_NOT_HERMITIAN, "a stored element has no transposed partner");
+        TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
+        TRY_HIP(eng.bwd_partner.ensure(sizeof(int32_t) * std::max<size_t>(part.size(), 1)), "alloc partner slots");
+        TRY_HIP(hipMemcpy(eng.bwd_partner.ptr, part.data(), sizeof(int32_t) * part.size(), hipMemcpyHostToDevice),
+                "upload partner slots");
+        eng.partner_ready = true;
+    }
     TRY_HIP(eng.partials.ensure(sizeof(double) * 3 * (size_t)n_tiles * s_pad), "alloc partials");
     TRY_HIP(eng.counter.ensure(sizeof(int32_t) * 64), "alloc counter");
     std::vector<PassCoef> hc(n_passes);
@@ -238,6 +247,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     qp.inv_f = 1.0 / f;
     qp.gacc = eng.bwd_gacc.ptr;
     qp.gdiag = (double *)eng.bwd_gdiag.ptr;
+    qp.partner = (const int32_t *)eng.bwd_partner.ptr;
     qp.uoff = (const int32_t *)eng.st_uoff.ptr;
     qp.n1 = (const int32_t *)eng.fu_n1.ptr;
     qp.ucol = (const int32_t *)eng.st_ucol.ptr;

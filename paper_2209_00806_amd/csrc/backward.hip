@@ -302,57 +302,56 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
         const int w = (int)((soff[sl + 1] - off) / kSliceRows);
         const uint32_t base = off + row % kSliceRows;
         const V aj = xs[u], aj1 = ys[u];
-        const V ga1 = aj * w1, ga2 = aj1 * w2;
         V lam;
         if constexpr (!FIRST) lam = ((const V *)p.lam_acc)[gu];
+        // b_{j+1}, b_{j+2} on this row, weighted: the gradient of an element
+        // (p, q) is w1 Re/Im sum_s alpha_j[p] conj(b_{j+1}[q]) + w2 (alpha_{j+1},
+        // b_{j+2}), so this row q forms it for its transposed elements (q, p)
+        // from alpha at p (staged, own or 1-hop) and writes it to the slot of
+        // (p, q); every slot has one transposed partner, so one writer
+        const V b1w = bq1[gu] * w1, b2w = bq2[gu] * w2;
         {
-            const V b1 = bq1[gu], b2 = bq2[gu];
-            const double dg = unit_row_sum(unit_dot<VS>(ga1, b1, false) + unit_dot<VS>(ga2, b2, false), log2u);
+            const double dg = unit_row_sum(unit_dot<VS>(aj, b1w, false) + unit_dot<VS>(aj1, b2w, false), log2u);
             if (usub == 0) p.gdiag[row] += dg;
         }
         V acc = p.onsite[row] * aj1;
         for (int k = 0; k < w; k += KG) {
-            uint32_t slot[KG], li[KG], gc[KG];
+            uint32_t li[KG];
+            int32_t pt[KG];
             HV h[KG];
-            bool valid[KG];
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
-                valid[i] = k + i < w;
-                slot[i] = valid[i] ? base + (uint32_t)(k + i) * kSliceRows : 0u;
-                const uint32_t l = valid[i] ? (uint32_t)p.lidx[slot[i]] : lr;
-                const int32_t c = p.col[slot[i]];
-                const HV hv = val[slot[i]];
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const uint32_t l = valid ? (uint32_t)p.lidx[slot] : lr;
+                const HV hv = val[slot];
+                const int32_t ps = p.partner[slot];
                 li[i] = (l << log2u) + usub;
-                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2u) + usub;
-                h[i] = valid[i] ? hv : HV{};
+                h[i] = valid ? hv : HV{};
+                pt[i] = valid ? ps : -1;  // -1: beyond the row or a padding slot
             }
-            V xb1[KG], xb2[KG];
             GV gold[KG];
 #pragma unroll
-            for (int i = 0; i < KG; ++i) {
-                xb1[i] = bq1[gc[i]];
-                xb2[i] = bq2[gc[i]];
-                gold[i] = gacc[slot[i]];
-            }
+            for (int i = 0; i < KG; ++i) gold[i] = pt[i] >= 0 ? gacc[pt[i]] : GV{};
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
+                const V xp = xs[li[i]], yp = ys[li[i]];
                 if constexpr (CH)
-                    unit_mad_cplx<double, VS>(h[i], ys[li[i]], acc);
+                    unit_mad_cplx<double, VS>(h[i], yp, acc);
                 else
-                    unit_mad_real<double, VS>(h[i], ys[li[i]], acc);
-                const double gr =
-                    unit_row_sum(unit_dot<VS>(ga1, xb1[i], false) + unit_dot<VS>(ga2, xb2[i], false), log2u);
+                    unit_mad_real<double, VS>(h[i], yp, acc);
+                const double gr = unit_row_sum(unit_dot<VS>(xp, b1w, false) + unit_dot<VS>(yp, b2w, false), log2u);
                 if constexpr (CH) {
                     const double gi =
-                        unit_row_sum(unit_dot<VS>(ga1, xb1[i], true) + unit_dot<VS>(ga2, xb2[i], true), log2u);
-                    if (usub == 0 && valid[i]) {
+                        unit_row_sum(unit_dot<VS>(xp, b1w, true) + unit_dot<VS>(yp, b2w, true), log2u);
+                    if (usub == 0 && pt[i] >= 0) {
                         d2 nv = gold[i];
                         nv.x += gr;
                         nv.y += gi;
-                        gacc[slot[i]] = nv;
+                        gacc[pt[i]] = nv;
                     }
                 } else {
-                    if (usub == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
+                    if (usub == 0 && pt[i] >= 0) gacc[pt[i]] = gold[i] + gr;
                 }
             }
         }

@@ -26,6 +26,9 @@ namespace tbpm {
 
 using cd = std::complex<double>;
 
+// time steps per replayed graph
+constexpr int32_t kStepsPerGraph = 16;
+
 hipError_t DevBuf::ensure(size_t need) {
     if (need <= bytes && ptr) return hipSuccess;
     if (ptr) {
@@ -78,7 +81,7 @@ bool GraphKey::operator==(const GraphKey &o) const {
         chunks != o.chunks || remap != o.remap || nt != o.nt || unroll != o.unroll || staged != o.staged || vec != o.vec ||
         fused != o.fused || n_tiles != o.n_tiles || tiles_chunks != o.tiles_chunks || tiles_unit != o.tiles_unit ||
         lds_units != o.lds_units || n_steps != o.n_steps || n_qe != o.n_qe || jc_states != o.jc_states ||
-        ckpt != o.ckpt)
+        steps != o.steps || ckpt != o.ckpt)
         return false;
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i)
         if (bufs[i] != o.bufs[i]) return false;
@@ -199,6 +202,7 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n, const std::
     const int64_t S = (int64_t)e.col.size();
     h_slice_off = e.slice_off;
     h_col = e.col;
+    partner_ready = false;
     std::vector<double> v64(cplx ? 2 * S : S, 0.0);
     std::vector<float> v32(cplx ? 2 * S : S, 0.0f);
     for (int64_t q = 0; q < S; ++q) {
@@ -256,10 +260,11 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n, const std::
 }
 
 void Engine::release() {
-    if (graph_exec) {
+    if (graph_exec || graph_exec1) {
         (void)hipDeviceSynchronize();
-        (void)hipGraphExecDestroy(graph_exec);
-        graph_exec = nullptr;
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph_exec1) (void)hipGraphExecDestroy(graph_exec1);
+        graph_exec = graph_exec1 = nullptr;
     }
     void *ptrs[] = {mat.slice_off, mat.col, mat.val64, mat.val32, mat.onsite64, mat.onsite32, mat.ell_csr, mat.perm};
     for (void *p : ptrs)
@@ -271,8 +276,10 @@ void Engine::release() {
                       &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
                       &qe_acc,   &qe_part,  &qe_norm2, &ac_ja,     &ac_jb,     &ac_csr,       &ac_zero,
                       &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s,
-                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &blk_psi,   &blk_corr,     &blk_norm};
+                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &blk_psi,   &blk_corr,     &blk_norm,
+                      &bwd_partner};
     for (DevBuf *b : bufs) b->release();
+    partner_ready = false;
     staging.release();
     if (staging_done) (void)hipEventDestroy(staging_done);
     staging_done = nullptr;
@@ -908,14 +915,24 @@ tbpm_status Engine::run(const RunArgs &a) {
                                   a.jc_states > 0 ? jc_norm.ptr : nullptr};
             static_assert(sizeof(kb) == sizeof(key.bufs), "graph key buffers");
             std::memcpy(key.bufs, kb, sizeof(kb));
-            if (!graph_exec || !(key == graph_key)) {
-                if (graph_exec) {
+            // Graphs of kStepsPerGraph time steps (small operators are bound by
+            // the cost of launching a graph, not by its kernels), and a graph of
+            // one step for the remainder; the device step counter tells every
+            // step's reduce which sample it writes.
+            const int32_t n_adv = a.n_steps - 1;
+            const int32_t spg = std::min<int32_t>(kStepsPerGraph, n_adv);
+            const int32_t n_full = n_adv / spg, n_rest = n_adv % spg;
+            auto cached = [&](hipGraphExec_t &exec, GraphKey &gkey, int32_t steps) -> tbpm_status {
+                key.steps = steps;
+                if (exec && key == gkey) return TBPM_OK;
+                if (exec) {
                     TRY_HIP(hipDeviceSynchronize(), "sync before graph rebuild");
-                    TRY_HIP(hipGraphExecDestroy(graph_exec), "hipGraphExecDestroy");
-                    graph_exec = nullptr;
+                    TRY_HIP(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+                    exec = nullptr;
                 }
                 TRY_HIP(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-                tbpm_status cst = enqueue_step(capture_stream);
+                tbpm_status cst = TBPM_OK;
+                for (int32_t q = 0; q < steps && cst == TBPM_OK; ++q) cst = enqueue_step(capture_stream);
                 hipGraph_t g = nullptr;
                 hipError_t ee = hipStreamEndCapture(capture_stream, &g);
                 if (cst != TBPM_OK) {
@@ -923,15 +940,20 @@ tbpm_status Engine::run(const RunArgs &a) {
                     return cst;
                 }
                 if (ee != hipSuccess) return hip_fail(ee, "end capture");
-                hipError_t ei = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+                hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 if (ei != hipSuccess) {
-                    graph_exec = nullptr;
+                    exec = nullptr;
                     return hip_fail(ei, "hipGraphInstantiate");
                 }
-                graph_key = key;
-            }
-            for (int32_t k = 1; k < a.n_steps; ++k) TRY_HIP(hipGraphLaunch(graph_exec, a.stream), "hipGraphLaunch");
+                gkey = key;
+                return TBPM_OK;
+            };
+            st = cached(graph_exec, graph_key, spg);
+            if (st == TBPM_OK && n_rest > 0) st = cached(graph_exec1, graph_key1, 1);
+            if (st != TBPM_OK) return st;
+            for (int32_t k = 0; k < n_full; ++k) TRY_HIP(hipGraphLaunch(graph_exec, a.stream), "hipGraphLaunch");
+            for (int32_t k = 0; k < n_rest; ++k) TRY_HIP(hipGraphLaunch(graph_exec1, a.stream), "hipGraphLaunch");
         }
     }
 

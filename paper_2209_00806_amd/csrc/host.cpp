@@ -96,6 +96,35 @@ int32_t num_terms(double z, double tol) {
 }
 
 // ---------------------------------------------------------------------------
+// transposed slots: for every stored element (r, c) of the sliced ELL, the
+// slot of (c, r); -1 for padding slots (column = row).  Empty if an element
+// has no transposed partner (H is validated Hermitian, so this does not
+// happen for a handle's matrix).
+// ---------------------------------------------------------------------------
+std::vector<int32_t> ell_partner_slots(int64_t n_rows, const std::vector<int64_t> &slice_off,
+                                       const std::vector<int32_t> &col) {
+    std::vector<int32_t> part(col.size(), -1);
+    if (col.size() >= (size_t)INT32_MAX) return {};
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t q = r / kSliceRows, off = slice_off[q] + r % kSliceRows;
+        const int64_t w = (slice_off[q + 1] - slice_off[q]) / kSliceRows;
+        for (int64_t k = 0; k < w; ++k) {
+            const int64_t s = off + k * kSliceRows;
+            const int64_t c = col[s];
+            if (c == r) continue;
+            const int64_t qc = c / kSliceRows, offc = slice_off[qc] + c % kSliceRows;
+            const int64_t wc = (slice_off[qc + 1] - slice_off[qc]) / kSliceRows;
+            int64_t found = -1;
+            for (int64_t kk = 0; kk < wc && found < 0; ++kk)
+                if (col[offc + kk * kSliceRows] == r) found = offc + kk * kSliceRows;
+            if (found < 0) return {};
+            part[s] = (int32_t)found;
+        }
+    }
+    return part;
+}
+
+// ---------------------------------------------------------------------------
 // sliced ELL
 // ---------------------------------------------------------------------------
 HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *col) {

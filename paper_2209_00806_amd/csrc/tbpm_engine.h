@@ -74,7 +74,7 @@ struct GraphKey {
     int32_t chunks = 0, remap = 0, nt = 0, unroll = 0, staged = 0, vec = 0, fused = 0;
     // identity of the tile tables the launches were captured with
     int32_t n_tiles = 0, tiles_chunks = 0, tiles_unit = 0, lds_units = 0;
-    int32_t n_steps = 0, n_qe = 0, jc_states = 0;
+    int32_t n_steps = 0, n_qe = 0, jc_states = 0, steps = 0;
     const void *ckpt = nullptr;
     const void *bufs[22] = {};
     bool operator==(const GraphKey &o) const;
@@ -118,8 +118,10 @@ struct Engine {
     // state blocks of the staged shape: one block of states, its correlation
     // and norms, in the caller's order
     DevBuf blk_psi, blk_corr, blk_norm;
-    // adjoint: segment store, four adjoint vectors, gradient accumulators
-    DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef;
+    // adjoint: segment store, four adjoint vectors, gradient accumulators,
+    // and the transposed-slot table of the two-order adjoint (built on first use)
+    DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef, bwd_partner;
+    bool partner_ready = false;
     PinnedBuf staging;
     hipEvent_t staging_done = nullptr;
     hipStream_t capture_stream = nullptr;
@@ -132,9 +134,9 @@ struct Engine {
     std::vector<TileDesc> h_tiles;
     std::vector<int32_t> h_inst_tile0;
 
-    // cached graph of one step
-    hipGraphExec_t graph_exec = nullptr;
-    GraphKey graph_key;
+    // cached graphs: several time steps, and one step for the remainder
+    hipGraphExec_t graph_exec = nullptr, graph_exec1 = nullptr;
+    GraphKey graph_key, graph_key1;
 
     int32_t n_inst() const { return (int32_t)inst_row0.size() - 1; }
 

@@ -129,6 +129,10 @@ struct AdjPairParams {
     double cc2_re, cc2_im;  // conj(c_{j+2})
     void *gacc;             // per ELL slot: double (real H) or double2
     double *gdiag;          // [rows]
+    // per ELL slot of (q, p), the slot of (p, q), -1 for padding: the
+    // gradient of (p, q) is formed by own row q from alpha at p (staged) and
+    // b at q (own), and written to that slot
+    const int32_t *partner;
     // two-hop tile tables (as FusedParams)
     const int32_t *uoff;
     const int32_t *n1;
@@ -234,6 +238,10 @@ const std::string &last_error();
 int32_t num_terms(double z, double tol);
 void bessel_j(double z, int32_t M, double *J);
 HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *col);
+// per sliced-ELL slot of element (r, c), the slot of (c, r); -1 for padding;
+// empty if some element has no transposed partner
+std::vector<int32_t> ell_partner_slots(int64_t n_rows, const std::vector<int64_t> &slice_off,
+                                       const std::vector<int32_t> &col);
 
 // Tiles of the fused launch shape: runs of at most R consecutive rows of one
 // member (R chosen for the least staged traffic; a run whose staged rows do
