@@ -157,6 +157,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     pp.ckpt = nullptr;
     pp.ckpt_slot = nullptr;
     pp.s_user = s_user;
+    pp.uniform_w = eng.mat.uniform_w;
 
     AdjParams ap{};
     ap.tiles = (const TileDesc *)eng.tiles.ptr;
@@ -194,6 +195,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     fp.hw = (const int32_t *)eng.fu_hw.ptr;
     fp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
     fp.lds_units = (int32_t)(eng.fu_max_rows << (log2s - log2pvs));
+    fp.uniform_w = eng.mat.uniform_w;
     const PassCoef *coefs = (const PassCoef *)eng.bwd_coef.ptr;
     auto replay_step_pairs = [&](int32_t t) -> hipError_t {
         // plan entry p evaluates order pass_j[p]: 0 FIRST (M-2), 1 NOB2 (M-3),
@@ -256,6 +258,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     qp.hw = (const int32_t *)eng.fu_hw.ptr;
     qp.hidx = (const uint16_t *)eng.fu_hidx.ptr;
     qp.lds_units = (int32_t)(eng.fu_max_rows << (log2s - log2pvs));
+    qp.uniform_w = eng.mat.uniform_w;
     qp.cc0_re = c[0].real();
     qp.cc0_im = -c[0].imag();
     auto adjoint_step_pairs = [&](int32_t t, int32_t l) -> hipError_t {

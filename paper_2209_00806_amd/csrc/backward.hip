@@ -219,6 +219,18 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
     GV *gacc = (GV *)p.gacc;
     const double inv_f = p.inv_f;
     auto grow_of = [&](uint32_t lr) -> uint32_t { return lr < n_own ? row0 + lr : (uint32_t)ucol[lr - n_own]; };
+    const int32_t uw = p.uniform_w;  // > 0: every slice has this width (no slice-offset load)
+    auto slots_of = [&](uint32_t grow, uint32_t &base, int &w) {
+        const uint32_t sl = grow / kSliceRows;
+        if (uw > 0) {
+            w = uw;
+            base = sl * (uint32_t)(uw * kSliceRows) + grow % kSliceRows;
+        } else {
+            const uint32_t off = soff[sl];
+            w = (int)((soff[sl + 1] - off) / kSliceRows);
+            base = off + grow % kSliceRows;
+        }
+    };
 
     // stage alpha_j: four loads in flight per thread
     for (uint32_t i0 = threadIdx.x; i0 < n_x; i0 += 4 * kWG) {
@@ -241,10 +253,9 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
         const uint32_t lr = u >> log2u;
         const uint32_t grow = grow_of(lr);
         const uint32_t gu = (grow << log2u) + usub;
-        const uint32_t sl = grow / kSliceRows;
-        const uint32_t off = soff[sl];
-        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const uint32_t base = off + grow % kSliceRows;
+        uint32_t base;
+        int w;
+        slots_of(grow, base, w);
         V ap;
         if constexpr (!FIRST) ap = ((const V *)p.a_prev)[gu];
         V acc = p.onsite[grow] * xs[u];
@@ -297,10 +308,9 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
         const uint32_t lr = u >> log2u;
         const uint32_t row = row0 + lr;
         const uint32_t gu = (row << log2u) + usub;
-        const uint32_t sl = row / kSliceRows;
-        const uint32_t off = soff[sl];
-        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const uint32_t base = off + row % kSliceRows;
+        uint32_t base;
+        int w;
+        slots_of(row, base, w);
         const V aj = xs[u], aj1 = ys[u];
         V lam;
         if constexpr (!FIRST) lam = ((const V *)p.lam_acc)[gu];

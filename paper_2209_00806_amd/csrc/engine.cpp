@@ -227,8 +227,13 @@ tbpm_status Engine::upload(const HostCsr *const *members, int32_t n, const std::
     mat.n_slices = (int64_t)e.slice_off.size() - 1;
     mat.ell_size = S;
     mat.max_width = 0;
-    for (int64_t q = 0; q < mat.n_slices; ++q)
-        mat.max_width = std::max<int32_t>(mat.max_width, (int32_t)((e.slice_off[q + 1] - e.slice_off[q]) / kSliceRows));
+    int32_t min_width = INT32_MAX;
+    for (int64_t q = 0; q < mat.n_slices; ++q) {
+        const int32_t wq = (int32_t)((e.slice_off[q + 1] - e.slice_off[q]) / kSliceRows);
+        mat.max_width = std::max<int32_t>(mat.max_width, wq);
+        min_width = std::min<int32_t>(min_width, wq);
+    }
+    mat.uniform_w = (mat.n_slices > 0 && min_width == mat.max_width) ? mat.max_width : 0;
     mat.is_complex = cplx;
     const size_t vb = (cplx ? 2 : 1) * (size_t)std::max<int64_t>(S, 1);
     if (S >= (int64_t)UINT32_MAX) return fail(TBPM_E_ARG, "sliced-ELL size must be < 2^32 entries");
@@ -797,6 +802,7 @@ tbpm_status Engine::run(const RunArgs &a) {
                     fp.hw = (const int32_t *)fu_hw.ptr;
                     fp.hidx = (const uint16_t *)fu_hidx.ptr;
                     fp.lds_units = fu_lds_units;
+                    fp.uniform_w = mat.uniform_w;
                     hipError_t e = launch_pair(l.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, fp, s);
                     if (e != hipSuccess) return hip_fail(e, "launch pair");
                     prev = l.o1;
@@ -828,6 +834,7 @@ tbpm_status Engine::run(const RunArgs &a) {
                 pp.ckpt_slot = a.ckpt ? (const int32_t *)ckpt_slot.ptr : nullptr;
                 pp.ckpt_stride = mat.n_rows * a.s_user;
                 pp.s_user = a.s_user;
+                pp.uniform_w = mat.uniform_w;
                 hipError_t e =
                     launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs, pp, s);
                 if (e != hipSuccess) return hip_fail(e, "launch pass");
@@ -867,6 +874,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.ucol = (const int32_t *)st_ucol.ptr;
             pp.lidx = (const uint16_t *)st_lidx.ptr;
             pp.stage_units = stage_units;
+            pp.uniform_w = staged ? 0 : mat.uniform_w;
             hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs,
                                                   mat.max_width > kStagedWide, pp, s)
                                   : launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs,
@@ -1077,6 +1085,7 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
         fp.hw = (const int32_t *)fu_hw.ptr;
         fp.hidx = (const uint16_t *)fu_hidx.ptr;
         fp.lds_units = (int32_t)(fu_max_rows << (log2s - log2pvs));
+        fp.uniform_w = mat.uniform_w;
         fp.v = src;
         void *wb[4] = {w0, w1, w2, w3};
         const PassCoef *cf = (const PassCoef *)coef.ptr;
@@ -1186,6 +1195,7 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.coef = (const PassCoef *)coef.ptr;  // the first pass's coefficients: finite, bounded
     pp.counter = (int32_t *)counter.ptr;
     pp.s_user = s_user;
+    pp.uniform_w = last_staged == 1 ? 0 : mat.uniform_w;  // as run() sets it
     pp.uoff = (const int32_t *)st_uoff.ptr;
     pp.ucol = (const int32_t *)st_ucol.ptr;
     pp.lidx = (const uint16_t *)st_lidx.ptr;
@@ -1217,6 +1227,7 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
         fp.hw = (const int32_t *)fu_hw.ptr;
         fp.hidx = (const uint16_t *)fu_hidx.ptr;
         fp.lds_units = fu_lds_units;
+        fp.uniform_w = mat.uniform_w;
         for (int32_t i = 0; i < n_launch; ++i) {
             hipError_t e = launch_pair(kPairMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, fp, stream);
             if (e != hipSuccess) return hip_fail(e, "launch pair");

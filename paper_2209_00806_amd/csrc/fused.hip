@@ -14,6 +14,12 @@
 // that no tile of the launch reads.  The first pair of a step (x = psi, no
 // b_{j+2}, b_{M-1} folded into alpha2) is the same kernel with KIND
 // kPairFirst.  Per element the arithmetic is that of k_pass.
+//
+// Latency: a workgroup's phases are chains of dependent loads.  When every
+// slice has the same width (uniform_w > 0, e.g. graphene) a row's slots are
+// computed without loading the slice offsets, and a thread whose first unit
+// of order j is an own row keeps that row's first batch of matrix entries in
+// registers for order j-1, which takes the same unit.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -62,6 +68,25 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
     // global row of local staged row lr (own, then 1-hop, then 2-hop)
     auto grow_of = [&](uint32_t lr) -> uint32_t { return lr < n_own ? row0 + lr : (uint32_t)ucol[lr - n_own]; };
 
+    // psi on the thread's first two own units, kept for the second order
+    V vk0{}, vk1{};
+    // the first batch of matrix entries of the thread's first unit when it is
+    // an own row (the same unit in both orders), kept for the second order
+    uint32_t kli[KG];
+    HV kh[KG];
+    const int32_t uw = p.uniform_w;
+    auto slots_of = [&](uint32_t grow, uint32_t &base, int &w) {
+        const uint32_t sl = grow / kSliceRows;
+        if (uw > 0) {
+            w = uw;
+            base = sl * (uint32_t)(uw * kSliceRows) + grow % kSliceRows;
+        } else {
+            const uint32_t off = soff[sl];
+            w = (int)((soff[sl + 1] - off) / kSliceRows);
+            base = off + grow % kSliceRows;
+        }
+    };
+
     // stage b_{j+1}: four independent loads in flight per thread
     for (uint32_t i0 = threadIdx.x; i0 < n_x; i0 += 4 * kWG) {
         V t[4];
@@ -78,9 +103,6 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
     }
     __syncthreads();
 
-    // psi on the thread's first two own units, kept for the second order
-    V vk0{}, vk1{};
-
     // order j on own + 1-hop rows
     {
         const R ar = (R)c1.ar, ai = (R)c1.ai, br = (R)c1.br, bi = (R)c1.bi;
@@ -89,10 +111,9 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
             const uint32_t lr = u >> log2u;
             const uint32_t grow = grow_of(lr);
             const uint32_t gu = (grow << log2u) + usub;
-            const uint32_t sl = grow / kSliceRows;
-            const uint32_t off = soff[sl];
-            const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-            const uint32_t base = off + grow % kSliceRows;
+            uint32_t base;
+            int w;
+            slots_of(grow, base, w);
             V vv, bq;
             if constexpr (!FIRST) {
                 vv = v[gu];
@@ -115,6 +136,13 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
                     const HV hv = val[slot];
                     li[i] = (l << log2u) + usub;
                     h[i] = valid ? hv : HV{};
+                }
+                if (it == 0 && k == 0) {
+#pragma unroll
+                    for (int i = 0; i < KG; ++i) {
+                        kli[i] = li[i];
+                        kh[i] = h[i];
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < KG; ++i) {
@@ -149,10 +177,9 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
             const uint32_t lr = u >> log2u;
             const uint32_t row = row0 + lr;
             const uint32_t gu = (row << log2u) + usub;
-            const uint32_t sl = row / kSliceRows;
-            const uint32_t off = soff[sl];
-            const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-            const uint32_t base = off + row % kSliceRows;
+            uint32_t base;
+            int w;
+            slots_of(row, base, w);
             V vv;
             if constexpr (FIRST)
                 vv = xs[u];
@@ -162,14 +189,22 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
             for (int k = 0; k < w; k += KG) {
                 uint32_t li[KG];
                 HV h[KG];
+                if (it == 0 && k == 0) {  // this unit was the thread's first of order j
 #pragma unroll
-                for (int i = 0; i < KG; ++i) {
-                    const bool valid = k + i < w;
-                    const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
-                    const uint32_t l = valid ? (uint32_t)p.lidx[slot] : lr;
-                    const HV hv = val[slot];
-                    li[i] = (l << log2u) + usub;
-                    h[i] = valid ? hv : HV{};
+                    for (int i = 0; i < KG; ++i) {
+                        li[i] = kli[i];
+                        h[i] = kh[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < KG; ++i) {
+                        const bool valid = k + i < w;
+                        const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                        const uint32_t l = valid ? (uint32_t)p.lidx[slot] : lr;
+                        const HV hv = val[slot];
+                        li[i] = (l << log2u) + usub;
+                        h[i] = valid ? hv : HV{};
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < KG; ++i) {

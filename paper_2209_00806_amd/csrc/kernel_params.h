@@ -77,6 +77,7 @@ struct PassParams {
     const int32_t *ucol;
     const uint16_t *lidx;
     int32_t stage_units;   // LDS capacity in units (VS states)
+    int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
 };
 
 // Two Clenshaw orders per launch (fused.hip).
@@ -111,6 +112,7 @@ struct FusedParams {
     const int32_t *hw;     // [n_tiles] entries per 1-hop row in that block
     const uint16_t *hidx;  // local indices of the stored elements of the 1-hop rows
     int32_t lds_units;     // LDS capacity in units: max over tiles of n_x + n_y
+    int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
 };
 
 struct InitParams {

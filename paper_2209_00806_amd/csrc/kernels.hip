@@ -68,6 +68,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
     const int32_t *__restrict__ col = p.col;
     const uint32_t *__restrict__ soff = p.slice_off;
     const uint32_t usub = threadIdx.x & umask;  // this thread's unit inside a row
+    const int32_t uw = p.uniform_w;  // > 0: every slice has this width (no slice-offset load)
 
     double dre[VS], dim[VS], nrm[VS];
 #pragma unroll
@@ -98,9 +99,14 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
             row[q] = row0 + (u >> log2u);
             gu[q] = u0 + u;
             const uint32_t sl = row[q] / kSliceRows;
-            const uint32_t off = soff[sl];
-            w[q] = (int)((soff[sl + 1] - off) / kSliceRows);
-            base[q] = off + row[q] % kSliceRows;
+            if (uw > 0) {
+                w[q] = uw;
+                base[q] = sl * (uint32_t)(uw * kSliceRows) + row[q] % kSliceRows;
+            } else {
+                const uint32_t off = soff[sl];
+                w[q] = (int)((soff[sl + 1] - off) / kSliceRows);
+                base[q] = off + row[q] % kSliceRows;
+            }
             xo[q] = x[gu[q]];
             on[q] = ons[row[q]];
             if constexpr (!X_IS_V) vv[q] = ldv<NT>(v + gu[q]);

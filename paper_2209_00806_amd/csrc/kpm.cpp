@@ -133,6 +133,7 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     fp.hw = (const int32_t *)fu_hw.ptr;
     fp.hidx = (const uint16_t *)fu_hidx.ptr;
     fp.lds_units = (int32_t)(fu_max_rows << (log2s - log2pvs));
+    fp.uniform_w = mat.uniform_w;
     fp.coef1 = fp.coef2 = c_2;
     // T_{k+1}, T_{k+2} = 2 H~ T_k - T_{k-1}, 2 H~ T_{k+1} - T_k
     auto pair = [&](const void *tk, const void *tkm1, void *o1, void *o2) -> hipError_t {

@@ -226,6 +226,7 @@ tbpm_status propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int32_t s
             pp.phi0_ld = s_pad;
             pp.partials = partials;
             pp.s_user = s_user;
+            pp.uniform_w = m.uniform_w;
             e = launch_pass(pl.kind, fp32, m.is_complex, cf.nontemporal != 0, cf.unroll, vs, pp, st);
             if (e != hipSuccess) return hip_fail(e, "launch pass");
         }

@@ -18,6 +18,7 @@ struct DevMatrix {
     int64_t n_slices = 0;
     int64_t ell_size = 0;    // slots incl. padding
     int32_t max_width = 0;   // stored elements per row of the widest slice
+    int32_t uniform_w = 0;   // that width when every slice has it, else 0
     bool is_complex = false;
     uint32_t *slice_off = nullptr; // [n_slices + 1]
     int32_t *col = nullptr;        // [ell_size]
@@ -142,6 +143,7 @@ struct AdjPairParams {
     const int32_t *hw;
     const uint16_t *hidx;
     int32_t lds_units;
+    int32_t uniform_w;      // stored elements per row when every slice has that width, else 0
 };
 // vs: states per thread (1, 2 or 4; at most the padded state count);
 // lds_units counts units of vs states
