@@ -749,7 +749,7 @@ def main():
     ap.add_argument("--hbm-cells", type=int, default=3072, help="cells per side of the HBM-resident leg")
     ap.add_argument("--hbm-nt", type=int, default=64)
     ap.add_argument("--no-hbm", action="store_true")
-    ap.add_argument("--only", choices=["small", "hbm"], default=None,
+    ap.add_argument("--only", choices=["small", "hbm", "backward"], default=None,
                     help="run one leg alone and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -769,6 +769,9 @@ def main():
         return
     if args.only == "hbm":
         print(json.dumps({"hbm_resident": bench_hbm_resident(args, log)}), flush=True)
+        return
+    if args.only == "backward":
+        print(json.dumps({"backward": bench_backward(args, log)}), flush=True)
         return
     dev = torch.device("cuda:0")
     f = 9.0

@@ -90,7 +90,7 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     TRY_HIP(eng.bwd_gacc.ensure((cplx ? 16 : 8) * (size_t)std::max<int64_t>(eng.mat.ell_size, 1)), "alloc gradient");
     TRY_HIP(eng.bwd_gdiag.ensure(8 * (size_t)n_rows), "alloc gradient");
     TRY_HIP(eng.bwd_coef.ensure(sizeof(PassCoef) * n_passes), "alloc coefficients");
-    if (pairs && !eng.partner_ready) {
+    if (!eng.partner_ready) {
         const std::vector<int32_t> part = ell_partner_slots(n_rows, eng.h_slice_off, eng.h_col);
         if (part.empty()) return fail(TBPM_E_NOT_HERMITIAN, "a stored element has no transposed partner");
         TRY_HIP(hipStreamSynchronize(st), "stream synchronize");
@@ -173,6 +173,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     ap.gacc = eng.bwd_gacc.ptr;
     ap.gdiag = (double *)eng.bwd_gdiag.ptr;
     ap.phi0 = phi0p;
+    ap.partner = (const int32_t *)eng.bwd_partner.ptr;
+    ap.uniform_w = eng.mat.uniform_w;
 
     // one step of the replay in the fused shape: orders (M-2, M-3) from psi,
     // then (j, j-1) pairs, a leftover order alone, and the last pass alone

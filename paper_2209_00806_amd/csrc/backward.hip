@@ -64,9 +64,16 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
         const uint32_t s = e & smask;
         const uint32_t g = e0 + e;
         const uint32_t sl = row / kSliceRows;
-        const uint32_t off = soff[sl];
-        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const uint32_t base = off + row % kSliceRows;
+        uint32_t base;
+        int w;
+        if (p.uniform_w > 0) {
+            w = p.uniform_w;
+            base = sl * (uint32_t)(p.uniform_w * kSliceRows) + row % kSliceRows;
+        } else {
+            const uint32_t off = soff[sl];
+            w = (int)((soff[sl + 1] - off) / kSliceRows);
+            base = off + row % kSliceRows;
+        }
         // every load that does not depend on a column index first
         const d2 a = acur[g];  // alpha_j at this row
         const d2 bown = bq[g];
@@ -78,53 +85,56 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
         }
         if constexpr (KIND == kAdjFinal) ph = ((const d2 *)p.phi0)[g];
         const double gd_old = p.gdiag[row];
-        const d2 ga = a * gw;
+        // gw b at this row: the gradient of an element (p, q) is
+        // gw Re/Im sum_s alpha_j[p] conj(b[q]); this row q forms it for its
+        // transposed elements (q, p) from alpha_j at p (gathered anyway for
+        // the product) and writes it to the slot of (p, q) (one writer per slot)
+        const d2 bw = cmul(bs, bown) * gw;
         d2 acc;
         acc.x = on * a.x;
         acc.y = on * a.y;
         {
             // diagonal gradient: Re(alpha_j[p] conj(b[p])) summed over states
-            const d2 b = cmul(bs, bown);
-            const double dg = row_sum(ga.x * b.x + ga.y * b.y, log2s);
+            const double dg = row_sum(a.x * bw.x + a.y * bw.y, log2s);
             if (s == 0) p.gdiag[row] = gd_old + dg;
         }
         for (int k = 0; k < w; k += KG) {
-            uint32_t slot[KG], gc[KG];
+            uint32_t gc[KG];
+            int32_t pt[KG];
             HV h[KG];
-            bool valid[KG];
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
-                valid[i] = k + i < w;
-                slot[i] = valid[i] ? base + (uint32_t)(k + i) * kSliceRows : 0u;
-                const int32_t c = col[slot[i]];
-                const HV hv = val[slot[i]];
-                gc[i] = ((valid[i] ? (uint32_t)c : row) << log2s) + s;
-                h[i] = valid[i] ? hv : HV{};
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const int32_t c = col[slot];
+                const HV hv = val[slot];
+                const int32_t ps = p.partner[slot];
+                gc[i] = ((valid ? (uint32_t)c : row) << log2s) + s;
+                h[i] = valid ? hv : HV{};
+                pt[i] = valid ? ps : -1;  // -1: beyond the row or a padding slot
             }
-            d2 xa[KG], xb[KG];
+            d2 xa[KG];
             GV gold[KG];
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
                 xa[i] = acur[gc[i]];
-                xb[i] = bq[gc[i]];
-                gold[i] = gacc[slot[i]];
+                gold[i] = pt[i] >= 0 ? gacc[pt[i]] : GV{};
             }
 #pragma unroll
             for (int i = 0; i < KG; ++i) {
                 acc = hmad(h[i], xa[i], acc);
-                const d2 b = cmul(bs, xb[i]);
-                // alpha_j[p] * conj(b[q]) summed over the states of the row
-                const double gr = row_sum(ga.x * b.x + ga.y * b.y, log2s);
+                // alpha_j[p] * conj(gw b[q]) summed over the states of the row
+                const double gr = row_sum(xa[i].x * bw.x + xa[i].y * bw.y, log2s);
                 if constexpr (CH) {
-                    const double gi = row_sum(ga.y * b.x - ga.x * b.y, log2s);
-                    if (s == 0 && valid[i]) {
+                    const double gi = row_sum(xa[i].y * bw.x - xa[i].x * bw.y, log2s);
+                    if (s == 0 && pt[i] >= 0) {
                         d2 nv = gold[i];
                         nv.x += gr;
                         nv.y += gi;
-                        gacc[slot[i]] = nv;
+                        gacc[pt[i]] = nv;
                     }
                 } else {
-                    if (s == 0 && valid[i]) gacc[slot[i]] = gold[i] + gr;
+                    if (s == 0 && pt[i] >= 0) gacc[pt[i]] = gold[i] + gr;
                 }
             }
         }

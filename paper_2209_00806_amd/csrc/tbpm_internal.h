@@ -96,6 +96,10 @@ struct AdjParams {
     double *gdiag;          // [rows] real part of the diagonal gradient
     const double *phi0;     // complex [rows][S] (final pass)
     const double *gcorr_l;  // complex [s_user]: dL/dC at this step (final pass)
+    // per ELL slot of (q, p), the slot of (p, q), -1 for padding (the
+    // gradient of (p, q) is formed by row q and written there)
+    const int32_t *partner;
+    int32_t uniform_w;      // stored elements per row when every slice has that width, else 0
 };
 
 // Two adjoint orders per launch (backward.hip), on the two-hop tiles of the
