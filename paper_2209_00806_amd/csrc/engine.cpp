@@ -327,10 +327,10 @@ tbpm_status Engine::build_tiles(int32_t s_pad, int32_t chunks, int32_t vs) {
 }
 
 // ---------------------------------------------------------------------------
-// staged tiles: R consecutive rows of one member; the rows of x a tile reads
-// are its own rows plus a sorted list of external rows.  R is the largest
-// power of two (<= 256) whose biggest staged set fits the LDS budget of the
-// tier (the fused shape's tiers: 1/(tier+2) of a CU's 160 KiB).
+// staged tiles: runs of at most 256 consecutive rows of one member; the rows
+// of x a tile reads are its own rows plus a sorted list of external rows, and
+// the staged set fits the LDS budget of the tier (the fused shape's tiers:
+// 1/(tier+2) of a CU's 160 KiB).
 // ---------------------------------------------------------------------------
 tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t unit_bytes, int32_t tier) {
     // the tables depend on the bytes of a row and the tier only (not on how a
@@ -355,31 +355,64 @@ tbpm_status Engine::build_staged_tiles(int32_t s_pad, int32_t log2u, int32_t uni
         std::sort(ext.begin(), ext.end());
         ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
     };
-    int64_t R = 0;
-    size_t max_stage = 0;
-    for (int64_t cand : {256, 128, 64, 32, 16, 8, 4, 2, 1}) {
-        size_t mx = 0;
-        for (int32_t i = 0; i < n_inst(); ++i)
-            for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += cand) {
-                const int64_t rows = std::min<int64_t>(cand, inst_row0[i + 1] - r0);
-                collect(r0, rows);
-                mx = std::max(mx, (size_t)rows + ext.size());
+    // Tiles are the parts of the recursive halving of each member's rows
+    // whose staged rows (own rows and the distinct rows they reference) fit
+    // the budget.  The bisection row order splits a part at its middle, so
+    // these are parts of that bisection: compact regions with short borders
+    // (a fixed tile height, set by the worst tile, stages several times the
+    // rows of such a part on lattices with long-range hoppings).
+    const size_t cap = budget / ((size_t)unit_bytes << log2u);
+    std::vector<int64_t> seen(mat.n_rows, -1);
+    int64_t visit = 0;
+    auto stage_rows = [&](int64_t r0, int64_t rows) {
+        ++visit;
+        size_t cnt = 0;
+        for (int64_t r = r0; r < r0 + rows; ++r) {
+            if (seen[r] != visit) {
+                seen[r] = visit;
+                ++cnt;
             }
-        if ((mx << log2u) * (size_t)unit_bytes <= budget) {
-            R = cand;
-            max_stage = mx;
-            break;
+            const int64_t q = r / SR, w = (h_slice_off[q + 1] - h_slice_off[q]) / SR;
+            for (int64_t k = 0; k < w; ++k) {
+                const int32_t c = h_col[h_slice_off[q] + k * SR + r % SR];
+                if (seen[c] != visit) {
+                    seen[c] = visit;
+                    ++cnt;
+                }
+            }
+        }
+        return cnt;
+    };
+    std::vector<std::pair<int64_t, int64_t>> parts, stack;
+    for (int32_t i = 0; i < n_inst(); ++i) {
+        stack.assign(1, {inst_row0[i], inst_row0[i + 1]});
+        while (!stack.empty()) {
+            const auto [lo, hi] = stack.back();
+            stack.pop_back();
+            if (hi <= lo) continue;
+            if ((size_t)(hi - lo) <= std::min<size_t>(cap, 256) && stage_rows(lo, hi - lo) <= cap) {
+                parts.push_back({lo, hi});
+                continue;
+            }
+            if (hi - lo == 1) return fail(TBPM_E_ARG, "no staged tile fits the LDS budget");
+            const int64_t mid = lo + (hi - lo) / 2;
+            stack.push_back({mid, hi});
+            stack.push_back({lo, mid});
         }
     }
-    if (R == 0) return fail(TBPM_E_ARG, "no staged tile fits the LDS budget");
+    int64_t R = 0;
+    size_t max_stage = 0;
     h_tiles.clear();
     h_inst_tile0.assign(n_inst() + 1, 0);
     std::vector<int32_t> uoff(1, 0), ucol;
     std::vector<uint16_t> lidx(std::max<size_t>(h_col.size(), 1), 0);
+    size_t pi = 0;
     for (int32_t i = 0; i < n_inst(); ++i) {
-        for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += R) {
-            const int64_t rows = std::min<int64_t>(R, inst_row0[i + 1] - r0);
+        for (; pi < parts.size() && parts[pi].first < inst_row0[i + 1]; ++pi) {
+            const int64_t r0 = parts[pi].first, rows = parts[pi].second - r0;
             collect(r0, rows);
+            R = std::max(R, rows);
+            max_stage = std::max(max_stage, (size_t)rows + ext.size());
             for (int64_t r = r0; r < r0 + rows; ++r) {
                 const int64_t q = r / SR, w = (h_slice_off[q + 1] - h_slice_off[q]) / SR;
                 for (int64_t k = 0; k < w; ++k) {

@@ -10,7 +10,7 @@
   the kernel has changed since the counters were taken.
 
     python -m paper_2209_00806_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
-    python -m paper_2209_00806_amd.profiling trace <kernel_trace.csv> <out.md> "<command>"
+    python -m paper_2209_00806_amd.profiling trace <kernel_trace.csv | results.db> <out.md> "<command>"
     python -m paper_2209_00806_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> \
         <kernel_regex> <kernel_sources,comma,separated> <out.json> "<command>" [grid]
 """
@@ -59,13 +59,31 @@ def stats(csv_path: str, out_md: str, command: str, top: int = 20) -> str:
     return text
 
 
-def trace(csv_path: str, out_md: str, command: str, top: int = 24) -> str:
-    """Per (kernel, grid size) statistics from a ``*_kernel_trace.csv``."""
-    groups = {}
-    for r in _rows(csv_path):
-        name = _col(r, "Kernel_Name")
+def _dispatches(path: str):
+    """(kernel name, grid threads, duration ns) of every dispatch in a
+    ``*_kernel_trace.csv`` or in a rocprofv3 ``*_results.db`` (its default
+    output format)."""
+    if path.endswith(".db"):
+        import sqlite3
+        db = sqlite3.connect(path)
+        try:
+            q = "select name, grid_x * grid_y * grid_z, end - start from kernels"
+            return [(n, int(g), int(d)) for n, g, d in db.execute(q)]
+        finally:
+            db.close()
+    out = []
+    for r in _rows(path):
         grid = int(_col(r, "Grid_Size_X")) * int(_col(r, "Grid_Size_Y")) * int(_col(r, "Grid_Size_Z"))
-        dur = int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))
+        out.append((_col(r, "Kernel_Name"), grid,
+                    int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))))
+    return out
+
+
+def trace(csv_path: str, out_md: str, command: str, top: int = 24) -> str:
+    """Per (kernel, grid size) statistics from a ``*_kernel_trace.csv`` or a
+    ``*_results.db``."""
+    groups = {}
+    for name, grid, dur in _dispatches(csv_path):
         groups.setdefault((name, grid), []).append(dur)
     total_all = sum(sum(v) for v in groups.values())
     recs = sorted(((sum(v), k, v) for k, v in groups.items()), reverse=True)
