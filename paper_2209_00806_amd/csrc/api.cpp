@@ -307,7 +307,7 @@ tbpm_status tbpm_propagate(tbpm_hamiltonian *H, const double *psi0, int32_t n_st
     a.flags = flags;
     a.stream = (hipStream_t)stream;
     try {
-        return H->eng.run_states(a);
+        return H->eng.run(a);
     } catch (const std::bad_alloc &) {
         return fail(TBPM_E_OOM, "host allocation failed");
     }

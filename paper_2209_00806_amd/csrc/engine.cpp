@@ -281,8 +281,7 @@ void Engine::release() {
                       &fu_hw,    &fu_hidx,  &bc,       &bd,        &ckpt_slot, &corr_scratch, &qe_coef,
                       &qe_acc,   &qe_part,  &qe_norm2, &ac_ja,     &ac_jb,     &ac_csr,       &ac_zero,
                       &ac_vec,   &ac_block, &jc_tab,   &jc_norm,   &hay_u,     &hay_y,        &hay_s,
-                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &blk_psi,   &blk_corr,     &blk_norm,
-                      &bwd_partner};
+                      &kp_store, &kp_rblk,  &kp_vec,   &kp_parts, &bwd_partner};
     for (DevBuf *b : bufs) b->release();
     partner_ready = false;
     staging.release();
@@ -555,47 +554,6 @@ int32_t cheb_coeffs(double z, double tol, std::vector<cd> &c) {
     return M;
 }
 
-tbpm_status Engine::run_states(const RunArgs &a) {
-    const tbpm_launch_config &c = cfgs[a.fp32 ? 1 : 0];
-    const int32_t esize = a.fp32 ? 8 : 16;  // bytes per state element of the recursion
-    const int32_t blk = kStagedRowBytes / esize;
-    int32_t s_pad = 1;
-    while (s_pad < a.s_user) s_pad <<= 1;
-    const bool plain = a.ckpt == nullptr && a.ckpt_every == 0 && a.n_snap == 0 && a.n_qe == 0 && a.jc_val == nullptr;
-    if (!(plain && n_inst() == 1 && c.staged != 0 && c.fused == 0 && s_pad > blk)) return run(a);
-    const int64_t n = inst_row0[1] - inst_row0[0];
-    const bool want_norm = a.norm2 && a.norm2[0];
-    TRY_HIP(blk_psi.ensure(sizeof(double) * 2 * (size_t)n * blk), "alloc state block");
-    TRY_HIP(blk_corr.ensure(sizeof(double) * 2 * (size_t)a.n_steps * blk), "alloc block correlation");
-    if (want_norm) TRY_HIP(blk_norm.ensure(sizeof(double) * (size_t)a.n_steps * blk), "alloc block norms");
-    const size_t row_in = sizeof(double) * 2 * (size_t)a.s_user;  // bytes per row of the caller's arrays
-    for (int32_t s0 = 0; s0 < a.s_user; s0 += blk) {
-        const int32_t nb = std::min(blk, a.s_user - s0);
-        const size_t w = sizeof(double) * 2 * (size_t)nb;
-        TRY_HIP(hipMemcpy2DAsync(blk_psi.ptr, w, a.psi0[0] + 2 * (size_t)s0, row_in, w, (size_t)n,
-                                 hipMemcpyDeviceToDevice, a.stream),
-                "gather state block");
-        const double *p0 = (const double *)blk_psi.ptr;
-        double *c0 = (double *)blk_corr.ptr;
-        double *n0 = want_norm ? (double *)blk_norm.ptr : nullptr;
-        RunArgs b = a;
-        b.psi0 = &p0;
-        b.s_user = nb;
-        b.corr = &c0;
-        b.norm2 = want_norm ? &n0 : nullptr;
-        const tbpm_status st = run(b);
-        if (st != TBPM_OK) return st;
-        TRY_HIP(hipMemcpy2DAsync(a.corr[0] + 2 * (size_t)s0, row_in, c0, w, w, (size_t)a.n_steps,
-                                 hipMemcpyDeviceToDevice, a.stream),
-                "scatter block correlation");
-        if (want_norm)
-            TRY_HIP(hipMemcpy2DAsync(a.norm2[0] + s0, sizeof(double) * (size_t)a.s_user, n0, sizeof(double) * nb,
-                                     sizeof(double) * nb, (size_t)a.n_steps, hipMemcpyDeviceToDevice, a.stream),
-                    "scatter block norms");
-    }
-    return TBPM_OK;
-}
-
 tbpm_status Engine::run(const RunArgs &a) {
     int dev = 0;
     TRY_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -631,9 +589,13 @@ tbpm_status Engine::run(const RunArgs &a) {
     const int32_t unit_bytes = (int32_t)esize * vs;
     bool fused = cfg.fused != 0 && mmax >= 4;
     bool staged = cfg.staged != 0 && !fused;
+    // the staged shape takes rows wider than kStagedRowBytes one block of
+    // states at a time (units of a block: 2^log2ub)
+    int32_t log2ub = log2u;
+    while (staged && log2ub > 0 && ((int64_t)unit_bytes << log2ub) > kStagedRowBytes) --log2ub;
     tbpm_status st = TBPM_OK;
     if (fused && build_fused_tiles(s_pad, log2u, unit_bytes, cfg.fused) != TBPM_OK) fused = false;  // fall back
-    if (staged && build_staged_tiles(s_pad, log2u, unit_bytes, cfg.staged) != TBPM_OK) staged = false;
+    if (staged && build_staged_tiles(s_pad, log2ub, unit_bytes, cfg.staged) != TBPM_OK) staged = false;
     if (!staged && !fused) st = build_tiles(s_pad, chunks, vs);
     if (st != TBPM_OK) return st;
     const int32_t n_tiles = (int32_t)h_tiles.size();
@@ -907,6 +869,7 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.ucol = (const int32_t *)st_ucol.ptr;
             pp.lidx = (const uint16_t *)st_lidx.ptr;
             pp.stage_units = stage_units;
+            pp.log2ub = log2ub;
             pp.uniform_w = staged ? 0 : mat.uniform_w;
             hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs,
                                                   mat.max_width > kStagedWide, pp, s)
@@ -1002,6 +965,7 @@ tbpm_status Engine::run(const RunArgs &a) {
     last_fp32 = fp32 ? 1 : 0;
     last_staged = fused ? 2 : (staged ? 1 : 0);
     last_vs = vs;
+    last_log2ub = log2ub;
     if (a.flags & TBPM_FLAG_ASYNC) return TBPM_OK;
     TRY_HIP(hipStreamSynchronize(a.stream), "stream synchronize");
     TRY_HIP(hipGetLastError(), "kernel execution");
@@ -1233,6 +1197,7 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.ucol = (const int32_t *)st_ucol.ptr;
     pp.lidx = (const uint16_t *)st_lidx.ptr;
     pp.stage_units = stage_units;
+    pp.log2ub = last_log2ub;
     if (last_staged == 2) {
         // the interior launch of the fused shape: a MID pair (b_{j+1} in B,
         // b_{j+2} in A, outputs to C and D)

@@ -78,6 +78,10 @@ struct PassParams {
     const uint16_t *lidx;
     int32_t stage_units;   // LDS capacity in units (VS states)
     int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
+    // staged launch shape: log2 of the units of one state block of a row (at
+    // most log2s - log2 VS); a tile stages and evaluates its rows one block of
+    // states at a time, so the LDS holds rows of one block
+    int32_t log2ub;
 };
 
 // Two Clenshaw orders per launch (fused.hip).

@@ -198,7 +198,11 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
 // k_pass, so results are identical.  A row's stored elements are taken KG at
 // a time (indices and values loaded together, then the LDS reads): 4 for
 // narrow rows, 12 for wide ones, where fewer dependent rounds of loads per
-// row matter more than the padded slots of the last batch.
+// row matter more than the padded slots of the last batch.  Rows wider than
+// the LDS row width are taken one block of states at a time (2^log2ub units):
+// the tile stages and evaluates block 0, then block 1, ..., so the LDS holds
+// rows of one block and the tile's matrix entries come from HBM once, the
+// later blocks finding them in L2.
 // ---------------------------------------------------------------------------
 template <typename R, bool CH, int KIND, bool NT, int VS, int KG>
 __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
@@ -215,15 +219,15 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     const TileDesc td = p.tiles[tile];
     const PassCoef pc = p.coef[td.inst];
     const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
-    const int log2s = p.log2s;
-    const int log2u = log2s - LOG2VS;
-    const uint32_t umask = (1u << log2u) - 1u;
+    const int log2u = p.log2s - LOG2VS;  // units of a whole row
+    const int log2ub = p.log2ub;         // units of one state block of a row
+    const int n_blk = 1 << (log2u - log2ub);
+    const uint32_t umask = (1u << log2ub) - 1u;
     const uint32_t n_own = (uint32_t)td.rows;
-    const uint32_t n_u = n_own << log2u;
+    const uint32_t n_u = n_own << log2ub;
     const uint32_t row0 = (uint32_t)td.row0;
-    const uint32_t u0 = row0 << log2u;
     const int32_t x0 = p.uoff[tile], x1 = p.uoff[tile + 1];
-    const uint32_t n_stage = (n_own + (uint32_t)(x1 - x0)) << log2u;
+    const uint32_t n_stage = (n_own + (uint32_t)(x1 - x0)) << log2ub;
 
     if (p.bump_counter && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(p.counter, 1);
 
@@ -235,18 +239,8 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     const HV *__restrict__ val = (const HV *)p.val;
     const uint16_t *__restrict__ lidx = p.lidx;
     const uint32_t *__restrict__ soff = p.slice_off;
-
-    for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
-        const uint32_t lr = i >> log2u;
-        const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
-        xs[i] = x[(grow << log2u) + (i & umask)];
-    }
-    __syncthreads();
-
     const uint32_t usub = threadIdx.x & umask;
-    double dre[VS], dim[VS], nrm[VS];
-#pragma unroll
-    for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
+
     bool do_ckpt = false;
     uint32_t ckpt_base = 0;
     if constexpr (CORR) {
@@ -259,72 +253,92 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
         }
     }
 
-    for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
-        const uint32_t lrow = u >> log2u;
-        const uint32_t row = row0 + lrow;
-        const uint32_t gu = u0 + u;
-        const uint32_t sl = row / kSliceRows;
-        const uint32_t off = soff[sl];
-        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-        const uint32_t base = off + row % kSliceRows;
-        V vv, bq;
-        if constexpr (!X_IS_V) vv = ldv<NT>(v + gu);
-        if constexpr (HAS_B2) bq = ldv<NT>(b2 + gu);
-        const V xo = xs[u];
-        V acc = ons[row] * xo;
-        for (int k = 0; k < w; k += KG) {
-            uint32_t li[KG];
-            HV h[KG];
-#pragma unroll
-            for (int i = 0; i < KG; ++i) {
-                const bool valid = k + i < w;
-                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
-                const uint32_t l = lidx[slot];
-                const HV hv = val[slot];
-                li[i] = ((valid ? l : lrow) << log2u) + usub;
-                h[i] = valid ? hv : HV{};
-            }
-#pragma unroll
-            for (int i = 0; i < KG; ++i) {
-                if constexpr (CH)
-                    unit_mad_cplx<R, VS>(h[i], xs[li[i]], acc);
-                else
-                    unit_mad_real<R, VS>(h[i], xs[li[i]], acc);
-            }
+    // one state block at a time: the tile's matrix entries are read again for
+    // every block after the first, from L2
+    for (int blk = 0; blk < n_blk; ++blk) {
+        const uint32_t boff = (uint32_t)blk << log2ub;  // unit offset of the block in a row
+        if (blk > 0) __syncthreads();                    // the previous block's LDS reads are done
+        for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
+            const uint32_t lr = i >> log2ub;
+            const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
+            xs[i] = x[(grow << log2u) + boff + (i & umask)];
         }
-        const V src = X_IS_V ? xo : vv;
-        V o;
+        __syncthreads();
+
+        double dre[VS], dim[VS], nrm[VS];
 #pragma unroll
-        for (int i = 0; i < VS; ++i) {
-            const R vr = src[2 * i], vi = src[2 * i + 1];
-            const R hr = acc[2 * i], hi = acc[2 * i + 1];
-            o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
-            o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
-        }
-        if constexpr (HAS_B2) o -= bq;
-        if constexpr (CORR) {
-            stv<false>(out + gu, o);
-            const uint32_t s0 = usub << LOG2VS;
+        for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
+
+        for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
+            const uint32_t lrow = u >> log2ub;
+            const uint32_t row = row0 + lrow;
+            const uint32_t gu = (row << log2u) + boff + usub;
+            const uint32_t sl = row / kSliceRows;
+            const uint32_t off = soff[sl];
+            const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+            const uint32_t base = off + row % kSliceRows;
+            V vv, bq;
+            if constexpr (!X_IS_V) vv = ldv<NT>(v + gu);
+            if constexpr (HAS_B2) bq = ldv<NT>(b2 + gu);
+            const V xo = xs[u];
+            V acc = ons[row] * xo;
+            for (int k = 0; k < w; k += KG) {
+                uint32_t li[KG];
+                HV h[KG];
 #pragma unroll
-            for (int i = 0; i < VS; ++i) {
-                const d2 ph = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + s0 + i];
-                const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
-                dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
-                dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
-                nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
-                if (do_ckpt && (int)(s0 + i) < p.s_user) {
-                    d2 oc;
-                    oc.x = oxr;
-                    oc.y = oyi;
-                    const int64_t crow = p.perm ? (int64_t)p.perm[row] : (int64_t)row;
-                    ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
+                for (int i = 0; i < KG; ++i) {
+                    const bool valid = k + i < w;
+                    const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                    const uint32_t l = lidx[slot];
+                    const HV hv = val[slot];
+                    li[i] = ((valid ? l : lrow) << log2ub) + usub;
+                    h[i] = valid ? hv : HV{};
+                }
+#pragma unroll
+                for (int i = 0; i < KG; ++i) {
+                    if constexpr (CH)
+                        unit_mad_cplx<R, VS>(h[i], xs[li[i]], acc);
+                    else
+                        unit_mad_real<R, VS>(h[i], xs[li[i]], acc);
                 }
             }
-        } else {
-            stv<NT>(out + gu, o);
+            const V src = X_IS_V ? xo : vv;
+            V o;
+#pragma unroll
+            for (int i = 0; i < VS; ++i) {
+                const R vr = src[2 * i], vi = src[2 * i + 1];
+                const R hr = acc[2 * i], hi = acc[2 * i + 1];
+                o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
+                o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
+            }
+            if constexpr (HAS_B2) o -= bq;
+            if constexpr (CORR) {
+                stv<false>(out + gu, o);
+                const uint32_t s0 = (boff + usub) << LOG2VS;  // first state of the unit
+#pragma unroll
+                for (int i = 0; i < VS; ++i) {
+                    const d2 ph = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + s0 + i];
+                    const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
+                    dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
+                    dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
+                    nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
+                    if (do_ckpt && (int)(s0 + i) < p.s_user) {
+                        d2 oc;
+                        oc.x = oxr;
+                        oc.y = oyi;
+                        const int64_t crow = p.perm ? (int64_t)p.perm[row] : (int64_t)row;
+                        ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
+                    }
+                }
+            } else {
+                stv<NT>(out + gu, o);
+            }
         }
+        // partials of the block's states: [S][3][n_tiles] from state blk * (units of a block) * VS on
+        if constexpr (CORR)
+            block_unit_partials<VS>(dre, dim, nrm, log2ub,
+                                    p.partials + (int64_t)(boff << LOG2VS) * 3 * p.n_tiles, tile, p.n_tiles);
     }
-    if constexpr (CORR) block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials, tile, p.n_tiles);
 }
 
 // ---------------------------------------------------------------------------

@@ -115,9 +115,6 @@ struct Engine {
     // per-chunk partial products; the product's workgroup tiling (kpm_product_shape)
     DevBuf kp_store, kp_rblk, kp_vec, kp_parts;
     int32_t kpm_shape = 0;
-    // state blocks of the staged shape: one block of states, its correlation
-    // and norms, in the caller's order
-    DevBuf blk_psi, blk_corr, blk_norm;
     // adjoint: segment store, four adjoint vectors, gradient accumulators,
     // and the transposed-slot table of the two-order adjoint (built on first use)
     DevBuf bwd_store, bwd_adj, bwd_gacc, bwd_gdiag, bwd_coef, bwd_partner;
@@ -149,13 +146,7 @@ struct Engine {
     void release();
 
     // the propagation driver (shared by single and batched entry points)
-    // run() for the plain propagation, except that the staged shape keeps
-    // rows of at most kStagedRowBytes: wider state blocks are propagated in
-    // blocks of that many bytes (states are independent; the matrix is read
-    // once per block, the staged tiles hold more rows and re-fetch fewer
-    // halo rows).  Falls back to run() for everything else.
     struct RunArgs;
-    tbpm_status run_states(const RunArgs &a);
     struct RunArgs {
         const double *const *psi0;  // n_inst device pointers
         int32_t s_user;
@@ -211,7 +202,7 @@ struct Engine {
                             double f, double *mu, hipStream_t st, KpmTiming *timing);
     // back-to-back launches of the interior pass on the current buffers
     tbpm_status bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipStream_t stream);
-    int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1;
+    int32_t last_s_pad = 0, last_fp32 = -1, last_staged = 0, last_vs = 1, last_log2ub = 0;
 
     tbpm_status build_tiles(int32_t s_pad, int32_t chunks, int32_t vs);
     // staged tiles for s_pad states of unit_bytes per VS states (log2u units per row);

@@ -93,10 +93,10 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
                 a.norm2 = nullptr;
                 a.flags = TBPM_FLAG_ASYNC;
                 a.stream = stream;
-                st = eng.run_states(a);  // warm-up (builds tiles and the graph)
+                st = eng.run(a);  // warm-up (builds tiles and the graph)
                 if (st != TBPM_OK) break;
                 e = hipEventRecord(t0, stream);
-                if (e == hipSuccess) st = eng.run_states(a);
+                if (e == hipSuccess) st = eng.run(a);
                 if (e == hipSuccess && st == TBPM_OK) e = hipEventRecord(t1, stream);
                 if (e == hipSuccess && st == TBPM_OK) e = hipEventSynchronize(t1);
                 float ms = 0;

@@ -512,12 +512,13 @@ def test_shortest_runs_and_series(fused):
         assert _rel(got, ref) < 1e-12, M
 
 
-@pytest.mark.parametrize("precision,S", [("fp64", 13), ("fp32", 24)])
+@pytest.mark.parametrize("precision,S", [("fp64", 13), ("fp32", 24), ("fp64", 32)])
 def test_staged_state_blocks(precision, S):
-    """The staged shape propagates rows wider than 128 B in state blocks
-    (FP64: 8 states, FP32: 16): 13 FP64 states run as 8 + 5 and 24 FP32
-    states as 16 + 8.  Correlations and norms land in the caller's columns and
-    match the unblocked plain shape and the oracle."""
+    """The staged shape takes rows wider than 128 B one block of states at a
+    time inside each tile (FP64: 8 states, FP32: 16): 13 FP64 states pad to 16
+    and run as two blocks, 24 FP32 states pad to 32 (two blocks), 32 FP64
+    states run as four.  Correlations, norms and (FP64) checkpoints land in
+    the caller's columns and match the plain shape and the oracle."""
     print(f"case staged state blocks {precision} S={S}", flush=True)
     rng = np.random.default_rng(59)
     lat = inputs.twisted_bilayer(20, 20, angle_deg=2.5)
@@ -527,14 +528,21 @@ def test_staged_state_blocks(precision, S):
     nt = 40
     H = tbpm.Hamiltonian.from_lattice(lat)
     H.set_launch_config(2, 1, 1, 1, staged=0, precision=precision)
-    plain, pn = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True)
-    for tier, vec in ((1, 4), (2, 2)):
+    ck = 8 if precision == "fp64" else 0  # checkpoints are taken in FP64 only
+    res = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True, ckpt_every=ck)
+    plain, pn = res[0], res[1]
+    bar = 1e-13 if precision == "fp64" else 1e-6
+    for tier, vec in ((1, 4), (2, 2), (3, 1)):
         H.set_launch_config(2, 0, 0, 1, staged=tier, vec=vec, precision=precision)
-        got, gn = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True)
+        got_all = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, return_norm=True, ckpt_every=ck)
+        got, gn = got_all[0], got_all[1]
         assert got.shape == (nt, S) and gn.shape == (nt, S)
-        bar = 1e-13 if precision == "fp64" else 1e-6
         assert _rel(got.cpu().numpy(), plain.cpu().numpy()) < bar, (tier, vec)
         assert float((gn - pn).abs().max()) < bar, (tier, vec)
+        if ck:
+            gck, pck = got_all[2], res[2]
+            assert gck.shape == pck.shape
+            assert float((gck - pck).abs().max()) < bar * max(1.0, float(pck.abs().max())), (tier, vec)
     ref, ref_n2, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
     if precision == "fp64":
         assert _rel(got.cpu().numpy(), ref) < 1e-10
