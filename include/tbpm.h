@@ -574,10 +574,13 @@ tbpm_status tbpm_stream_copy(const void *src, void *dst, size_t bytes, void *str
 
 /*
  * Enqueue n_launch back-to-back launches of the interior Clenshaw pass kernel
- * (b_j = c_j v + 2 H~ b_{j+1} - b_{j+2}) on H's work buffers, for timing the
- * dominant kernel in isolation.  A tbpm_propagate call with the same
- * n_states and prec must have been made on H first (it sizes and fills the
- * buffers); the buffers' contents stay bounded but are overwritten.
+ * (b_j = c_j v + 2 H~ b_{j+1} - b_{j+2}), or of the two-order launch when the
+ * fused shape is configured, on H's work buffers, for timing the dominant
+ * kernel in isolation.  The launches chain as in a time step: each reads what
+ * the one before wrote, and consecutive launches walk the tiles in opposite
+ * directions.  A tbpm_propagate call with the same n_states and prec must
+ * have been made on H first (it sizes and fills the buffers); the buffers'
+ * contents stay bounded but are overwritten.
  */
 tbpm_status tbpm_bench_pass(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec, int32_t n_launch,
                             void *stream);

@@ -199,6 +199,9 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
     fp.lds_units = (int32_t)(eng.fu_max_rows << (log2s - log2pvs));
     fp.uniform_w = eng.mat.uniform_w;
     const PassCoef *coefs = (const PassCoef *)eng.bwd_coef.ptr;
+    // consecutive launches walk the tiles in opposite directions, so that a
+    // launch starts on the tiles whose rows the one before left in the caches
+    int32_t walk = 0;
     auto replay_step_pairs = [&](int32_t t) -> hipError_t {
         // plan entry p evaluates order pass_j[p]: 0 FIRST (M-2), 1 NOB2 (M-3),
         // 2 .. n_passes-2 MID (M-4 .. 1), n_passes-1 LAST (0)
@@ -209,6 +212,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
         fp.out2 = b_slot(t, M - 3);
         fp.coef1 = coefs;
         fp.coef2 = coefs + 1;
+        fp.reverse = walk;
+        walk ^= 1;
         hipError_t e = launch_pair(kPairFirst, false, cplx, pnt, pvs, fp, st);
         int p = 2;
         for (; e == hipSuccess && p + 1 < n_passes - 1; p += 2) {
@@ -219,6 +224,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             fp.out2 = b_slot(t, j - 1);
             fp.coef1 = coefs + p;
             fp.coef2 = coefs + p + 1;
+            fp.reverse = walk;
+            walk ^= 1;
             e = launch_pair(kPairMid, false, cplx, pnt, pvs, fp, st);
         }
         for (; e == hipSuccess && p < n_passes; ++p) {  // a leftover MID, then LAST
@@ -228,6 +235,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             pp.b2 = b_slot(t, j + 2);
             pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
             pp.coef = coefs + p;
+            pp.reverse = walk;
+            walk ^= 1;
             e = launch_pass(replay_kind(plan[p].kind), false, cplx, pnt, eng.cfg.unroll, pvs, pp, st);
         }
         return e;
@@ -284,6 +293,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             qp.cc1_im = -c[j + 1].imag();
             qp.cc2_re = c[j + 2].real();
             qp.cc2_im = -c[j + 2].imag();
+            qp.reverse = walk;
+            walk ^= 1;
             e = launch_adjoint_pair(j == 0 ? kAdjPairFirst : kAdjPairMid, cplx, pvs, qp, st);
             // alpha_{j+2} is the next x, alpha_{j+1} the next prev; the old x and
             // prev (or the spare buffer after the first pair) take the outputs
@@ -314,6 +325,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
             ap.ccn_re = c[j + 1].real();
             ap.ccn_im = -c[j + 1].imag();
             ap.gcorr_l = gcorr + 2 * (size_t)l * s_user;
+            ap.reverse = walk;
+            walk ^= 1;
             e = launch_adjoint_pass(kind, cplx, ap, st);
             double *nx = fr[0];
             fr[0] = P;
@@ -352,6 +365,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
                 pp.b2 = (pl.kind == kPassMid || pl.kind == kPassLast) ? b_slot(t, j + 2) : nullptr;
                 pp.out = (j == 0) ? psi_slot(t + 1) : b_slot(t, j);
                 pp.coef = (const PassCoef *)eng.bwd_coef.ptr + p;
+                pp.reverse = walk;
+                walk ^= 1;
                 TRY_HIP(launch_pass(replay_kind(pl.kind), false, cplx, false, eng.cfg.unroll, 1, pp, st), "replay pass");
             }
         }
@@ -385,6 +400,8 @@ tbpm_status backward_impl(tbpm_hamiltonian *H, const double *psi0, int32_t s_use
                 ap.gcorr_l = gcorr + 2 * (size_t)l * s_user;
                 // the first pass (j = 0) writes alpha_1 = H~ lambda; the final pass
                 // (j = M-2) leaves the new lambda in 'acc'
+                ap.reverse = walk;
+                walk ^= 1;
                 TRY_HIP(launch_adjoint_pass(kind, cplx, ap, st), "adjoint pass");
             }
             // lambda_l is in acc; the old lambda buffer becomes the accumulator

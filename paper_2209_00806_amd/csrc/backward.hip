@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kWG) void k_adj_pass(const AdjParams p) {
     using HV = std::conditional_t<CH, d2, double>;
     using GV = std::conditional_t<CH, d2, double>;
     constexpr int KG = 4;
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const int log2s = p.log2s;
     const uint32_t smask = (1u << log2s) - 1u;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kWG) void k_adj_pair(const AdjPairParams p) {
     constexpr int KG = 4;
     constexpr bool FIRST = (KIND == kAdjPairFirst);
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const int log2u = p.log2s - LOG2VS;
     const uint32_t umask = (1u << log2u) - 1u;

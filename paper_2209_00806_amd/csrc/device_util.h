@@ -63,12 +63,18 @@ __device__ __forceinline__ void stv(T *p, T v) {
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that XCD x
 // works through one contiguous range of tiles (the neighbour rows gathered
-// by a tile were then most likely brought into the same XCD's L2).
-__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap) {
-    if (!remap) return b;
+// by a tile were then most likely brought into the same XCD's L2).  Launches
+// that read what the previous launch wrote alternate the walking direction:
+// the tiles a launch starts with are then the ones the previous launch
+// finished with, whose rows are still in the caches.
+__device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap, int reverse = 0) {
+    if (!remap) return reverse ? n_tiles - 1 - b : b;
     const int q = n_tiles >> 3, r = n_tiles & 7;
     const int x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
+    // XCD x walks its contiguous range of q (+1) tiles, first to last or, with
+    // reverse, last to first
+    const int cnt = q + (x < r ? 1 : 0);
+    return x * q + (x < r ? x : r) + (reverse ? cnt - 1 - i : i);
 }
 
 // Sum (dre, dim, nrm) over the threads of the workgroup that hold the same

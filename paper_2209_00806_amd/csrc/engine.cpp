@@ -764,7 +764,9 @@ tbpm_status Engine::run(const RunArgs &a) {
         for (; p < n_passes; ++p) sched.push_back({p, -1, -1, -1, -1, -1});
     }
 
-    // one time step
+    // one time step; consecutive launches walk the tiles in opposite
+    // directions (walk: the direction of the next launch)
+    int32_t walk = 0;
     auto enqueue_step = [&](hipStream_t s) -> tbpm_status {
         if (fused) {
             int cur = 2, prev = 1;
@@ -798,6 +800,8 @@ tbpm_status Engine::run(const RunArgs &a) {
                     fp.hidx = (const uint16_t *)fu_hidx.ptr;
                     fp.lds_units = fu_lds_units;
                     fp.uniform_w = mat.uniform_w;
+                    fp.reverse = walk;
+                    walk ^= 1;
                     hipError_t e = launch_pair(l.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, fp, s);
                     if (e != hipSuccess) return hip_fail(e, "launch pair");
                     prev = l.o1;
@@ -830,6 +834,8 @@ tbpm_status Engine::run(const RunArgs &a) {
                 pp.ckpt_stride = mat.n_rows * a.s_user;
                 pp.s_user = a.s_user;
                 pp.uniform_w = mat.uniform_w;
+                pp.reverse = walk;
+                walk ^= 1;
                 hipError_t e =
                     launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs, pp, s);
                 if (e != hipSuccess) return hip_fail(e, "launch pass");
@@ -871,6 +877,8 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.stage_units = stage_units;
             pp.log2ub = log2ub;
             pp.uniform_w = staged ? 0 : mat.uniform_w;
+            pp.reverse = walk;
+            walk ^= 1;
             hipError_t e = staged ? launch_pass_staged(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs,
                                                   mat.max_width > kStagedWide, pp, s)
                                   : launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs,
@@ -935,6 +943,7 @@ tbpm_status Engine::run(const RunArgs &a) {
                     exec = nullptr;
                 }
                 TRY_HIP(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+                walk = 0;  // a graph of an even number of launches keeps the alternation across replays
                 tbpm_status cst = TBPM_OK;
                 for (int32_t q = 0; q < steps && cst == TBPM_OK; ++q) cst = enqueue_step(capture_stream);
                 hipGraph_t g = nullptr;
@@ -1094,6 +1103,10 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
         fp.out2 = n_ord == 2 ? dst : wb[1];
         fp.coef1 = cf;
         fp.coef2 = cf + 1;
+        // consecutive launches walk the tiles in opposite directions
+        int32_t walk = 0;
+        fp.reverse = walk;
+        walk ^= 1;
         hipError_t e = launch_pair(kPairFirst, false, mat.is_complex, nt, pvs, fp, st);
         int x = 1, b2 = 0;  // b_{k+1} in wb[x], b_{k+2} in wb[b2]
         size_t i = 2;
@@ -1107,6 +1120,8 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
             fp.out2 = (i + 1 == n_ord - 1) ? dst : wb[free_[1]];
             fp.coef1 = cf + i;
             fp.coef2 = cf + i + 1;
+            fp.reverse = walk;
+            walk ^= 1;
             e = launch_pair(kPairMid, false, mat.is_complex, nt, pvs, fp, st);
             b2 = free_[0];
             x = free_[1];
@@ -1116,6 +1131,7 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
             pp.b2 = wb[b2];
             pp.out = dst;
             pp.coef = cf + i;
+            pp.reverse = walk;
             e = launch_pass(kPassMid, false, mat.is_complex, nt, 1, pvs, pp, st);
         }
         if (e != hipSuccess) return hip_fail(e, "launch series pair");
@@ -1126,6 +1142,7 @@ tbpm_status Engine::apply_series(const std::vector<double> &a_in, double f, int3
         pp.b2 = seq[i].b2;
         pp.out = seq[i].out;
         pp.coef = (const PassCoef *)coef.ptr + i;
+        pp.reverse = (int32_t)(i & 1);  // consecutive launches walk the tiles in opposite directions
         hipError_t e = launch_pass(seq[i].kind, false, mat.is_complex, false, 1, 1, pp, st);
         if (e != hipSuccess) return hip_fail(e, "launch series pass");
     }
@@ -1226,13 +1243,27 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
         fp.hidx = (const uint16_t *)fu_hidx.ptr;
         fp.lds_units = fu_lds_units;
         fp.uniform_w = mat.uniform_w;
+        // as in a time step: each launch reads the two outputs of the one
+        // before and walks the tiles the other way
         for (int32_t i = 0; i < n_launch; ++i) {
+            const bool odd = (i & 1) != 0;
+            fp.x = odd ? bd.ptr : bb.ptr;
+            fp.b2 = odd ? bc.ptr : ba.ptr;
+            fp.out1 = odd ? ba.ptr : bc.ptr;
+            fp.out2 = odd ? bb.ptr : bd.ptr;
+            fp.reverse = odd ? 1 : 0;
             hipError_t e = launch_pair(kPairMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs, fp, stream);
             if (e != hipSuccess) return hip_fail(e, "launch pair");
         }
         return TBPM_OK;
     }
+    // as in a time step: the order just written is the next one's gathered
+    // vector, and the tiles are walked the other way
     for (int32_t i = 0; i < n_launch; ++i) {
+        const bool odd = (i & 1) != 0;
+        pp.x = odd ? bb.ptr : ba.ptr;
+        pp.b2 = pp.out = odd ? ba.ptr : bb.ptr;
+        pp.reverse = odd ? 1 : 0;
         hipError_t e = last_staged
                            ? launch_pass_staged(kPassMid, fp32, mat.is_complex, cfg.nontemporal != 0, last_vs,
                                                 mat.max_width > kStagedWide, pp, stream)

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
     constexpr bool FIRST = (KIND == kPairFirst);
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
 
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const PassCoef c1 = p.coef1[td.inst], c2 = p.coef2[td.inst];
     const int log2u = p.log2s - LOG2VS;

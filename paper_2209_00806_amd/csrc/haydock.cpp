@@ -46,7 +46,7 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
     // u_0 = psi0 (internal order, padded states zero), u_{-1} = 0, 1/b_0 = 1/||psi0||
     TRY_HIP(launch_expand_states(psi0, mat.perm, s_user, u[0], log2s, n, st), "load start vectors");
     TRY_HIP(launch_fill_zero(u[1], 2 * n * s_pad, st), "clear Lanczos vector");
-    TRY_HIP(launch_hay_axpy(td, n_tiles, cfg.xcd_remap, log2s, u[0], nullptr, nullptr, hs, part, st), "start norm");
+    TRY_HIP(launch_hay_axpy(td, n_tiles, cfg.xcd_remap, 0, log2s, u[0], nullptr, nullptr, hs, part, st), "start norm");
     TRY_HIP(launch_hay_reduce(part, n_tiles, s_pad, s_user, 2, thr, hs, cnt, n_iter, a_out, b_out, fold, st),
             "start norm reduce");
 
@@ -56,7 +56,7 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
                                        mat.slice_off, mat.onsite64, cur, prev, y, hs, cnt, part, s);
         if (e == hipSuccess)
             e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 0, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
-        if (e == hipSuccess) e = launch_hay_axpy(td, n_tiles, cfg.xcd_remap, log2s, y, cur, prev, hs, part, s);
+        if (e == hipSuccess) e = launch_hay_axpy(td, n_tiles, cfg.xcd_remap, 1, log2s, y, cur, prev, hs, part, s);
         if (e == hipSuccess)
             e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 1, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
         return e;

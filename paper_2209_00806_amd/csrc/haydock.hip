@@ -90,11 +90,14 @@ __global__ __launch_bounds__(kWG) void k_hay_spmv(const TileDesc *__restrict__ t
 }
 
 // unext = y - (a_i/b_i) u  (unext may be the buffer of u_{i-1}), with the
-// partials of ||unext||^2; with unext null it only measures ||y||^2
+// partials of ||unext||^2; with unext null it only measures ||y||^2.  The
+// iteration walks it last tile to first (reverse), so it starts on the tiles
+// whose y the product pass wrote last, and the next product pass starts on
+// the tiles whose u_{i+1} it wrote last.
 __global__ __launch_bounds__(kWG) void k_hay_axpy(const TileDesc *__restrict__ tiles, int n_tiles, int xcd_remap,
-                                                  int log2s, const d2 *y, const d2 *u, d2 *unext,
+                                                  int reverse, int log2s, const d2 *y, const d2 *u, d2 *unext,
                                                   const double *__restrict__ hs, double *__restrict__ partials) {
-    const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, n_tiles, xcd_remap, reverse);
     const TileDesc td = tiles[tile];
     const uint32_t smask = (1u << log2s) - 1u;
     const uint32_t s = threadIdx.x & smask;
@@ -237,9 +240,10 @@ hipError_t launch_hay_spmv(bool cplx, const TileDesc *tiles, int32_t n_tiles, in
     return hipGetLastError();
 }
 
-hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s, const double *y,
-                           const double *u, double *unext, const double *hs, double *partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_hay_axpy, dim3((unsigned)n_tiles), dim3(kWG), 0, st, tiles, n_tiles, xcd_remap, log2s,
+hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t reverse, int32_t log2s,
+                           const double *y, const double *u, double *unext, const double *hs, double *partials,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_hay_axpy, dim3((unsigned)n_tiles), dim3(kWG), 0, st, tiles, n_tiles, xcd_remap, reverse, log2s,
                        (const d2 *)y, (const d2 *)u, (d2 *)unext, hs, partials);
     return hipGetLastError();
 }

@@ -78,6 +78,7 @@ struct PassParams {
     const uint16_t *lidx;
     int32_t stage_units;   // LDS capacity in units (VS states)
     int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
+    int32_t reverse;  // walk the tiles last to first (see tile_of_block)
     // staged launch shape: log2 of the units of one state block of a row (at
     // most log2s - log2 VS); a tile stages and evaluates its rows one block of
     // states at a time, so the LDS holds rows of one block
@@ -117,6 +118,7 @@ struct FusedParams {
     const uint16_t *hidx;  // local indices of the stored elements of the 1-hop rows
     int32_t lds_units;     // LDS capacity in units: max over tiles of n_x + n_y
     int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
+    int32_t reverse;       // walk the tiles last to first (see tile_of_block)
 };
 
 struct InitParams {

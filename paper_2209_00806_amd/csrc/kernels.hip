@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
     constexpr bool CORR = (KIND == kPassLast || KIND == kPassLastNoB2);
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
 
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const PassCoef pc = p.coef[td.inst];
     const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
     V *xs = reinterpret_cast<V *>(stage_mem);
 
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap);
+    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const PassCoef pc = p.coef[td.inst];
     const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;

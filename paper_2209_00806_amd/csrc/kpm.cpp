@@ -94,9 +94,13 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
     TRY_HIP(hipEventRecord(staging_done, st), "record staging");
     const PassCoef *c_j = (const PassCoef *)coef.ptr, *c_1 = c_j + 1, *c_2 = c_j + 2;
 
+    // consecutive launches walk the tiles in opposite directions
+    int32_t walk = 0;
     auto pass = [&](int kind, bool jop, const double *jval, const void *x, const void *b2, void *out,
                     const PassCoef *c) -> hipError_t {
         PassParams pp{};
+        pp.reverse = walk;
+        walk ^= 1;
         pp.tiles = (const TileDesc *)tiles.ptr;
         pp.n_tiles = (int32_t)h_tiles.size();
         pp.xcd_remap = cfg.xcd_remap;
@@ -142,6 +146,8 @@ tbpm_status Engine::kpm_moments(const double *ja, const double *jb, const double
         fp.b2 = tkm1;
         fp.out1 = o1;
         fp.out2 = o2;
+        fp.reverse = walk;
+        walk ^= 1;
         return launch_pair(kPairMid, false, mat.is_complex, pnt, pvs, fp, st);
     };
 

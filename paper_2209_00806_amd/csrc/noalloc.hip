@@ -227,6 +227,8 @@ tbpm_status propagate_noalloc(tbpm_hamiltonian *H, const double *psi0, int32_t s
             pp.partials = partials;
             pp.s_user = s_user;
             pp.uniform_w = m.uniform_w;
+            // consecutive launches walk the tiles in opposite directions
+            pp.reverse = (int32_t)(((int64_t)k * n_passes + p) & 1);
             e = launch_pass(pl.kind, fp32, m.is_complex, cf.nontemporal != 0, cf.unroll, vs, pp, st);
             if (e != hipSuccess) return hip_fail(e, "launch pass");
         }

@@ -76,6 +76,7 @@ struct AdjParams {
     const TileDesc *tiles;
     int32_t n_tiles;
     int32_t xcd_remap;
+    int32_t reverse;  // walk the tiles last to first (see tile_of_block)
     int32_t log2s;
     int32_t s_user;
     const int32_t *col;
@@ -115,6 +116,7 @@ struct AdjPairParams {
     const TileDesc *tiles;
     int32_t n_tiles;
     int32_t xcd_remap;
+    int32_t reverse;  // walk the tiles last to first (see tile_of_block)
     int32_t log2s;
     const int32_t *col;
     const void *val;        // double or double2 (FP64)
@@ -189,8 +191,9 @@ hipError_t launch_hay_spmv(bool cplx, const TileDesc *tiles, int32_t n_tiles, in
                            const int32_t *col, const void *val, const uint32_t *slice_off, const double *onsite,
                            const double *u, const double *uprev, double *y, const double *hs, int32_t *counter,
                            double *partials, hipStream_t st);
-hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s, const double *y,
-                           const double *u, double *unext, const double *hs, double *partials, hipStream_t st);
+hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t reverse, int32_t log2s,
+                           const double *y, const double *u, double *unext, const double *hs, double *partials,
+                           hipStream_t st);
 // Per-state sum of the tile partials and the scalar update of `mode`; above
 // 4 kWG tiles the sum runs in two stages through `fold`, which must hold
 // hay_fold_count(n_tiles) * s_pad doubles (0: unused).
