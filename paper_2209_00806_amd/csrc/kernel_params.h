@@ -83,6 +83,10 @@ struct PassParams {
     // most log2s - log2 VS); a tile stages and evaluates its rows one block of
     // states at a time, so the LDS holds rows of one block
     int32_t log2ub;
+    // with several blocks: one workgroup per (tile, block), the blocks of a
+    // tile on the same XCD at the same time (else one workgroup per tile
+    // takes its blocks in turn)
+    int32_t blk_split;
 };
 
 // Two Clenshaw orders per launch (fused.hip).

@@ -199,10 +199,12 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
 // a time (indices and values loaded together, then the LDS reads): 4 for
 // narrow rows, 12 for wide ones, where fewer dependent rounds of loads per
 // row matter more than the padded slots of the last batch.  Rows wider than
-// the LDS row width are taken one block of states at a time (2^log2ub units):
-// the tile stages and evaluates block 0, then block 1, ..., so the LDS holds
-// rows of one block and the tile's matrix entries come from HBM once, the
-// later blocks finding them in L2.
+// the LDS row width are taken one block of states at a time (2^log2ub units),
+// so the LDS holds rows of one block: either one workgroup per tile stages
+// and evaluates block 0, then block 1, ..., or (blk_split) one workgroup per
+// (tile, block), the blocks of a tile on one XCD at about the same time, so
+// that the tile's matrix entries come from HBM once and the other blocks
+// find them in that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename R, bool CH, int KIND, bool NT, int VS, int KG>
 __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
@@ -215,13 +217,26 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
     V *xs = reinterpret_cast<V *>(stage_mem);
 
-    const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
-    const TileDesc td = p.tiles[tile];
-    const PassCoef pc = p.coef[td.inst];
-    const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
     const int log2u = p.log2s - LOG2VS;  // units of a whole row
     const int log2ub = p.log2ub;         // units of one state block of a row
     const int n_blk = 1 << (log2u - log2ub);
+    // blocks of states: all in turn, or (blk_split) the one of this workgroup.
+    // Workgroup g of a split launch takes block (g >> 3) % n_blk of tile
+    // slot ((g >> 3) / n_blk) * 8 + (g & 7): the blocks of a tile run on
+    // one XCD (blocks are dispatched to XCD g & 7) at about the same time,
+    // so the later ones find the tile's matrix entries in that XCD's L2
+    int blk_lo = 0, blk_hi = n_blk, slot = (int)blockIdx.x;
+    if (p.blk_split) {
+        const int r = (int)blockIdx.x >> 3;
+        blk_lo = r % n_blk;
+        blk_hi = blk_lo + 1;
+        slot = (r / n_blk) * 8 + ((int)blockIdx.x & 7);
+        if (slot >= p.n_tiles) return;  // the last group of 8 slots is partial
+    }
+    const int tile = tile_of_block(slot, p.n_tiles, p.xcd_remap, p.reverse);
+    const TileDesc td = p.tiles[tile];
+    const PassCoef pc = p.coef[td.inst];
+    const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
     const uint32_t umask = (1u << log2ub) - 1u;
     const uint32_t n_own = (uint32_t)td.rows;
     const uint32_t n_u = n_own << log2ub;
@@ -255,9 +270,9 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
 
     // one state block at a time: the tile's matrix entries are read again for
     // every block after the first, from L2
-    for (int blk = 0; blk < n_blk; ++blk) {
+    for (int blk = blk_lo; blk < blk_hi; ++blk) {
         const uint32_t boff = (uint32_t)blk << log2ub;  // unit offset of the block in a row
-        if (blk > 0) __syncthreads();                    // the previous block's LDS reads are done
+        if (blk > blk_lo) __syncthreads();               // the previous block's LDS reads are done
         for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
             const uint32_t lr = i >> log2ub;
             const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
@@ -618,7 +633,9 @@ hipError_t launch_pass_r(int kind, bool cplx, bool nt, int ne, const PassParams 
 
 template <typename R, bool CH, bool NT, int VS, int KG>
 hipError_t launch_staged_t(int kind, const PassParams &p, hipStream_t st) {
-    const dim3 grid(p.n_tiles), block(kWG);
+    constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
+    const int n_blk = 1 << (p.log2s - LOG2VS - p.log2ub);
+    const dim3 grid(p.blk_split ? (unsigned)(((p.n_tiles + 7) / 8) * 8 * n_blk) : (unsigned)p.n_tiles), block(kWG);
     const size_t lds = (size_t)p.stage_units * sizeof(VecT<R, VS>);
     switch (kind) {
         case kPassFirst:
