@@ -553,10 +553,11 @@ tbpm_status tbpm_batch_get_launch_config(const tbpm_batch *B, tbpm_precision pre
 
 /*
  * Autotune the launch configuration of H (or of a batch) for n_states and
- * prec by timing every candidate on a few Chebyshev steps of scratch states
- * on 'stream' (synchronises).  The best configuration is stored in the
- * handle for that precision and returned in *best (may be NULL); its mean
- * step time in ms in *best_ms (may be NULL).  Candidates with more elements
+ * prec by timing every candidate on three Chebyshev time steps of scratch
+ * states, then the three fastest on eight, on 'stream' (synchronises).  The
+ * best configuration is stored in the handle for that precision and returned
+ * in *best (may be NULL); its mean step time in ms over the eight steps in
+ * *best_ms (may be NULL).  Candidates with more elements
  * per thread than chunks per workgroup are skipped (they idle threads).
  */
 tbpm_status tbpm_autotune(tbpm_hamiltonian *H, int32_t n_states, tbpm_precision prec,

@@ -876,7 +876,6 @@ tbpm_status Engine::run(const RunArgs &a) {
             pp.lidx = (const uint16_t *)st_lidx.ptr;
             pp.stage_units = stage_units;
             pp.log2ub = log2ub;
-            pp.blk_split = log2ub < log2u ? 1 : 0;
             pp.uniform_w = staged ? 0 : mat.uniform_w;
             pp.reverse = walk;
             walk ^= 1;
@@ -1216,7 +1215,6 @@ tbpm_status Engine::bench_pass(int32_t s_user, bool fp32, int32_t n_launch, hipS
     pp.lidx = (const uint16_t *)st_lidx.ptr;
     pp.stage_units = stage_units;
     pp.log2ub = last_log2ub;
-    pp.blk_split = last_log2ub < log2s - (last_vs == 4 ? 2 : (last_vs == 2 ? 1 : 0)) ? 1 : 0;
     if (last_staged == 2) {
         // the interior launch of the fused shape: a MID pair (b_{j+1} in B,
         // b_{j+2} in A, outputs to C and D)

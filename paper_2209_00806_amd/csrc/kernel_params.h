@@ -80,13 +80,10 @@ struct PassParams {
     int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
     int32_t reverse;  // walk the tiles last to first (see tile_of_block)
     // staged launch shape: log2 of the units of one state block of a row (at
-    // most log2s - log2 VS); a tile stages and evaluates its rows one block of
-    // states at a time, so the LDS holds rows of one block
+    // most log2s - log2 VS); with several blocks, one workgroup per (tile,
+    // block) stages and evaluates the tile's rows of that block, so the LDS
+    // holds rows of one block
     int32_t log2ub;
-    // with several blocks: one workgroup per (tile, block), the blocks of a
-    // tile on the same XCD at the same time (else one workgroup per tile
-    // takes its blocks in turn)
-    int32_t blk_split;
 };
 
 // Two Clenshaw orders per launch (fused.hip).

@@ -199,12 +199,10 @@ __global__ __launch_bounds__(kWG) void k_pass(const PassParams p) {
 // a time (indices and values loaded together, then the LDS reads): 4 for
 // narrow rows, 12 for wide ones, where fewer dependent rounds of loads per
 // row matter more than the padded slots of the last batch.  Rows wider than
-// the LDS row width are taken one block of states at a time (2^log2ub units),
-// so the LDS holds rows of one block: either one workgroup per tile stages
-// and evaluates block 0, then block 1, ..., or (blk_split) one workgroup per
-// (tile, block), the blocks of a tile on one XCD at about the same time, so
-// that the tile's matrix entries come from HBM once and the other blocks
-// find them in that XCD's L2.
+// the LDS row width are taken one block of states (2^log2ub units) per
+// workgroup, so the LDS holds rows of one block; the blocks of a tile run on
+// one XCD at about the same time, so that the tile's matrix entries come
+// from HBM once and the other blocks find them in that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename R, bool CH, int KIND, bool NT, int VS, int KG>
 __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
@@ -220,20 +218,20 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
     const int log2u = p.log2s - LOG2VS;  // units of a whole row
     const int log2ub = p.log2ub;         // units of one state block of a row
     const int n_blk = 1 << (log2u - log2ub);
-    // blocks of states: all in turn, or (blk_split) the one of this workgroup.
-    // Workgroup g of a split launch takes block (g >> 3) % n_blk of tile
-    // slot ((g >> 3) / n_blk) * 8 + (g & 7): the blocks of a tile run on
-    // one XCD (blocks are dispatched to XCD g & 7) at about the same time,
-    // so the later ones find the tile's matrix entries in that XCD's L2
-    int blk_lo = 0, blk_hi = n_blk, slot = (int)blockIdx.x;
-    if (p.blk_split) {
+    // the block of states of this workgroup: with several blocks, workgroup
+    // g takes block (g >> 3) % n_blk of tile slot ((g >> 3) / n_blk) * 8 +
+    // (g & 7), so the blocks of a tile run on one XCD (workgroups are
+    // dispatched to XCD g & 7) at about the same time and the later ones find
+    // the tile's matrix entries in that XCD's L2
+    int blk = 0, tslot = (int)blockIdx.x;
+    if (n_blk > 1) {
         const int r = (int)blockIdx.x >> 3;
-        blk_lo = r % n_blk;
-        blk_hi = blk_lo + 1;
-        slot = (r / n_blk) * 8 + ((int)blockIdx.x & 7);
-        if (slot >= p.n_tiles) return;  // the last group of 8 slots is partial
+        blk = r % n_blk;
+        tslot = (r / n_blk) * 8 + ((int)blockIdx.x & 7);
+        if (tslot >= p.n_tiles) return;  // the last group of 8 slots is partial
     }
-    const int tile = tile_of_block(slot, p.n_tiles, p.xcd_remap, p.reverse);
+    const uint32_t boff = (uint32_t)blk << log2ub;  // unit offset of the block in a row
+    const int tile = tile_of_block(tslot, p.n_tiles, p.xcd_remap, p.reverse);
     const TileDesc td = p.tiles[tile];
     const PassCoef pc = p.coef[td.inst];
     const R ar = (R)pc.ar, ai = (R)pc.ai, br = (R)pc.br, bi = (R)pc.bi;
@@ -268,92 +266,86 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
         }
     }
 
-    // one state block at a time: the tile's matrix entries are read again for
-    // every block after the first, from L2
-    for (int blk = blk_lo; blk < blk_hi; ++blk) {
-        const uint32_t boff = (uint32_t)blk << log2ub;  // unit offset of the block in a row
-        if (blk > blk_lo) __syncthreads();               // the previous block's LDS reads are done
-        for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
-            const uint32_t lr = i >> log2ub;
-            const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
-            xs[i] = x[(grow << log2u) + boff + (i & umask)];
-        }
-        __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
+        const uint32_t lr = i >> log2ub;
+        const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
+        xs[i] = x[(grow << log2u) + boff + (i & umask)];
+    }
+    __syncthreads();
 
-        double dre[VS], dim[VS], nrm[VS];
+    double dre[VS], dim[VS], nrm[VS];
 #pragma unroll
-        for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
+    for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
 
-        for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
-            const uint32_t lrow = u >> log2ub;
-            const uint32_t row = row0 + lrow;
-            const uint32_t gu = (row << log2u) + boff + usub;
-            const uint32_t sl = row / kSliceRows;
-            const uint32_t off = soff[sl];
-            const int w = (int)((soff[sl + 1] - off) / kSliceRows);
-            const uint32_t base = off + row % kSliceRows;
-            V vv, bq;
-            if constexpr (!X_IS_V) vv = ldv<NT>(v + gu);
-            if constexpr (HAS_B2) bq = ldv<NT>(b2 + gu);
-            const V xo = xs[u];
-            V acc = ons[row] * xo;
-            for (int k = 0; k < w; k += KG) {
-                uint32_t li[KG];
-                HV h[KG];
+    for (uint32_t u = threadIdx.x; u < n_u; u += kWG) {
+        const uint32_t lrow = u >> log2ub;
+        const uint32_t row = row0 + lrow;
+        const uint32_t gu = (row << log2u) + boff + usub;
+        const uint32_t sl = row / kSliceRows;
+        const uint32_t off = soff[sl];
+        const int w = (int)((soff[sl + 1] - off) / kSliceRows);
+        const uint32_t base = off + row % kSliceRows;
+        V vv, bq;
+        if constexpr (!X_IS_V) vv = ldv<NT>(v + gu);
+        if constexpr (HAS_B2) bq = ldv<NT>(b2 + gu);
+        const V xo = xs[u];
+        V acc = ons[row] * xo;
+        for (int k = 0; k < w; k += KG) {
+            uint32_t li[KG];
+            HV h[KG];
 #pragma unroll
-                for (int i = 0; i < KG; ++i) {
-                    const bool valid = k + i < w;
-                    const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
-                    const uint32_t l = lidx[slot];
-                    const HV hv = val[slot];
-                    li[i] = ((valid ? l : lrow) << log2ub) + usub;
-                    h[i] = valid ? hv : HV{};
-                }
-#pragma unroll
-                for (int i = 0; i < KG; ++i) {
-                    if constexpr (CH)
-                        unit_mad_cplx<R, VS>(h[i], xs[li[i]], acc);
-                    else
-                        unit_mad_real<R, VS>(h[i], xs[li[i]], acc);
-                }
+            for (int i = 0; i < KG; ++i) {
+                const bool valid = k + i < w;
+                const uint32_t slot = valid ? base + (uint32_t)(k + i) * kSliceRows : 0u;
+                const uint32_t l = lidx[slot];
+                const HV hv = val[slot];
+                li[i] = ((valid ? l : lrow) << log2ub) + usub;
+                h[i] = valid ? hv : HV{};
             }
-            const V src = X_IS_V ? xo : vv;
-            V o;
+#pragma unroll
+            for (int i = 0; i < KG; ++i) {
+                if constexpr (CH)
+                    unit_mad_cplx<R, VS>(h[i], xs[li[i]], acc);
+                else
+                    unit_mad_real<R, VS>(h[i], xs[li[i]], acc);
+            }
+        }
+        const V src = X_IS_V ? xo : vv;
+        V o;
+#pragma unroll
+        for (int i = 0; i < VS; ++i) {
+            const R vr = src[2 * i], vi = src[2 * i + 1];
+            const R hr = acc[2 * i], hi = acc[2 * i + 1];
+            o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
+            o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
+        }
+        if constexpr (HAS_B2) o -= bq;
+        if constexpr (CORR) {
+            stv<false>(out + gu, o);
+            const uint32_t s0 = (boff + usub) << LOG2VS;  // first state of the unit
 #pragma unroll
             for (int i = 0; i < VS; ++i) {
-                const R vr = src[2 * i], vi = src[2 * i + 1];
-                const R hr = acc[2 * i], hi = acc[2 * i + 1];
-                o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
-                o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
-            }
-            if constexpr (HAS_B2) o -= bq;
-            if constexpr (CORR) {
-                stv<false>(out + gu, o);
-                const uint32_t s0 = (boff + usub) << LOG2VS;  // first state of the unit
-#pragma unroll
-                for (int i = 0; i < VS; ++i) {
-                    const d2 ph = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + s0 + i];
-                    const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
-                    dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
-                    dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
-                    nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
-                    if (do_ckpt && (int)(s0 + i) < p.s_user) {
-                        d2 oc;
-                        oc.x = oxr;
-                        oc.y = oyi;
-                        const int64_t crow = p.perm ? (int64_t)p.perm[row] : (int64_t)row;
-                        ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
-                    }
+                const d2 ph = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + s0 + i];
+                const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
+                dre[i] = fma(ph.x, oxr, fma(ph.y, oyi, dre[i]));
+                dim[i] = fma(ph.x, oyi, fma(-ph.y, oxr, dim[i]));
+                nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
+                if (do_ckpt && (int)(s0 + i) < p.s_user) {
+                    d2 oc;
+                    oc.x = oxr;
+                    oc.y = oyi;
+                    const int64_t crow = p.perm ? (int64_t)p.perm[row] : (int64_t)row;
+                    ((d2 *)p.ckpt)[(int64_t)ckpt_base * p.ckpt_stride + crow * p.s_user + s0 + i] = oc;
                 }
-            } else {
-                stv<NT>(out + gu, o);
             }
+        } else {
+            stv<NT>(out + gu, o);
         }
-        // partials of the block's states: [S][3][n_tiles] from state blk * (units of a block) * VS on
-        if constexpr (CORR)
-            block_unit_partials<VS>(dre, dim, nrm, log2ub,
-                                    p.partials + (int64_t)(boff << LOG2VS) * 3 * p.n_tiles, tile, p.n_tiles);
     }
+    // partials of the block's states: [S][3][n_tiles] from state blk * (units of a block) * VS on
+    if constexpr (CORR)
+        block_unit_partials<VS>(dre, dim, nrm, log2ub,
+                                p.partials + (int64_t)(boff << LOG2VS) * 3 * p.n_tiles, tile, p.n_tiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +627,7 @@ template <typename R, bool CH, bool NT, int VS, int KG>
 hipError_t launch_staged_t(int kind, const PassParams &p, hipStream_t st) {
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
     const int n_blk = 1 << (p.log2s - LOG2VS - p.log2ub);
-    const dim3 grid(p.blk_split ? (unsigned)(((p.n_tiles + 7) / 8) * 8 * n_blk) : (unsigned)p.n_tiles), block(kWG);
+    const dim3 grid(n_blk > 1 ? (unsigned)(((p.n_tiles + 7) / 8) * 8 * n_blk) : (unsigned)p.n_tiles), block(kWG);
     const size_t lds = (size_t)p.stage_units * sizeof(VecT<R, VS>);
     switch (kind) {
         case kPassFirst:

@@ -1,10 +1,12 @@
 // Autotuner of the Chebyshev pass launch shape: times every candidate
 // (workgroup chunks x XCD remap x non-temporal streaming x elements per
-// thread x states per thread; LDS-staged and two-order fused shapes) on a few
-// time steps
-// of scratch states and keeps the fastest in the handle.
+// thread x states per thread; LDS-staged and two-order fused shapes) on three
+// time steps of scratch states, times the three fastest again on eight steps
+// (shapes within a few percent of each other swap places between short runs)
+// and keeps the fastest of those in the handle.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -15,7 +17,8 @@ namespace tbpm {
 tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32_t n_states, bool fp32,
                           tbpm_launch_config *best, double *best_ms, hipStream_t stream) {
     const int32_t ni = eng.n_inst();
-    const int32_t n_steps = 4;  // three timed Chebyshev steps
+    const int32_t n_steps = 4;   // three timed Chebyshev steps per candidate
+    const int32_t n_steps2 = 9;  // eight for the finalists
     int64_t max_rows = 0;
     for (int32_t i = 0; i < ni; ++i) max_rows = std::max(max_rows, eng.inst_row0[i + 1] - eng.inst_row0[i]);
     std::vector<double> h_psi(2 * (size_t)max_rows * n_states);
@@ -26,7 +29,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     DevBuf psi, corr;
     hipError_t e = psi.ensure(sizeof(double) * h_psi.size());
     if (e != hipSuccess) return hip_fail(e, "autotune alloc");
-    e = corr.ensure(sizeof(double) * 2 * (size_t)ni * n_steps * n_states);
+    e = corr.ensure(sizeof(double) * 2 * (size_t)ni * n_steps2 * n_states);
     if (e != hipSuccess) {
         psi.release();
         return hip_fail(e, "autotune alloc");
@@ -34,7 +37,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     e = hipMemcpy(psi.ptr, h_psi.data(), sizeof(double) * h_psi.size(), hipMemcpyHostToDevice);
     std::vector<const double *> p0(ni, (const double *)psi.ptr);
     std::vector<double *> c0(ni);
-    for (int32_t i = 0; i < ni; ++i) c0[i] = (double *)corr.ptr + 2 * (size_t)i * n_steps * n_states;
+    for (int32_t i = 0; i < ni; ++i) c0[i] = (double *)corr.ptr + 2 * (size_t)i * n_steps2 * n_states;
     std::vector<double> dt(ni);
     for (int32_t i = 0; i < ni; ++i) dt[i] = M_PI / rescale[i];
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -77,40 +80,48 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
         for (int tier = 1; tier <= kFusedTiers; ++tier)
             for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2)
                 if (!(fp32 && vec == 1 && s_pad > 1)) cands.push_back(tbpm_launch_config{2, 1, 1, 1, 0, vec, tier});
-    for (const tbpm_launch_config &cand : cands) {
-        {
-            {
-                eng.cfgs[fp32 ? 1 : 0] = cand;
-                Engine::RunArgs a{};
-                a.psi0 = p0.data();
-                a.s_user = n_states;
-                a.n_steps = n_steps;
-                a.dt = dt.data();
-                a.rescale = rescale.data();
-                a.tol = 1e-12;
-                a.fp32 = fp32;
-                a.corr = c0.data();
-                a.norm2 = nullptr;
-                a.flags = TBPM_FLAG_ASYNC;
-                a.stream = stream;
-                st = eng.run(a);  // warm-up (builds tiles and the graph)
-                if (st != TBPM_OK) break;
-                e = hipEventRecord(t0, stream);
-                if (e == hipSuccess) st = eng.run(a);
-                if (e == hipSuccess && st == TBPM_OK) e = hipEventRecord(t1, stream);
-                if (e == hipSuccess && st == TBPM_OK) e = hipEventSynchronize(t1);
-                float ms = 0;
-                if (e == hipSuccess && st == TBPM_OK) e = hipEventElapsedTime(&ms, t0, t1);
-                if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-                if (st != TBPM_OK) break;
-                const double per_step = ms / (n_steps - 1);
-                if (per_step < win_ms) {
-                    win_ms = per_step;
-                    win = eng.cfgs[fp32 ? 1 : 0];
-                }
+    // time one shape on `steps` time steps (after a warm-up run that builds
+    // its tiles and graphs); ms per step, or a negative value on failure
+    auto time_cfg = [&](const tbpm_launch_config &cand, int32_t steps) -> double {
+        eng.cfgs[fp32 ? 1 : 0] = cand;
+        Engine::RunArgs a{};
+        a.psi0 = p0.data();
+        a.s_user = n_states;
+        a.n_steps = steps;
+        a.dt = dt.data();
+        a.rescale = rescale.data();
+        a.tol = 1e-12;
+        a.fp32 = fp32;
+        a.corr = c0.data();
+        a.norm2 = nullptr;
+        a.flags = TBPM_FLAG_ASYNC;
+        a.stream = stream;
+        st = eng.run(a);
+        if (st != TBPM_OK) return -1.0;
+        e = hipEventRecord(t0, stream);
+        if (e == hipSuccess) st = eng.run(a);
+        if (e == hipSuccess && st == TBPM_OK) e = hipEventRecord(t1, stream);
+        if (e == hipSuccess && st == TBPM_OK) e = hipEventSynchronize(t1);
+        float ms = 0;
+        if (e == hipSuccess && st == TBPM_OK) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e != hipSuccess && st == TBPM_OK) st = hip_fail(e, "autotune timing");
+        if (st != TBPM_OK) return -1.0;
+        return ms / (steps - 1);
+    };
+    std::vector<std::pair<double, size_t>> timed;
+    for (size_t c = 0; c < cands.size() && st == TBPM_OK; ++c) {
+        const double per_step = time_cfg(cands[c], n_steps);
+        if (per_step >= 0.0) timed.push_back({per_step, c});
+    }
+    if (st == TBPM_OK) {
+        std::sort(timed.begin(), timed.end());
+        for (size_t k = 0; k < timed.size() && k < 3 && st == TBPM_OK; ++k) {
+            const double per_step = time_cfg(cands[timed[k].second], n_steps2);
+            if (per_step >= 0.0 && per_step < win_ms) {
+                win_ms = per_step;
+                win = cands[timed[k].second];
             }
         }
-        if (st != TBPM_OK) break;
     }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);

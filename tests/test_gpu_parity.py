@@ -199,6 +199,40 @@ def test_batched_vs_single_and_oracle(precision):
             assert _rel(c, ref) < 1e-4
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_stores_a_valid_shape(precision):
+    """The autotuner (every candidate on three steps, the three fastest on
+    eight) returns a valid shape with a positive step time, stores it in the
+    handle for that precision only, and a propagation in that shape matches
+    the oracle; the same for a batch, on a sparse lattice (fused shapes among
+    the candidates) and a wide-row one (staged tiers)."""
+    print(f"case autotune {precision}", flush=True)
+    rng = np.random.default_rng(71)
+    other = "fp32" if precision == "fp64" else "fp64"
+    for lat in (inputs.graphene(24, 20, onsite=inputs.anderson(rng, 960, 1.0)),
+                inputs.twisted_bilayer(12, 12, angle_deg=2.5)):
+        S, nt = 4, 24
+        psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+        f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+        dt = math.pi / f
+        H = tbpm.Hamiltonian.from_lattice(lat)
+        before_other = H.launch_config(other)
+        cfg, ms = H.autotune(S, precision)
+        assert ms > 0.0 and math.isfinite(ms)
+        assert cfg == H.launch_config(precision)
+        assert H.launch_config(other) == before_other
+        assert cfg["vec"] in (1, 2, 4) and 0 <= cfg["staged"] <= 6 and 0 <= cfg["fused"] <= 6
+        got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision).cpu().numpy()
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+        assert _rel(got, ref) < (1e-10 if precision == "fp64" else 1e-5), cfg
+        B = tbpm.Batch([H, tbpm.Hamiltonian.from_lattice(lat)])
+        bcfg, bms = B.autotune(S, precision)
+        assert bms > 0.0 and math.isfinite(bms)
+        corrs = B.propagate([_dev(psi0), _dev(psi0)], nt, [dt, dt], [f, f], precision=precision)
+        for c in corrs:
+            assert _rel(c.cpu().numpy(), ref) < (1e-10 if precision == "fp64" else 1e-5), bcfg
+
+
 def test_dos_kernel_and_adjoint_vs_oracle():
     print("case dos kernel", flush=True)
     rng = np.random.default_rng(12)
