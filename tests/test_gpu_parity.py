@@ -583,6 +583,34 @@ def test_staged_state_blocks(precision, S):
         assert np.max(np.abs(gn.cpu().numpy() - ref_n2)) < 1e-10
 
 
+def test_staged_state_blocks_in_a_batch():
+    """A batch of a twisted bilayer, a complex-hopping graphene flake and a
+    one-orbital member with 16 FP64 states (two blocks of 8 per tile) in the
+    staged shape at tiers 1-3 against single plain-shape runs and the oracle."""
+    print("case staged state blocks batch", flush=True)
+    rng = np.random.default_rng(61)
+    lats = [inputs.twisted_bilayer(14, 14, angle_deg=3.5), _complex_graphene(9, 8, 13),
+            inputs.from_bonds(1, np.zeros(0, int), np.zeros(0, int), np.zeros(0), np.array([0.3]))]
+    S, nt = 16, 32
+    psis = [inputs.random_phase_states(rng, l.n_orb, S) for l in lats]
+    fs = [max(oracle.gershgorin(l.row_ptr, l.val, l.onsite), 0.5) * 1.05 for l in lats]
+    dts = [math.pi / f for f in fs]
+    hams = [tbpm.Hamiltonian.from_lattice(l) for l in lats]
+    singles = []
+    for h, p, f, dt in zip(hams, psis, fs, dts):
+        h.set_launch_config(2, 1, 1, 1, staged=0, precision="fp64")
+        singles.append(tbpm.propagate(h, _dev(p), nt, dt, f).cpu().numpy())
+    B = tbpm.Batch(hams)
+    for tier, vec in ((1, 4), (2, 2), (3, 4)):
+        B.set_launch_config(2, tier % 2, 0, 1, staged=tier, vec=vec, precision="fp64")
+        corrs = B.propagate([_dev(p) for p in psis], nt, dts, fs)
+        for c, single in zip(corrs, singles):
+            assert _rel(c.cpu().numpy(), single) < 1e-12, (tier, vec)
+    for l, p, f, dt, c in zip(lats, psis, fs, dts, corrs):
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, nt, dt, f)
+        assert _rel(c.cpu().numpy(), ref) < 1e-10
+
+
 def _dt_for_terms(f, parity):
     """A time step whose Bessel series has M terms of the given parity (M >= 5),
     so that the MID orders pair up exactly (M even) or leave one over (M odd)."""
