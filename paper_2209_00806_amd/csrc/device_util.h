@@ -141,12 +141,13 @@ __device__ __forceinline__ void unit_mad_cplx(C h, VecT<R, VS> x, VecT<R, VS> &a
 }
 
 // Per-state partial sums for units of VS states: lane l holds states
-// (l & (U-1))*VS + i, U = units per row.
+// (l & (U-1))*VS + i, U = units per row.  red: kWG/64 x 64 x 3 doubles of LDS
+// that no thread of the workgroup uses any more.
 template <int VS>
 __device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
                                                     const double (&nrm)[VS], int log2u,
-                                                    double *__restrict__ out, int tile, int n_tiles) {
-    __shared__ double red[kWG / 64][64][3];
+                                                    double *__restrict__ out, int tile, int n_tiles,
+                                                    double (*red)[64][3]) {
     const int U = 1 << log2u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -178,6 +179,13 @@ __device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], con
         out[o + n_tiles] = b;
         out[o + 2 * (int64_t)n_tiles] = c;
     }
+}
+template <int VS>
+__device__ __forceinline__ void block_unit_partials(const double (&dre)[VS], const double (&dim)[VS],
+                                                    const double (&nrm)[VS], int log2u,
+                                                    double *__restrict__ out, int tile, int n_tiles) {
+    __shared__ double red[kWG / 64][64][3];
+    block_unit_partials<VS>(dre, dim, nrm, log2u, out, tile, n_tiles, red);
 }
 
 }  // namespace

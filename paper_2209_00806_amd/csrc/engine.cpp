@@ -742,26 +742,60 @@ tbpm_status Engine::run(const RunArgs &a) {
     st = enqueue_qe(a.stream);
     if (st != TBPM_OK) return st;
 
-    // Fused schedule: FIRST and NOB2 as one pair (psi -> A, B), then MID
-    // orders in pairs alternating between (A, B) and (C, D), since a pair
-    // reads its inputs on rows other tiles write; a leftover MID runs alone
-    // (in place), and LAST alone.  Entries: {plan index, kind, x, b2, out1, out2}
-    // with kind < 0 for an unpaired pass.
+    // Fused schedule (plan: 0 FIRST, 1 NOB2, 2 .. n_passes-2 MID,
+    // n_passes-1 LAST).  Orders run two per launch wherever they can: FIRST
+    // and NOB2 as one pair, then MID orders in pairs; a pair reads its inputs
+    // on rows other tiles write, so its outputs go to the two work buffers
+    // (of A, B, C, D) it does not read.  The last MID and LAST run as one
+    // pair when nothing but the correlation is taken from psi_{k+1} (no
+    // stored states, quasi-eigenstates or current correlation): psi_{k+1}
+    // then goes to a free buffer, which becomes the next step's psi
+    // (bufptr[0] and that buffer trade places after every step, so a graph
+    // of an even number of steps ends where it began).  With an even number
+    // of MID orders FIRST then runs alone and NOB2 pairs with the first MID,
+    // so that no MID is left over; otherwise a leftover MID runs alone, in
+    // place over b_{j+2}, and LAST alone, in place over psi.
+    // Entries: {plan index, pair kind or -1 for one order, x, b2, out1, out2}
+    // with buffer indices into bufptr (-1: none).
     struct Launch {
         int p, kind, x, b2, o1, o2;
     };
     std::vector<Launch> sched;
+    const bool last_pair = fused && n_passes >= 4 && !a.ckpt && a.n_qe == 0 && a.jc_states == 0;
     if (fused) {
-        // plan: 0 FIRST, 1 NOB2, 2 .. n_passes-2 MID, n_passes-1 LAST
-        sched.push_back({0, kPairFirst, 0, -1, 1, 2});
-        int cur = 2;  // buffer of b_{j+1} (2 or 4); b_{j+2} is in buffer cur - 1
-        int p = 2;
-        for (; p + 1 <= n_passes - 2; p += 2) {
-            const int o1 = (cur <= 2) ? 3 : 1;
-            sched.push_back({p, kPairMid, cur, cur - 1, o1, o1 + 1});
-            cur = o1 + 1;
+        const int n_mid = n_passes - 3;
+        int cur = 0, prev = -1;  // buffers of b_{j+1} and b_{j+2} (0: psi, -1: none)
+        auto free_buf = [&](int k) {  // the k-th lowest work buffer other than cur and prev
+            for (int b = 1; b <= 4; ++b)
+                if (b != cur && b != prev && k-- == 0) return b;
+            return -1;
+        };
+        auto pair = [&](int p, int kind) {
+            const int o1 = free_buf(0), o2 = free_buf(1);
+            sched.push_back({p, kind, cur, prev, o1, o2});
+            prev = o1;
+            cur = o2;
+        };
+        int p = 0;
+        if (last_pair && n_mid % 2 == 0) {
+            sched.push_back({0, -1, 0, -1, 1, -1});
+            cur = 1;
+            pair(1, kPairSecond);
+            p = 3;
+        } else {
+            pair(0, kPairFirst);
+            p = 2;
         }
-        for (; p < n_passes; ++p) sched.push_back({p, -1, -1, -1, -1, -1});
+        const int mid_end = last_pair ? n_passes - 2 : n_passes - 1;  // MIDs before the last launch
+        for (; p + 1 < mid_end; p += 2) pair(p, kPairMid);
+        for (; p < mid_end; ++p) {
+            sched.push_back({p, -1, cur, prev, prev, -1});
+            std::swap(cur, prev);
+        }
+        if (last_pair)
+            sched.push_back({n_passes - 2, kPairLast, cur, prev, -1, free_buf(0)});
+        else
+            sched.push_back({n_passes - 1, -1, cur, prev, 0, -1});
     }
 
     // one time step; consecutive launches walk the tiles in opposite
@@ -769,7 +803,6 @@ tbpm_status Engine::run(const RunArgs &a) {
     int32_t walk = 0;
     auto enqueue_step = [&](hipStream_t s) -> tbpm_status {
         if (fused) {
-            int cur = 2, prev = 1;
             for (size_t q = 0; q < sched.size(); ++q) {
                 const Launch &l = sched[q];
                 if (l.kind >= 0) {
@@ -786,7 +819,7 @@ tbpm_status Engine::run(const RunArgs &a) {
                     fp.x = bufptr[l.x];
                     fp.v = bufptr[0];
                     fp.b2 = l.b2 >= 0 ? bufptr[l.b2] : nullptr;
-                    fp.out1 = bufptr[l.o1];
+                    fp.out1 = l.o1 >= 0 ? bufptr[l.o1] : nullptr;
                     fp.out2 = bufptr[l.o2];
                     fp.coef1 = (const PassCoef *)coef.ptr + (size_t)l.p * ni;
                     fp.coef2 = (const PassCoef *)coef.ptr + (size_t)(l.p + 1) * ni;
@@ -802,10 +835,12 @@ tbpm_status Engine::run(const RunArgs &a) {
                     fp.uniform_w = mat.uniform_w;
                     fp.reverse = walk;
                     walk ^= 1;
+                    fp.phi0 = (const double *)phi0.ptr;
+                    fp.phi0_ld = s_pad;
+                    fp.partials = (double *)partials.ptr;
                     hipError_t e = launch_pair(l.kind, fp32, mat.is_complex, cfg.nontemporal != 0, vs, fp, s);
                     if (e != hipSuccess) return hip_fail(e, "launch pair");
-                    prev = l.o1;
-                    cur = l.o2;
+                    if (l.kind == kPairLast) std::swap(bufptr[0], bufptr[l.o2]);
                     continue;
                 }
                 const PassPlan &pl = plan[l.p];
@@ -814,15 +849,15 @@ tbpm_status Engine::run(const RunArgs &a) {
                 pp.n_tiles = n_tiles;
                 pp.xcd_remap = cfg.xcd_remap;
                 pp.log2s = log2s;
-                pp.bump_counter = 0;
+                pp.bump_counter = (q == 0);
                 pp.col = mat.col;
                 pp.val = fp32 ? mat.val32 : mat.val64;
                 pp.slice_off = mat.slice_off;
                 pp.onsite = fp32 ? (const void *)mat.onsite32 : (const void *)mat.onsite64;
-                pp.x = bufptr[cur];
+                pp.x = bufptr[l.x];
                 pp.v = bufptr[0];
-                pp.b2 = bufptr[prev];
-                pp.out = pl.kind == kPassLast ? bufptr[0] : bufptr[prev];
+                pp.b2 = l.b2 >= 0 ? bufptr[l.b2] : nullptr;
+                pp.out = bufptr[l.o1];
                 pp.coef = (const PassCoef *)coef.ptr + (size_t)l.p * ni;
                 pp.counter = (int32_t *)counter.ptr;
                 pp.phi0 = (const double *)phi0.ptr;
@@ -839,7 +874,6 @@ tbpm_status Engine::run(const RunArgs &a) {
                 hipError_t e =
                     launch_pass(pl.kind, fp32, mat.is_complex, cfg.nontemporal != 0, cfg.unroll, vs, pp, s);
                 if (e != hipSuccess) return hip_fail(e, "launch pass");
-                if (pl.kind == kPassMid) std::swap(cur, prev);
             }
             hipError_t e = launch_reduce(ni, s_pad, rp, s);
             if (e != hipSuccess) return hip_fail(e, "launch reduce");
@@ -962,11 +996,19 @@ tbpm_status Engine::run(const RunArgs &a) {
                 gkey = key;
                 return TBPM_OK;
             };
+            // With the last pair a step moves psi to another buffer, so a graph
+            // replayed more than once must hold an even number of steps: the
+            // remainder is then one graph of n_rest steps, launched once (the
+            // full graphs, when replayed, hold kStepsPerGraph steps, an even
+            // number, and leave the buffers as they found them).
+            static_assert(kStepsPerGraph % 2 == 0, "a replayed step graph must hold an even number of steps");
+            const int32_t rest_steps = last_pair ? std::max<int32_t>(n_rest, 1) : 1;
             st = cached(graph_exec, graph_key, spg);
-            if (st == TBPM_OK && n_rest > 0) st = cached(graph_exec1, graph_key1, 1);
+            if (st == TBPM_OK && n_rest > 0) st = cached(graph_exec1, graph_key1, rest_steps);
             if (st != TBPM_OK) return st;
             for (int32_t k = 0; k < n_full; ++k) TRY_HIP(hipGraphLaunch(graph_exec, a.stream), "hipGraphLaunch");
-            for (int32_t k = 0; k < n_rest; ++k) TRY_HIP(hipGraphLaunch(graph_exec1, a.stream), "hipGraphLaunch");
+            for (int32_t k = 0; k < n_rest / rest_steps; ++k)
+                TRY_HIP(hipGraphLaunch(graph_exec1, a.stream), "hipGraphLaunch");
         }
     }
 

@@ -13,7 +13,16 @@
 // vectors, instead of reading six and writing two.  Outputs go to buffers
 // that no tile of the launch reads.  The first pair of a step (x = psi, no
 // b_{j+2}, b_{M-1} folded into alpha2) is the same kernel with KIND
-// kPairFirst.  Per element the arithmetic is that of k_pass.
+// kPairFirst.  The last pair (KIND kPairLast) takes b_1 and the new state
+//     psi' = c_0 psi + H~ b_1 - b_2
+// (Eq. (eq:psi_t) by Clenshaw's recurrence): b_1 stays in LDS, and psi' is
+// written to a buffer other than psi (other tiles still read psi on their
+// 1-hop rows) with <phi0|psi'> and ||psi'||^2 accumulated as in the last
+// single pass (Eq. (eq:corr_dos)).  When the first order of a step runs
+// alone, the second pair (KIND kPairSecond) is a middle pair whose first
+// order has no b_{j+2} term.  Per element the arithmetic is that of
+// k_pass, so every result, the tile partials of the correlation included,
+// is the one the single passes give on the same tiles.
 //
 // Latency: a workgroup's phases are chains of dependent loads.  When every
 // slice has the same width (uniform_w > 0, e.g. graphene) a row's slots are
@@ -21,6 +30,8 @@
 // of order j is an own row keeps that row's first batch of matrix entries in
 // registers for order j-1, which takes the same unit.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_util.h"
 #include "tbpm_internal.h"
@@ -35,6 +46,8 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
     using HV = typename HValT<R, CH>::T;
     constexpr int KG = 4;
     constexpr bool FIRST = (KIND == kPairFirst);
+    constexpr bool LAST = (KIND == kPairLast);
+    constexpr bool B2_1 = !FIRST && KIND != kPairSecond;  // order j subtracts b_{j+2}
     constexpr int LOG2VS = VS == 4 ? 2 : (VS == 2 ? 1 : 0);
 
     const int tile = tile_of_block(blockIdx.x, p.n_tiles, p.xcd_remap, p.reverse);
@@ -117,7 +130,7 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
             V vv, bq;
             if constexpr (!FIRST) {
                 vv = v[gu];
-                bq = (lr < n_own) ? ldv<NT>(b2 + gu) : b2[gu];
+                if constexpr (B2_1) bq = (lr < n_own) ? ldv<NT>(b2 + gu) : b2[gu];
                 if (it == 0) vk0 = vv;
                 if (it == 1) vk1 = vv;
             }
@@ -161,14 +174,18 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
                 o[2 * i] = ar * vr - ai * vi + (br * hr - bi * hi);
                 o[2 * i + 1] = ar * vi + ai * vr + (br * hi + bi * hr);
             }
-            if constexpr (!FIRST) o -= bq;
+            if constexpr (B2_1) o -= bq;
             ys[u] = o;
-            if (own) stv<NT>(out1 + gu, o);
+            if constexpr (!LAST)
+                if (own) stv<NT>(out1 + gu, o);
         }
     }
     __syncthreads();
 
     // order j-1 on own rows
+    double dre[VS], dim[VS], nrm[VS];
+#pragma unroll
+    for (int i = 0; i < VS; ++i) dre[i] = dim[i] = nrm[i] = 0.0;
     {
         const R ar = (R)c2.ar, ai = (R)c2.ai, br = (R)c2.br, bi = (R)c2.bi;
         const uint32_t n_u = n_own << log2u;
@@ -185,6 +202,12 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
                 vv = xs[u];
             else
                 vv = it == 0 ? vk0 : (it == 1 ? vk1 : v[gu]);
+            d2 ph[LAST ? VS : 1];  // phi0 of this unit, loaded before the gathers
+            if constexpr (LAST) {
+#pragma unroll
+                for (int i = 0; i < VS; ++i)
+                    ph[i] = ((const d2 *)p.phi0)[(int64_t)row * p.phi0_ld + (usub << LOG2VS) + i];
+            }
             V acc = ons[row] * ys[u];
             for (int k = 0; k < w; k += KG) {
                 uint32_t li[KG];
@@ -224,7 +247,21 @@ __global__ __launch_bounds__(kWG) void k_pair(const FusedParams p) {
             }
             if constexpr (!FIRST) o -= xs[u];  // b_{j+1} on own rows
             stv<NT>(out2 + gu, o);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int i = 0; i < VS; ++i) {
+                    const double oxr = (double)o[2 * i], oyi = (double)o[2 * i + 1];
+                    dre[i] = fma(ph[i].x, oxr, fma(ph[i].y, oyi, dre[i]));
+                    dim[i] = fma(ph[i].x, oyi, fma(-ph[i].y, oxr, dim[i]));
+                    nrm[i] = fma(oxr, oxr, fma(oyi, oyi, nrm[i]));
+                }
+            }
         }
+    }
+    if constexpr (LAST) {
+        __syncthreads();  // the staged rows are dead: their LDS takes the partial sums
+        block_unit_partials<VS>(dre, dim, nrm, log2u, p.partials, tile, p.n_tiles,
+                                reinterpret_cast<double (*)[64][3]>(pair_mem));
     }
 }
 
@@ -236,6 +273,11 @@ hipError_t launch_pair_t(int kind, const FusedParams &p, hipStream_t st) {
         hipLaunchKernelGGL((k_pair<R, CH, kPairFirst, NT, VS>), grid, block, lds, st, p);
     else if (kind == kPairMid)
         hipLaunchKernelGGL((k_pair<R, CH, kPairMid, NT, VS>), grid, block, lds, st, p);
+    else if (kind == kPairSecond)
+        hipLaunchKernelGGL((k_pair<R, CH, kPairSecond, NT, VS>), grid, block, lds, st, p);
+    else if (kind == kPairLast)  // the partial sums reuse the LDS: at least kWG/64 x 64 x 3 doubles
+        hipLaunchKernelGGL((k_pair<R, CH, kPairLast, NT, VS>), grid, block,
+                           std::max(lds, sizeof(double) * kWG * 3), st, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -89,7 +89,11 @@ struct PassParams {
 // Two Clenshaw orders per launch (fused.hip).
 enum PairKind : int {
     kPairFirst = 0,  // b_{M-2}, b_{M-3} from psi (x = psi, no b_{j+2})
-    kPairMid = 1     // b_j, b_{j-1} from b_{j+1} (x) and b_{j+2}
+    kPairMid = 1,    // b_j, b_{j-1} from b_{j+1} (x) and b_{j+2}
+    kPairLast = 2,   // b_1 (kept in LDS only) and psi_{k+1} from b_2 (x) and b_3,
+                     // with the fused correlation of psi_{k+1}
+    kPairSecond = 3  // b_{M-3} (b_{M-1} folded into alpha1, no b_{j+2}) and
+                     // b_{M-4} from b_{M-2} (x), after the first order ran alone
 };
 
 struct FusedParams {
@@ -105,8 +109,8 @@ struct FusedParams {
     const void *x;     // b_{j+1} (or psi for kPairFirst), staged
     const void *v;     // psi
     const void *b2;    // b_{j+2} (kPairMid)
-    void *out1;        // b_j on own rows
-    void *out2;        // b_{j-1} on own rows
+    void *out1;        // b_j on own rows (not written by kPairLast)
+    void *out2;        // b_{j-1} on own rows; never a buffer the launch reads
     const PassCoef *coef1, *coef2;  // [n_inst] for orders j and j-1
     int32_t *counter;
     // 2-hop tiles: staged rows are own, then 1-hop (n1 of them), then 2-hop
@@ -120,6 +124,10 @@ struct FusedParams {
     int32_t lds_units;     // LDS capacity in units: max over tiles of n_x + n_y
     int32_t uniform_w;     // stored elements per row when every slice has that width, else 0
     int32_t reverse;       // walk the tiles last to first (see tile_of_block)
+    // fused correlation (kPairLast): as in PassParams
+    const double *phi0;
+    int64_t phi0_ld;
+    double *partials;
 };
 
 struct InitParams {

@@ -772,3 +772,66 @@ def test_create_from_device_pointers():
     assert st == 1 and not h.value
     H_host.close()
     H_dev.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_last_pair(precision):
+    """The fused shape's last launch of a step: with nothing but the
+    correlation taken from psi(k dt), the last middle order and the final
+    order run as one pair that writes psi((k+1) dt) to another buffer, which
+    becomes the next step's psi; with stored states they run one order per
+    launch, in place.  Both schedules evaluate every element with the same
+    arithmetic on the same tiles, so the correlations agree to rounding.
+    Runs of 1-35 samples (graphs of 16 steps replayed, remainders of either
+    parity, no graph), both parities of the middle-order count (with an even
+    count the first order runs alone and the second pair takes the order
+    without b_{j+2} with the first middle one), the shortest series that
+    pair the last orders, several tiers, a second call on cached graphs and
+    a batch, against the run with checkpoints (FP64), the plain shape and
+    the oracle."""
+    print(f"case fused last pair {precision}", flush=True)
+    rng = np.random.default_rng(97)
+    lat = inputs.graphene(37, 34, onsite=inputs.anderson(rng, 2 * 37 * 34, 1.0))
+    S = 4
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, S)
+    f = oracle.gershgorin(lat.row_ptr, lat.val, lat.onsite) * 1.01
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    tol_same = 1e-14 if precision == "fp64" else 1e-6
+    for parity in (0, 1):
+        dt, M = _dt_for_terms(f, parity)
+        for tier in (1, 2, 4):
+            H.set_launch_config(2, 1, 1, 1, vec=2, precision=precision, fused=tier)
+            for nt in (1, 2, 3, 17, 18, 35, 35):
+                got = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision).cpu().numpy()
+                if precision == "fp64":  # checkpoints (FP64 only) keep the single last order
+                    one, _ = tbpm.propagate(H, _dev(psi0), nt, dt, f, ckpt_every=4)
+                    assert _rel(got, one.cpu().numpy()) < tol_same, (M, tier, nt)
+                nog = tbpm.propagate(H, _dev(psi0), nt, dt, f, precision=precision, graph=False).cpu().numpy()
+                assert _rel(nog, got) < tol_same, (M, tier, nt)
+        H.set_launch_config(2, 1, 1, 1, vec=2, precision=precision, fused=0)
+        plain = tbpm.propagate(H, _dev(psi0), 35, dt, f, precision=precision).cpu().numpy()
+        assert _rel(got, plain) < (1e-13 if precision == "fp64" else 1e-5), M
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 35, dt, f)
+        assert _rel(got, ref) < (1e-10 if precision == "fp64" else 1e-5), M
+    # the shortest series with a last pair: M = 5 (one MID, paired with LAST),
+    # 6 (FIRST alone, NOB2 with the first MID) and 7
+    H.set_launch_config(2, 1, 1, 1, vec=2, precision=precision, fused=2)
+    for M in (5, 6, 7):
+        z = next(z for z in np.geomspace(1e-3, 3.0, 600) if tbpm.num_terms(z) == M)
+        ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, 20, z / f, f)
+        got = tbpm.propagate(H, _dev(psi0), 20, z / f, f, precision=precision).cpu().numpy()
+        assert _rel(got, ref) < (1e-10 if precision == "fp64" else 1e-5), M
+        if precision == "fp64":
+            one, _ = tbpm.propagate(H, _dev(psi0), 20, z / f, f, ckpt_every=4)
+            assert _rel(got, one.cpu().numpy()) < tol_same, M
+    # a batch of uneven members in the fused shape
+    lats = [lat, inputs.square(19, 17), inputs.twisted_bilayer(10, 10, angle_deg=5.0)]
+    psis = [psi0] + [inputs.random_phase_states(rng, l.n_orb, S) for l in lats[1:]]
+    fs = [oracle.gershgorin(l.row_ptr, l.val, l.onsite) * 1.02 for l in lats]
+    dts = [math.pi / g for g in fs]
+    B = tbpm.Batch([tbpm.Hamiltonian.from_lattice(l) for l in lats])
+    B.set_launch_config(2, 1, 1, 1, vec=2, precision=precision, fused=2)
+    corrs = B.propagate([_dev(p) for p in psis], 21, dts, fs, precision=precision)
+    for l, p, g, dt, c in zip(lats, psis, fs, dts, corrs):
+        ref, _, _ = oracle.propagate(l.row_ptr, l.col, l.val, l.onsite, p, 21, dt, g)
+        assert _rel(c.cpu().numpy(), ref) < (1e-10 if precision == "fp64" else 1e-5)
