@@ -89,17 +89,28 @@ def hay_iter_bytes(n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
 
 
 def schedule_bytes(M: int, fused: bool, n_orb: int, nnz: int, S: int, b: int, v: int) -> int:
-    """Bytes one time step must move at least with the launch schedule in use:
-    M-1 passes, or (fused) FIRST+NOB2 as one launch (read psi, write two
-    vectors), the middle orders in pairs, a leftover middle order and LAST
-    alone; plus the phi0 stream."""
+    """Bytes one time step of a plain propagation (no stored states) must move
+    at least with the launch schedule in use, plus the phi0 stream: M-1
+    passes; or (fused) the last middle order and LAST as one launch (read
+    b_2, b_3 and psi, write psi') after the other middle orders in pairs
+    (read three vectors, write two), led by FIRST+NOB2 as one launch (read
+    psi, write two) when the number of middle orders is odd, else by FIRST
+    alone (read psi, write one) and NOB2 with the first middle order (read
+    two, write two); with M = 4 (no middle order) FIRST+NOB2, then LAST
+    alone."""
     mat = nnz * (4 + v) + n_orb * v
     vec = b * n_orb * S
     phi0 = 16 * n_orb * S
     if not fused or M < 4:
         return (M - 1) * (4 * vec + mat) + phi0
     n_mid = M - 4
-    return (3 * vec + mat) + (n_mid // 2) * (5 * vec + mat) + (n_mid % 2) * (4 * vec + mat) + (4 * vec + mat) + phi0
+    if n_mid == 0:
+        return (3 * vec + mat) + (4 * vec + mat) + phi0
+    if n_mid % 2:
+        lead, rest = (3 * vec + mat), n_mid - 1
+    else:
+        lead, rest = (2 * vec + mat) + (4 * vec + mat), n_mid - 2
+    return lead + (rest // 2) * (5 * vec + mat) + (4 * vec + mat) + phi0
 
 
 ORACLE_PREFIX = 24  # correlation samples of a member / state the cpu_baseline leg checks against the oracle

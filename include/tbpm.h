@@ -531,9 +531,14 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *               smaller halos, or more resident workgroups).  Two
  *               extra state-sized work vectors are allocated; staged and
  *               wg_chunks are unused and unroll applies to the orders left
- *               unpaired (the last one, and a middle one when their count is
- *               odd).  Falls back to the plain shape when the series has
- *               fewer than 4 terms or no tile fits.  0: one order per launch.
+ *               unpaired.  When only the correlation is taken from each
+ *               psi(k dt) (no checkpoints, snapshots, quasi-eigenstates or
+ *               current correlation) the last middle order and the final
+ *               order share a launch, and with an even number of middle
+ *               orders the first order runs alone; otherwise the final order
+ *               runs alone, and a middle one when their count is odd.  Falls
+ *               back to the plain shape when the series has fewer than 4
+ *               terms or no tile fits.  0: one order per launch.
  */
 typedef struct {
     int32_t wg_chunks;

@@ -19,13 +19,22 @@ def test_pair_and_step_bytes():
     assert bench.pair_bytes(N, NNZ, S, 16, 8) == 5 * VEC64 + MAT64 == 1_434_451_968
     # 17 passes plus the FP64 phi0 stream of the correlation
     assert bench.step_bytes(18, N, NNZ, S, 16, 8) == 17 * 1_166_016_512 + VEC64
-    # fused schedule: FIRST+NOB2 (psi in, two vectors out), 7 middle pairs, LAST alone, phi0
-    fused = (3 * VEC64 + MAT64) + 7 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
-    assert bench.schedule_bytes(18, True, N, NNZ, S, 16, 8) == fused == 12_373_196_800
+    # fused schedule at M = 18 (14 middle orders, an even number): FIRST alone
+    # (psi in, one vector out), NOB2 with the first middle order (two in, two
+    # out), 6 middle pairs, the last middle order with LAST (b_2, b_3, psi in,
+    # psi' out), phi0
+    fused = (2 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + 6 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(18, True, N, NNZ, S, 16, 8) == fused == 11_836_325_888
     assert bench.schedule_bytes(18, False, N, NNZ, S, 16, 8) == bench.step_bytes(18, N, NNZ, S, 16, 8)
-    # an odd number of middle orders leaves one single middle pass
-    odd = (3 * VEC64 + MAT64) + 6 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
-    assert bench.schedule_bytes(17, True, N, NNZ, S, 16, 8) == odd
+    # an odd number of middle orders: FIRST+NOB2 as one launch, 6 middle pairs, the last pair
+    odd = (3 * VEC64 + MAT64) + 6 * (5 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(17, True, N, NNZ, S, 16, 8) == odd == 10_938_744_832
+    # the shortest series: M = 4 (FIRST+NOB2, LAST alone), 5 (FIRST+NOB2, the
+    # last pair), 6 (FIRST alone, NOB2 with the middle order, the last pair)
+    assert bench.schedule_bytes(4, True, N, NNZ, S, 16, 8) == (3 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(5, True, N, NNZ, S, 16, 8) == (3 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64
+    assert bench.schedule_bytes(6, True, N, NNZ, S, 16, 8) == (
+        (2 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + (4 * VEC64 + MAT64) + VEC64)
 
 
 def test_haydock_and_wide_row_bytes():
