@@ -266,10 +266,28 @@ __global__ __launch_bounds__(kWG) void k_pass_staged(const PassParams p) {
         }
     }
 
-    for (uint32_t i = threadIdx.x; i < n_stage; i += kWG) {
-        const uint32_t lr = i >> log2ub;
-        const uint32_t grow = lr < n_own ? row0 + lr : (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
-        xs[i] = x[(grow << log2u) + boff + (i & umask)];
+    // stage the rows: four units per thread in flight, their row indices
+    // (the external rows' through the tile's list) loaded first, then the
+    // rows, then the LDS writes
+    for (uint32_t i0 = threadIdx.x; i0 < n_stage; i0 += 4 * kWG) {
+        uint32_t g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * kWG;
+            const uint32_t lr = i >> log2ub;
+            uint32_t grow = row0 + lr;
+            if (i < n_stage && lr >= n_own) grow = (uint32_t)p.ucol[x0 + (int32_t)(lr - n_own)];
+            g[q] = (grow << log2u) + boff + (i & umask);
+        }
+        V t[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i0 + (uint32_t)q * kWG < n_stage) t[q] = x[g[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * kWG;
+            if (i < n_stage) xs[i] = t[q];
+        }
     }
     __syncthreads();
 
