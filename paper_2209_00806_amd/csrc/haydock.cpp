@@ -24,7 +24,10 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
         ++log2s;
     }
     const int64_t n = mat.n_rows;
-    tbpm_status s0 = build_tiles(s_pad, cfg.wg_chunks, 1);
+    // tiles and tile order of the FP64 launch configuration (the kernels take
+    // one state per thread whatever its states per thread)
+    const tbpm_launch_config &lc = cfgs[0];
+    tbpm_status s0 = build_tiles(s_pad, lc.wg_chunks, 1);
     if (s0 != TBPM_OK) return s0;
     const int32_t n_tiles = (int32_t)h_tiles.size();
     const size_t vec = sizeof(double) * 2 * (size_t)n * s_pad;
@@ -46,17 +49,17 @@ tbpm_status Engine::haydock(const double *psi0, int32_t s_user, int32_t n_iter, 
     // u_0 = psi0 (internal order, padded states zero), u_{-1} = 0, 1/b_0 = 1/||psi0||
     TRY_HIP(launch_expand_states(psi0, mat.perm, s_user, u[0], log2s, n, st), "load start vectors");
     TRY_HIP(launch_fill_zero(u[1], 2 * n * s_pad, st), "clear Lanczos vector");
-    TRY_HIP(launch_hay_axpy(td, n_tiles, cfg.xcd_remap, 0, log2s, u[0], nullptr, nullptr, hs, part, st), "start norm");
+    TRY_HIP(launch_hay_axpy(td, n_tiles, lc.xcd_remap, 0, log2s, u[0], nullptr, nullptr, hs, part, st), "start norm");
     TRY_HIP(launch_hay_reduce(part, n_tiles, s_pad, s_user, 2, thr, hs, cnt, n_iter, a_out, b_out, fold, st),
             "start norm reduce");
 
     auto iteration = [&](int par, hipStream_t s) -> hipError_t {
         double *cur = u[par], *prev = u[1 - par];
-        hipError_t e = launch_hay_spmv(mat.is_complex, td, n_tiles, cfg.xcd_remap, log2s, mat.col, val,
-                                       mat.slice_off, mat.onsite64, cur, prev, y, hs, cnt, part, s);
+        hipError_t e = launch_hay_spmv(mat.is_complex, td, n_tiles, lc.xcd_remap, log2s, mat.col, val,
+                                       mat.slice_off, mat.uniform_w, mat.onsite64, cur, prev, y, hs, cnt, part, s);
         if (e == hipSuccess)
             e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 0, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
-        if (e == hipSuccess) e = launch_hay_axpy(td, n_tiles, cfg.xcd_remap, 1, log2s, y, cur, prev, hs, part, s);
+        if (e == hipSuccess) e = launch_hay_axpy(td, n_tiles, lc.xcd_remap, 1, log2s, y, cur, prev, hs, part, s);
         if (e == hipSuccess)
             e = launch_hay_reduce(part, n_tiles, s_pad, s_user, 1, thr, hs, cnt, n_iter, a_out, b_out, fold, s);
         return e;

@@ -187,10 +187,11 @@ std::vector<double> fermi_cheb_coeffs(double beta, double mu, double rescale, do
 
 // backward launchers (backward.hip)
 // Haydock recursion launchers (haydock.hip); mode: 0 a_i, 1 b_{i+1}, 2 initial norm
+// uniform_w as in PassParams
 hipError_t launch_hay_spmv(bool cplx, const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t log2s,
-                           const int32_t *col, const void *val, const uint32_t *slice_off, const double *onsite,
-                           const double *u, const double *uprev, double *y, const double *hs, int32_t *counter,
-                           double *partials, hipStream_t st);
+                           const int32_t *col, const void *val, const uint32_t *slice_off, int32_t uniform_w,
+                           const double *onsite, const double *u, const double *uprev, double *y, const double *hs,
+                           int32_t *counter, double *partials, hipStream_t st);
 hipError_t launch_hay_axpy(const TileDesc *tiles, int32_t n_tiles, int32_t xcd_remap, int32_t reverse, int32_t log2s,
                            const double *y, const double *u, double *unext, const double *hs, double *partials,
                            hipStream_t st);
