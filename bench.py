@@ -791,7 +791,7 @@ def main():
     ap.add_argument("--hbm-cells", type=int, default=3072, help="cells per side of the HBM-resident leg")
     ap.add_argument("--hbm-nt", type=int, default=64)
     ap.add_argument("--no-hbm", action="store_true")
-    ap.add_argument("--only", choices=["small", "hbm", "backward"], default=None,
+    ap.add_argument("--only", choices=["small", "hbm", "backward", "next", "tbg"], default=None,
                     help="run one leg alone and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -814,6 +814,22 @@ def main():
         return
     if args.only == "backward":
         print(json.dumps({"backward": bench_backward(args, log)}), flush=True)
+        return
+    if args.only == "tbg":
+        print(json.dumps({"twisted_bilayer": bench_tbg(args, log)}), flush=True)
+        return
+    if args.only == "next":
+        # the next-rows legs on the headline's FP64 launch shape (autotuned on
+        # the headline operator, or read from --tune-cache)
+        cfg64 = None
+        if not args.no_autotune:
+            lat, _ = inputs.workload_disordered_graphene(args.cells, args.states)
+            H = tbpm.Hamiltonian.from_lattice(lat)
+            cfg64, _, _ = tbpm.autotune_cached(H, args.states, "fp64", args.tune_cache)
+            H.close()
+            del H, lat
+            torch.cuda.empty_cache()
+        print(json.dumps(bench_ldos_psi_t(args, log, cfg64)), flush=True)
         return
     dev = torch.device("cuda:0")
     f = 9.0
