@@ -67,8 +67,23 @@ __device__ __forceinline__ void stv(T *p, T v) {
 // that read what the previous launch wrote alternate the walking direction:
 // the tiles a launch starts with are then the ones the previous launch
 // finished with, whose rows are still in the caches.
+// remap = g in 2..4: runs of G = 2^g consecutive tiles per XCD, the runs
+// dealt to the XCDs in turn, so that a tile's neighbours in the row order
+// share its XCD's L2 while all XCDs work on one compact front: block b (on
+// XCD b & 7, its i = (b >> 3)-th there) takes tile ((i / G) 8 + (b & 7)) G +
+// i mod G.  That maps every group of 8 G blocks onto the same 8 G tiles; the
+// tiles past the last whole group are taken in order.
 __device__ __forceinline__ int tile_of_block(int b, int n_tiles, int remap, int reverse = 0) {
     if (!remap) return reverse ? n_tiles - 1 - b : b;
+    if (remap >= 2) {
+        const int full = (n_tiles >> (remap + 3)) << (remap + 3);
+        int t = b;
+        if (b < full) {
+            const int i = b >> 3;
+            t = ((((i >> remap) << 3) + (b & 7)) << remap) + (i & ((1 << remap) - 1));
+        }
+        return reverse ? n_tiles - 1 - t : t;
+    }
     const int q = n_tiles >> 3, r = n_tiles & 7;
     const int x = b & 7, i = b >> 3;
     // XCD x walks its contiguous range of q (+1) tiles, first to last or, with

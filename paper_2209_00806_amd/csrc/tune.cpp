@@ -47,9 +47,9 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     tbpm_launch_config keep = eng.cfgs[fp32 ? 1 : 0], win = keep;
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
-    // plain shapes: chunks x unroll x vec x (remap, non-temporal); staged shapes, tier outer: LDS tier 1 x vec x
-    // (remap, non-temporal), and for wide rows tiers 2-4 x vec x remap; fused shapes (sparse rows): LDS tier x vec,
-    // XCD remap and non-temporal streams.  Staged and fused tile tables depend on the row bytes and the tier only,
+    // plain shapes: chunks x unroll x vec x (remap 0/1, non-temporal); staged shapes, tier outer: LDS tier 1 x vec x
+    // (remap, non-temporal), and for wide rows tiers 2-4 x vec x remap (remap 0-4 for wide rows); fused shapes
+    // (sparse rows): LDS tier x vec x remap 1-4, non-temporal streams.  Staged and fused tile tables depend on the row bytes and the tier only,
     // so the vec variants of a tier share them when they are tried one after the other.
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
@@ -66,11 +66,12 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
                         if (un <= ch) cands.push_back(tbpm_launch_config{ch, remap, nt, un, 0, vec, 0});
     }
     // the staged shape; for wide rows also the smaller LDS tiers, where the
-    // halo sets the trade between tile size and resident workgroups
+    // halo sets the trade between tile size and resident workgroups, and the
+    // tile orders that give each XCD runs of consecutive tiles
     for (int tier = 1; tier <= (wide_rows ? 4 : 1); ++tier)
         for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
             if (!vec_ok(vec)) continue;
-            for (int remap = 0; remap <= 1; ++remap)
+            for (int remap = 0; remap <= (wide_rows ? 4 : 1); ++remap)
                 for (int nt = 0; nt <= (tier == 1 ? 1 : 0); ++nt)
                     cands.push_back(tbpm_launch_config{2, remap, nt, 1, tier, vec, 0});
         }
@@ -79,7 +80,9 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     if (!wide_rows)
         for (int tier = 1; tier <= kFusedTiers; ++tier)
             for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2)
-                if (!(fp32 && vec == 1 && s_pad > 1)) cands.push_back(tbpm_launch_config{2, 1, 1, 1, 0, vec, tier});
+                if (!(fp32 && vec == 1 && s_pad > 1))
+                    for (int remap = 1; remap <= 4; ++remap)
+                        cands.push_back(tbpm_launch_config{2, remap, 1, 1, 0, vec, tier});
     // time one shape on `steps` time steps (after a warm-up run that builds
     // its tiles and graphs); ms per step, or a negative value on failure
     auto time_cfg = [&](const tbpm_launch_config &cand, int32_t steps) -> double {

@@ -143,6 +143,51 @@ def test_launch_configs_and_graph_agree():
     assert np.array_equal(again, got)
 
 
+def test_grouped_tile_orders():
+    """Tile orders 2-4 give each XCD runs of 4, 8 or 16 consecutive tiles.
+    On lattices with a few hundred tiles (a whole number of groups of 8 runs
+    plus a tail taken in order, walked in both directions by alternate
+    launches) the plain, staged and fused shapes, and the staged shape's
+    FP64 state blocks on wide rows, give the result of the round-robin order
+    and of the oracle: every tile is taken exactly once."""
+    print("case grouped tile orders", flush=True)
+    rng = np.random.default_rng(67)
+    lat = inputs.graphene(96, 96, onsite=inputs.anderson(rng, 2 * 96 * 96, 1.0))
+    psi0 = inputs.random_phase_states(rng, lat.n_orb, 4)
+    f = 9.0
+    dt = math.pi / f
+    nt = 12
+    H = tbpm.Hamiltonian.from_lattice(lat)
+    H.set_launch_config(1, 0, 0, 1, vec=1)
+    base = tbpm.propagate(H, _dev(psi0), nt, dt, f, graph=False).cpu().numpy()
+    ref, _, _ = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0, nt, dt, f)
+    assert _rel(base, ref) < 1e-12
+    shapes = (dict(wg_chunks=1, vec=1), dict(wg_chunks=2, vec=2), dict(staged=1, vec=2), dict(fused=2, vec=2),
+              dict(fused=5, vec=1))
+    for remap in (2, 3, 4):
+        for kw in shapes:
+            H.set_launch_config(**dict(dict(wg_chunks=2, xcd_remap=remap, nontemporal=1, unroll=1), **kw))
+            got = tbpm.propagate(H, _dev(psi0), nt, dt, f).cpu().numpy()
+            assert _rel(got, base) < 1e-13, (remap, kw)
+    # wide rows: FP64 rows of 16 states run as two blocks of 8, each block of
+    # a tile a workgroup of its own on the tile's XCD
+    tb = inputs.twisted_bilayer(48, 48, angle_deg=2.0)
+    S = 16
+    psi_t = inputs.random_phase_states(rng, tb.n_orb, S)
+    ft = oracle.gershgorin(tb.row_ptr, tb.val, tb.onsite) * 1.01
+    dtt = math.pi / ft
+    Ht = tbpm.Hamiltonian.from_lattice(tb)
+    Ht.set_launch_config(2, 1, 1, 1, staged=0)
+    plain = tbpm.propagate(Ht, _dev(psi_t), 8, dtt, ft).cpu().numpy()
+    ref_t, _, _ = oracle.propagate(tb.row_ptr, tb.col, tb.val, tb.onsite, psi_t, 8, dtt, ft)
+    assert _rel(plain, ref_t) < 1e-12
+    for remap in (2, 3, 4):
+        for tier, vec in ((3, 2), (4, 4)):
+            Ht.set_launch_config(2, remap, 0, 1, staged=tier, vec=vec)
+            got = tbpm.propagate(Ht, _dev(psi_t), 8, dtt, ft).cpu().numpy()
+            assert _rel(got, plain) < 1e-13, (remap, tier, vec)
+
+
 @pytest.mark.parametrize("name", ["graphene6x6_disorder", "graphene4x5_complex", "tbg8x8"])
 def test_fp32_mixed_small(name):
     print(f"case fp32 {name}", flush=True)
@@ -486,7 +531,7 @@ def test_staged_lds_tiers(precision):
     # out-of-range shapes are rejected on the host, the handle keeps its shape
     before = H.launch_config(precision)
     for bad in (dict(staged=7), dict(staged=-1), dict(fused=7), dict(vec=3), dict(unroll=3),
-                dict(wg_chunks=3), dict(xcd_remap=2)):
+                dict(wg_chunks=3), dict(xcd_remap=5), dict(xcd_remap=-1)):
         with pytest.raises(tbpm.TBPMError):
             H.set_launch_config(**dict(dict(wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1), **bad),
                                 precision=precision)
