@@ -475,13 +475,16 @@ def bench_backward(args, log):
     # shapes can tie on this cache-resident lattice while the backward runs
     # much faster fused (two adjoint orders per launch), so the shape is
     # chosen on a short forward + backward among the tuner's pick and the
-    # fused shape at LDS tiers 2-4
+    # fused shape at LDS tiers 2-4, with one contiguous range of tiles per XCD
+    # or runs of 16 tiles dealt to the XCDs in turn
     cfg, _, _ = tbpm.autotune_cached(H, 4, "fp64", args.tune_cache)
     cands = [cfg]
     for tier in (2, 3, 4):
-        c = {"wg_chunks": 2, "xcd_remap": 1, "nontemporal": 1, "unroll": 1, "staged": 0, "vec": 2, "fused": tier}
-        if all(c != d for d in cands):
-            cands.append(c)
+        for remap in (1, 4):
+            c = {"wg_chunks": 2, "xcd_remap": remap, "nontemporal": 1, "unroll": 1, "staged": 0, "vec": 2,
+                 "fused": tier}
+            if all(c != d for d in cands):
+                cands.append(c)
     trials = []
     for c in cands:
         H.set_launch_config(c["wg_chunks"], c["xcd_remap"], c["nontemporal"], c["unroll"], c.get("staged", 0),
@@ -791,7 +794,7 @@ def main():
     ap.add_argument("--hbm-cells", type=int, default=3072, help="cells per side of the HBM-resident leg")
     ap.add_argument("--hbm-nt", type=int, default=64)
     ap.add_argument("--no-hbm", action="store_true")
-    ap.add_argument("--only", choices=["small", "hbm", "backward", "next", "tbg"], default=None,
+    ap.add_argument("--only", choices=["small", "hbm", "backward", "next", "tbg", "batched"], default=None,
                     help="run one leg alone and print its record (for profiling)")
     args = ap.parse_args()
 
@@ -814,6 +817,9 @@ def main():
         return
     if args.only == "backward":
         print(json.dumps({"backward": bench_backward(args, log)}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(args, log)}), flush=True)
         return
     if args.only == "tbg":
         print(json.dumps({"twisted_bilayer": bench_tbg(args, log)}), flush=True)
