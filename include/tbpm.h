@@ -514,9 +514,9 @@ tbpm_status tbpm_propagate_batched(tbpm_batch *B, const double *const *psi0, int
  *               one chunk is 256 state elements
  *   xcd_remap   order in which the 8 XCDs take the tiles.  0: workgroup b
  *               takes tile b (consecutive tiles on different XCDs);
- *               1: each XCD a contiguous range of tiles; 2, 3, 4: runs of
- *               4, 8, 16 consecutive tiles per XCD, the runs dealt to the
- *               XCDs in turn
+ *               1: each XCD a contiguous range of tiles; 2 .. 6: runs of
+ *               2^xcd_remap (4 .. 64) consecutive tiles per XCD, the runs
+ *               dealt to the XCDs in turn
  *   nontemporal 1: stream the read-once vectors with non-temporal hints
  *   unroll      elements each thread handles at once (1 or 2)
  *   staged      1 .. 6: each workgroup first copies the distinct rows of x

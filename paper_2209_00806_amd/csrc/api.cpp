@@ -25,7 +25,7 @@ namespace {
 
 bool valid_cfg(const tbpm_launch_config &c) {
     const int ok[] = {1, 2, 4, 8, 16, 32};
-    return std::find(std::begin(ok), std::end(ok), c.wg_chunks) != std::end(ok) && (c.xcd_remap >= 0 && c.xcd_remap <= 4) &&
+    return std::find(std::begin(ok), std::end(ok), c.wg_chunks) != std::end(ok) && (c.xcd_remap >= 0 && c.xcd_remap <= 6) &&
            (c.nontemporal == 0 || c.nontemporal == 1) && (c.unroll == 1 || c.unroll == 2) &&
            (c.staged >= 0 && c.staged <= kFusedTiers) && (c.vec == 1 || c.vec == 2 || c.vec == 4) &&
            (c.fused >= 0 && c.fused <= kFusedTiers);

@@ -67,7 +67,7 @@ __device__ __forceinline__ void stv(T *p, T v) {
 // that read what the previous launch wrote alternate the walking direction:
 // the tiles a launch starts with are then the ones the previous launch
 // finished with, whose rows are still in the caches.
-// remap = g in 2..4: runs of G = 2^g consecutive tiles per XCD, the runs
+// remap = g in 2..6: runs of G = 2^g consecutive tiles per XCD, the runs
 // dealt to the XCDs in turn, so that a tile's neighbours in the row order
 // share its XCD's L2 while all XCDs work on one compact front: block b (on
 // XCD b & 7, its i = (b >> 3)-th there) takes tile ((i / G) 8 + (b & 7)) G +

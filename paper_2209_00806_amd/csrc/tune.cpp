@@ -48,8 +48,8 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     double win_ms = 1e300;
     if (e != hipSuccess) st = hip_fail(e, "autotune setup");
     // plain shapes: chunks x unroll x vec x (remap 0/1, non-temporal); staged shapes, tier outer: LDS tier 1 x vec x
-    // (remap, non-temporal), and for wide rows tiers 2-4 x vec x remap (remap 0-4 for wide rows); fused shapes
-    // (sparse rows): LDS tier x vec x remap 1-4, non-temporal streams.  Staged and fused tile tables depend on the row bytes and the tier only,
+    // (remap, non-temporal), and for wide rows tiers 2-4 x vec x remap (remap 0-6 for wide rows); fused shapes
+    // (sparse rows): LDS tier x vec x remap 1-6, non-temporal streams.  Staged and fused tile tables depend on the row bytes and the tier only,
     // so the vec variants of a tier share them when they are tried one after the other.
     std::vector<tbpm_launch_config> cands;
     int32_t s_pad = 1;
@@ -71,7 +71,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
     for (int tier = 1; tier <= (wide_rows ? 4 : 1); ++tier)
         for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2) {
             if (!vec_ok(vec)) continue;
-            for (int remap = 0; remap <= (wide_rows ? 4 : 1); ++remap)
+            for (int remap = 0; remap <= (wide_rows ? 6 : 1); ++remap)
                 for (int nt = 0; nt <= (tier == 1 ? 1 : 0); ++nt)
                     cands.push_back(tbpm_launch_config{2, remap, nt, 1, tier, vec, 0});
         }
@@ -81,7 +81,7 @@ tbpm_status autotune_impl(Engine &eng, const std::vector<double> &rescale, int32
         for (int tier = 1; tier <= kFusedTiers; ++tier)
             for (int vec = 1; vec <= 4 && vec <= s_pad; vec *= 2)
                 if (!(fp32 && vec == 1 && s_pad > 1))
-                    for (int remap = 1; remap <= 4; ++remap)
+                    for (int remap = 1; remap <= 6; ++remap)
                         cands.push_back(tbpm_launch_config{2, remap, 1, 1, 0, vec, tier});
     // time one shape on `steps` time steps (after a warm-up run that builds
     // its tiles and graphs); ms per step, or a negative value on failure

@@ -144,7 +144,7 @@ def test_launch_configs_and_graph_agree():
 
 
 def test_grouped_tile_orders():
-    """Tile orders 2-4 give each XCD runs of 4, 8 or 16 consecutive tiles.
+    """Tile orders 2-6 give each XCD runs of 4 to 64 consecutive tiles.
     On lattices with a few hundred tiles (a whole number of groups of 8 runs
     plus a tail taken in order, walked in both directions by alternate
     launches) the plain, staged and fused shapes, and the staged shape's
@@ -152,7 +152,7 @@ def test_grouped_tile_orders():
     and of the oracle: every tile is taken exactly once."""
     print("case grouped tile orders", flush=True)
     rng = np.random.default_rng(67)
-    lat = inputs.graphene(96, 96, onsite=inputs.anderson(rng, 2 * 96 * 96, 1.0))
+    lat = inputs.graphene(136, 128, onsite=inputs.anderson(rng, 2 * 136 * 128, 1.0))
     psi0 = inputs.random_phase_states(rng, lat.n_orb, 4)
     f = 9.0
     dt = math.pi / f
@@ -164,7 +164,7 @@ def test_grouped_tile_orders():
     assert _rel(base, ref) < 1e-12
     shapes = (dict(wg_chunks=1, vec=1), dict(wg_chunks=2, vec=2), dict(staged=1, vec=2), dict(fused=2, vec=2),
               dict(fused=5, vec=1))
-    for remap in (2, 3, 4):
+    for remap in (2, 3, 4, 5, 6):
         for kw in shapes:
             H.set_launch_config(**dict(dict(wg_chunks=2, xcd_remap=remap, nontemporal=1, unroll=1), **kw))
             got = tbpm.propagate(H, _dev(psi0), nt, dt, f).cpu().numpy()
@@ -181,7 +181,7 @@ def test_grouped_tile_orders():
     plain = tbpm.propagate(Ht, _dev(psi_t), 8, dtt, ft).cpu().numpy()
     ref_t, _, _ = oracle.propagate(tb.row_ptr, tb.col, tb.val, tb.onsite, psi_t, 8, dtt, ft)
     assert _rel(plain, ref_t) < 1e-12
-    for remap in (2, 3, 4):
+    for remap in (2, 3, 4, 5):
         for tier, vec in ((3, 2), (4, 4)):
             Ht.set_launch_config(2, remap, 0, 1, staged=tier, vec=vec)
             got = tbpm.propagate(Ht, _dev(psi_t), 8, dtt, ft).cpu().numpy()
@@ -531,7 +531,7 @@ def test_staged_lds_tiers(precision):
     # out-of-range shapes are rejected on the host, the handle keeps its shape
     before = H.launch_config(precision)
     for bad in (dict(staged=7), dict(staged=-1), dict(fused=7), dict(vec=3), dict(unroll=3),
-                dict(wg_chunks=3), dict(xcd_remap=5), dict(xcd_remap=-1)):
+                dict(wg_chunks=3), dict(xcd_remap=7), dict(xcd_remap=-1)):
         with pytest.raises(tbpm.TBPMError):
             H.set_launch_config(**dict(dict(wg_chunks=2, xcd_remap=1, nontemporal=1, unroll=1), **bad),
                                 precision=precision)
