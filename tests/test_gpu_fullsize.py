@@ -105,16 +105,16 @@ def test_batch_workload_full_size_sampled():
     """64 uneven members (square/graphene, 1e4..1e6 orbitals), 4 states, one
     launch sequence, in the default launch shape and in the shapes the bench's
     tuner picks (two orders per launch, LDS tier 2; 2 states per thread in
-    FP64, 4 in FP32-mixed): a 24-step prefix of sampled members/states against
-    the oracle (FP64 to 1e-10, FP32 to 1e-5 of max |C|), and norm conservation
-    of every member."""
+    FP64, 4 in FP32-mixed): a 128-sample prefix (127 time steps, 2159 sparse
+    passes) of sampled members/states against the oracle (FP64 to 1e-10, FP32
+    to 1e-5 of max |C|), and norm conservation of every member."""
     print("case batch 64 members", flush=True)
     lats, states = inputs.workload_batch(64)
     hams = [tbpm.Hamiltonian.from_lattice(l) for l in lats]
     fs = [h.info()["gershgorin"] for h in hams]
     dts = [math.pi / f for f in fs]
     B = tbpm.Batch(hams)
-    nt = 24
+    nt = 128
     order = np.argsort([l.n_orb for l in lats])
     sample = [int(i) for i in (order[0], order[len(order) // 2], order[-1])]
     refs = {i: oracle.propagate(lats[i].row_ptr, lats[i].col, lats[i].val, lats[i].onsite,
