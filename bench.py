@@ -696,10 +696,10 @@ def cpu_baseline_leg(args, log, stash, extra, S, nt):
         return e
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    c2 = stash["c2"]
-    lat, f, dt = c2["lat"], c2["f"], c2["dt"]
+    hl = stash["headline"]
+    lat, f, dt = hl["lat"], hl["f"], hl["dt"]
     n_pass = tbpm.num_terms(f * dt, 1e-12) - 1
-    one_state = c2["psi0"]
+    one_state = hl["psi0"]
     # calibrate: 2 correlation samples = 1 time step
     tc = time.perf_counter()
     oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, one_state, 2, dt, f)
@@ -715,9 +715,9 @@ def cpu_baseline_leg(args, log, stash, extra, S, nt):
     log(f"cpu oracle: {cpu['value']:.3e} nnz-updates/s on {threads} threads ({tcpu:.1f}s)")
     par = {}
     n = ref.shape[0]
-    par["headline_fp64"] = errs(c2["fp64"][:n], ref[:, 0], dt)
-    if "fp32" in c2:
-        par["headline_fp32_mixed"] = errs(c2["fp32"][:n], ref[:, 0], dt)
+    par["headline_fp64"] = errs(hl["fp64"][:n], ref[:, 0], dt)
+    if "fp32" in hl:
+        par["headline_fp32_mixed"] = errs(hl["fp32"][:n], ref[:, 0], dt)
         extra["fp32_mixed"]["vs_fp64_oracle"] = par["headline_fp32_mixed"]
     sm = stash.get("small")
     if sm:
@@ -847,7 +847,7 @@ def main():
     log(f"workload built: N={lat.n_orb} nnz={lat.nnz} in {time.time() - t0:.1f}s")
     H = tbpm.Hamiltonian.from_lattice(lat)
     psi0 = torch.from_numpy(psi0_np).to(dev)
-    stash = {"c2": {"lat": lat, "psi0": psi0_np[:, :1].copy(), "dt": dt, "f": f}}
+    stash = {"headline": {"lat": lat, "psi0": psi0_np[:, :1].copy(), "dt": dt, "f": f}}
     del psi0_np
     M = tbpm.num_terms(f * dt, 1e-12)
     n_pass = M - 1
@@ -956,7 +956,7 @@ def main():
     extra = {}
     c64 = corr64.cpu().numpy()
     d64 = D64.cpu().numpy()
-    stash["c2"]["fp64"] = c64[:, 0].copy()
+    stash["headline"]["fp64"] = c64[:, 0].copy()
     # plain FP64 with a single state (the per-GPU share of an 8-way state split)
     psi1 = psi0[:, :1].contiguous()
     nt1 = min(nt, 256)
@@ -988,7 +988,7 @@ def main():
         torch.cuda.synchronize()
         ms32 = e0.elapsed_time(e1)
         d32 = D32.cpu().numpy()
-        stash["c2"]["fp32"] = corr32[:, 0].cpu().numpy()
+        stash["headline"]["fp32"] = corr32[:, 0].cpu().numpy()
         l1 = float(np.sum(np.abs(d32 - d64)) / np.sum(np.abs(d64)))
         cerr = float(np.max(np.abs(corr32.cpu().numpy().mean(1) - c64.mean(1))) / np.max(np.abs(c64.mean(1))))
         extra["fp32_mixed"] = {"ms_per_step": round(ms32, 2), "nnz_updates_per_s": updates / (ms32 / 1e3),

@@ -92,9 +92,9 @@ def test_multi_tile_ragged_tail(S, chunks):
     assert np.max(np.abs(n2 - ref_n2)) < 1e-10
 
 
-def test_config1_full_size():
+def test_graphene64_full_size():
     """64x64 periodic graphene, 1 state, 512 steps, f = 9 eV, dt = pi/f, 1024 energies."""
-    print("case config1 64x64 S=1 nt=512", flush=True)
+    print("case graphene 64x64 S=1 nt=512", flush=True)
     lat, psi0 = inputs.workload_graphene_dos(64, 1)
     f = 9.0
     dt = math.pi / f
@@ -199,8 +199,8 @@ def test_fp32_mixed_small(name):
     assert np.max(np.abs(n2 - 1)) < 1e-4
 
 
-def test_fp32_mixed_config1():
-    print("case fp32 config1", flush=True)
+def test_fp32_mixed_graphene64():
+    print("case fp32 graphene 64x64", flush=True)
     lat, psi0 = inputs.workload_graphene_dos(64, 2)
     f = 9.0
     dt = math.pi / f
@@ -210,7 +210,7 @@ def test_fp32_mixed_config1():
     _, Dr = oracle.dos(ref, dt)
     _, D = tbpm.dos(_dev(got), dt)
     err = _l1(D.cpu().numpy(), Dr)
-    print(f"fp32 config1 DOS L1-relative error {err:.3e}", flush=True)
+    print(f"fp32 graphene 64x64 DOS L1-relative error {err:.3e}", flush=True)
     assert err < 1e-4
 
 
@@ -346,17 +346,17 @@ def test_gershgorin_default_rescale_and_set_values():
     del lat2
 
 
-C2_STEPS = 256
+PREFIX_STEPS = 256
 
 
 @pytest.fixture(scope="module")
-def config2_runs():
+def disordered1024_runs():
     """Disordered 1024x1024 graphene (2,097,152 orbitals), 8 states, the first
     256 correlation samples on the GPU: FP64 in the default launch shape and
     in the shape the bench's tuner picks (two orders per launch, LDS tier 2,
     2 states per thread), and FP32-mixed in its tuned shape (4 states per
     thread)."""
-    print("case config2 full size: GPU runs", flush=True)
+    print("case disordered graphene 1024x1024: GPU runs", flush=True)
     lat, psi0 = inputs.workload_disordered_graphene(1024, 8)
     f = 9.0
     dt = math.pi / f
@@ -365,7 +365,7 @@ def config2_runs():
     for shape, prec in (("default", "fp64"), ("bench", "fp64"), ("bench", "fp32")):
         if shape == "bench":
             H.set_launch_config(2, 1, 1, 1, vec=2 if prec == "fp64" else 4, precision=prec, fused=2)
-        corr, n2 = tbpm.propagate(H, _dev(psi0), C2_STEPS, dt, f, precision=prec, return_norm=True)
+        corr, n2 = tbpm.propagate(H, _dev(psi0), PREFIX_STEPS, dt, f, precision=prec, return_norm=True)
         runs[(shape, prec)] = (corr.cpu().numpy(), n2.cpu().numpy())
     H.close()
     return lat, psi0, f, dt, runs
@@ -373,15 +373,15 @@ def config2_runs():
 
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("s", [0, 5])
-def test_config2_full_size_256_steps(config2_runs, s):
+def test_disordered_graphene1024_256_steps(disordered1024_runs, s):
     """A 256-sample prefix (255 time steps, 4335 sparse passes) of one sampled
     state of the disordered 1024x1024 workload against the oracle, in every
     launch shape the bench times: FP64 to 1e-10 of max |C|; FP32-mixed to
     1e-5 of max |C| and its prefix DOS to 1e-4 (L1) of the FP64 oracle's;
     the norm at every sample."""
-    lat, psi0, f, dt, runs = config2_runs
-    print(f"case config2 full size: oracle state {s}", flush=True)
-    ref = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), C2_STEPS, dt, f)[0]
+    lat, psi0, f, dt, runs = disordered1024_runs
+    print(f"case disordered graphene 1024x1024: oracle state {s}", flush=True)
+    ref = oracle.propagate(lat.row_ptr, lat.col, lat.val, lat.onsite, psi0[:, s:s + 1].copy(), PREFIX_STEPS, dt, f)[0]
     _, Dr = oracle.dos(ref, dt)
     for (shape, prec), (corr, n2) in runs.items():
         bar = 1e-10 if prec == "fp64" else 1e-5

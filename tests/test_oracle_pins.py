@@ -131,7 +131,7 @@ def test_small_lattices_vs_ed(name, tol, bound):
     assert np.max(np.abs(norm2 - 1)) < bound
 
 
-def test_config1_full_size_vs_bloch():
+def test_graphene64_full_size_vs_bloch():
     """64x64 periodic graphene, 512 steps at f = 9 eV, dt = pi/f: the oracle's
     C_k against the exact Bloch-basis correlation of the same state."""
     lat, psi0 = inputs.workload_graphene_dos(64, 1)
