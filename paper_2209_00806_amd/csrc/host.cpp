@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -13,6 +14,8 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "tbpm_engine.h"
@@ -384,16 +387,31 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
 // ---------------------------------------------------------------------------
 // locality order: recursive bisection of the row graph
 // ---------------------------------------------------------------------------
-std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf) {
-    std::vector<int32_t> order(n), mark(n, 0), seen(n, 0), q, du(n, 0), dv(n, 0);
+std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf,
+                                     int32_t max_threads) {
+    std::vector<int32_t> order(n);
     for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
-    int32_t stamp = 0, visit = 0;
-    // breadth-first order of the part (rows with mark == stamp) from s, then
-    // from the first unvisited row of each remaining piece, with the level of
-    // every row in dist (pieces after the first continue the level count);
-    // returns the last row
-    auto bfs = [&](int32_t s, int64_t lo, int64_t hi, std::vector<int32_t> &dist) {
-        ++visit;
+    // The parts of one level of the recursion are disjoint sets of rows, and
+    // each part is reordered inside its own range of `order`, so the parts of
+    // a level are processed by several threads at once; the result does not
+    // depend on which thread takes which part.  Per-row state (seen, du, dv)
+    // is touched only for the rows of the part being processed.  `mark` is
+    // also read for neighbour rows that belong to other parts, so it is
+    // atomic; every part and every breadth-first search takes a tag of its
+    // own, so a row of another part never carries the reader's tag.
+    std::unique_ptr<std::atomic<int32_t>[]> mark(new std::atomic<int32_t>[std::max<int64_t>(n, 1)]());
+    std::vector<int32_t> seen(n, 0), du(n, 0), dv(n, 0);
+    std::atomic<int32_t> tags{0};
+    struct Scratch {
+        std::vector<int32_t> q, rank;
+    };
+    // breadth-first order of the part (rows tagged `stamp`) from s, then from
+    // the first unvisited row of each remaining piece, with the level of every
+    // row in dist (pieces after the first continue the level count); returns
+    // the last row
+    auto bfs = [&](Scratch &w, int32_t stamp, int32_t s, int64_t lo, int64_t hi, std::vector<int32_t> &dist) {
+        const int32_t visit = tags.fetch_add(1, std::memory_order_relaxed) + 1;
+        std::vector<int32_t> &q = w.q;
         q.clear();
         int64_t next = lo;
         int32_t base = 0;
@@ -409,7 +427,7 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
             for (size_t h = q.size() - 1; h < q.size(); ++h)
                 for (int64_t p = row_ptr[q[h]]; p < row_ptr[q[h] + 1]; ++p) {
                     const int32_t c = col[p];
-                    if (mark[c] == stamp && seen[c] != visit) {
+                    if (mark[c].load(std::memory_order_relaxed) == stamp && seen[c] != visit) {
                         seen[c] = visit;
                         dist[c] = dist[q[h]] + 1;
                         q.push_back(c);
@@ -418,25 +436,23 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
         }
         return q.back();
     };
-    std::vector<std::pair<int64_t, int64_t>> stack{{0, n}};
-    std::vector<int32_t> rank;
-    while (!stack.empty()) {
-        const auto [lo, hi] = stack.back();
-        stack.pop_back();
-        if (hi - lo < 2) continue;
-        ++stamp;
-        for (int64_t k = lo; k < hi; ++k) mark[order[k]] = stamp;
+    // one part: reorder [lo, hi) and return the split point, or -1 when the
+    // part is not split further
+    auto part = [&](Scratch &w, int64_t lo, int64_t hi) -> int64_t {
+        if (hi - lo < 2) return -1;
+        const int32_t stamp = tags.fetch_add(1, std::memory_order_relaxed) + 1;
+        for (int64_t k = lo; k < hi; ++k) mark[order[k]].store(stamp, std::memory_order_relaxed);
         // pseudo-peripheral rows u (reached last from the first row) and v
         // (reached last from u)
-        const int32_t u = bfs(order[lo], lo, hi, du);
-        const int32_t v = bfs(u, lo, hi, du);
-        std::copy(q.begin(), q.end(), order.begin() + lo);
-        if (hi - lo <= std::max<int64_t>(leaf, 2)) continue;
+        const int32_t u = bfs(w, stamp, order[lo], lo, hi, du);
+        const int32_t v = bfs(w, stamp, u, lo, hi, du);
+        std::copy(w.q.begin(), w.q.end(), order.begin() + lo);
+        if (hi - lo <= std::max<int64_t>(leaf, 2)) return -1;
         // split along the bisector of u and v: rows ordered by
         // d(u, r) - d(v, r) (ties in breadth-first order from u), so the cut
         // runs straight across the part rather than along a level of one
         // breadth-first search
-        bfs(v, lo, hi, dv);
+        bfs(w, stamp, v, lo, hi, dv);
         // counting sort on the integer key (stable, so ties keep the order from u)
         int32_t kmin = INT32_MAX, kmax = INT32_MIN;
         for (int64_t k = lo; k < hi; ++k) {
@@ -444,15 +460,55 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
             kmin = std::min(kmin, key);
             kmax = std::max(kmax, key);
         }
+        std::vector<int32_t> &rank = w.rank;
         rank.assign((size_t)(kmax - kmin) + 2, 0);
         for (int64_t k = lo; k < hi; ++k) ++rank[(size_t)(du[order[k]] - dv[order[k]] - kmin) + 1];
         for (size_t b = 1; b < rank.size(); ++b) rank[b] += rank[b - 1];
-        q.assign(hi - lo, 0);
-        for (int64_t k = lo; k < hi; ++k) q[rank[(size_t)(du[order[k]] - dv[order[k]] - kmin)]++] = order[k];
-        std::copy(q.begin(), q.end(), order.begin() + lo);
-        const int64_t mid = lo + (hi - lo) / 2;
-        stack.push_back({mid, hi});
-        stack.push_back({lo, mid});
+        w.q.assign(hi - lo, 0);
+        for (int64_t k = lo; k < hi; ++k) w.q[rank[(size_t)(du[order[k]] - dv[order[k]] - kmin)]++] = order[k];
+        std::copy(w.q.begin(), w.q.end(), order.begin() + lo);
+        return lo + (hi - lo) / 2;
+    };
+    // threads for large graphs only (at most 16; one below 2^16 rows)
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int n_threads = max_threads > 0 ? max_threads : (n >= (1 << 16) ? (int)std::min(16u, hw) : 1);
+    std::vector<std::pair<int64_t, int64_t>> level{{0, n}}, next;
+    while (!level.empty()) {
+        next.assign(2 * level.size(), {0, 0});
+        std::atomic<size_t> at{0};
+        std::atomic<bool> failed{false};
+        // an exception must not leave a worker thread: it is recorded, and
+        // the calling thread throws once every worker has ended
+        auto run = [&]() {
+            try {
+                Scratch w;
+                for (size_t k = at.fetch_add(1); k < level.size() && !failed.load(); k = at.fetch_add(1)) {
+                    const auto [lo, hi] = level[k];
+                    const int64_t mid = part(w, lo, hi);
+                    if (mid >= 0) {
+                        next[2 * k] = {lo, mid};
+                        next[2 * k + 1] = {mid, hi};
+                    }
+                }
+            } catch (...) {
+                failed.store(true);
+            }
+        };
+        const int t = (int)std::min<size_t>((size_t)n_threads, level.size());
+        std::vector<std::thread> pool;
+        for (int i = 1; i < t; ++i) {
+            try {
+                pool.emplace_back(run);
+            } catch (const std::system_error &) {
+                break;  // fewer threads: the calling thread still takes every remaining part
+            }
+        }
+        run();
+        for (std::thread &th : pool) th.join();
+        if (failed.load()) throw std::bad_alloc();
+        level.clear();
+        for (const auto &pr : next)
+            if (pr.second - pr.first >= 2) level.push_back(pr);
     }
     return order;
 }

@@ -278,8 +278,12 @@ inline size_t fused_lds_budget(int tier) { return (size_t)(160 * 1024 / (tier + 
 // bisection of the row graph; each part is split at the median of
 // d(u, r) - d(v, r) for two pseudo-peripheral rows u, v (graph distances), a
 // cut across the middle of the part; parts of at most 'leaf' rows keep the
-// breadth-first order from u.  perm[new row] = old row.
-std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf);
+// breadth-first order from u.  perm[new row] = old row.  The parts of one
+// level are processed by up to max_threads host threads (0: up to 16 for
+// graphs of at least 2^16 rows, else one); the order does not depend on the
+// thread count.
+std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t leaf,
+                                     int32_t max_threads = 0);
 // false if no R fits the LDS budget of budget bytes (units of unit_bytes,
 // 2^log2u units per row)
 bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int32_t> &col,

@@ -2,12 +2,27 @@
 // (built by tests/test_host_sanitize.py with AddressSanitizer and UBSan; no
 // GPU involved): random Hermitian patterns with duplicate entries, unsorted
 // rows, complex values and, now and then, an out-of-range column that must be
-// rejected.  Prints "ok <accepted> rejected <rejected>".
+// rejected.  The row order must not depend on the number of host threads
+// that build it: every pattern is also ordered on three threads, and two
+// graphs above the threading threshold (a periodic square lattice and a
+// random graph of four components with isolated rows) on 1, 2, 5 and 16
+// threads and on the automatic count.  Prints "ok <accepted> rejected
+// <rejected> orders <graphs whose orders agreed>".
+#include <algorithm>
 #include <cstdio>
 #include <random>
 #include <vector>
 #include "../paper_2209_00806_amd/csrc/tbpm_engine.h"
 using namespace tbpm;
+static bool is_perm(const std::vector<int32_t> &perm, int64_t n) {
+    if ((int64_t)perm.size() != n) return false;
+    std::vector<char> seen(n, 0);
+    for (int32_t p : perm) {
+        if (p < 0 || p >= n || seen[p]) return false;
+        seen[p] = 1;
+    }
+    return true;
+}
 int main() {
     std::mt19937_64 g(7);
     int ok = 0, rej = 0;
@@ -44,12 +59,59 @@ int main() {
         s = check_values(h, hmax);
         if (s != TBPM_OK) { ++rej; continue; }
         HostEll e = build_sliced_ell(h.n, h.row_ptr.data(), h.col.data());
-        std::vector<int32_t> perm = bisection_order(h.n, h.row_ptr.data(), h.col.data(), 1 + g() % 40);
-        std::vector<char> seen(h.n, 0);
-        for (int32_t p : perm) { if (p < 0 || p >= h.n || seen[p]) { std::printf("bad perm\n"); return 1; } seen[p] = 1; }
+        const int32_t leaf = 1 + (int32_t)(g() % 40);
+        std::vector<int32_t> perm = bisection_order(h.n, h.row_ptr.data(), h.col.data(), leaf);
+        if (!is_perm(perm, h.n)) { std::printf("bad perm\n"); return 1; }
+        if (bisection_order(h.n, h.row_ptr.data(), h.col.data(), leaf, 3) != perm) {
+            std::printf("order depends on the thread count (trial %d)\n", trial);
+            return 1;
+        }
         ++ok;
         (void)e;
     }
-    std::printf("ok %d rejected %d\n", ok, rej);
+    int orders = 0;
+    for (int graph = 0; graph < 2; ++graph) {
+        std::vector<int64_t> rp;
+        std::vector<int32_t> col;
+        if (graph == 0) {  // periodic 320 x 320 square lattice
+            const int32_t L = 320;
+            rp.push_back(0);
+            for (int32_t y = 0; y < L; ++y)
+                for (int32_t x = 0; x < L; ++x) {
+                    const int32_t nb[4] = {y * L + (x + L - 1) % L, y * L + (x + 1) % L, ((y + L - 1) % L) * L + x,
+                                           ((y + 1) % L) * L + x};
+                    std::vector<int32_t> r(nb, nb + 4);
+                    std::sort(r.begin(), r.end());
+                    col.insert(col.end(), r.begin(), r.end());
+                    rp.push_back((int64_t)col.size());
+                }
+        } else {  // four random components of 32768 rows, every 97th row isolated
+            const int32_t n = 131072, blk = n / 4;
+            std::vector<std::vector<int32_t>> adj(n);
+            for (int q = 0; q < 3 * n; ++q) {
+                const int32_t i = (int32_t)(g() % n), j = (i / blk) * blk + (int32_t)(g() % blk);
+                if (i == j || i % 97 == 0 || j % 97 == 0) continue;
+                adj[i].push_back(j);
+                adj[j].push_back(i);
+            }
+            rp.push_back(0);
+            for (auto &r : adj) {
+                std::sort(r.begin(), r.end());
+                r.erase(std::unique(r.begin(), r.end()), r.end());
+                col.insert(col.end(), r.begin(), r.end());
+                rp.push_back((int64_t)col.size());
+            }
+        }
+        const int64_t n = (int64_t)rp.size() - 1;
+        const std::vector<int32_t> ref = bisection_order(n, rp.data(), col.data(), 32, 1);
+        if (!is_perm(ref, n)) { std::printf("bad perm\n"); return 1; }
+        for (int32_t t : {2, 5, 16, 0})
+            if (bisection_order(n, rp.data(), col.data(), 32, t) != ref) {
+                std::printf("order of graph %d depends on the thread count (%d threads)\n", graph, t);
+                return 1;
+            }
+        ++orders;
+    }
+    std::printf("ok %d rejected %d orders %d\n", ok, rej, orders);
     return 0;
 }

@@ -1,7 +1,8 @@
 """The library's host code (CSR ingest, sliced-ELL build, row order, two-hop
 tile tables, Fermi-Dirac coefficients) built with AddressSanitizer and UBSan
-by the host compiler and run on seeded inputs (CPU only; the device code is not
-involved).  Any sanitizer report fails the test."""
+by the host compiler, and the row order's threads also with ThreadSanitizer,
+and run on seeded inputs (CPU only; the device code is not involved).  Any
+sanitizer report fails the test."""
 import os
 import shutil
 import subprocess
@@ -17,12 +18,12 @@ HOST = os.path.join(ROOT, "paper_2209_00806_amd", "csrc", "host.cpp")
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
 
 
-def _build(tmp, main):
+def _build(tmp, main, sanitizers="address,undefined"):
     cxx = shutil.which("g++")
     if not cxx or not os.path.exists("/opt/rocm/lib/libamdhip64.so"):
         pytest.skip("g++ or the HIP runtime library is not available")
-    out = os.path.join(tmp, os.path.splitext(os.path.basename(main))[0])
-    cmd = [cxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+    out = os.path.join(tmp, os.path.splitext(os.path.basename(main))[0] + "_" + sanitizers.replace(",", "_"))
+    cmd = [cxx, "-O1", "-g", "-std=c++17", f"-fsanitize={sanitizers}", "-fno-omit-frame-pointer",
            "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", os.path.join(ROOT, "tests", main), HOST,
            "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", out]
     subprocess.run(cmd, check=True, capture_output=True, timeout=600)
@@ -39,8 +40,20 @@ def test_csr_ingest_ell_and_order_under_sanitizers(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=ENV)
     _clean(r)
     assert r.returncode == 0, r.stdout + r.stderr
-    ok, rejected = int(r.stdout.split()[1]), int(r.stdout.split()[3])
-    assert ok > 300 and rejected > 0
+    ok, rejected, orders = int(r.stdout.split()[1]), int(r.stdout.split()[3]), int(r.stdout.split()[5])
+    assert ok > 300 and rejected > 0 and orders == 2
+
+
+def test_row_order_threads_under_thread_sanitizer(tmp_path):
+    """The same sweep built with ThreadSanitizer: the row order's worker
+    threads share the row arrays of disjoint parts, and any reported race
+    fails the test."""
+    exe = _build(str(tmp_path), "host_csr_check.cpp", "thread")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert "ThreadSanitizer" not in r.stdout + r.stderr, r.stdout + r.stderr
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert int(r.stdout.split()[5]) == 2
 
 
 def test_tile_tables_under_sanitizers(tmp_path):
