@@ -101,22 +101,30 @@ bool GraphKey::operator==(const GraphKey &o) const {
 // that its rows reference: the 1-hop halo a tile of the fused shape stages.
 static double halo_cost(const HostCsr &h, const std::vector<int32_t> &perm, const std::vector<int32_t> &inv) {
     const int64_t T = 128;
-    double cost = 0;
-    std::vector<int32_t> ext;
-    for (int64_t t0 = 0; t0 < h.n; t0 += T) {
-        const int64_t t1 = std::min<int64_t>(h.n, t0 + T);
-        ext.clear();
-        for (int64_t r = t0; r < t1; ++r) {
-            const int64_t src = perm.empty() ? r : perm[r];
-            for (int64_t p = h.row_ptr[src]; p < h.row_ptr[src + 1]; ++p) {
-                const int32_t c = perm.empty() ? h.col[p] : inv[h.col[p]];
-                if (c < t0 || c >= t1) ext.push_back(c);
+    const int64_t n_tiles = (h.n + T - 1) / T;
+    // tiles in chunks on host threads; the counts are integers, so the sum
+    // does not depend on the chunking
+    const int threads = host_threads(h.nnz());
+    std::vector<int64_t> part(threads, 0);
+    run_chunks(n_tiles, threads, [&](int k, int64_t lo, int64_t hi) {
+        std::vector<int32_t> ext;
+        for (int64_t t = lo; t < hi; ++t) {
+            const int64_t t0 = t * T, t1 = std::min<int64_t>(h.n, t0 + T);
+            ext.clear();
+            for (int64_t r = t0; r < t1; ++r) {
+                const int64_t src = perm.empty() ? r : perm[r];
+                for (int64_t p = h.row_ptr[src]; p < h.row_ptr[src + 1]; ++p) {
+                    const int32_t c = perm.empty() ? h.col[p] : inv[h.col[p]];
+                    if (c < t0 || c >= t1) ext.push_back(c);
+                }
             }
+            std::sort(ext.begin(), ext.end());
+            part[k] += std::unique(ext.begin(), ext.end()) - ext.begin();
         }
-        std::sort(ext.begin(), ext.end());
-        cost += (double)(std::unique(ext.begin(), ext.end()) - ext.begin());
-    }
-    return cost;
+    });
+    int64_t cost = 0;
+    for (int64_t c : part) cost += c;
+    return (double)cost;
 }
 
 // Row order of one member: empty = the caller's order.  mode 0 keeps it,

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <memory>
 #include <mutex>
@@ -165,6 +166,41 @@ HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *
 // ---------------------------------------------------------------------------
 // CSR validation and canonicalisation (merge duplicates, sort columns)
 // ---------------------------------------------------------------------------
+// Host threads for a pass over `work` items: up to 16 from 2^20 items on,
+// else one.
+int host_threads(int64_t work) {
+    if (work < ((int64_t)1 << 20)) return 1;
+    return (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+}
+
+// f(chunk, lo, hi) for `threads` contiguous chunks of [0, n), chunk k on its
+// own thread (k = 0 on the calling thread).  An exception in a chunk is
+// rethrown as std::bad_alloc once every chunk has ended.
+void run_chunks(int64_t n, int threads, const std::function<void(int, int64_t, int64_t)> &f) {
+    threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n));
+    std::atomic<bool> failed{false};
+    auto chunk = [&](int k) {
+        try {
+            f(k, n * k / threads, n * (k + 1) / threads);
+        } catch (...) {
+            failed.store(true);
+        }
+    };
+    std::vector<std::thread> pool;
+    int k = 1;
+    for (; k < threads; ++k) {
+        try {
+            pool.emplace_back(chunk, k);
+        } catch (const std::system_error &) {
+            break;
+        }
+    }
+    chunk(0);
+    for (; k < threads; ++k) chunk(k);  // chunks no thread could be started for
+    for (std::thread &th : pool) th.join();
+    if (failed.load()) throw std::bad_alloc();
+}
+
 tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                           const double *onsite, HostCsr &out) {
     if (n < 1 || n >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb must be in [1, 2^31-1)");
@@ -177,87 +213,176 @@ tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col,
     if (nnz > 0 && (!col || !val)) return fail(TBPM_E_ARG, "col_idx and val must not be NULL when nnz > 0");
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(onsite[i])) return fail(TBPM_E_ARG, "non-finite on-site energy at " + std::to_string(i));
-    double hmax = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
-            const int64_t c = col[p];
-            if (c < 0 || c >= n)
-                return fail(TBPM_E_CSR, "column " + std::to_string(c) + " out of range in row " + std::to_string(i));
-            if (c == i)
-                return fail(TBPM_E_CSR, "diagonal entry in row " + std::to_string(i) +
-                                            " (pass on-site energies in 'onsite')");
-            if (!std::isfinite(val[2 * p]) || !std::isfinite(val[2 * p + 1]))
-                return fail(TBPM_E_ARG, "non-finite matrix element in row " + std::to_string(i));
-        }
+    // rows in contiguous chunks, one per thread; each chunk notes its first
+    // invalid entry, and the first chunk that has one reports it, so the
+    // error is the one a pass in row order meets first
+    const int threads = host_threads(nnz);
+    struct Bad {
+        int64_t row = -1, c = 0;
+        int kind = 0;  // 1 column out of range, 2 diagonal, 3 non-finite
+    };
+    std::vector<Bad> bad(threads);
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                const int64_t c = col[p];
+                const int kind = (c < 0 || c >= n) ? 1 : c == i ? 2
+                                 : (!std::isfinite(val[2 * p]) || !std::isfinite(val[2 * p + 1])) ? 3 : 0;
+                if (kind) {
+                    bad[k] = Bad{i, c, kind};
+                    return;
+                }
+            }
+    });
+    for (const Bad &b : bad) {
+        if (b.row < 0) continue;
+        if (b.kind == 1)
+            return fail(TBPM_E_CSR, "column " + std::to_string(b.c) + " out of range in row " + std::to_string(b.row));
+        if (b.kind == 2)
+            return fail(TBPM_E_CSR, "diagonal entry in row " + std::to_string(b.row) +
+                                        " (pass on-site energies in 'onsite')");
+        return fail(TBPM_E_ARG, "non-finite matrix element in row " + std::to_string(b.row));
     }
+    // sort each row by column (stable) and sum duplicate columns; chunks
+    // build their rows apart and are then joined in row order
+    struct Part {
+        std::vector<int32_t> col;
+        std::vector<double> val;
+        std::vector<int64_t> len;
+    };
+    std::vector<Part> parts(threads);
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t hi) {
+        Part &pt = parts[k];
+        pt.col.reserve(row_ptr[hi] - row_ptr[lo]);
+        pt.val.reserve(2 * (row_ptr[hi] - row_ptr[lo]));
+        pt.len.reserve(hi - lo);
+        std::vector<std::pair<int32_t, int64_t>> tmp;
+        for (int64_t i = lo; i < hi; ++i) {
+            const size_t before = pt.col.size();
+            tmp.clear();
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) tmp.emplace_back(col[p], p);
+            std::stable_sort(tmp.begin(), tmp.end(),
+                             [](const std::pair<int32_t, int64_t> &a, const std::pair<int32_t, int64_t> &b) {
+                                 return a.first < b.first;
+                             });
+            for (size_t q = 0; q < tmp.size(); ++q) {
+                const int64_t p = tmp[q].second;
+                if (q > 0 && tmp[q].first == tmp[q - 1].first) {
+                    pt.val[pt.val.size() - 2] += val[2 * p];
+                    pt.val[pt.val.size() - 1] += val[2 * p + 1];
+                } else {
+                    pt.col.push_back(tmp[q].first);
+                    pt.val.push_back(val[2 * p]);
+                    pt.val.push_back(val[2 * p + 1]);
+                }
+            }
+            pt.len.push_back((int64_t)(pt.col.size() - before));
+        }
+    });
     out.n = n;
     out.row_ptr.assign(n + 1, 0);
-    out.col.clear();
-    out.val.clear();
-    out.col.reserve(nnz);
-    out.val.reserve(2 * nnz);
-    std::vector<std::pair<int32_t, int64_t>> tmp;
-    for (int64_t i = 0; i < n; ++i) {
-        tmp.clear();
-        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) tmp.emplace_back(col[p], p);
-        std::stable_sort(tmp.begin(), tmp.end(),
-                         [](const std::pair<int32_t, int64_t> &a, const std::pair<int32_t, int64_t> &b) {
-                             return a.first < b.first;
-                         });
-        for (size_t q = 0; q < tmp.size(); ++q) {
-            const int64_t p = tmp[q].second;
-            if (q > 0 && tmp[q].first == tmp[q - 1].first) {
-                out.val[out.val.size() - 2] += val[2 * p];
-                out.val[out.val.size() - 1] += val[2 * p + 1];
-            } else {
-                out.col.push_back(tmp[q].first);
-                out.val.push_back(val[2 * p]);
-                out.val.push_back(val[2 * p + 1]);
+    {
+        int64_t i = 0;
+        for (const Part &pt : parts)
+            for (int64_t l : pt.len) {
+                out.row_ptr[i + 1] = out.row_ptr[i] + l;
+                ++i;
             }
-        }
-        out.row_ptr[i + 1] = (int64_t)out.col.size();
     }
+    out.col.resize(out.row_ptr[n]);
+    out.val.resize(2 * out.row_ptr[n]);
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t) {
+        std::copy(parts[k].col.begin(), parts[k].col.end(), out.col.begin() + out.row_ptr[lo]);
+        std::copy(parts[k].val.begin(), parts[k].val.end(), out.val.begin() + 2 * out.row_ptr[lo]);
+    });
+    parts.clear();
     out.onsite.assign(onsite, onsite + n);
+    double hmax = 0.0;
     return check_values(out, hmax);
 }
 
 tbpm_status check_values(HostCsr &h, double &hmax) {
     const int64_t n = h.n;
+    const int threads = host_threads(h.nnz());
+    // per chunk of rows: the largest |H_ij| and |eps_i|, whether any value is
+    // complex, the first entry without a conjugate partner, the Gershgorin
+    // row sums and the widest row; maxima and the flag do not depend on the
+    // order they are taken in, and the first chunk with a bad entry reports
+    // it, as a pass in row order would
+    struct Acc {
+        double hmax = 0.0, g = 0.0;
+        int64_t mr = 0;
+        bool cplx = false;
+        int64_t bad_row = -1, bad_p = 0;
+    };
+    std::vector<Acc> acc(threads);
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t hi) {
+        Acc &a = acc[k];
+        for (int64_t p = h.row_ptr[lo]; p < h.row_ptr[hi]; ++p) {
+            a.hmax = std::max(a.hmax, std::hypot(h.val[2 * p], h.val[2 * p + 1]));
+            if (h.val[2 * p + 1] != 0.0) a.cplx = true;
+        }
+        for (int64_t i = lo; i < hi; ++i) a.hmax = std::max(a.hmax, std::fabs(h.onsite[i]));
+    });
     hmax = 0.0;
     bool cplx = false;
-    for (size_t p = 0; p < h.col.size(); ++p) {
-        hmax = std::max(hmax, std::hypot(h.val[2 * p], h.val[2 * p + 1]));
-        if (h.val[2 * p + 1] != 0.0) cplx = true;
+    for (const Acc &a : acc) {
+        hmax = std::max(hmax, a.hmax);
+        cplx = cplx || a.cplx;
     }
-    for (int64_t i = 0; i < n; ++i) hmax = std::max(hmax, std::fabs(h.onsite[i]));
     const double tol = 1e-13 * hmax;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) {
-            const int32_t j = h.col[p];
-            const int32_t *b = h.col.data() + h.row_ptr[j];
-            const int32_t *e = h.col.data() + h.row_ptr[j + 1];
-            const int32_t *f = std::lower_bound(b, e, (int32_t)i);
-            if (f == e || *f != i)
-                return fail(TBPM_E_NOT_HERMITIAN, "entry (" + std::to_string(i) + "," + std::to_string(j) +
-                                                      ") has no transposed partner (" + std::to_string(j) + "," +
-                                                      std::to_string(i) + ")");
-            const int64_t q = f - h.col.data();
-            const double dr = h.val[2 * p] - h.val[2 * q];
-            const double di = h.val[2 * p + 1] + h.val[2 * q + 1];
-            if (std::hypot(dr, di) > tol)
-                return fail(TBPM_E_NOT_HERMITIAN, "H(" + std::to_string(i) + "," + std::to_string(j) +
-                                                      ") != conj(H(" + std::to_string(j) + "," +
-                                                      std::to_string(i) + "))");
+    // 0: no partner, 1: partner's value is not the conjugate
+    std::vector<int> bad_kind(threads, 0);
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t hi) {
+        Acc &a = acc[k];
+        for (int64_t i = lo; i < hi; ++i) {
+            for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) {
+                const int32_t j = h.col[p];
+                const int32_t *b = h.col.data() + h.row_ptr[j];
+                const int32_t *e = h.col.data() + h.row_ptr[j + 1];
+                const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+                if (f == e || *f != i) {
+                    a.bad_row = i;
+                    a.bad_p = p;
+                    bad_kind[k] = 0;
+                    return;
+                }
+                const int64_t q = f - h.col.data();
+                const double dr = h.val[2 * p] - h.val[2 * q];
+                const double di = h.val[2 * p + 1] + h.val[2 * q + 1];
+                if (std::hypot(dr, di) > tol) {
+                    a.bad_row = i;
+                    a.bad_p = p;
+                    bad_kind[k] = 1;
+                    return;
+                }
+            }
         }
+    });
+    for (int k = 0; k < threads; ++k) {
+        const Acc &a = acc[k];
+        if (a.bad_row < 0) continue;
+        const std::string i = std::to_string(a.bad_row), j = std::to_string(h.col[a.bad_p]);
+        if (bad_kind[k] == 0)
+            return fail(TBPM_E_NOT_HERMITIAN,
+                        "entry (" + i + "," + j + ") has no transposed partner (" + j + "," + i + ")");
+        return fail(TBPM_E_NOT_HERMITIAN, "H(" + i + "," + j + ") != conj(H(" + j + "," + i + "))");
     }
     h.is_complex = cplx;
+    run_chunks(n, threads, [&](int k, int64_t lo, int64_t hi) {
+        Acc &a = acc[k];
+        for (int64_t i = lo; i < hi; ++i) {
+            double r = std::fabs(h.onsite[i]);
+            for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) r += std::hypot(h.val[2 * p], h.val[2 * p + 1]);
+            a.g = std::max(a.g, r);
+            a.mr = std::max(a.mr, h.row_ptr[i + 1] - h.row_ptr[i]);
+        }
+    });
     double g = 0.0;
     int64_t mr = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        double r = std::fabs(h.onsite[i]);
-        for (int64_t p = h.row_ptr[i]; p < h.row_ptr[i + 1]; ++p) r += std::hypot(h.val[2 * p], h.val[2 * p + 1]);
-        g = std::max(g, r);
-        mr = std::max(mr, h.row_ptr[i + 1] - h.row_ptr[i]);
+    for (const Acc &a : acc) {
+        g = std::max(g, a.g);
+        mr = std::max(mr, a.mr);
     }
     h.gershgorin = g;
     h.max_row = mr;

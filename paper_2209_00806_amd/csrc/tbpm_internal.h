@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -273,6 +274,13 @@ struct TwoHopTables {
 // 160 KiB, i.e. room for t+2 resident workgroups per CU
 constexpr int kFusedTiers = 6;
 inline size_t fused_lds_budget(int tier) { return (size_t)(160 * 1024 / (tier + 2)) & ~(size_t)255; }
+
+// Host threads for a pass over `work` items (up to 16 from 2^20 items on,
+// else one), and f(chunk, lo, hi) run on that many contiguous chunks of
+// [0, n), each on its own thread; an exception in a chunk is rethrown as
+// std::bad_alloc once every chunk has ended.
+int host_threads(int64_t work);
+void run_chunks(int64_t n, int threads, const std::function<void(int, int64_t, int64_t)> &f);
 
 // Row order with locality at every scale, without coordinates: recursive
 // bisection of the row graph; each part is split at the median of

@@ -7,9 +7,12 @@
 // graphs above the threading threshold (a periodic square lattice and a
 // random graph of four components with isolated rows) on 1, 2, 5 and 16
 // threads and on the automatic count.  Prints "ok <accepted> rejected
-// <rejected> orders <graphs whose orders agreed>".
+// <rejected> orders <checks passed>" (3: the two orders and the large
+// pattern below, whose ingest runs on several threads).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <string>
 #include <random>
 #include <vector>
 #include "../paper_2209_00806_amd/csrc/tbpm_engine.h"
@@ -110,6 +113,98 @@ int main() {
                 std::printf("order of graph %d depends on the thread count (%d threads)\n", graph, t);
                 return 1;
             }
+        ++orders;
+    }
+    // a pattern large enough for the ingest to run on several threads:
+    // duplicates and unsorted rows merged as in a single pass, the Gershgorin
+    // bound and the widest row, and the first of two planted errors (in rows
+    // far apart) reported, as a pass in row order meets them
+    {
+        const int64_t n = 300000;
+        std::vector<std::vector<std::pair<int32_t, std::pair<double, double>>>> rows(n);
+        for (int64_t q = 0; q < 3 * n; ++q) {
+            const int32_t i = (int32_t)(g() % n), j = (int32_t)(g() % n);
+            if (i == j) continue;
+            const double re = ((int)(g() % 9) - 4) * 0.25, im = ((int)(g() % 3) - 1) * 0.5;
+            rows[i].push_back({j, {re, im}});
+            rows[j].push_back({i, {re, -im}});
+        }
+        std::vector<int64_t> rp(n + 1, 0);
+        std::vector<int32_t> col;
+        std::vector<double> val, ons(n);
+        for (int64_t i = 0; i < n; ++i) {
+            for (auto &e : rows[i]) {
+                col.push_back(e.first);
+                val.push_back(e.second.first);
+                val.push_back(e.second.second);
+            }
+            rp[i + 1] = (int64_t)col.size();
+            ons[i] = 0.01 * (double)(i % 7);
+        }
+        HostCsr h;
+        if (canonical_csr(n, rp.data(), col.data(), val.data(), ons.data(), h) != TBPM_OK) {
+            std::printf("large pattern rejected: %s\n", last_error().c_str());
+            return 1;
+        }
+        double gmax = 0.0;
+        int64_t widest = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            // merged row: ascending columns, duplicates summed in input order
+            std::vector<std::pair<int32_t, std::pair<double, double>>> r = rows[i];
+            std::stable_sort(r.begin(), r.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            std::vector<std::pair<int32_t, std::pair<double, double>>> m;
+            for (auto &e : r) {
+                if (!m.empty() && m.back().first == e.first) {
+                    m.back().second.first += e.second.first;
+                    m.back().second.second += e.second.second;
+                } else {
+                    m.push_back(e);
+                }
+            }
+            if (h.row_ptr[i + 1] - h.row_ptr[i] != (int64_t)m.size()) {
+                std::printf("large pattern: row %lld merged wrongly\n", (long long)i);
+                return 1;
+            }
+            double rs = std::fabs(ons[i]);
+            for (size_t k = 0; k < m.size(); ++k) {
+                const int64_t p = h.row_ptr[i] + (int64_t)k;
+                if (h.col[p] != m[k].first || h.val[2 * p] != m[k].second.first ||
+                    h.val[2 * p + 1] != m[k].second.second) {
+                    std::printf("large pattern: row %lld merged wrongly\n", (long long)i);
+                    return 1;
+                }
+                rs += std::hypot(m[k].second.first, m[k].second.second);
+            }
+            gmax = std::max(gmax, rs);
+            widest = std::max<int64_t>(widest, (int64_t)m.size());
+        }
+        if (h.gershgorin != gmax || h.max_row != widest || !h.is_complex) {
+            std::printf("large pattern: bound or widest row wrong\n");
+            return 1;
+        }
+        // a diagonal entry early and a column out of range late: the diagonal
+        // comes first in row order
+        const int64_t early = 1000, late = n - 1000;
+        auto c2 = col;
+        c2[rp[early]] = (int32_t)early;
+        c2[rp[late]] = (int32_t)n;
+        HostCsr h2;
+        if (canonical_csr(n, rp.data(), c2.data(), val.data(), ons.data(), h2) != TBPM_E_CSR ||
+            last_error().find("diagonal entry in row 1000 ") == std::string::npos) {
+            std::printf("large pattern: wrong first error: %s\n", last_error().c_str());
+            return 1;
+        }
+        // a value that breaks Hermiticity early and a missing partner late
+        auto v2 = val;
+        v2[2 * rp[early]] += 1.0;
+        c2 = col;
+        c2[rp[late]] = (int32_t)((col[rp[late]] + 1) % n == late ? (col[rp[late]] + 2) % n : (col[rp[late]] + 1) % n);
+        HostCsr h3;
+        if (canonical_csr(n, rp.data(), c2.data(), v2.data(), ons.data(), h3) != TBPM_E_NOT_HERMITIAN ||
+            last_error().find("H(1000,") != 0) {
+            std::printf("large pattern: wrong first Hermiticity error: %s\n", last_error().c_str());
+            return 1;
+        }
         ++orders;
     }
     std::printf("ok %d rejected %d orders %d\n", ok, rej, orders);

@@ -41,7 +41,7 @@ def test_csr_ingest_ell_and_order_under_sanitizers(tmp_path):
     _clean(r)
     assert r.returncode == 0, r.stdout + r.stderr
     ok, rejected, orders = int(r.stdout.split()[1]), int(r.stdout.split()[3]), int(r.stdout.split()[5])
-    assert ok > 300 and rejected > 0 and orders == 2
+    assert ok > 300 and rejected > 0 and orders == 3
 
 
 def test_row_order_threads_under_thread_sanitizer(tmp_path):
@@ -53,7 +53,7 @@ def test_row_order_threads_under_thread_sanitizer(tmp_path):
                        env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
     assert "ThreadSanitizer" not in r.stdout + r.stderr, r.stdout + r.stderr
     assert r.returncode == 0, r.stdout + r.stderr
-    assert int(r.stdout.split()[5]) == 2
+    assert int(r.stdout.split()[5]) == 3
 
 
 def test_tile_tables_under_sanitizers(tmp_path):
