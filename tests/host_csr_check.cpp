@@ -120,7 +120,7 @@ int main() {
     // bound and the widest row, and the first of two planted errors (in rows
     // far apart) reported, as a pass in row order meets them
     {
-        const int64_t n = 300000;
+        const int64_t n = 200000;  // 1.2M stored entries: above the threading threshold of 2^20
         std::vector<std::vector<std::pair<int32_t, std::pair<double, double>>>> rows(n);
         for (int64_t q = 0; q < 3 * n; ++q) {
             const int32_t i = (int32_t)(g() % n), j = (int32_t)(g() % n);
