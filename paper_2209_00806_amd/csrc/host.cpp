@@ -164,7 +164,7 @@ HostEll build_sliced_ell(int64_t n_rows, const int64_t *row_ptr, const int32_t *
 }
 
 // ---------------------------------------------------------------------------
-// CSR validation and canonicalisation (merge duplicates, sort columns)
+// host threads
 // ---------------------------------------------------------------------------
 // Host threads for a pass over `work` items: up to 16 from 2^20 items on,
 // else one.
@@ -187,6 +187,7 @@ void run_chunks(int64_t n, int threads, const std::function<void(int, int64_t, i
         }
     };
     std::vector<std::thread> pool;
+    pool.reserve(threads);  // only a thread that cannot be started throws below
     int k = 1;
     for (; k < threads; ++k) {
         try {
@@ -201,6 +202,9 @@ void run_chunks(int64_t n, int threads, const std::function<void(int, int64_t, i
     if (failed.load()) throw std::bad_alloc();
 }
 
+// ---------------------------------------------------------------------------
+// CSR validation and canonicalisation (merge duplicates, sort columns)
+// ---------------------------------------------------------------------------
 tbpm_status canonical_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                           const double *onsite, HostCsr &out) {
     if (n < 1 || n >= (int64_t)INT32_MAX) return fail(TBPM_E_ARG, "n_orb must be in [1, 2^31-1)");
@@ -621,6 +625,7 @@ std::vector<int32_t> bisection_order(int64_t n, const int64_t *row_ptr, const in
         };
         const int t = (int)std::min<size_t>((size_t)n_threads, level.size());
         std::vector<std::thread> pool;
+        pool.reserve(t);  // only a thread that cannot be started throws below
         for (int i = 1; i < t; ++i) {
             try {
                 pool.emplace_back(run);
