@@ -102,6 +102,10 @@ typedef enum {
  * before the device copy of H is built), TBPM_E_OOM, TBPM_E_DEVICE.  On
  * error *out is NULL.  If every stored element has zero imaginary part the
  * device copy is real.
+ * Host work: the checks, the merge and the internal row order run on up to
+ * 16 host threads for large inputs (from 2^20 stored elements, or 2^16 rows
+ * for the row order), started and joined inside the call; the handle and
+ * every error are the same on any number of threads.
  */
 tbpm_status tbpm_hamiltonian_create(int64_t n_orb, const int64_t *row_ptr, const int32_t *col_idx,
                                     const double *val, const double *onsite, uint32_t flags,
