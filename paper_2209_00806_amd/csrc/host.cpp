@@ -401,11 +401,15 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
                     TwoHopTables &t) {
     const int64_t SR = kSliceRows;
     const int32_t n_inst = (int32_t)inst_row0.size() - 1;
-    std::vector<int32_t> e1, e2;
     auto width = [&](int64_t r) { return (slice_off[r / SR + 1] - slice_off[r / SR]) / SR; };
     auto slot_of = [&](int64_t r, int64_t k) { return slice_off[r / SR] + k * SR + r % SR; };
     auto outside = [](int32_t c, int64_t r0, int64_t rows) { return c < r0 || c >= r0 + rows; };
-    auto collect = [&](int64_t r0, int64_t rows) {
+    // the 1-hop rows e1 and the 2-hop rows e2 of a tile, sorted (per thread)
+    struct Halo {
+        std::vector<int32_t> e1, e2;
+    };
+    auto collect = [&](Halo &hl, int64_t r0, int64_t rows) {
+        std::vector<int32_t> &e1 = hl.e1, &e2 = hl.e2;
         e1.clear();
         e2.clear();
         for (int64_t r = r0; r < r0 + rows; ++r)
@@ -425,41 +429,68 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
     };
     // a tile fits if its two LDS arrays fit the budget: b_{j+1} on x rows and
     // b_j on y rows (local indices are 16-bit)
-    auto fits = [&](int64_t rows) {
-        const size_t x = (size_t)rows + e1.size() + e2.size(), y = (size_t)rows + e1.size();
+    auto fits = [&](const Halo &hl, int64_t rows) {
+        const size_t x = (size_t)rows + hl.e1.size() + hl.e2.size(), y = (size_t)rows + hl.e1.size();
         return ((x + y) << log2u) * (size_t)unit_bytes <= budget && x <= 65535;
     };
-    // tiles of R rows, halved until they fit; visit(r0, rows) for each
-    auto tiling = [&](int64_t R, auto &&visit) {
-        std::vector<std::pair<int64_t, int64_t>> st;
+    // tiles of R rows of one member, halved until they fit: the tiles that
+    // start at the multiples of R are independent, so they are taken in
+    // contiguous chunks on host threads, and each chunk's tiles are visited
+    // (visit(chunk, halo, member, r0, rows)) in row order; false if a single
+    // row does not fit
+    struct Top {
+        int32_t inst;
+        int64_t r0, rows;
+    };
+    std::vector<Top> tops;
+    const int threads = host_threads((int64_t)col.size());
+    auto tiling = [&](int64_t R, int &n_chunks,
+                      const std::function<void(int, const Halo &, int32_t, int64_t, int64_t)> &visit) {
+        tops.clear();
         for (int32_t i = 0; i < n_inst; ++i)
-            for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += R) {
-                st.push_back({r0, std::min<int64_t>(R, inst_row0[i + 1] - r0)});
+            for (int64_t r0 = inst_row0[i]; r0 < inst_row0[i + 1]; r0 += R)
+                tops.push_back(Top{i, r0, std::min<int64_t>(R, inst_row0[i + 1] - r0)});
+        n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (int64_t)tops.size()));
+        std::atomic<bool> ok{true};
+        run_chunks((int64_t)tops.size(), n_chunks, [&](int k, int64_t lo, int64_t hi) {
+            Halo hl;
+            std::vector<std::pair<int64_t, int64_t>> st;
+            for (int64_t q = lo; q < hi && ok.load(std::memory_order_relaxed); ++q) {
+                st.push_back({tops[q].r0, tops[q].rows});
                 while (!st.empty()) {
                     const auto [a, rows] = st.back();
                     st.pop_back();
-                    collect(a, rows);
-                    if (!fits(rows)) {
-                        if (rows == 1) return false;
+                    collect(hl, a, rows);
+                    if (!fits(hl, rows)) {
+                        if (rows == 1) {
+                            ok.store(false);
+                            return;
+                        }
                         st.push_back({a + rows / 2, rows - rows / 2});
                         st.push_back({a, rows / 2});
                         continue;
                     }
-                    visit(i, a, rows);
+                    visit(k, hl, tops[q].inst, a, rows);
                 }
             }
-        return true;
+        });
+        return ok.load();
     };
     // R: the target tile size with the least staged traffic per pair of orders
     // (x on own + 1-hop + 2-hop rows, psi and b_{j+2} on own + 1-hop rows, two
-    // outputs on own rows); ties go to the larger R
+    // outputs on own rows); ties go to the larger R.  Each cost is a sum of
+    // integers, exact in any order.
     t.R = 0;
     double best = 0;
     for (int64_t cand : {256, 128, 64, 32, 16, 8, 4, 2, 1}) {
-        double cost = 0;
-        const bool ok = tiling(cand, [&](int32_t, int64_t, int64_t rows) {
-            cost += (double)(rows + e1.size() + e2.size()) + 2.0 * (double)(rows + e1.size()) + 2.0 * (double)rows;
+        std::vector<double> part(threads, 0.0);
+        int n_chunks = 1;
+        const bool ok = tiling(cand, n_chunks, [&](int k, const Halo &hl, int32_t, int64_t, int64_t rows) {
+            part[k] += (double)(rows + hl.e1.size() + hl.e2.size()) + 2.0 * (double)(rows + hl.e1.size()) +
+                       2.0 * (double)rows;
         });
+        double cost = 0;
+        for (double c : part) cost += c;
         if (ok && (t.R == 0 || cost < best * (1 - 1e-9))) {
             t.R = cand;
             best = cost;
@@ -467,6 +498,51 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
         if (t.R != 0 && t.R >= 4 * cand) break;  // smaller targets only split more
     }
     if (t.R == 0) return false;
+    // the tables of each chunk are built apart and joined in tile order; the
+    // local indices of a slot (lidx) are written in place, each by the tile
+    // that owns the slot's row
+    struct Part {
+        std::vector<TileDesc> tiles;
+        std::vector<int32_t> ucol, n1, hw, usz;  // usz: ucol entries of each tile
+        std::vector<int64_t> hsz;               // hidx entries of each tile
+        std::vector<uint16_t> hidx;
+        size_t max_x = 0, max_y = 0, max_xy = 0;
+    };
+    std::vector<Part> parts(threads);
+    t.lidx.assign(std::max<size_t>(col.size(), 1), 0);
+    int n_chunks = 1;
+    tiling(t.R, n_chunks, [&](int k, const Halo &hl, int32_t i, int64_t r0, int64_t rows) {
+        Part &pt = parts[k];
+        const std::vector<int32_t> &e1 = hl.e1, &e2 = hl.e2;
+        const int64_t n1 = (int64_t)e1.size();
+        pt.max_x = std::max(pt.max_x, (size_t)(rows + n1) + e2.size());
+        pt.max_y = std::max(pt.max_y, (size_t)(rows + n1));
+        pt.max_xy = std::max(pt.max_xy, (size_t)(2 * (rows + n1)) + e2.size());
+        // local row numbering: own rows, then the 1-hop rows, then the 2-hop rows
+        auto local = [&](int32_t c) -> uint16_t {
+            if (!outside(c, r0, rows)) return (uint16_t)(c - r0);
+            auto it = std::lower_bound(e1.begin(), e1.end(), c);
+            if (it != e1.end() && *it == c) return (uint16_t)(rows + (it - e1.begin()));
+            return (uint16_t)(rows + n1 + (std::lower_bound(e2.begin(), e2.end(), c) - e2.begin()));
+        };
+        for (int64_t r = r0; r < r0 + rows; ++r)
+            for (int64_t k2 = 0, w = width(r); k2 < w; ++k2) t.lidx[slot_of(r, k2)] = local(col[slot_of(r, k2)]);
+        int64_t hw = 0;
+        for (int32_t h : e1) hw = std::max<int64_t>(hw, width(h));
+        const size_t h0 = pt.hidx.size();
+        pt.hw.push_back((int32_t)hw);
+        for (int32_t h : e1) {
+            const size_t at = pt.hidx.size();
+            pt.hidx.resize(at + hw, 0);
+            for (int64_t k2 = 0, w = width(h); k2 < w; ++k2) pt.hidx[at + k2] = local(col[slot_of(h, k2)]);
+        }
+        pt.hsz.push_back((int64_t)(pt.hidx.size() - h0));
+        pt.ucol.insert(pt.ucol.end(), e1.begin(), e1.end());
+        pt.ucol.insert(pt.ucol.end(), e2.begin(), e2.end());
+        pt.usz.push_back((int32_t)(e1.size() + e2.size()));
+        pt.n1.push_back((int32_t)n1);
+        pt.tiles.push_back(TileDesc{r0, (int32_t)rows, i});
+    });
     t.tiles.clear();
     t.inst_tile0.assign(n_inst + 1, 0);
     t.uoff.assign(1, 0);
@@ -476,37 +552,32 @@ bool two_hop_tables(const std::vector<int64_t> &slice_off, const std::vector<int
     t.hw.clear();
     t.hidx.clear();
     t.max_x = t.max_y = t.max_xy = 0;
-    t.lidx.assign(std::max<size_t>(col.size(), 1), 0);
-    tiling(t.R, [&](int32_t i, int64_t r0, int64_t rows) {
-        const int64_t n1 = (int64_t)e1.size();
-        t.max_x = std::max(t.max_x, (size_t)(rows + n1) + e2.size());
-        t.max_y = std::max(t.max_y, (size_t)(rows + n1));
-        t.max_xy = std::max(t.max_xy, (size_t)(2 * (rows + n1)) + e2.size());
-        // local row numbering: own rows, then the 1-hop rows, then the 2-hop rows
-        auto local = [&](int32_t c) -> uint16_t {
-            if (!outside(c, r0, rows)) return (uint16_t)(c - r0);
-            auto it = std::lower_bound(e1.begin(), e1.end(), c);
-            if (it != e1.end() && *it == c) return (uint16_t)(rows + (it - e1.begin()));
-            return (uint16_t)(rows + n1 + (std::lower_bound(e2.begin(), e2.end(), c) - e2.begin()));
-        };
-        for (int64_t r = r0; r < r0 + rows; ++r)
-            for (int64_t k = 0, w = width(r); k < w; ++k) t.lidx[slot_of(r, k)] = local(col[slot_of(r, k)]);
-        int64_t hw = 0;
-        for (int32_t h : e1) hw = std::max<int64_t>(hw, width(h));
-        t.hoff.push_back((int32_t)t.hidx.size());
-        t.hw.push_back((int32_t)hw);
-        for (int32_t h : e1) {
-            const size_t at = t.hidx.size();
-            t.hidx.resize(at + hw, 0);
-            for (int64_t k = 0, w = width(h); k < w; ++k) t.hidx[at + k] = local(col[slot_of(h, k)]);
+    for (int k = 0; k < n_chunks; ++k) {
+        const Part &pt = parts[k];
+        t.max_x = std::max(t.max_x, pt.max_x);
+        t.max_y = std::max(t.max_y, pt.max_y);
+        t.max_xy = std::max(t.max_xy, pt.max_xy);
+        for (size_t q = 0; q < pt.tiles.size(); ++q) {
+            t.hoff.push_back((int32_t)t.hidx.size());
+            t.hidx.resize(t.hidx.size() + pt.hsz[q], 0);
+            t.uoff.push_back((int32_t)(t.ucol.size() + pt.usz[q]));
+            t.ucol.resize(t.ucol.size() + pt.usz[q]);
+            t.tiles.push_back(pt.tiles[q]);
+            t.inst_tile0[pt.tiles[q].inst + 1] = (int32_t)t.tiles.size();
         }
-        t.ucol.insert(t.ucol.end(), e1.begin(), e1.end());
-        t.ucol.insert(t.ucol.end(), e2.begin(), e2.end());
-        t.uoff.push_back((int32_t)t.ucol.size());
-        t.n1.push_back((int32_t)n1);
-        t.tiles.push_back(TileDesc{r0, (int32_t)rows, i});
-        t.inst_tile0[i + 1] = (int32_t)t.tiles.size();
-    });
+        t.n1.insert(t.n1.end(), pt.n1.begin(), pt.n1.end());
+        t.hw.insert(t.hw.end(), pt.hw.begin(), pt.hw.end());
+    }
+    // copy each chunk's ucol and hidx into place
+    {
+        size_t u0 = 0, h0 = 0;
+        for (int k = 0; k < n_chunks; ++k) {
+            std::copy(parts[k].ucol.begin(), parts[k].ucol.end(), t.ucol.begin() + u0);
+            std::copy(parts[k].hidx.begin(), parts[k].hidx.end(), t.hidx.begin() + h0);
+            u0 += parts[k].ucol.size();
+            h0 += parts[k].hidx.size();
+        }
+    }
     for (int32_t i = 0; i < n_inst; ++i) t.inst_tile0[i + 1] = std::max(t.inst_tile0[i + 1], t.inst_tile0[i]);
     if (t.ucol.size() >= (size_t)INT32_MAX || t.hidx.size() >= (size_t)INT32_MAX) return false;
     if (t.hidx.empty()) t.hidx.push_back(0);

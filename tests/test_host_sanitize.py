@@ -44,16 +44,23 @@ def test_csr_ingest_ell_and_order_under_sanitizers(tmp_path):
     assert ok > 300 and rejected > 0 and orders == 3
 
 
-def test_row_order_threads_under_thread_sanitizer(tmp_path):
-    """The same sweep built with ThreadSanitizer: the row order's worker
-    threads share the row arrays of disjoint parts, and any reported race
-    fails the test."""
+def test_threaded_host_code_under_thread_sanitizer(tmp_path):
+    """The same sweep built with ThreadSanitizer (the row order's worker
+    threads share the row arrays of disjoint parts; the ingest's chunks share
+    the input), then the two-hop tile tables of a lattice large enough to be
+    built on threads; any reported race fails the test."""
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1")
     exe = _build(str(tmp_path), "host_csr_check.cpp", "thread")
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600,
-                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     assert "ThreadSanitizer" not in r.stdout + r.stderr, r.stdout + r.stderr
     assert r.returncode == 0, r.stdout + r.stderr
     assert int(r.stdout.split()[5]) == 3
+    # the two-hop tile tables of a lattice large enough to be built on threads
+    exe = _build(str(tmp_path), "host_tables_check.cpp", "thread")
+    paths = tables._write(tempfile.mkdtemp(dir=str(tmp_path)), [tables.inputs.graphene(420, 420)])
+    r = subprocess.run([exe, *paths, "1", "2", "32", "2"], capture_output=True, text=True, timeout=600, env=env)
+    assert "ThreadSanitizer" not in r.stdout + r.stderr, r.stdout + r.stderr
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout + r.stderr
 
 
 def test_tile_tables_under_sanitizers(tmp_path):

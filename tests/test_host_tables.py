@@ -76,3 +76,17 @@ def test_two_hop_tables_and_row_order(checker, tmp_path, case, order):
             assert r.stdout.startswith("OK")
             fits += 1
     assert fits > 0
+
+
+def test_two_hop_tables_threaded_build(checker, tmp_path):
+    """A lattice above the threading threshold (420 x 420 graphene, 1.06M
+    stored elements): the tables are built in chunks on host threads and
+    joined in tile order, and must pass the same checks (tables against the
+    CSR, a pair of orders through them against the direct evaluation), in
+    both row orders."""
+    paths = _write(str(tmp_path), [inputs.graphene(420, 420)])
+    for order in (0, 1):
+        for log2u, ub in ((2, 32), (0, 16)):
+            r = subprocess.run([checker, *paths, str(order), str(log2u), str(ub), "2"], capture_output=True,
+                               text=True, timeout=300)
+            assert r.returncode == 0 and r.stdout.startswith("OK"), (order, log2u, ub, r.stdout, r.stderr)
